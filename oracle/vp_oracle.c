@@ -1,0 +1,830 @@
+/*
+ * vp_oracle.c -- plain, slow FP64 CPU oracle for one vegas+ iteration.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source with the HIP library.
+ *
+ * Source: G. P. Lepage, "Adaptive Multidimensional Integration: VEGAS
+ * Enhanced" (arXiv:2009.05112).  Every function names the passage it follows.
+ * The paper leaves the random-number generator, the enumeration order of the
+ * hypercubes and the rounding of each step open; the readings taken here are
+ * listed in the repository's design notes and restated next to the code.
+ *
+ * Every floating-point operation is a single IEEE round-to-nearest operation
+ * (the file is compiled with -ffp-contract=off); fused multiply-adds appear
+ * only where fma() is written.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from its published definition (Salmon, Moraes, Dror and    */
+/* Shaw, "Parallel Random Numbers: As Easy as 1, 2, 3", SC'11, Sec. 3.2).     */
+/* A round multiplies counter words 0 and 2 by two fixed odd constants, and  */
+/* builds the next counter from the high halves xored with the other two     */
+/* words and the round key, and the low halves.  The key is advanced by two  */
+/* Weyl constants between rounds.  The paper fixes no generator; this one is */
+/* keyed by the 64-bit seed and counted by (sample, hypercube, iteration,    */
+/* block), so every sample is reproducible in isolation.                     */
+/* ------------------------------------------------------------------------ */
+#define OR_PHILOX_M0 0xD2511F53u
+#define OR_PHILOX_M1 0xCD9E8D57u
+#define OR_PHILOX_W0 0x9E3779B9u
+#define OR_PHILOX_W1 0xBB67AE85u
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += OR_PHILOX_W0;
+            k1 += OR_PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)OR_PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)OR_PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stratification count, Sec. 3, Eq. (Nst_vegasp): N_st = floor((N_ev/4)^(1/D)).  */
+/* Taken as the largest integer n >= 1 with 4 n^D <= N_ev, found by integer */
+/* search so exact powers are not lost to rounding of the real root.         */
+/* Returns 1 when even n = 1 does not satisfy the bound (then there is a      */
+/* single hypercube), 0 on invalid input.                                     */
+/* ------------------------------------------------------------------------ */
+static int or_pow_le(int64_t n, int32_t dim, int64_t limit)
+{
+    /* 1 if 4 * n^dim <= limit, computed without overflow */
+    int64_t acc = 4;
+    if (acc > limit) return 0;
+    for (int32_t d = 0; d < dim; ++d) {
+        if (acc > limit / n) return 0;
+        acc *= n;
+    }
+    return acc <= limit;
+}
+
+int32_t or_nst(int32_t dim, int64_t n_ev)
+{
+    if (dim < 1 || n_ev < 1) return 0;
+    int64_t n = 1;
+    while (or_pow_le(n + 1, dim, n_ev)) ++n;
+    return (int32_t)n;
+}
+
+/* Classic vegas stratification, Sec. 3, Eq. (Nst): largest n >= 1 with 2 n^D <= N_ev. */
+int32_t or_nst_classic(int32_t dim, int64_t n_ev)
+{
+    if (dim < 1 || n_ev < 1) return 0;
+    int64_t n = 1;
+    for (;;) {
+        int64_t m = n + 1, acc = 2;
+        int ok = 1;
+        for (int32_t d = 0; d < dim; ++d) {
+            if (acc > n_ev / m) { ok = 0; break; }
+            acc *= m;
+        }
+        if (!ok || acc > n_ev) break;
+        n = m;
+    }
+    return (int32_t)n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Integrands.  f(x) as the user defines it; the sampler multiplies by J.     */
+/* ------------------------------------------------------------------------ */
+enum {
+    OR_F_GAUSS_MIX = 1,  /* scale * sum_k amp_k exp(-coef_k |x - c_k|^2)      */
+    OR_F_CORR_GAUSS = 2, /* scale * exp(-1/2 |U (x - mu)|^2), U upper-tri     */
+    OR_F_EXP_ABS = 3,    /* scale * sum_k amp_k exp(-coef_k |x - c_k|)        */
+    OR_F_CONST = 4,      /* scale                                             */
+    OR_F_AFFINE = 5,     /* scale * (a_0 + sum_d a_{d+1} x_d), a in centers   */
+    OR_F_BALLS = 6       /* scale * sum_k amp_k [|x - c_k| < coef_k]          */
+};
+
+typedef struct {
+    int32_t kind;
+    int32_t dim;
+    int32_t n_terms;
+    const double* centers; /* n_terms x dim; CORR_GAUSS: mean (dim); AFFINE: dim+1 */
+    const double* coefs;   /* n_terms */
+    const double* amps;    /* n_terms */
+    const double* chol;    /* dim x dim row-major upper-triangular U (CORR_GAUSS) */
+    double scale;
+} or_integrand;
+
+double or_integrand_eval(const or_integrand* f, const double* x)
+{
+    const int32_t D = f->dim;
+    switch (f->kind) {
+    case OR_F_GAUSS_MIX: {
+        double acc = 0.0;
+        for (int32_t k = 0; k < f->n_terms; ++k) {
+            double q = 0.0;
+            for (int32_t d = 0; d < D; ++d) {
+                double t = x[d] - f->centers[(int64_t)k * D + d];
+                q = fma(t, t, q);
+            }
+            double e = exp(-(f->coefs[k] * q));
+            acc = fma(f->amps[k], e, acc);
+        }
+        return f->scale * acc;
+    }
+    case OR_F_CORR_GAUSS: {
+        double q = 0.0;
+        for (int32_t d = 0; d < D; ++d) {
+            double z = 0.0;
+            for (int32_t e = d; e < D; ++e) {
+                double t = x[e] - f->centers[e];
+                z = fma(f->chol[(int64_t)d * D + e], t, z);
+            }
+            q = fma(z, z, q);
+        }
+        return f->scale * exp(-0.5 * q);
+    }
+    case OR_F_EXP_ABS: {
+        double acc = 0.0;
+        for (int32_t k = 0; k < f->n_terms; ++k) {
+            double q = 0.0;
+            for (int32_t d = 0; d < D; ++d) {
+                double t = x[d] - f->centers[(int64_t)k * D + d];
+                q = fma(t, t, q);
+            }
+            double e = exp(-(f->coefs[k] * sqrt(q)));
+            acc = fma(f->amps[k], e, acc);
+        }
+        return f->scale * acc;
+    }
+    case OR_F_CONST:
+        return f->scale;
+    case OR_F_AFFINE: {
+        double acc = f->centers[0];
+        for (int32_t d = 0; d < D; ++d) acc = fma(f->centers[d + 1], x[d], acc);
+        return f->scale * acc;
+    }
+    case OR_F_BALLS: {
+        double acc = 0.0;
+        for (int32_t k = 0; k < f->n_terms; ++k) {
+            double q = 0.0;
+            for (int32_t d = 0; d < D; ++d) {
+                double t = x[d] - f->centers[(int64_t)k * D + d];
+                q = fma(t, t, q);
+            }
+            double r2 = f->coefs[k] * f->coefs[k];
+            if (q < r2) acc = acc + f->amps[k];
+        }
+        return f->scale * acc;
+    }
+    default:
+        return NAN;
+    }
+}
+
+/* Single-precision evaluation of the same integrands, for the precision split
+ * (FP32 map and integrand).  Same operation order, float arithmetic, expf. */
+float or_integrand_eval_f32(const or_integrand* f, const float* x)
+{
+    const int32_t D = f->dim;
+    switch (f->kind) {
+    case OR_F_GAUSS_MIX: {
+        float acc = 0.0f;
+        for (int32_t k = 0; k < f->n_terms; ++k) {
+            float q = 0.0f;
+            for (int32_t d = 0; d < D; ++d) {
+                float t = x[d] - (float)f->centers[(int64_t)k * D + d];
+                q = fmaf(t, t, q);
+            }
+            float e = expf(-((float)f->coefs[k] * q));
+            acc = fmaf((float)f->amps[k], e, acc);
+        }
+        return (float)f->scale * acc;
+    }
+    case OR_F_CORR_GAUSS: {
+        float q = 0.0f;
+        for (int32_t d = 0; d < D; ++d) {
+            float z = 0.0f;
+            for (int32_t e = d; e < D; ++e) {
+                float t = x[e] - (float)f->centers[e];
+                z = fmaf((float)f->chol[(int64_t)d * D + e], t, z);
+            }
+            q = fmaf(z, z, q);
+        }
+        return (float)f->scale * expf(-0.5f * q);
+    }
+    case OR_F_EXP_ABS: {
+        float acc = 0.0f;
+        for (int32_t k = 0; k < f->n_terms; ++k) {
+            float q = 0.0f;
+            for (int32_t d = 0; d < D; ++d) {
+                float t = x[d] - (float)f->centers[(int64_t)k * D + d];
+                q = fmaf(t, t, q);
+            }
+            float e = expf(-((float)f->coefs[k] * sqrtf(q)));
+            acc = fmaf((float)f->amps[k], e, acc);
+        }
+        return (float)f->scale * acc;
+    }
+    case OR_F_CONST:
+        return (float)f->scale;
+    case OR_F_AFFINE: {
+        float acc = (float)f->centers[0];
+        for (int32_t d = 0; d < D; ++d) acc = fmaf((float)f->centers[d + 1], x[d], acc);
+        return (float)f->scale * acc;
+    }
+    case OR_F_BALLS: {
+        float acc = 0.0f;
+        for (int32_t k = 0; k < f->n_terms; ++k) {
+            float q = 0.0f;
+            for (int32_t d = 0; d < D; ++d) {
+                float t = x[d] - (float)f->centers[(int64_t)k * D + d];
+                q = fmaf(t, t, q);
+            }
+            float r = (float)f->coefs[k];
+            if (q < r * r) acc = acc + (float)f->amps[k];
+        }
+        return (float)f->scale * acc;
+    }
+    default:
+        return NAN;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Problem description shared by the steps below.                             */
+/* ------------------------------------------------------------------------ */
+enum { OR_FP64 = 0, OR_FP32_ACC64 = 1, OR_FP32_NEUMAIER = 2 };
+enum { OR_HIST_WEIGHTED = 0, OR_HIST_LITERAL = 1 };
+
+typedef struct {
+    int32_t dim;
+    int64_t n_ev;
+    int32_t n_g;
+    int32_t n_st;
+    double alpha;
+    double beta;
+    uint64_t seed;
+    int32_t precision;      /* OR_FP64 / OR_FP32_ACC64 / OR_FP32_NEUMAIER */
+    int32_t hist_mode;      /* OR_HIST_WEIGHTED / OR_HIST_LITERAL */
+    int32_t realloc_plus2;  /* 1: n_h = floor(q) + 2 (Sec. 3, alternative rule) */
+} or_params;
+
+int64_t or_n_hypercubes(const or_params* p)
+{
+    int64_t n = 1;
+    for (int32_t d = 0; d < p->dim; ++d) n *= p->n_st;
+    return n;
+}
+
+/* Initial vegas map, Sec. 2.3: a uniform grid, x_i = a + (b - a) i / N_g, with
+ * the last point set to b exactly.  Layout: map[mu * (N_g + 1) + i]. */
+void or_map_init(int32_t dim, int32_t n_g, const double* lower, const double* upper, double* map)
+{
+    for (int32_t mu = 0; mu < dim; ++mu) {
+        double a = lower ? lower[mu] : 0.0;
+        double b = upper ? upper[mu] : 1.0;
+        double* x = map + (int64_t)mu * (n_g + 1);
+        for (int32_t i = 0; i < n_g; ++i) x[i] = a + (b - a) * ((double)i / (double)n_g);
+        x[n_g] = b;
+    }
+}
+
+/* First allocation, Sec. 3: every hypercube gets the classic share
+ * floor(N_ev / N_st^D), at least 2. */
+void or_alloc_init(const or_params* p, int32_t* n_h)
+{
+    int64_t nhc = or_n_hypercubes(p);
+    int64_t n = p->n_ev / nhc;
+    if (n < 2) n = 2;
+    for (int64_t h = 0; h < nhc; ++h) n_h[h] = (int32_t)n;
+}
+
+/* Neumaier's compensated summation (improved Kahan-Babuska), single precision. */
+static void or_neumaier_add(float* s, float* c, float v)
+{
+    float t = *s + v;
+    if (fabsf(*s) >= fabsf(v)) *c += (*s - t) + v;
+    else *c += (v - t) + *s;
+    *s = t;
+}
+
+/* Optional per-sample record for inspection tests. */
+typedef struct {
+    int64_t h;
+    int32_t j;
+    int32_t pad;
+    double v;          /* J f */
+    double jac;        /* J */
+    double fx;         /* f(x) */
+} or_sample_rec;
+
+/* ------------------------------------------------------------------------ */
+/* One iteration of sampling over hypercubes [h_begin, h_end).                */
+/*                                                                            */
+/* Sec. 2.4 (multidimensional map) and Sec. 3 (stratified sampling): in each  */
+/* hypercube h with digits k_mu (axis 0 most significant), n_h points y are  */
+/* drawn uniformly in the hypercube; y is mapped through the per-axis vegas  */
+/* map of Sec. 2.2, Eqs. (y) and (jac): i = floor(y N_g), delta = y N_g - i,  */
+/* x = x_i + Delta x_i delta, J = prod_mu N_g Delta x_i.  The sums of J f and */
+/* (J f)^2 per hypercube (Sec. 3, step 2) and the per-axis, per-increment    */
+/* training data d_i of Sec. 2.3 / 2.4 are accumulated.                       */
+/*                                                                            */
+/* Readings: y^mu = (k_mu + u) / N_st, so t = y N_g = (k_mu + u) R with       */
+/* R = N_g / N_st rounded once; i = min(floor t, N_g - 1), delta = min(t - i, */
+/* 1).  u takes 53 bits from two Philox words per axis: the high words of    */
+/* axes 0..D-1 come first in the stream, then the low words.  The FP32 split */
+/* takes u = (w >> 8) 2^-24 from the high words alone.                         */
+/*                                                                            */
+/* Training data.  Weighted mode: H += (J f)^2 / n_h and W += 1 / n_h, so the */
+/* refinement uses d_i = H / W, the (1/n_i) sum of J^2 f^2 of Sec. 2.3 with   */
+/* each sample weighted by its hypercube's share of y-space.  Literal mode:  */
+/* H += (J f)^2 and W += 1, the formula as printed.                           */
+/*                                                                            */
+/* Outputs S1[h - h_begin], S2[h - h_begin] are written for every h in the   */
+/* range; H and W (dim x n_g) are accumulated into (callers zero them).       */
+/* ------------------------------------------------------------------------ */
+int or_sample_range(const or_params* p, const or_integrand* f, const double* map,
+                    const int32_t* n_h, int32_t it, int64_t h_begin, int64_t h_end,
+                    double* S1, double* S2, double* H, double* W,
+                    or_sample_rec* rec, int64_t rec_cap, int64_t* rec_count)
+{
+    const int32_t D = p->dim, NG = p->n_g, NST = p->n_st;
+    if (D < 1 || D > 64 || NG < 1 || NST < 1) return -1;
+    const double R = (double)NG / (double)NST;
+    const float R32 = (float)NG / (float)NST;
+    const uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32)};
+    const int fp32 = (p->precision != OR_FP64);
+    const int nwords = fp32 ? D : 2 * D;
+    const int nblk = (nwords + 3) / 4;
+    uint32_t w[4 * 33];
+    int32_t k[64];
+    int32_t idx[64];
+    double xs[64];
+    float xs32[64];
+    float* map32 = NULL;
+    if (fp32) {
+        map32 = (float*)malloc(sizeof(float) * (size_t)D * (NG + 1));
+        if (!map32) return -2;
+        for (int64_t q = 0; q < (int64_t)D * (NG + 1); ++q) map32[q] = (float)map[q];
+    }
+    float* nH = NULL;
+    float* nW = NULL;
+    if (p->precision == OR_FP32_NEUMAIER) {
+        nH = (float*)calloc((size_t)2 * D * NG, sizeof(float));
+        nW = (float*)calloc((size_t)2 * D * NG, sizeof(float));
+        if (!nH || !nW) {
+            free(nH); free(nW); free(map32);
+            return -2;
+        }
+    }
+    int64_t nrec = 0;
+
+    for (int64_t h = h_begin; h < h_end; ++h) {
+        /* digits of h in base N_st, axis 0 most significant */
+        int64_t rem = h;
+        for (int32_t mu = D - 1; mu >= 0; --mu) {
+            k[mu] = (int32_t)(rem % NST);
+            rem /= NST;
+        }
+        const int32_t n = n_h[h];
+        const double inv_n = 1.0 / (double)n;
+        const float inv_n32 = 1.0f / (float)n;
+        double s1 = 0.0, s2 = 0.0;
+        float ns1 = 0.0f, nc1 = 0.0f, ns2 = 0.0f, nc2 = 0.0f;
+
+        for (int32_t j = 0; j < n; ++j) {
+            for (int b = 0; b < nblk; ++b) {
+                uint32_t ctr[4] = {(uint32_t)j, (uint32_t)h, (uint32_t)it, (uint32_t)b};
+                or_philox4x32_10(ctr, key, &w[4 * b]);
+            }
+            double v, jac_out, f_out;
+            if (!fp32) {
+                double jac = 1.0;
+                for (int32_t mu = 0; mu < D; ++mu) {
+                    uint64_t a = (uint64_t)(w[mu] >> 5);
+                    uint64_t bb = (uint64_t)(w[D + mu] >> 6);
+                    double u = (double)((a << 26) | bb) * 0x1p-53;
+                    double t = ((double)k[mu] + u) * R;
+                    int32_t i = (int32_t)floor(t);
+                    if (i > NG - 1) i = NG - 1;
+                    double delta = t - (double)i;
+                    if (delta > 1.0) delta = 1.0;
+                    const double* xm = map + (int64_t)mu * (NG + 1);
+                    double dx = xm[i + 1] - xm[i];
+                    xs[mu] = fma(dx, delta, xm[i]);
+                    jac = jac * ((double)NG * dx);
+                    idx[mu] = i;
+                }
+                double fx = or_integrand_eval(f, xs);
+                v = jac * fx;
+                jac_out = jac;
+                f_out = fx;
+            } else {
+                float jac = 1.0f;
+                for (int32_t mu = 0; mu < D; ++mu) {
+                    float u = (float)(w[mu] >> 8) * 0x1p-24f;
+                    float t = ((float)k[mu] + u) * R32;
+                    int32_t i = (int32_t)floorf(t);
+                    if (i > NG - 1) i = NG - 1;
+                    float delta = t - (float)i;
+                    if (delta > 1.0f) delta = 1.0f;
+                    const float* xm = map32 + (int64_t)mu * (NG + 1);
+                    float dx = xm[i + 1] - xm[i];
+                    xs32[mu] = fmaf(dx, delta, xm[i]);
+                    jac = jac * ((float)NG * dx);
+                    idx[mu] = i;
+                }
+                float fx = or_integrand_eval_f32(f, xs32);
+                float v32 = jac * fx;
+                v = (double)v32;
+                jac_out = (double)jac;
+                f_out = (double)fx;
+                if (p->precision == OR_FP32_NEUMAIER) {
+                    or_neumaier_add(&ns1, &nc1, v32);
+                    or_neumaier_add(&ns2, &nc2, v32 * v32);
+                }
+            }
+            if (p->precision != OR_FP32_NEUMAIER) {
+                s1 = s1 + v;
+                s2 = s2 + v * v;
+                const double v2 = v * v;
+                for (int32_t mu = 0; mu < D; ++mu) {
+                    int64_t bin = (int64_t)mu * NG + idx[mu];
+                    if (p->hist_mode == OR_HIST_WEIGHTED) {
+                        H[bin] = H[bin] + v2 * inv_n;
+                        W[bin] = W[bin] + inv_n;
+                    } else {
+                        H[bin] = H[bin] + v2;
+                        W[bin] = W[bin] + 1.0;
+                    }
+                }
+            } else {
+                const float v32 = (float)v;
+                const float v2 = v32 * v32;
+                for (int32_t mu = 0; mu < D; ++mu) {
+                    int64_t bin = (int64_t)mu * NG + idx[mu];
+                    if (p->hist_mode == OR_HIST_WEIGHTED) {
+                        or_neumaier_add(&nH[2 * bin], &nH[2 * bin + 1], v2 * inv_n32);
+                        or_neumaier_add(&nW[2 * bin], &nW[2 * bin + 1], inv_n32);
+                    } else {
+                        or_neumaier_add(&nH[2 * bin], &nH[2 * bin + 1], v2);
+                        or_neumaier_add(&nW[2 * bin], &nW[2 * bin + 1], 1.0f);
+                    }
+                }
+            }
+            if (rec && nrec < rec_cap) {
+                rec[nrec].h = h;
+                rec[nrec].j = j;
+                rec[nrec].pad = 0;
+                rec[nrec].v = v;
+                rec[nrec].jac = jac_out;
+                rec[nrec].fx = f_out;
+            }
+            ++nrec;
+        }
+        if (p->precision == OR_FP32_NEUMAIER) {
+            s1 = (double)ns1 + (double)nc1;
+            s2 = (double)ns2 + (double)nc2;
+        }
+        S1[h - h_begin] = s1;
+        S2[h - h_begin] = s2;
+    }
+    if (nH) {
+        /* compensated single-precision bins are merged in double precision */
+        for (int64_t bin = 0; bin < (int64_t)D * NG; ++bin) {
+            H[bin] = H[bin] + ((double)nH[2 * bin] + (double)nH[2 * bin + 1]);
+            W[bin] = W[bin] + ((double)nW[2 * bin] + (double)nW[2 * bin + 1]);
+        }
+    }
+    if (rec_count) *rec_count = nrec;
+    free(nH);
+    free(nW);
+    free(map32);
+    return 0;
+}
+
+/* Per-sample indices for inspection: increment index of every axis and the
+ * hypercube of every sample, in (h, j) order.  idx_out is [n_samples][dim]. */
+int or_sample_indices(const or_params* p, const int32_t* n_h, int32_t it, int64_t h_begin,
+                      int64_t h_end, int32_t* idx_out, double* t_out, int64_t cap)
+{
+    const int32_t D = p->dim, NG = p->n_g, NST = p->n_st;
+    const double R = (double)NG / (double)NST;
+    const float R32 = (float)NG / (float)NST;
+    const uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32)};
+    const int fp32 = (p->precision != OR_FP64);
+    const int nblk = ((fp32 ? D : 2 * D) + 3) / 4;
+    uint32_t w[4 * 33];
+    int64_t s = 0;
+    for (int64_t h = h_begin; h < h_end; ++h) {
+        int32_t k[64];
+        int64_t rem = h;
+        for (int32_t mu = D - 1; mu >= 0; --mu) {
+            k[mu] = (int32_t)(rem % NST);
+            rem /= NST;
+        }
+        for (int32_t j = 0; j < n_h[h]; ++j, ++s) {
+            if (s >= cap) return -1;
+            for (int b = 0; b < nblk; ++b) {
+                uint32_t ctr[4] = {(uint32_t)j, (uint32_t)h, (uint32_t)it, (uint32_t)b};
+                or_philox4x32_10(ctr, key, &w[4 * b]);
+            }
+            for (int32_t mu = 0; mu < D; ++mu) {
+                int32_t i;
+                double tt;
+                if (!fp32) {
+                    uint64_t a = (uint64_t)(w[mu] >> 5);
+                    uint64_t bb = (uint64_t)(w[D + mu] >> 6);
+                    double u = (double)((a << 26) | bb) * 0x1p-53;
+                    tt = ((double)k[mu] + u) * R;
+                    i = (int32_t)floor(tt);
+                } else {
+                    float u = (float)(w[mu] >> 8) * 0x1p-24f;
+                    float t32 = ((float)k[mu] + u) * R32;
+                    tt = (double)t32;
+                    i = (int32_t)floorf(t32);
+                }
+                if (i > NG - 1) i = NG - 1;
+                idx_out[s * D + mu] = i;
+                if (t_out) t_out[s * D + mu] = tt;
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Iteration estimate, Sec. 2.1 Eqs. (MCIy), (sigest) applied per hypercube  */
+/* and summed over hypercubes as in Sec. 3, Eq. (sumI):                       */
+/*   I = sum_h Omega S1_h / n_h,                                              */
+/*   V = sum_h max(0, Omega^2 S2_h / n_h - (Omega S1_h / n_h)^2) / (n_h - 1). */
+/* Sums are taken in hypercube order.                                         */
+/* ------------------------------------------------------------------------ */
+void or_reduce(const or_params* p, const int32_t* n_h, const double* S1, const double* S2,
+               double* I_out, double* V_out)
+{
+    const int64_t nhc = or_n_hypercubes(p);
+    const double omega = 1.0 / (double)nhc;
+    const double omega2 = omega * omega;
+    double I = 0.0, V = 0.0;
+    for (int64_t h = 0; h < nhc; ++h) {
+        const double n = (double)n_h[h];
+        const double m = (omega * S1[h]) / n;
+        double var = (omega2 * S2[h]) / n - m * m;
+        if (var < 0.0) var = 0.0;
+        I = I + m;
+        V = V + var / (n - 1.0);
+    }
+    *I_out = I;
+    *V_out = V;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reallocation, Sec. 3 steps 2-4, Eqs. (dh), (nh):                           */
+/*   sigma_h = sqrt(max(0, Omega^2 S2_h/n_h - (Omega S1_h/n_h)^2)),           */
+/*   d_h = sigma_h^beta (d_h = 1 when beta = 0),                              */
+/*   n_h' = max(2, floor(N_ev d_h / sum d)), or floor(...) + 2 in the         */
+/* alternative rule.  sum d is taken in hypercube order; when it is zero the  */
+/* allocation is kept.  Counts near-ties |q - round q| <= 1e-9 max(1, q) at   */
+/* integers where floor(q) decides n_h (>= 3 for the max(2, .) rule, >= 1 for */
+/* the +2 rule): there a last-bit difference in sum d could move n_h.         */
+/* ------------------------------------------------------------------------ */
+int64_t or_realloc(const or_params* p, const double* S1, const double* S2, const int32_t* n_in,
+                   int32_t* n_out)
+{
+    const int64_t nhc = or_n_hypercubes(p);
+    const double omega = 1.0 / (double)nhc;
+    const double omega2 = omega * omega;
+    double* dh = (double*)malloc(sizeof(double) * (size_t)nhc);
+    if (!dh) return -1;
+    double sum = 0.0;
+    for (int64_t h = 0; h < nhc; ++h) {
+        const double n = (double)n_in[h];
+        const double m = (omega * S1[h]) / n;
+        double var = (omega2 * S2[h]) / n - m * m;
+        if (var < 0.0) var = 0.0;
+        const double sig = sqrt(var);
+        dh[h] = (p->beta == 0.0) ? 1.0 : pow(sig, p->beta);
+        sum = sum + dh[h];
+    }
+    int64_t ties = 0;
+    if (!(sum > 0.0)) {
+        for (int64_t h = 0; h < nhc; ++h) n_out[h] = n_in[h];
+        free(dh);
+        return 0;
+    }
+    const double nev = (double)p->n_ev;
+    for (int64_t h = 0; h < nhc; ++h) {
+        const double q = (nev * dh[h]) / sum;
+        double fl = floor(q);
+        double r = nearbyint(q);
+        double tol = 1e-9 * (q > 1.0 ? q : 1.0);
+        /* a tie only matters where floor(q) is not hidden by the max(2, .) */
+        double first_visible = p->realloc_plus2 ? 1.0 : 3.0;
+        if (r >= first_visible && fabs(q - r) <= tol) ++ties;
+        int64_t n = (int64_t)fl;
+        if (p->realloc_plus2) n = n + 2;
+        else if (n < 2) n = 2;
+        if (n > 2147483647) n = 2147483647;
+        n_out[h] = (int32_t)n;
+    }
+    free(dh);
+    return ties;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Map refinement of one axis, Sec. 2.3.                                      */
+/*  1. d_i from the training data (weighted: H/W; literal: H/count), 0 for an */
+/*     increment with no samples.                                             */
+/*  2. Smoothing with weights (7,1)/8, (1,6,1)/8, (1,7)/8 and normalisation   */
+/*     by the raw sum of the d_i.                                             */
+/*  3. Range compression d -> ((1 - d) / ln(1/d))^alpha, 0 for d = 0.         */
+/*  4. The four-step regrid that puts an equal share of sum d into each new  */
+/*     increment by linear interpolation inside the old increments.           */
+/* An axis is left untouched when alpha = 0, N_g = 1, or every d_i is zero.  */
+/* x: the axis's N_g + 1 grid points, replaced in place.  work: 2 N_g doubles.*/
+/* ------------------------------------------------------------------------ */
+int or_refine_axis(const or_params* p, const double* H, const double* W, double* x, double* work)
+{
+    const int32_t NG = p->n_g;
+    if (p->alpha == 0.0 || NG < 2) return 0;
+    double* d = work;
+    double* c = work + NG;
+    double s = 0.0;
+    for (int32_t i = 0; i < NG; ++i) {
+        d[i] = (W[i] > 0.0) ? H[i] / W[i] : 0.0;
+        s = s + d[i];
+    }
+    if (!(s > 0.0)) return 0;
+    /* smoothing, then normalisation */
+    c[0] = (7.0 * d[0] + d[1]) / 8.0;
+    for (int32_t i = 1; i < NG - 1; ++i) c[i] = (d[i - 1] + 6.0 * d[i] + d[i + 1]) / 8.0;
+    c[NG - 1] = (d[NG - 2] + 7.0 * d[NG - 1]) / 8.0;
+    for (int32_t i = 0; i < NG; ++i) c[i] = c[i] / s;
+    /* compression */
+    double csum = 0.0;
+    for (int32_t i = 0; i < NG; ++i) {
+        double di = c[i];
+        c[i] = (di == 0.0) ? 0.0 : pow((1.0 - di) / (-log(di)), p->alpha);
+        csum = csum + c[i];
+    }
+    /* regrid */
+    const double delta_d = csum / (double)NG;
+    double* xn = d; /* d no longer needed; reuse for the new points */
+    xn[0] = x[0];
+    int32_t j = 0;
+    double acc = 0.0;
+    for (int32_t i = 1; i < NG; ++i) {
+        while (acc < delta_d && j < NG) {
+            acc = acc + c[j];
+            j = j + 1;
+        }
+        acc = acc - delta_d;
+        double frac_left = (acc > 0.0) ? acc / c[j - 1] : 0.0;
+        xn[i] = x[j] - frac_left * (x[j] - x[j - 1]);
+    }
+    for (int32_t i = 1; i < NG; ++i) x[i] = xn[i];
+    return 1;
+}
+
+/* The first three refinement stages of one axis, for inspection: raw d_i,
+ * smoothed-and-normalised d_i, compressed d_i (Sec. 2.3).  Returns 0 when the
+ * axis would be left untouched (then the outputs are not all written). */
+int or_refine_stages(const or_params* p, const double* H, const double* W, double* d_raw,
+                     double* d_smooth, double* d_comp)
+{
+    const int32_t NG = p->n_g;
+    if (NG < 2) return 0;
+    double s = 0.0;
+    for (int32_t i = 0; i < NG; ++i) {
+        d_raw[i] = (W[i] > 0.0) ? H[i] / W[i] : 0.0;
+        s = s + d_raw[i];
+    }
+    if (!(s > 0.0)) return 0;
+    const double* d = d_raw;
+    double* c = d_smooth;
+    c[0] = (7.0 * d[0] + d[1]) / 8.0;
+    for (int32_t i = 1; i < NG - 1; ++i) c[i] = (d[i - 1] + 6.0 * d[i] + d[i + 1]) / 8.0;
+    c[NG - 1] = (d[NG - 2] + 7.0 * d[NG - 1]) / 8.0;
+    for (int32_t i = 0; i < NG; ++i) c[i] = c[i] / s;
+    for (int32_t i = 0; i < NG; ++i)
+        d_comp[i] = (c[i] == 0.0) ? 0.0 : pow((1.0 - c[i]) / (-log(c[i])), p->alpha);
+    return 1;
+}
+
+int or_refine(const or_params* p, const double* H, const double* W, double* map)
+{
+    const int32_t D = p->dim, NG = p->n_g;
+    double* work = (double*)malloc(sizeof(double) * 2 * (size_t)(NG > 1 ? NG : 2));
+    if (!work) return -1;
+    for (int32_t mu = 0; mu < D; ++mu)
+        or_refine_axis(p, H + (int64_t)mu * NG, W + (int64_t)mu * NG, map + (int64_t)mu * (NG + 1),
+                       work);
+    free(work);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Combining iterations, Sec. 2.5: inverse-variance weighted mean, its        */
+/* standard error and chi^2 over iterations n_discard..n-1.  When any sigma_j */
+/* is zero the weights are undefined: the plain mean is returned with zero    */
+/* error and chi^2 = NaN.                                                     */
+/* ------------------------------------------------------------------------ */
+void or_combine(const double* I, const double* sig, int32_t n, int32_t n_discard,
+                double* mean, double* sdev, double* chi2, int32_t* dof)
+{
+    int32_t first = n_discard < 0 ? 0 : n_discard;
+    int32_t cnt = n - first;
+    if (cnt <= 0) {
+        *mean = NAN; *sdev = NAN; *chi2 = NAN; *dof = 0;
+        return;
+    }
+    int zero = 0;
+    for (int32_t j = first; j < n; ++j)
+        if (!(sig[j] > 0.0)) zero = 1;
+    *dof = cnt - 1;
+    if (zero) {
+        double s = 0.0;
+        for (int32_t j = first; j < n; ++j) s = s + I[j];
+        *mean = s / (double)cnt;
+        *sdev = 0.0;
+        *chi2 = NAN;
+        return;
+    }
+    double sw = 0.0, swi = 0.0;
+    for (int32_t j = first; j < n; ++j) {
+        double w = 1.0 / (sig[j] * sig[j]);
+        sw = sw + w;
+        swi = swi + I[j] * w;
+    }
+    double m = swi / sw;
+    double c2 = 0.0;
+    for (int32_t j = first; j < n; ++j) {
+        double r = I[j] - m;
+        c2 = c2 + r * r / (sig[j] * sig[j]);
+    }
+    *mean = m;
+    *sdev = 1.0 / sqrt(sw);
+    *chi2 = c2;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One full iteration: sample every hypercube, estimate, reallocate, refine.  */
+/* The two adaptations both use this iteration's samples and take effect in  */
+/* the next iteration (Sec. 3, after step 4).  map and n_h are updated in    */
+/* place.  S1, S2 (N_hc) and H, W (dim x N_g) receive this iteration's sums. */
+/* ------------------------------------------------------------------------ */
+int64_t or_iteration(const or_params* p, const or_integrand* f, double* map, int32_t* n_h,
+                     int32_t it, double* S1, double* S2, double* H, double* W, double* I_out,
+                     double* V_out)
+{
+    const int64_t nhc = or_n_hypercubes(p);
+    memset(H, 0, sizeof(double) * (size_t)p->dim * p->n_g);
+    memset(W, 0, sizeof(double) * (size_t)p->dim * p->n_g);
+    if (or_sample_range(p, f, map, n_h, it, 0, nhc, S1, S2, H, W, NULL, 0, NULL) != 0) return -1;
+    or_reduce(p, n_h, S1, S2, I_out, V_out);
+    int32_t* n_new = (int32_t*)malloc(sizeof(int32_t) * (size_t)nhc);
+    if (!n_new) return -1;
+    int64_t ties = or_realloc(p, S1, S2, n_h, n_new);
+    memcpy(n_h, n_new, sizeof(int32_t) * (size_t)nhc);
+    free(n_new);
+    or_refine(p, H, W, map);
+    return ties;
+}
+
+/* Full driver over n_iter iterations starting from the given map and
+ * allocation (callers use or_map_init / or_alloc_init for a fresh start).
+ * I_j and V_j (variances) of each iteration are returned; ties_total counts
+ * near-ties over all reallocations. */
+int or_integrate(const or_params* p, const or_integrand* f, double* map, int32_t* n_h,
+                 int32_t it0, int32_t n_iter, double* I_j, double* V_j, int64_t* ties_total)
+{
+    const int64_t nhc = or_n_hypercubes(p);
+    double* S1 = (double*)malloc(sizeof(double) * (size_t)nhc);
+    double* S2 = (double*)malloc(sizeof(double) * (size_t)nhc);
+    double* H = (double*)malloc(sizeof(double) * (size_t)p->dim * p->n_g);
+    double* W = (double*)malloc(sizeof(double) * (size_t)p->dim * p->n_g);
+    if (!S1 || !S2 || !H || !W) {
+        free(S1); free(S2); free(H); free(W);
+        return -1;
+    }
+    int64_t ties = 0;
+    for (int32_t j = 0; j < n_iter; ++j) {
+        int64_t t = or_iteration(p, f, map, n_h, it0 + j, S1, S2, H, W, &I_j[j], &V_j[j]);
+        if (t < 0) { ties = -1; break; }
+        ties += t;
+    }
+    free(S1); free(S2); free(H); free(W);
+    if (ties_total) *ties_total = ties;
+    return ties < 0 ? -1 : 0;
+}
