@@ -1,0 +1,211 @@
+/*
+ * vegasp.h -- C ABI of the MI355X (gfx950) vegas+ library.
+ *
+ * The library runs the per-iteration hot path of vegas+ (G. P. Lepage,
+ * "Adaptive Multidimensional Integration: VEGAS Enhanced", arXiv:2009.05112)
+ * on one GPU: stratified sampling with a counter-based Philox stream, the
+ * vegas map with its Jacobian, integrand evaluation, per-hypercube sums,
+ * per-increment training data, reallocation of samples across hypercubes and
+ * refinement of the map.  Every step runs in the library's own HIP kernels.
+ *
+ * Conventions
+ *  - Every function returns a vp_status and never throws or exits.  On error
+ *    vp_last_error() returns a description (thread-local, valid until the next
+ *    call on the same thread).
+ *  - Pointers documented as "host" point to host memory owned by the caller;
+ *    the library copies what it needs before returning.  The library owns all
+ *    device memory it allocates; results are copied into caller buffers.
+ *  - Handles are not thread-safe, except the vp_server_* calls documented so.
+ *  - Work is enqueued on the context's HIP stream; calls documented as
+ *    "synchronising" wait for that stream.
+ */
+#ifndef VEGASP_H
+#define VEGASP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VP_OK = 0,
+    VP_ERR_INVALID_ARG = 1, /* an argument violates the documented contract        */
+    VP_ERR_OOM = 2,         /* device or host allocation failed / over budget       */
+    VP_ERR_DEVICE = 3,      /* a HIP runtime call failed                            */
+    VP_ERR_NUMERIC = 4,     /* non-finite integrand values were produced            */
+    VP_ERR_NOT_READY = 5,   /* a served request has not finished                    */
+    VP_ERR_CANCELLED = 6,   /* a served request was cancelled                       */
+    VP_ERR_STATE = 7        /* the call does not fit the object's current state     */
+} vp_status;
+
+/* Static description of a status; the caller does not free it. */
+const char* vp_status_string(vp_status s);
+/* Detail of the last failing call on this thread (never NULL). */
+const char* vp_last_error(void);
+
+typedef struct vp_ctx vp_ctx;
+typedef struct vp_problem vp_problem;
+typedef struct vp_server vp_server;
+
+/* A context binds one GPU and one HIP stream.  device: HIP ordinal.
+ * hip_stream: a hipStream_t to enqueue on, or NULL for a stream the context
+ * creates (default priority) and destroys. */
+vp_status vp_ctx_create(int device, void* hip_stream, vp_ctx** out);
+vp_status vp_ctx_destroy(vp_ctx* ctx);
+/* Number of compute units of the context's device. */
+vp_status vp_ctx_info(vp_ctx* ctx, int32_t* n_cu, int64_t* lds_bytes_per_block);
+
+/* Integrands (f(x) as the user defines it; the sampler multiplies by J).
+ *  VP_F_GAUSS_MIX:  scale * sum_k amps[k] exp(-coefs[k] |x - c_k|^2),
+ *                   c_k = centers[k*dim .. k*dim+dim-1], 1 <= n_terms <= 4
+ *  VP_F_CORR_GAUSS: scale * exp(-1/2 |U (x - m)|^2), m = centers[0..dim-1],
+ *                   U = chol, dim x dim row-major upper-triangular
+ *                   (U^T U is the inverse covariance)
+ *  VP_F_EXP_ABS:    scale * sum_k amps[k] exp(-coefs[k] |x - c_k|), n_terms <= 4
+ *  VP_F_CONST:      scale
+ *  VP_F_AFFINE:     scale * (a_0 + sum_d a_{d+1} x_d), a = centers[0..dim]
+ *  VP_F_BALLS:      scale * sum_k amps[k] [ |x - c_k| < coefs[k] ], n_terms <= 4
+ * The host arrays are copied at create time. */
+enum {
+    VP_F_GAUSS_MIX = 1,
+    VP_F_CORR_GAUSS = 2,
+    VP_F_EXP_ABS = 3,
+    VP_F_CONST = 4,
+    VP_F_AFFINE = 5,
+    VP_F_BALLS = 6
+};
+
+typedef struct {
+    int32_t kind;
+    int32_t dim;
+    int32_t n_terms;
+    const double* centers; /* host */
+    const double* coefs;   /* host, n_terms */
+    const double* amps;    /* host, n_terms */
+    const double* chol;    /* host, dim*dim (VP_F_CORR_GAUSS only, else NULL) */
+    double scale;
+} vp_integrand;
+
+/* Arithmetic of the sampling path (the split is not in the paper):
+ *  VP_FP64:          everything in double precision;
+ *  VP_FP32_ACC64:    uniforms, map, x, J and f in single precision, all sums
+ *                    (per hypercube and per increment) in double precision;
+ *  VP_FP32_NEUMAIER: as VP_FP32_ACC64, with the sums kept as Neumaier-
+ *                    compensated single-precision pairs, merged in double.
+ * Estimates, reallocation and refinement are always double precision. */
+enum { VP_FP64 = 0, VP_FP32_ACC64 = 1, VP_FP32_NEUMAIER = 2 };
+
+/* Training data for the map (Sec. 2.3, 2.4):
+ *  VP_HIST_WEIGHTED: d_i = sum(v^2 / n_h) / sum(1 / n_h) over the samples in
+ *                    increment i (each sample weighted by its hypercube's
+ *                    share of y-space; equals the printed average when all
+ *                    n_h are equal);
+ *  VP_HIST_LITERAL:  d_i = (1 / n_i) sum v^2, as printed. */
+enum { VP_HIST_WEIGHTED = 0, VP_HIST_LITERAL = 1 };
+
+/* The problem statement (Sec. 2 and 3): dimension, samples per iteration
+ * N_ev, map increments N_g per axis, damping alpha (map, Sec. 2.3) and beta
+ * (allocation, Sec. 3 Eq. dh), iteration count, integration box.
+ *  dim 1..24 (split precisions: 1..16); n_ev 4 .. 2^31-1; n_g 1 .. 65535;
+ *  alpha >= 0; beta >= 0; lower/upper: host arrays of dim or NULL for [0,1].
+ *  n_st: stratifications per axis, 0 for the rule of Sec. 3 Eq. Nst_vegasp
+ *        (largest n with 4 n^dim <= n_ev); a user value must keep
+ *        2 n_st^dim <= n_ev.
+ *  n_discard: iterations left out of the combined estimate (Sec. 2.5).
+ *  realloc_plus2: use n_h = floor(q) + 2 instead of max(2, floor(q)). */
+typedef struct {
+    int32_t dim;
+    int64_t n_ev;
+    int32_t n_g;
+    int32_t n_iter;
+    double alpha;
+    double beta;
+    const double* lower;
+    const double* upper;
+    uint64_t seed;
+    int32_t precision;
+    int32_t hist_mode;
+    int32_t realloc_plus2;
+    int32_t n_discard;
+    int32_t n_st;
+} vp_params;
+
+/* Combined estimate over the iterations done so far (Sec. 2.5):
+ * inverse-variance weighted mean, its error, chi^2 with dof = used - 1.
+ * n_evals counts actual integrand evaluations (sum of n_h over iterations).
+ * n_near_ties counts allocations where N_ev d_h / sum d lay within 1e-9
+ * (relative) of an integer that decides n_h. */
+typedef struct {
+    double mean;
+    double sdev;
+    double chi2;
+    int32_t dof;
+    int32_t n_iter_done;
+    int64_t n_evals;
+    int64_t n_near_ties;
+    int64_t n_nonfinite;
+} vp_result;
+
+/* Creates the device state of one integration: uniform map, uniform
+ * allocation max(2, floor(N_ev / N_st^D)), iteration counter 0.
+ * Fails with VP_ERR_INVALID_ARG on parameters outside the ranges above and
+ * with VP_ERR_OOM when the device state does not fit. */
+vp_status vp_problem_create(vp_ctx* ctx, const vp_params* params, const vp_integrand* f,
+                            vp_problem** out);
+vp_status vp_problem_destroy(vp_problem* p);
+/* Derived sizes: stratifications per axis and number of hypercubes. */
+vp_status vp_problem_info(vp_problem* p, int32_t* n_st, int64_t* n_hc);
+
+/* Enqueues n_iter iterations (asynchronous).  Each iteration (Sec. 2.3 and 3):
+ * scan of n_h into sample offsets; sampling, map, integrand, per-hypercube
+ * sums and increment training data; the iteration estimate I_j, sigma_j^2;
+ * reallocation n_h' = max(2, floor(N_ev sigma_h^beta / sum)); refinement of
+ * every axis of the map.  Both adaptations use this iteration's samples and
+ * apply to the next. */
+vp_status vp_iterate(vp_problem* p, int32_t n_iter);
+/* Waits for the problem's enqueued work (synchronising). */
+vp_status vp_sync(vp_problem* p);
+
+/* Synchronising.  Combined estimate; optionally the per-iteration estimates
+ * I_j and variances V_j = sigma_j^2 (host arrays of at least cap entries;
+ * the first min(cap, n_iter_done) are written). */
+vp_status vp_result_get(vp_problem* p, vp_result* out, double* I_j, double* V_j, int32_t cap);
+
+/* Synchronising state access for inspection, checkpoints and parity tests.
+ * map: host [dim][n_g + 1]; n_h: host [n_hc]. */
+vp_status vp_map_get(vp_problem* p, double* map);
+vp_status vp_map_set(vp_problem* p, const double* map);       /* must be non-decreasing */
+vp_status vp_alloc_get(vp_problem* p, int32_t* n_h);
+vp_status vp_alloc_set(vp_problem* p, const int32_t* n_h);    /* every n_h >= 2 */
+/* Iteration index used by the next iteration's Philox counters. */
+vp_status vp_iteration_get(vp_problem* p, int32_t* it);
+vp_status vp_iteration_set(vp_problem* p, int32_t it);
+/* Sums of the last iteration: S1, S2 host [n_hc] (sum of J f and (J f)^2 per
+ * hypercube), H, W host [dim][n_g] (training-data numerator and weight per
+ * increment).  Any pointer may be NULL. */
+vp_status vp_accum_get(vp_problem* p, double* S1, double* S2, double* H, double* W);
+
+/* Checkpoint: map, n_h, iteration index and estimate history, as an opaque
+ * byte blob.  With buf == NULL, *size receives the required size. */
+vp_status vp_state_export(vp_problem* p, void* buf, size_t* size);
+vp_status vp_state_import(vp_problem* p, const void* buf, size_t size);
+
+/* Profiling: total device time (ms, from HIP events on the context stream)
+ * and launch count of one kernel family since creation or the last reset.
+ * which: 0 sampling kernel, 1 whole iteration.  Timing is off until
+ * vp_profile_enable(p, 1). */
+vp_status vp_profile_enable(vp_problem* p, int32_t on);
+vp_status vp_kernel_time(vp_problem* p, int32_t which, double* total_ms, int64_t* launches);
+
+/* Convenience: create, run params->n_iter iterations, read the result,
+ * destroy (synchronising). */
+vp_status vp_integrate(vp_ctx* ctx, const vp_params* params, const vp_integrand* f,
+                       vp_result* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VEGASP_H */

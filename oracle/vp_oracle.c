@@ -318,6 +318,24 @@ static void or_neumaier_add(float* s, float* c, float v)
     *s = t;
 }
 
+/* Neumaier's compensated summation in double precision: the oracle takes its
+ * sums (per hypercube, per increment, over hypercubes) to within about one
+ * rounding of the exact sum, so that its own summation error stays far below
+ * the comparison tolerance even over 1e7 terms. */
+typedef struct {
+    double s, c;
+} or_ksum;
+
+static void or_kadd(or_ksum* k, double v)
+{
+    double t = k->s + v;
+    if (fabs(k->s) >= fabs(v)) k->c += (k->s - t) + v;
+    else k->c += (v - t) + k->s;
+    k->s = t;
+}
+
+static double or_kval(const or_ksum* k) { return k->s + k->c; }
+
 /* Optional per-sample record for inspection tests. */
 typedef struct {
     int64_t h;
@@ -377,6 +395,16 @@ int or_sample_range(const or_params* p, const or_integrand* f, const double* map
         if (!map32) return -2;
         for (int64_t q = 0; q < (int64_t)D * (NG + 1); ++q) map32[q] = (float)map[q];
     }
+    or_ksum* kH = NULL;
+    or_ksum* kW = NULL;
+    if (p->precision != OR_FP32_NEUMAIER) {
+        kH = (or_ksum*)calloc((size_t)D * NG, sizeof(or_ksum));
+        kW = (or_ksum*)calloc((size_t)D * NG, sizeof(or_ksum));
+        if (!kH || !kW) {
+            free(kH); free(kW); free(map32);
+            return -2;
+        }
+    }
     float* nH = NULL;
     float* nW = NULL;
     if (p->precision == OR_FP32_NEUMAIER) {
@@ -399,6 +427,7 @@ int or_sample_range(const or_params* p, const or_integrand* f, const double* map
         const int32_t n = n_h[h];
         const double inv_n = 1.0 / (double)n;
         const float inv_n32 = 1.0f / (float)n;
+        or_ksum k1 = {0.0, 0.0}, k2 = {0.0, 0.0};
         double s1 = 0.0, s2 = 0.0;
         float ns1 = 0.0f, nc1 = 0.0f, ns2 = 0.0f, nc2 = 0.0f;
 
@@ -455,17 +484,17 @@ int or_sample_range(const or_params* p, const or_integrand* f, const double* map
                 }
             }
             if (p->precision != OR_FP32_NEUMAIER) {
-                s1 = s1 + v;
-                s2 = s2 + v * v;
                 const double v2 = v * v;
+                or_kadd(&k1, v);
+                or_kadd(&k2, v2);
                 for (int32_t mu = 0; mu < D; ++mu) {
                     int64_t bin = (int64_t)mu * NG + idx[mu];
                     if (p->hist_mode == OR_HIST_WEIGHTED) {
-                        H[bin] = H[bin] + v2 * inv_n;
-                        W[bin] = W[bin] + inv_n;
+                        or_kadd(&kH[bin], v2 * inv_n);
+                        or_kadd(&kW[bin], inv_n);
                     } else {
-                        H[bin] = H[bin] + v2;
-                        W[bin] = W[bin] + 1.0;
+                        or_kadd(&kH[bin], v2);
+                        or_kadd(&kW[bin], 1.0);
                     }
                 }
             } else {
@@ -495,9 +524,18 @@ int or_sample_range(const or_params* p, const or_integrand* f, const double* map
         if (p->precision == OR_FP32_NEUMAIER) {
             s1 = (double)ns1 + (double)nc1;
             s2 = (double)ns2 + (double)nc2;
+        } else {
+            s1 = or_kval(&k1);
+            s2 = or_kval(&k2);
         }
         S1[h - h_begin] = s1;
         S2[h - h_begin] = s2;
+    }
+    if (kH) {
+        for (int64_t bin = 0; bin < (int64_t)D * NG; ++bin) {
+            H[bin] = H[bin] + or_kval(&kH[bin]);
+            W[bin] = W[bin] + or_kval(&kW[bin]);
+        }
     }
     if (nH) {
         /* compensated single-precision bins are merged in double precision */
@@ -507,6 +545,8 @@ int or_sample_range(const or_params* p, const or_integrand* f, const double* map
         }
     }
     if (rec_count) *rec_count = nrec;
+    free(kH);
+    free(kW);
     free(nH);
     free(nW);
     free(map32);
@@ -568,7 +608,7 @@ int or_sample_indices(const or_params* p, const int32_t* n_h, int32_t it, int64_
 /* and summed over hypercubes as in Sec. 3, Eq. (sumI):                       */
 /*   I = sum_h Omega S1_h / n_h,                                              */
 /*   V = sum_h max(0, Omega^2 S2_h / n_h - (Omega S1_h / n_h)^2) / (n_h - 1). */
-/* Sums are taken in hypercube order.                                         */
+/* Sums are compensated (see or_ksum).                                        */
 /* ------------------------------------------------------------------------ */
 void or_reduce(const or_params* p, const int32_t* n_h, const double* S1, const double* S2,
                double* I_out, double* V_out)
@@ -576,17 +616,17 @@ void or_reduce(const or_params* p, const int32_t* n_h, const double* S1, const d
     const int64_t nhc = or_n_hypercubes(p);
     const double omega = 1.0 / (double)nhc;
     const double omega2 = omega * omega;
-    double I = 0.0, V = 0.0;
+    or_ksum I = {0.0, 0.0}, V = {0.0, 0.0};
     for (int64_t h = 0; h < nhc; ++h) {
         const double n = (double)n_h[h];
         const double m = (omega * S1[h]) / n;
         double var = (omega2 * S2[h]) / n - m * m;
         if (var < 0.0) var = 0.0;
-        I = I + m;
-        V = V + var / (n - 1.0);
+        or_kadd(&I, m);
+        or_kadd(&V, var / (n - 1.0));
     }
-    *I_out = I;
-    *V_out = V;
+    *I_out = or_kval(&I);
+    *V_out = or_kval(&V);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -594,8 +634,8 @@ void or_reduce(const or_params* p, const int32_t* n_h, const double* S1, const d
 /*   sigma_h = sqrt(max(0, Omega^2 S2_h/n_h - (Omega S1_h/n_h)^2)),           */
 /*   d_h = sigma_h^beta (d_h = 1 when beta = 0),                              */
 /*   n_h' = max(2, floor(N_ev d_h / sum d)), or floor(...) + 2 in the         */
-/* alternative rule.  sum d is taken in hypercube order; when it is zero the  */
-/* allocation is kept.  Counts near-ties |q - round q| <= 1e-9 max(1, q) at   */
+/* alternative rule.  sum d is compensated; when it is zero the allocation is  */
+/* kept.  Counts near-ties |q - round q| <= 1e-9 max(1, q) at                 */
 /* integers where floor(q) decides n_h (>= 3 for the max(2, .) rule, >= 1 for */
 /* the +2 rule): there a last-bit difference in sum d could move n_h.         */
 /* ------------------------------------------------------------------------ */
@@ -607,7 +647,7 @@ int64_t or_realloc(const or_params* p, const double* S1, const double* S2, const
     const double omega2 = omega * omega;
     double* dh = (double*)malloc(sizeof(double) * (size_t)nhc);
     if (!dh) return -1;
-    double sum = 0.0;
+    or_ksum ksum = {0.0, 0.0};
     for (int64_t h = 0; h < nhc; ++h) {
         const double n = (double)n_in[h];
         const double m = (omega * S1[h]) / n;
@@ -615,8 +655,9 @@ int64_t or_realloc(const or_params* p, const double* S1, const double* S2, const
         if (var < 0.0) var = 0.0;
         const double sig = sqrt(var);
         dh[h] = (p->beta == 0.0) ? 1.0 : pow(sig, p->beta);
-        sum = sum + dh[h];
+        or_kadd(&ksum, dh[h]);
     }
+    const double sum = or_kval(&ksum);
     int64_t ties = 0;
     if (!(sum > 0.0)) {
         for (int64_t h = 0; h < nhc; ++h) n_out[h] = n_in[h];
@@ -678,8 +719,10 @@ int or_refine_axis(const or_params* p, const double* H, const double* W, double*
         c[i] = (di == 0.0) ? 0.0 : pow((1.0 - di) / (-log(di)), p->alpha);
         csum = csum + c[i];
     }
-    /* regrid */
+    /* regrid; with nothing to share out (the compressed sum underflowed or is
+     * not finite) step 1's delta d is not positive and the axis is kept */
     const double delta_d = csum / (double)NG;
+    if (!(delta_d > 0.0)) return 0;
     double* xn = d; /* d no longer needed; reuse for the new points */
     xn[0] = x[0];
     int32_t j = 0;

@@ -1,0 +1,285 @@
+"""ctypes binding of libvegasp.so (include/vegasp.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels.  If the library is not
+built, or no GPU is visible, the calls raise instead of falling back to
+anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvegasp.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "vegasp.h")
+
+_KIND = {"gauss_mix": 1, "corr_gauss": 2, "exp_abs": 3, "const": 4, "affine": 5, "balls": 6}
+_PREC = {"fp64": 0, "fp32_acc64": 1, "fp32_neumaier": 2}
+_HIST = {"weighted": 0, "literal": 1}
+
+VP_OK, VP_ERR_INVALID_ARG, VP_ERR_OOM, VP_ERR_DEVICE, VP_ERR_NUMERIC, VP_ERR_NOT_READY, \
+    VP_ERR_CANCELLED, VP_ERR_STATE = range(8)
+
+
+class VegaspError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+class vp_integrand(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("n_terms", C.c_int32),
+                ("centers", C.POINTER(C.c_double)), ("coefs", C.POINTER(C.c_double)),
+                ("amps", C.POINTER(C.c_double)), ("chol", C.POINTER(C.c_double)),
+                ("scale", C.c_double)]
+
+
+class vp_params(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_ev", C.c_int64), ("n_g", C.c_int32), ("n_iter", C.c_int32),
+                ("alpha", C.c_double), ("beta", C.c_double), ("lower", C.POINTER(C.c_double)),
+                ("upper", C.POINTER(C.c_double)), ("seed", C.c_uint64), ("precision", C.c_int32),
+                ("hist_mode", C.c_int32), ("realloc_plus2", C.c_int32), ("n_discard", C.c_int32),
+                ("n_st", C.c_int32)]
+
+
+class vp_result(C.Structure):
+    _fields_ = [("mean", C.c_double), ("sdev", C.c_double), ("chi2", C.c_double), ("dof", C.c_int32),
+                ("n_iter_done", C.c_int32), ("n_evals", C.c_int64), ("n_near_ties", C.c_int64),
+                ("n_nonfinite", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libvegasp.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int32)
+        sig = {
+            "vp_status_string": ([C.c_int], C.c_char_p),
+            "vp_last_error": ([], C.c_char_p),
+            "vp_ctx_create": ([C.c_int, vp, C.POINTER(vp)], C.c_int),
+            "vp_ctx_destroy": ([vp], C.c_int),
+            "vp_ctx_info": ([vp, ip, C.POINTER(C.c_int64)], C.c_int),
+            "vp_problem_create": ([vp, C.POINTER(vp_params), C.POINTER(vp_integrand), C.POINTER(vp)], C.c_int),
+            "vp_problem_destroy": ([vp], C.c_int),
+            "vp_problem_info": ([vp, ip, C.POINTER(C.c_int64)], C.c_int),
+            "vp_iterate": ([vp, C.c_int32], C.c_int),
+            "vp_sync": ([vp], C.c_int),
+            "vp_result_get": ([vp, C.POINTER(vp_result), dp, dp, C.c_int32], C.c_int),
+            "vp_map_get": ([vp, dp], C.c_int),
+            "vp_map_set": ([vp, dp], C.c_int),
+            "vp_alloc_get": ([vp, ip], C.c_int),
+            "vp_alloc_set": ([vp, ip], C.c_int),
+            "vp_iteration_get": ([vp, ip], C.c_int),
+            "vp_iteration_set": ([vp, C.c_int32], C.c_int),
+            "vp_accum_get": ([vp, dp, dp, dp, dp], C.c_int),
+            "vp_state_export": ([vp, vp, C.POINTER(C.c_size_t)], C.c_int),
+            "vp_state_import": ([vp, vp, C.c_size_t], C.c_int),
+            "vp_profile_enable": ([vp, C.c_int32], C.c_int),
+            "vp_kernel_time": ([vp, C.c_int32, dp, C.POINTER(C.c_int64)], C.c_int),
+            "vp_integrate": ([vp, C.POINTER(vp_params), C.POINTER(vp_integrand), C.POINTER(vp_result)], C.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str = ""):
+    if status != VP_OK:
+        msg = lib().vp_last_error().decode(errors="replace")
+        raise VegaspError(status, f"{what}: {msg}" if what else msg)
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+class Context:
+    """One GPU and one HIP stream (NULL: a stream of the library's own)."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        self.h = C.c_void_p()
+        check(lib().vp_ctx_create(device, C.c_void_p(stream) if stream else None, C.byref(self.h)),
+              "vp_ctx_create")
+
+    def info(self):
+        n = C.c_int32()
+        lds = C.c_int64()
+        check(lib().vp_ctx_info(self.h, C.byref(n), C.byref(lds)))
+        return {"n_cu": n.value, "lds_bytes": lds.value}
+
+    def close(self):
+        if self.h:
+            lib().vp_ctx_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        # at interpreter exit the process teardown releases device memory
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def marshal(params, integrand):
+    """(vp_params, vp_integrand, keep-alive list) from workloads.Params / Integrand."""
+    keep = []
+    f = integrand
+
+    def arr(a):
+        if a is None:
+            return None
+        x = np.ascontiguousarray(a, dtype=np.float64).ravel()
+        keep.append(x)
+        return _dp(x)
+
+    fi = vp_integrand(_KIND[f.kind], f.dim, f.n_terms, arr(f.centers), arr(f.coefs), arr(f.amps),
+                      arr(f.chol), float(f.scale))
+    p = params
+    pp = vp_params(p.dim, int(p.n_ev), p.n_g, p.n_iter, float(p.alpha), float(p.beta), arr(p.lower),
+                   arr(p.upper), int(p.seed) & ((1 << 64) - 1), _PREC[p.precision], _HIST[p.hist_mode],
+                   1 if p.realloc_plus2 else 0, int(p.n_discard), int(getattr(p, "n_st", 0) or 0))
+    return pp, fi, keep
+
+
+class Problem:
+    """Device state of one integration (vp_problem)."""
+
+    def __init__(self, ctx: Context, params, integrand, n_st: int = 0):
+        self.ctx = ctx
+        self.params = params
+        pp, fi, keep = marshal(params, integrand)
+        if n_st:
+            pp.n_st = n_st
+        self.h = C.c_void_p()
+        check(lib().vp_problem_create(ctx.h, C.byref(pp), C.byref(fi), C.byref(self.h)), "vp_problem_create")
+        ns = C.c_int32()
+        nh = C.c_int64()
+        check(lib().vp_problem_info(self.h, C.byref(ns), C.byref(nh)))
+        self.n_st, self.n_hc = ns.value, nh.value
+
+    def iterate(self, n: int = 1):
+        check(lib().vp_iterate(self.h, n), "vp_iterate")
+
+    def sync(self):
+        check(lib().vp_sync(self.h), "vp_sync")
+
+    def result(self, cap: int | None = None, allow_nonfinite: bool = False):
+        r = vp_result()
+        cap = cap if cap is not None else 65536
+        I = np.zeros(cap)
+        V = np.zeros(cap)
+        st = lib().vp_result_get(self.h, C.byref(r), _dp(I), _dp(V), cap)
+        if not (allow_nonfinite and st == VP_ERR_NUMERIC):
+            check(st, "vp_result_get")
+        n = r.n_iter_done
+        return {"mean": r.mean, "sdev": r.sdev, "chi2": r.chi2, "dof": r.dof, "n_iter_done": n,
+                "n_evals": r.n_evals, "ties": r.n_near_ties, "nonfinite": r.n_nonfinite,
+                "I": I[:n].copy(), "V": V[:n].copy(), "sig": np.sqrt(V[:n])}
+
+    def map(self):
+        P = self.params
+        m = np.empty((P.dim, P.n_g + 1))
+        check(lib().vp_map_get(self.h, _dp(m)), "vp_map_get")
+        return m
+
+    def set_map(self, m):
+        m = np.ascontiguousarray(m, dtype=np.float64)
+        check(lib().vp_map_set(self.h, _dp(m)), "vp_map_set")
+
+    def alloc(self):
+        n = np.empty(self.n_hc, dtype=np.int32)
+        check(lib().vp_alloc_get(self.h, _ip(n)), "vp_alloc_get")
+        return n
+
+    def set_alloc(self, n_h):
+        n = np.ascontiguousarray(n_h, dtype=np.int32)
+        check(lib().vp_alloc_set(self.h, _ip(n)), "vp_alloc_set")
+
+    @property
+    def it(self) -> int:
+        v = C.c_int32()
+        check(lib().vp_iteration_get(self.h, C.byref(v)))
+        return v.value
+
+    def set_it(self, it: int):
+        check(lib().vp_iteration_set(self.h, it), "vp_iteration_set")
+
+    def accum(self):
+        P = self.params
+        S1 = np.empty(self.n_hc)
+        S2 = np.empty(self.n_hc)
+        H = np.empty((P.dim, P.n_g))
+        W = np.empty((P.dim, P.n_g))
+        check(lib().vp_accum_get(self.h, _dp(S1), _dp(S2), _dp(H), _dp(W)), "vp_accum_get")
+        return {"S1": S1, "S2": S2, "H": H, "W": W}
+
+    def export_state(self) -> bytes:
+        n = C.c_size_t(0)
+        check(lib().vp_state_export(self.h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        check(lib().vp_state_export(self.h, buf, C.byref(n)), "vp_state_export")
+        return buf.raw[: n.value]
+
+    def import_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        check(lib().vp_state_import(self.h, buf, len(blob)), "vp_state_import")
+
+    def profile(self, on: bool = True):
+        check(lib().vp_profile_enable(self.h, 1 if on else 0))
+
+    def kernel_time(self, which: int = 0):
+        t = C.c_double()
+        n = C.c_int64()
+        check(lib().vp_kernel_time(self.h, which, C.byref(t), C.byref(n)), "vp_kernel_time")
+        return t.value, n.value
+
+    def close(self):
+        if self.h:
+            lib().vp_problem_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        # at interpreter exit the process teardown releases device memory
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def integrate(ctx: Context, params, integrand):
+    pp, fi, keep = marshal(params, integrand)
+    r = vp_result()
+    check(lib().vp_integrate(ctx.h, C.byref(pp), C.byref(fi), C.byref(r)), "vp_integrate")
+    return {"mean": r.mean, "sdev": r.sdev, "chi2": r.chi2, "dof": r.dof, "n_evals": r.n_evals,
+            "n_iter_done": r.n_iter_done, "ties": r.n_near_ties}
+
+
+def declared_symbols() -> list:
+    """Function names declared in include/vegasp.h."""
+    import re
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(vp_\w+)\s*\(", src, flags=re.M)))

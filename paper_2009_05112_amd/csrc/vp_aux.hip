@@ -1,0 +1,466 @@
+// vp_aux.hip -- the per-hypercube and per-increment kernels of one iteration:
+// allocation scan, edge fix-up, training-data reduction, iteration estimate
+// and combination, reallocation, and map refinement.
+#include "vp_aux.hpp"
+
+namespace vp {
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int64_t lo = __shfl_up((int)(uint32_t)v, d);
+        const int64_t hi = __shfl_up((int)(uint32_t)((uint64_t)v >> 32), d);
+        const int64_t p = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+        if (lane >= d) v += p;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread across a block of kScanBlock
+// threads; returns the block total in *total.
+__device__ int64_t block_excl_scan(int64_t v, int64_t* total)
+{
+    __shared__ int64_t wsum[kScanBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t incl = wave_incl_scan(v, lane);
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    if (w == 0) {
+        int64_t x = lane < kScanBlock / kWave ? wsum[lane] : 0;
+        x = wave_incl_scan(x, lane);
+        if (lane < kScanBlock / kWave) wsum[lane] = x;
+    }
+    __syncthreads();
+    const int64_t before = (w > 0 ? wsum[w - 1] : 0) + incl - v;
+    *total = wsum[kScanBlock / kWave - 1];
+    __syncthreads();
+    return before;
+}
+
+// ---------------------------------------------------------------- allocation scan
+// Sample offsets of every hypercube: offs[h] = sum_{h' < h} n_h', and
+// offs[n_hc] = N_tot (the samples actually drawn this iteration, Sec. 3).
+__global__ __launch_bounds__(kScanBlock) void k_scan_local(const int32_t* __restrict__ n_h,
+                                                           int64_t n_hc, int64_t* __restrict__ offs,
+                                                           int64_t* __restrict__ bsum)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int64_t v[kScanPer];
+    int64_t t = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        const int64_t h = base + i;
+        v[i] = h < n_hc ? (int64_t)n_h[h] : 0;
+        t += v[i];
+    }
+    int64_t total;
+    int64_t run = block_excl_scan(t, &total);
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        const int64_t h = base + i;
+        if (h < n_hc) offs[h] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// Exclusive scan of the block totals by one block; writes N_tot.
+__global__ __launch_bounds__(kScanBlock) void k_scan_top(int64_t* __restrict__ bsum, int64_t nb,
+                                                         int64_t* __restrict__ offs, int64_t n_hc)
+{
+    const int64_t per = (nb + kScanBlock - 1) / kScanBlock;
+    const int64_t b0 = (int64_t)threadIdx.x * per;
+    int64_t t = 0;
+    for (int64_t i = 0; i < per; ++i)
+        if (b0 + i < nb) t += bsum[b0 + i];
+    int64_t total;
+    int64_t run = block_excl_scan(t, &total);
+    for (int64_t i = 0; i < per; ++i) {
+        if (b0 + i < nb) {
+            const int64_t x = bsum[b0 + i];
+            bsum[b0 + i] = run;
+            run += x;
+        }
+    }
+    if (threadIdx.x == 0) offs[n_hc] = total;
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ offs, int64_t n_hc, const int64_t* __restrict__ bsum)
+{
+    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h < n_hc) offs[h] += bsum[h / kScanTile];
+}
+
+// ---------------------------------------------------------------- edge fix-up
+// Records arrive sorted by hypercube (wave order); each run of records of
+// one hypercube is summed in record order by the thread holding its first.
+__global__ void k_edge_fixup(const EdgeRec* __restrict__ e, int64_t n_rec, double* __restrict__ S1,
+                             double* __restrict__ S2)
+{
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rec;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t h = e[r].h;
+        if (h < 0) continue;
+        int64_t p = r - 1;
+        while (p >= 0 && e[p].h < 0) --p;
+        if (p >= 0 && e[p].h == h) continue;
+        double a = e[r].s1, b = e[r].s2;
+        for (int64_t q = r + 1; q < n_rec; ++q) {
+            const int64_t hq = e[q].h;
+            if (hq < 0) continue;
+            if (hq != h) break;
+            a = a + e[q].s1;
+            b = b + e[q].s2;
+        }
+        S1[h] = a;
+        S2[h] = b;
+    }
+}
+
+// ---------------------------------------------------------------- training data
+// Sum of the per-workgroup partials in workgroup order; splits the
+// interleaved (numerator, weight) pairs into H and W.
+__global__ void k_hist_reduce(const double* __restrict__ part, int n_part, int64_t nbins,
+                              double* __restrict__ H, double* __restrict__ W)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * nbins;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int p = 0; p < n_part; ++p) s = s + part[(int64_t)p * 2 * nbins + i];
+        if (i & 1) W[i >> 1] = s;
+        else H[i >> 1] = s;
+    }
+}
+
+__global__ void k_fill_f64(double* __restrict__ x, int64_t n, double v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ x, int64_t n, int32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+// ---------------------------------------------------------------- estimate
+// Per hypercube (Sec. 2.1 Eq. sigest per hypercube, Sec. 3 step 2):
+// m = Omega S1 / n, var = max(0, Omega^2 S2 / n - m^2); the iteration takes
+// I = sum m and V = sum var / (n - 1); the allocation takes
+// d = sqrt(var)^beta (1 when beta = 0).
+__device__ __forceinline__ void hypercube_terms(double s1, double s2, int32_t n_i, double omega,
+                                                double omega2, double beta, double* m_out,
+                                                double* var_out, double* d_out)
+{
+    const double n = (double)n_i;
+    const double m = (omega * s1) / n;
+    double var = (omega2 * s2) / n - m * m;
+    if (var < 0.0) var = 0.0;
+    *m_out = m;
+    *var_out = var;
+    *d_out = (beta == 0.0) ? 1.0 : pow(sqrt(var), beta);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) v = v + __shfl_down(v, d);
+    return v;
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_est_partial(const int32_t* __restrict__ n_h,
+                                                           const double* __restrict__ S1,
+                                                           const double* __restrict__ S2,
+                                                           int64_t n_hc, double omega, double omega2,
+                                                           double beta, double* __restrict__ part)
+{
+    double I = 0.0, V = 0.0, Sd = 0.0;
+    for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < n_hc;
+         h += (int64_t)gridDim.x * blockDim.x) {
+        double m, var, d;
+        const int32_t n = n_h[h];
+        hypercube_terms(S1[h], S2[h], n, omega, omega2, beta, &m, &var, &d);
+        I = I + m;
+        V = V + var / ((double)n - 1.0);
+        Sd = Sd + d;
+    }
+    __shared__ double red[3][kRedBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    I = wave_sum(I);
+    V = wave_sum(V);
+    Sd = wave_sum(Sd);
+    if (lane == 0) {
+        red[0][w] = I;
+        red[1][w] = V;
+        red[2][w] = Sd;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int i = 0; i < kRedBlock / kWave; ++i) {
+            a = a + red[0][i];
+            b = b + red[1][i];
+            c = c + red[2][i];
+        }
+        part[3 * blockIdx.x + 0] = a;
+        part[3 * blockIdx.x + 1] = b;
+        part[3 * blockIdx.x + 2] = c;
+    }
+}
+
+// One thread: totals over the partials in block order, the iteration's
+// record, and the combination over iterations n_discard..it (Sec. 2.5).
+__global__ void k_est_final(const double* __restrict__ part, int n_part, DevState* st,
+                            double* __restrict__ hist_I, double* __restrict__ hist_V,
+                            const int64_t* __restrict__ offs, int64_t n_hc, int32_t it_slot,
+                            int32_t n_discard)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double I = 0.0, V = 0.0, Sd = 0.0;
+    for (int p = 0; p < n_part; ++p) {
+        I = I + part[3 * p + 0];
+        V = V + part[3 * p + 1];
+        Sd = Sd + part[3 * p + 2];
+    }
+    st->sumd = Sd;
+    hist_I[it_slot] = I;
+    hist_V[it_slot] = V;
+    st->n_iter_done = it_slot + 1;
+    st->n_evals += offs[n_hc];
+    const int first = n_discard < 0 ? 0 : n_discard;
+    const int n = it_slot + 1;
+    const int cnt = n - first;
+    if (cnt <= 0) {
+        st->mean = __builtin_nan("");
+        st->sdev = __builtin_nan("");
+        st->chi2 = __builtin_nan("");
+        st->dof = 0;
+        return;
+    }
+    st->dof = cnt - 1;
+    bool zero = false;
+    for (int j = first; j < n; ++j)
+        if (!(hist_V[j] > 0.0)) zero = true;
+    if (zero) {
+        double s = 0.0;
+        for (int j = first; j < n; ++j) s = s + hist_I[j];
+        st->mean = s / (double)cnt;
+        st->sdev = 0.0;
+        st->chi2 = __builtin_nan("");
+        return;
+    }
+    double sw = 0.0, swi = 0.0;
+    for (int j = first; j < n; ++j) {
+        const double sig = sqrt(hist_V[j]);
+        const double w = 1.0 / (sig * sig);
+        sw = sw + w;
+        swi = swi + hist_I[j] * w;
+    }
+    const double m = swi / sw;
+    double c2 = 0.0;
+    for (int j = first; j < n; ++j) {
+        const double sig = sqrt(hist_V[j]);
+        const double r = hist_I[j] - m;
+        c2 = c2 + r * r / (sig * sig);
+    }
+    st->mean = m;
+    st->sdev = 1.0 / sqrt(sw);
+    st->chi2 = c2;
+}
+
+// ---------------------------------------------------------------- reallocation
+// Sec. 3 steps 3-4: n_h = max(2, floor(N_ev d_h / sum d)), or floor(.) + 2.
+// Near-ties (within 1e-9 relative of an integer that decides n_h) are counted.
+__global__ __launch_bounds__(kRedBlock) void k_realloc(int32_t* __restrict__ n_h,
+                                                       const double* __restrict__ S1,
+                                                       const double* __restrict__ S2, int64_t n_hc,
+                                                       double omega, double omega2, double beta,
+                                                       double n_ev, int32_t plus2,
+                                                       const DevState* __restrict__ st,
+                                                       unsigned long long* __restrict__ ties)
+{
+    const double sumd = st->sumd;
+    if (!(sumd > 0.0)) return;
+    unsigned long long nt = 0;
+    const double first_visible = plus2 ? 1.0 : 3.0;
+    for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < n_hc;
+         h += (int64_t)gridDim.x * blockDim.x) {
+        double m, var, d;
+        hypercube_terms(S1[h], S2[h], n_h[h], omega, omega2, beta, &m, &var, &d);
+        const double q = (n_ev * d) / sumd;
+        const double fl = floor(q);
+        const double r = rint(q);
+        const double tol = 1e-9 * (q > 1.0 ? q : 1.0);
+        if (r >= first_visible && fabs(q - r) <= tol) ++nt;
+        int64_t n = (int64_t)fl;
+        if (plus2) n = n + 2;
+        else if (n < 2) n = 2;
+        if (n > 2147483647) n = 2147483647;
+        n_h[h] = (int32_t)n;
+    }
+    for (int d = kWave / 2; d >= 1; d >>= 1) nt += __shfl_down(nt, d);
+    if ((threadIdx.x & (kWave - 1)) == 0 && nt) atomicAdd(ties, nt);
+}
+
+// ---------------------------------------------------------------- refinement
+// One workgroup per axis (Sec. 2.3): d_i = H_i / W_i (0 without samples);
+// smoothing (7,1)/8, (1,6,1)/8, (1,7)/8 and division by the raw sum;
+// compression ((1 - d) / ln(1/d))^alpha (0 at d = 0); regrid so that every
+// new increment holds an equal share of the compressed d.  The two running
+// sums and the regrid walk are sequential, in increment order.
+__global__ __launch_bounds__(kRefineBlock) void k_refine(double* __restrict__ map,
+                                                         float* __restrict__ map32,
+                                                         const double* __restrict__ H,
+                                                         const double* __restrict__ W, int n_g,
+                                                         double alpha)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    double* x = reinterpret_cast<double*>(lds_raw);  // [n_g + 1]
+    double* c = x + (n_g + 1);                        // [n_g]
+    double* y = c + n_g;                              // [n_g + 1]
+    __shared__ double s_sum;
+    const int mu = blockIdx.x;
+    double* xm = map + (int64_t)mu * (n_g + 1);
+    float* xm32 = map32 + (int64_t)mu * (n_g + 1);
+    const double* Hm = H + (int64_t)mu * n_g;
+    const double* Wm = W + (int64_t)mu * n_g;
+    if (alpha == 0.0 || n_g < 2) return;
+
+    for (int i = threadIdx.x; i <= n_g; i += blockDim.x) x[i] = xm[i];
+    for (int i = threadIdx.x; i < n_g; i += blockDim.x) {
+        const double w = Wm[i];
+        c[i] = (w > 0.0) ? Hm[i] / w : 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n_g; ++i) s = s + c[i];
+        s_sum = s;
+    }
+    __syncthreads();
+    const double s = s_sum;
+    if (!(s > 0.0)) return;
+    // smoothing and normalisation into y
+    for (int i = threadIdx.x; i < n_g; i += blockDim.x) {
+        double v;
+        if (i == 0) v = (7.0 * c[0] + c[1]) / 8.0;
+        else if (i == n_g - 1) v = (c[n_g - 2] + 7.0 * c[n_g - 1]) / 8.0;
+        else v = (c[i - 1] + 6.0 * c[i] + c[i + 1]) / 8.0;
+        y[i] = v / s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_g; i += blockDim.x) {
+        const double di = y[i];
+        c[i] = (di == 0.0) ? 0.0 : pow((1.0 - di) / (-log(di)), alpha);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double csum = 0.0;
+        for (int i = 0; i < n_g; ++i) csum = csum + c[i];
+        const double delta_d = csum / (double)n_g;
+        y[0] = x[0];
+        y[n_g] = x[n_g];
+        if (!(delta_d > 0.0)) {
+            // nothing to share out (underflow or non-finite data): keep the axis
+            for (int i = 1; i < n_g; ++i) y[i] = x[i];
+        } else {
+        int j = 0;
+        double acc = 0.0;
+        for (int i = 1; i < n_g; ++i) {
+            while (acc < delta_d && j < n_g) {
+                acc = acc + c[j];
+                j = j + 1;
+            }
+            acc = acc - delta_d;
+            const double frac_left = (acc > 0.0) ? acc / c[j - 1] : 0.0;
+            y[i] = x[j] - frac_left * (x[j] - x[j - 1]);
+        }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= n_g; i += blockDim.x) {
+        xm[i] = y[i];
+        xm32[i] = (float)y[i];
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+void launch_scan(const int32_t* n_h, int64_t n_hc, int64_t* offs, int64_t* bsum, hipStream_t s)
+{
+    const int64_t nb = (n_hc + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kScanBlock), 0, s, n_h, n_hc, offs, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, bsum, nb, offs, n_hc);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n_hc + 255) / 256)), dim3(256), 0, s, offs, n_hc,
+                       (const int64_t*)bsum);
+}
+
+void launch_edge_fixup(const EdgeRec* e, int64_t n_rec, double* S1, double* S2, hipStream_t s)
+{
+    const int64_t g = (n_rec + 255) / 256;
+    hipLaunchKernelGGL(k_edge_fixup, dim3((unsigned)(g > 0 ? g : 1)), dim3(256), 0, s, e, n_rec, S1, S2);
+}
+
+void launch_hist_reduce(const double* part, int n_part, int64_t nbins, double* H, double* W,
+                        hipStream_t s)
+{
+    const int64_t g = (2 * nbins + 255) / 256;
+    hipLaunchKernelGGL(k_hist_reduce, dim3((unsigned)g), dim3(256), 0, s, part, n_part, nbins, H, W);
+}
+
+void launch_fill_f64(double* x, int64_t n, double v, hipStream_t s)
+{
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)g), dim3(256), 0, s, x, n, v);
+}
+
+void launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s)
+{
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)g), dim3(256), 0, s, x, n, v);
+}
+
+int est_grid(int64_t n_hc)
+{
+    int64_t g = (n_hc + kRedBlock - 1) / kRedBlock;
+    if (g > kRedMaxGrid) g = kRedMaxGrid;
+    return (int)(g < 1 ? 1 : g);
+}
+
+void launch_estimate(const int32_t* n_h, const double* S1, const double* S2, int64_t n_hc,
+                     double omega, double omega2, double beta, double* part, DevState* st,
+                     double* hist_I, double* hist_V, const int64_t* offs, int32_t it_slot,
+                     int32_t n_discard, hipStream_t s)
+{
+    const int g = est_grid(n_hc);
+    hipLaunchKernelGGL(k_est_partial, dim3(g), dim3(kRedBlock), 0, s, n_h, S1, S2, n_hc, omega, omega2,
+                       beta, part);
+    hipLaunchKernelGGL(k_est_final, dim3(1), dim3(64), 0, s, (const double*)part, g, st, hist_I, hist_V,
+                       offs, n_hc, it_slot, n_discard);
+}
+
+void launch_realloc(int32_t* n_h, const double* S1, const double* S2, int64_t n_hc, double omega,
+                    double omega2, double beta, double n_ev, int32_t plus2, const DevState* st,
+                    unsigned long long* ties, hipStream_t s)
+{
+    const int g = est_grid(n_hc);
+    hipLaunchKernelGGL(k_realloc, dim3(g), dim3(kRedBlock), 0, s, n_h, S1, S2, n_hc, omega, omega2,
+                       beta, n_ev, plus2, st, ties);
+}
+
+void launch_refine(double* map, float* map32, const double* H, const double* W, int dim, int n_g,
+                   double alpha, hipStream_t s)
+{
+    const size_t lds = (size_t)(3 * n_g + 2) * sizeof(double);
+    hipLaunchKernelGGL(k_refine, dim3(dim), dim3(kRefineBlock), lds, s, map, map32, H, W, n_g, alpha);
+}
+
+}  // namespace vp

@@ -1,0 +1,86 @@
+// vp_internal.hpp -- types shared by the library's kernels and host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vp {
+
+constexpr int kWave = 64;
+constexpr int kMaxTerms = 4;
+constexpr int kMaxDim = 24;       // FP64 sampling path
+constexpr int kMaxDimSplit = 16;  // FP32 sampling paths
+constexpr int kMaxNg = 4096;      // refinement keeps one axis in LDS
+// Sampling workgroup size: the FP64 body needs ~180 VGPRs (two waves per
+// SIMD), the FP32 bodies fit four waves per SIMD.
+constexpr int sample_block(int prec) { return prec == 0 ? 512 : 1024; }
+
+enum Prec { P_FP64 = 0, P_FP32_ACC64 = 1, P_FP32_NEUMAIER = 2 };
+enum Kind { K_GAUSS_MIX = 1, K_CORR_GAUSS = 2, K_EXP_ABS = 3, K_CONST = 4, K_AFFINE = 5, K_BALLS = 6 };
+
+// Integrand coefficients, in device memory; every lane reads the same
+// addresses, so the compiler turns the reads into scalar loads.
+struct IntegrandDev {
+    int32_t kind, dim, n_terms, pad;
+    double scale;
+    double coefs[kMaxTerms];
+    double amps[kMaxTerms];
+    double rad2[kMaxTerms];                 // balls: coefs[k]^2
+    double centers[kMaxTerms * kMaxDim + 1];
+    double chol[kMaxDim * kMaxDim];
+    float scale32;
+    float coefs32[kMaxTerms];
+    float amps32[kMaxTerms];
+    float rad2_32[kMaxTerms];
+    float centers32[kMaxTerms * kMaxDim + 1];
+    float chol32[kMaxDim * kMaxDim];
+};
+
+// Partial sums of the hypercubes a wave's sample range starts and ends in;
+// h < 0 marks an empty record.
+struct EdgeRec {
+    int64_t h;
+    double s1, s2;
+};
+
+struct SampleArgs {
+    const double* map;      // [dim][n_g + 1]
+    const float* map32;     // FP32 copy (split paths)
+    const int64_t* offs;    // [n_hc + 1] exclusive scan of n_h; offs[n_hc] = N_tot
+    double* S1;             // [n_hc]
+    double* S2;             // [n_hc]
+    double* hist_part;      // [grid][dim * n_g][2] per-workgroup training data (LDS path)
+    double* hist_glob;      // [dim * n_g][2] (global-atomic path, zeroed before launch)
+    EdgeRec* edges;         // [2 * n_waves]
+    unsigned long long* nonfinite;
+    const IntegrandDev* f;
+    int64_t n_hc;
+    int32_t n_g, n_st;
+    double R;               // n_g / n_st
+    float R32;
+    uint32_t key0, key1, it;
+    int32_t hist_mode;      // 0 weighted, 1 literal
+    int32_t hist_lds;       // 1: privatised in LDS; 0: global atomics
+    int32_t map_lds;        // 1: map staged in LDS
+    int32_t chunk;          // samples per lane per tile
+};
+
+typedef void (*SampleLauncher)(const SampleArgs& a, int grid, int block, size_t lds, hipStream_t s);
+typedef int (*SampleOccupancy)(int block, size_t lds);
+struct SampleEntry {
+    SampleLauncher launch;
+    SampleOccupancy occupancy;  // resident workgroups per CU at this block size and LDS
+};
+
+SampleEntry sample_entry_fp64(int dim, bool map_lds);
+SampleEntry sample_entry_fp32acc(int dim, bool map_lds);
+SampleEntry sample_entry_fp32neu(int dim, bool map_lds);
+
+// sampling kernels' LDS needs (bytes) for histogram and map
+inline size_t hist_lds_bytes(int dim, int n_g) { return (size_t)dim * n_g * 2 * sizeof(double); }
+inline size_t map_lds_bytes(int prec, int dim, int n_g)
+{
+    return (size_t)dim * (n_g + 1) * (prec == P_FP64 ? sizeof(double) : sizeof(float));
+}
+
+}  // namespace vp

@@ -1,0 +1,779 @@
+// vp_runtime.hip -- host runtime and C ABI of the vegas+ library (vegasp.h).
+//
+// A problem owns its device state: the vegas map (FP64 and an FP32 copy),
+// the allocation n_h, the sample offsets, per-hypercube sums, training data,
+// estimate history and a few device scalars.  vp_iterate enqueues the
+// kernels of each iteration on the context stream without host round trips:
+// the sampling kernel reads the number of samples from device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vegasp.h"
+#include "vp_aux.hpp"
+#include "vp_internal.hpp"
+
+using namespace vp;
+
+namespace {
+
+thread_local std::string g_err;
+
+vp_status fail(vp_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define VP_HIP(call)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(e_ == hipErrorOutOfMemory ? VP_ERR_OOM : VP_ERR_DEVICE, "%s: %s (%s:%d)", \
+                        #call, hipGetErrorString(e_), __FILE__, __LINE__);                      \
+    } while (0)
+
+constexpr int kMaxHistory = 65536;
+constexpr uint32_t kStateMagic = 0x56504C53u;  // "SLPV"
+
+}  // namespace
+
+// A context lives until its handle and every problem created on it are
+// destroyed, whatever the order of the destroy calls.
+struct vp_ctx {
+    int device;
+    hipStream_t stream;
+    bool own_stream;
+    int n_cu;
+    size_t lds_max;
+    int refs;
+};
+
+static void ctx_release(vp_ctx* c)
+{
+    if (--c->refs > 0) return;
+    hipSetDevice(c->device);
+    if (c->own_stream) {
+        hipStreamSynchronize(c->stream);
+        hipStreamDestroy(c->stream);
+    }
+    delete c;
+}
+
+struct vp_problem {
+    vp_ctx* ctx;
+    vp_params P;
+    std::vector<double> lower, upper;
+    IntegrandDev fh;
+    int32_t n_st;
+    int64_t n_hc;
+    double omega, omega2, R;
+    int32_t it;  // iteration index of the next iteration
+    int32_t slot;  // history slot of the next iteration
+    // device state
+    IntegrandDev* f_d = nullptr;
+    double* map = nullptr;
+    float* map32 = nullptr;
+    int32_t* n_h = nullptr;
+    int64_t* offs = nullptr;
+    int64_t* bsum = nullptr;
+    double* S1 = nullptr;
+    double* S2 = nullptr;
+    double* H = nullptr;
+    double* W = nullptr;
+    double* hist_part = nullptr;
+    double* hist_glob = nullptr;
+    EdgeRec* edges = nullptr;
+    double* est_part = nullptr;
+    double* hist_I = nullptr;
+    double* hist_V = nullptr;
+    DevState* st = nullptr;
+    // sampling launch
+    SampleEntry entry;
+    int block, grid, chunk;
+    int hist_lds, map_lds;
+    size_t lds;
+    int64_t n_waves;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pending;  // pairs: k1 start, k1 end, it start, it end
+    std::vector<hipEvent_t> ev_free;
+    double t_sample_ms = 0.0, t_iter_ms = 0.0;
+    int64_t n_sample = 0, n_iter = 0;
+};
+
+// ---------------------------------------------------------------- helpers
+static int32_t nst_rule(int32_t dim, int64_t n_ev)
+{
+    // largest n >= 1 with 4 n^dim <= n_ev (Sec. 3, Eq. Nst_vegasp)
+    auto ok = [&](int64_t n) {
+        int64_t acc = 4;
+        if (acc > n_ev) return false;
+        for (int d = 0; d < dim; ++d) {
+            if (acc > n_ev / n) return false;
+            acc *= n;
+        }
+        return acc <= n_ev;
+    };
+    int64_t n = 1;
+    while (ok(n + 1)) ++n;
+    return (int32_t)n;
+}
+
+static bool pow_le(int64_t n, int dim, int64_t mult, int64_t limit)
+{
+    int64_t acc = mult;
+    for (int d = 0; d < dim; ++d) {
+        if (acc > limit / n) return false;
+        acc *= n;
+    }
+    return acc <= limit;
+}
+
+static vp_status validate(const vp_params* P, const vp_integrand* f)
+{
+    if (!P || !f) return fail(VP_ERR_INVALID_ARG, "params and integrand are required");
+    const int maxd = P->precision == VP_FP64 ? kMaxDim : kMaxDimSplit;
+    if (P->precision < 0 || P->precision > 2) return fail(VP_ERR_INVALID_ARG, "unknown precision %d", P->precision);
+    if (P->dim < 1 || P->dim > maxd)
+        return fail(VP_ERR_INVALID_ARG, "dim %d outside 1..%d for this precision", P->dim, maxd);
+    if (P->n_ev < 4 || P->n_ev > 2147483647LL) return fail(VP_ERR_INVALID_ARG, "n_ev %lld outside 4..2^31-1", (long long)P->n_ev);
+    if (P->n_g < 1 || P->n_g > kMaxNg) return fail(VP_ERR_INVALID_ARG, "n_g %d outside 1..%d", P->n_g, kMaxNg);
+    if (!(P->alpha >= 0.0) || !std::isfinite(P->alpha)) return fail(VP_ERR_INVALID_ARG, "alpha must be >= 0");
+    if (!(P->beta >= 0.0) || !std::isfinite(P->beta)) return fail(VP_ERR_INVALID_ARG, "beta must be >= 0");
+    if (P->n_iter < 0) return fail(VP_ERR_INVALID_ARG, "n_iter must be >= 0");
+    if (P->hist_mode != VP_HIST_WEIGHTED && P->hist_mode != VP_HIST_LITERAL)
+        return fail(VP_ERR_INVALID_ARG, "unknown hist_mode %d", P->hist_mode);
+    if (P->n_st < 0) return fail(VP_ERR_INVALID_ARG, "n_st must be >= 0");
+    if (P->n_st > 0 && !pow_le(P->n_st, P->dim, 2, P->n_ev))
+        return fail(VP_ERR_INVALID_ARG, "n_st %d leaves fewer than 2 samples per hypercube", P->n_st);
+    if (P->lower && P->upper)
+        for (int d = 0; d < P->dim; ++d)
+            if (!(P->lower[d] < P->upper[d])) return fail(VP_ERR_INVALID_ARG, "lower[%d] >= upper[%d]", d, d);
+    if ((P->lower == nullptr) != (P->upper == nullptr))
+        return fail(VP_ERR_INVALID_ARG, "lower and upper must be given together");
+    if (f->dim != P->dim) return fail(VP_ERR_INVALID_ARG, "integrand dim %d != problem dim %d", f->dim, P->dim);
+    switch (f->kind) {
+    case VP_F_GAUSS_MIX:
+    case VP_F_EXP_ABS:
+    case VP_F_BALLS:
+        if (f->n_terms < 1 || f->n_terms > kMaxTerms)
+            return fail(VP_ERR_INVALID_ARG, "n_terms %d outside 1..%d", f->n_terms, kMaxTerms);
+        if (!f->centers || !f->coefs || !f->amps) return fail(VP_ERR_INVALID_ARG, "centers, coefs, amps required");
+        break;
+    case VP_F_CORR_GAUSS:
+        if (!f->centers || !f->chol) return fail(VP_ERR_INVALID_ARG, "centers and chol required");
+        break;
+    case VP_F_AFFINE:
+        if (!f->centers) return fail(VP_ERR_INVALID_ARG, "centers (affine coefficients) required");
+        break;
+    case VP_F_CONST:
+        break;
+    default:
+        return fail(VP_ERR_INVALID_ARG, "unknown integrand kind %d", f->kind);
+    }
+    return VP_OK;
+}
+
+static void fill_integrand(IntegrandDev& d, const vp_integrand* f)
+{
+    memset(&d, 0, sizeof d);
+    d.kind = f->kind;
+    d.dim = f->dim;
+    d.n_terms = f->n_terms;
+    d.scale = f->scale;
+    const int D = f->dim;
+    int K = 0;
+    if (f->kind == VP_F_GAUSS_MIX || f->kind == VP_F_EXP_ABS || f->kind == VP_F_BALLS) {
+        K = f->n_terms;
+        for (int k = 0; k < K; ++k) {
+            d.coefs[k] = f->coefs[k];
+            d.amps[k] = f->amps[k];
+            d.rad2[k] = f->coefs[k] * f->coefs[k];
+            for (int m = 0; m < D; ++m) d.centers[k * D + m] = f->centers[k * D + m];
+        }
+    } else if (f->kind == VP_F_CORR_GAUSS) {
+        for (int m = 0; m < D; ++m) d.centers[m] = f->centers[m];
+        for (int i = 0; i < D * D; ++i) d.chol[i] = f->chol[i];
+    } else if (f->kind == VP_F_AFFINE) {
+        for (int m = 0; m <= D; ++m) d.centers[m] = f->centers[m];
+    }
+    d.scale32 = (float)d.scale;
+    for (int k = 0; k < kMaxTerms; ++k) {
+        d.coefs32[k] = (float)d.coefs[k];
+        d.amps32[k] = (float)d.amps[k];
+        d.rad2_32[k] = d.coefs32[k] * d.coefs32[k];
+    }
+    for (int i = 0; i < kMaxTerms * kMaxDim + 1; ++i) d.centers32[i] = (float)d.centers[i];
+    for (int i = 0; i < kMaxDim * kMaxDim; ++i) d.chol32[i] = (float)d.chol[i];
+}
+
+template <typename T>
+static hipError_t dalloc(T** p, size_t n)
+{
+    return hipMalloc((void**)p, sizeof(T) * (n ? n : 1));
+}
+
+static void free_problem(vp_problem* p)
+{
+    if (!p) return;
+    vp_ctx* ctx = p->ctx;
+    hipFree(p->f_d);
+    hipFree(p->map);
+    hipFree(p->map32);
+    hipFree(p->n_h);
+    hipFree(p->offs);
+    hipFree(p->bsum);
+    hipFree(p->S1);
+    hipFree(p->S2);
+    hipFree(p->H);
+    hipFree(p->W);
+    hipFree(p->hist_part);
+    hipFree(p->hist_glob);
+    hipFree(p->edges);
+    hipFree(p->est_part);
+    hipFree(p->hist_I);
+    hipFree(p->hist_V);
+    hipFree(p->st);
+    for (auto e : p->ev_pending) hipEventDestroy(e);
+    for (auto e : p->ev_free) hipEventDestroy(e);
+    delete p;
+    if (ctx) ctx_release(ctx);
+}
+
+static hipEvent_t take_event(vp_problem* p)
+{
+    if (!p->ev_free.empty()) {
+        hipEvent_t e = p->ev_free.back();
+        p->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+static vp_status drain_events(vp_problem* p)
+{
+    for (size_t i = 0; i + 3 < p->ev_pending.size(); i += 4) {
+        float a = 0.f, b = 0.f;
+        VP_HIP(hipEventSynchronize(p->ev_pending[i + 3]));
+        VP_HIP(hipEventElapsedTime(&a, p->ev_pending[i], p->ev_pending[i + 1]));
+        VP_HIP(hipEventElapsedTime(&b, p->ev_pending[i + 2], p->ev_pending[i + 3]));
+        p->t_sample_ms += a;
+        p->t_iter_ms += b;
+        p->n_sample += 1;
+        p->n_iter += 1;
+    }
+    for (auto e : p->ev_pending) p->ev_free.push_back(e);
+    p->ev_pending.clear();
+    return VP_OK;
+}
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+const char* vp_status_string(vp_status s)
+{
+    switch (s) {
+    case VP_OK: return "ok";
+    case VP_ERR_INVALID_ARG: return "invalid argument";
+    case VP_ERR_OOM: return "out of memory";
+    case VP_ERR_DEVICE: return "device error";
+    case VP_ERR_NUMERIC: return "non-finite integrand values";
+    case VP_ERR_NOT_READY: return "not ready";
+    case VP_ERR_CANCELLED: return "cancelled";
+    case VP_ERR_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* vp_last_error(void) { return g_err.c_str(); }
+
+vp_status vp_ctx_create(int device, void* hip_stream, vp_ctx** out)
+{
+    if (!out) return fail(VP_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    VP_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(VP_ERR_INVALID_ARG, "device %d not in 0..%d", device, n - 1);
+    VP_HIP(hipSetDevice(device));
+    vp_ctx* c = new vp_ctx();
+    c->device = device;
+    c->refs = 1;
+    c->own_stream = (hip_stream == nullptr);
+    if (c->own_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(VP_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+    } else {
+        c->stream = (hipStream_t)hip_stream;
+    }
+    int cu = 0, lds = 0;
+    hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device);
+    hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    c->n_cu = cu > 0 ? cu : 1;
+    c->lds_max = lds > 0 ? (size_t)lds : 65536;
+    *out = c;
+    return VP_OK;
+}
+
+vp_status vp_ctx_destroy(vp_ctx* c)
+{
+    if (!c) return VP_OK;
+    ctx_release(c);
+    return VP_OK;
+}
+
+vp_status vp_ctx_info(vp_ctx* c, int32_t* n_cu, int64_t* lds)
+{
+    if (!c) return fail(VP_ERR_INVALID_ARG, "ctx is NULL");
+    if (n_cu) *n_cu = c->n_cu;
+    if (lds) *lds = (int64_t)c->lds_max;
+    return VP_OK;
+}
+
+vp_status vp_problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, vp_problem** out)
+{
+    if (!ctx || !out) return fail(VP_ERR_INVALID_ARG, "ctx and out are required");
+    *out = nullptr;
+    vp_status s = validate(P, f);
+    if (s != VP_OK) return s;
+    VP_HIP(hipSetDevice(ctx->device));
+    vp_problem* p = new vp_problem();
+    p->ctx = ctx;
+    ctx->refs += 1;
+    p->P = *P;
+    const int D = P->dim, NG = P->n_g;
+    p->lower.assign(D, 0.0);
+    p->upper.assign(D, 1.0);
+    if (P->lower)
+        for (int d = 0; d < D; ++d) {
+            p->lower[d] = P->lower[d];
+            p->upper[d] = P->upper[d];
+        }
+    p->P.lower = p->lower.data();
+    p->P.upper = p->upper.data();
+    fill_integrand(p->fh, f);
+    p->n_st = P->n_st > 0 ? P->n_st : nst_rule(D, P->n_ev);
+    int64_t nhc = 1;
+    for (int d = 0; d < D; ++d) nhc *= p->n_st;
+    p->n_hc = nhc;
+    p->omega = 1.0 / (double)nhc;
+    p->omega2 = p->omega * p->omega;
+    p->R = (double)NG / (double)p->n_st;
+    p->it = 0;
+    p->slot = 0;
+
+    // sampling launch shape
+    const int prec = P->precision;
+    p->block = sample_block(prec);
+    const size_t hb = hist_lds_bytes(D, NG), mb = map_lds_bytes(prec, D, NG);
+    p->hist_lds = hb <= ctx->lds_max ? 1 : 0;
+    if (prec == VP_FP32_NEUMAIER && !p->hist_lds) {
+        free_problem(p);
+        return fail(VP_ERR_INVALID_ARG, "compensated sums need dim * n_g * 16 <= %zu bytes of LDS", ctx->lds_max);
+    }
+    p->map_lds = (p->hist_lds ? hb : 0) + mb <= ctx->lds_max ? 1 : 0;
+    p->lds = (p->hist_lds ? hb : 0) + (p->map_lds ? mb : 0);
+    p->entry = prec == VP_FP64 ? sample_entry_fp64(D, p->map_lds)
+             : prec == VP_FP32_ACC64 ? sample_entry_fp32acc(D, p->map_lds)
+                                     : sample_entry_fp32neu(D, p->map_lds);
+    if (!p->entry.launch) {
+        free_problem(p);
+        return fail(VP_ERR_INVALID_ARG, "no sampling kernel for dim %d", D);
+    }
+    const char* env_chunk = getenv("VEGASP_CHUNK");
+    p->chunk = env_chunk ? std::max(1, atoi(env_chunk)) : 8;
+    int occ = p->entry.occupancy(p->block, p->lds);
+    if (occ < 1) occ = 1;
+    const int64_t n_tot_max = P->n_ev + 2 * nhc;
+    const int64_t waves_per_block = p->block / kWave;
+    const int64_t useful_waves = std::max<int64_t>(1, n_tot_max / ((int64_t)kWave * p->chunk));
+    int64_t grid = (int64_t)ctx->n_cu * occ;
+    grid = std::min<int64_t>(grid, (useful_waves + waves_per_block - 1) / waves_per_block);
+    p->grid = (int)std::max<int64_t>(1, grid);
+    p->n_waves = (int64_t)p->grid * waves_per_block;
+
+    // device state
+    const int64_t nbins = (int64_t)D * NG;
+    hipError_t e = hipSuccess;
+#define VP_ALLOC(ptr, n)                                                                    \
+    if (e == hipSuccess) e = dalloc(&(ptr), (size_t)(n));
+    VP_ALLOC(p->f_d, 1);
+    VP_ALLOC(p->map, (int64_t)D * (NG + 1));
+    VP_ALLOC(p->map32, (int64_t)D * (NG + 1));
+    VP_ALLOC(p->n_h, nhc);
+    VP_ALLOC(p->offs, nhc + 1);
+    VP_ALLOC(p->bsum, scan_blocks(nhc) + 1);
+    VP_ALLOC(p->S1, nhc);
+    VP_ALLOC(p->S2, nhc);
+    VP_ALLOC(p->H, nbins);
+    VP_ALLOC(p->W, nbins);
+    if (p->hist_lds) VP_ALLOC(p->hist_part, (int64_t)p->grid * 2 * nbins);
+    if (!p->hist_lds) VP_ALLOC(p->hist_glob, 2 * nbins);
+    VP_ALLOC(p->edges, 2 * p->n_waves);
+    VP_ALLOC(p->est_part, 3 * (int64_t)est_grid(nhc));
+    VP_ALLOC(p->hist_I, kMaxHistory);
+    VP_ALLOC(p->hist_V, kMaxHistory);
+    VP_ALLOC(p->st, 1);
+#undef VP_ALLOC
+    if (e != hipSuccess) {
+        free_problem(p);
+        return fail(e == hipErrorOutOfMemory ? VP_ERR_OOM : VP_ERR_DEVICE, "allocating problem state: %s",
+                    hipGetErrorString(e));
+    }
+    // initial map (Sec. 2.3: start from a uniform grid), uniform allocation
+    std::vector<double> m((size_t)D * (NG + 1));
+    std::vector<float> m32(m.size());
+    for (int d = 0; d < D; ++d) {
+        const double a = p->lower[d], b = p->upper[d];
+        for (int i = 0; i < NG; ++i) m[(size_t)d * (NG + 1) + i] = a + (b - a) * ((double)i / (double)NG);
+        m[(size_t)d * (NG + 1) + NG] = b;
+    }
+    for (size_t i = 0; i < m.size(); ++i) m32[i] = (float)m[i];
+    DevState st0;
+    memset(&st0, 0, sizeof st0);
+    hipStream_t sm = ctx->stream;
+    int64_t n0 = P->n_ev / nhc;
+    if (n0 < 2) n0 = 2;
+    e = hipMemcpyAsync(p->f_d, &p->fh, sizeof(IntegrandDev), hipMemcpyHostToDevice, sm);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->map, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice, sm);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->map32, m32.data(), m32.size() * sizeof(float), hipMemcpyHostToDevice, sm);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->st, &st0, sizeof st0, hipMemcpyHostToDevice, sm);
+    if (e == hipSuccess) {
+        launch_fill_i32(p->n_h, nhc, (int32_t)n0, sm);
+        launch_fill_f64(p->H, nbins, 0.0, sm);
+        launch_fill_f64(p->W, nbins, 0.0, sm);
+        launch_fill_f64(p->S1, nhc, 0.0, sm);
+        launch_fill_f64(p->S2, nhc, 0.0, sm);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(sm);
+    if (e != hipSuccess) {
+        free_problem(p);
+        return fail(VP_ERR_DEVICE, "initialising problem state: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return VP_OK;
+}
+
+vp_status vp_problem_destroy(vp_problem* p)
+{
+    if (!p) return VP_OK;
+    hipSetDevice(p->ctx->device);
+    hipStreamSynchronize(p->ctx->stream);
+    free_problem(p);
+    return VP_OK;
+}
+
+vp_status vp_problem_info(vp_problem* p, int32_t* n_st, int64_t* n_hc)
+{
+    if (!p) return fail(VP_ERR_INVALID_ARG, "problem is NULL");
+    if (n_st) *n_st = p->n_st;
+    if (n_hc) *n_hc = p->n_hc;
+    return VP_OK;
+}
+
+vp_status vp_iterate(vp_problem* p, int32_t n_iter)
+{
+    if (!p || n_iter < 0) return fail(VP_ERR_INVALID_ARG, "problem is NULL or n_iter < 0");
+    if (p->slot + n_iter > kMaxHistory) return fail(VP_ERR_STATE, "more than %d iterations", kMaxHistory);
+    VP_HIP(hipSetDevice(p->ctx->device));
+    hipStream_t s = p->ctx->stream;
+    const vp_params& P = p->P;
+    const int D = P.dim, NG = P.n_g;
+    const int64_t nbins = (int64_t)D * NG;
+    for (int32_t r = 0; r < n_iter; ++r) {
+        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+        if (p->prof) {
+            e0 = take_event(p);
+            e1 = take_event(p);
+            e2 = take_event(p);
+            e3 = take_event(p);
+            VP_HIP(hipEventRecord(e2, s));
+        }
+        // 1. sample offsets and N_tot
+        launch_scan(p->n_h, p->n_hc, p->offs, p->bsum, s);
+        if (!p->hist_lds) launch_fill_f64(p->hist_glob, 2 * nbins, 0.0, s);
+        // 2. fused sampling, map, integrand, sums and training data
+        SampleArgs a;
+        a.map = p->map;
+        a.map32 = p->map32;
+        a.offs = p->offs;
+        a.S1 = p->S1;
+        a.S2 = p->S2;
+        a.hist_part = p->hist_part;
+        a.hist_glob = p->hist_glob;
+        a.edges = p->edges;
+        a.nonfinite = &p->st->nonfinite;
+        a.f = p->f_d;
+        a.n_hc = p->n_hc;
+        a.n_g = NG;
+        a.n_st = p->n_st;
+        a.R = p->R;
+        a.R32 = (float)NG / (float)p->n_st;
+        a.key0 = (uint32_t)(P.seed & 0xffffffffu);
+        a.key1 = (uint32_t)(P.seed >> 32);
+        a.it = (uint32_t)p->it;
+        a.hist_mode = P.hist_mode;
+        a.hist_lds = p->hist_lds;
+        a.map_lds = p->map_lds;
+        a.chunk = p->chunk;
+        if (p->prof) VP_HIP(hipEventRecord(e0, s));
+        p->entry.launch(a, p->grid, p->block, p->lds, s);
+        if (p->prof) VP_HIP(hipEventRecord(e1, s));
+        VP_HIP(hipGetLastError());
+        launch_edge_fixup(p->edges, 2 * p->n_waves, p->S1, p->S2, s);
+        if (p->hist_lds) launch_hist_reduce(p->hist_part, p->grid, nbins, p->H, p->W, s);
+        else launch_hist_reduce(p->hist_glob, 1, nbins, p->H, p->W, s);
+        // 3. iteration estimate and combination
+        launch_estimate(p->n_h, p->S1, p->S2, p->n_hc, p->omega, p->omega2, P.beta, p->est_part, p->st,
+                        p->hist_I, p->hist_V, p->offs, p->slot, P.n_discard, s);
+        // 4. reallocation and 5. refinement, both for the next iteration
+        launch_realloc(p->n_h, p->S1, p->S2, p->n_hc, p->omega, p->omega2, P.beta, (double)P.n_ev,
+                       P.realloc_plus2, p->st, &p->st->ties, s);
+        launch_refine(p->map, p->map32, p->H, p->W, D, NG, P.alpha, s);
+        VP_HIP(hipGetLastError());
+        if (p->prof) {
+            VP_HIP(hipEventRecord(e3, s));
+            p->ev_pending.push_back(e0);
+            p->ev_pending.push_back(e1);
+            p->ev_pending.push_back(e2);
+            p->ev_pending.push_back(e3);
+        }
+        p->it += 1;
+        p->slot += 1;
+    }
+    return VP_OK;
+}
+
+vp_status vp_sync(vp_problem* p)
+{
+    if (!p) return fail(VP_ERR_INVALID_ARG, "problem is NULL");
+    VP_HIP(hipStreamSynchronize(p->ctx->stream));
+    return VP_OK;
+}
+
+vp_status vp_result_get(vp_problem* p, vp_result* out, double* I_j, double* V_j, int32_t cap)
+{
+    if (!p || !out) return fail(VP_ERR_INVALID_ARG, "problem and out are required");
+    VP_HIP(hipStreamSynchronize(p->ctx->stream));
+    DevState st;
+    VP_HIP(hipMemcpy(&st, p->st, sizeof st, hipMemcpyDeviceToHost));
+    out->mean = st.mean;
+    out->sdev = st.sdev;
+    out->chi2 = st.chi2;
+    out->dof = st.dof;
+    out->n_iter_done = st.n_iter_done;
+    out->n_evals = st.n_evals;
+    out->n_near_ties = (int64_t)st.ties;
+    out->n_nonfinite = (int64_t)st.nonfinite;
+    const int32_t n = std::min<int32_t>(cap, st.n_iter_done);
+    if (I_j && n > 0) VP_HIP(hipMemcpy(I_j, p->hist_I, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (V_j && n > 0) VP_HIP(hipMemcpy(V_j, p->hist_V, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (st.nonfinite) return fail(VP_ERR_NUMERIC, "%llu non-finite integrand values", st.nonfinite);
+    return VP_OK;
+}
+
+vp_status vp_map_get(vp_problem* p, double* map)
+{
+    if (!p || !map) return fail(VP_ERR_INVALID_ARG, "problem and map are required");
+    VP_HIP(hipStreamSynchronize(p->ctx->stream));
+    VP_HIP(hipMemcpy(map, p->map, sizeof(double) * p->P.dim * (p->P.n_g + 1), hipMemcpyDeviceToHost));
+    return VP_OK;
+}
+
+vp_status vp_map_set(vp_problem* p, const double* map)
+{
+    if (!p || !map) return fail(VP_ERR_INVALID_ARG, "problem and map are required");
+    const int D = p->P.dim, NG = p->P.n_g;
+    std::vector<float> m32((size_t)D * (NG + 1));
+    for (int d = 0; d < D; ++d)
+        for (int i = 0; i <= NG; ++i) {
+            const double v = map[(size_t)d * (NG + 1) + i];
+            if (!std::isfinite(v)) return fail(VP_ERR_INVALID_ARG, "map has a non-finite point");
+            if (i > 0 && v < map[(size_t)d * (NG + 1) + i - 1])
+                return fail(VP_ERR_INVALID_ARG, "map axis %d decreases at %d", d, i);
+            m32[(size_t)d * (NG + 1) + i] = (float)v;
+        }
+    VP_HIP(hipStreamSynchronize(p->ctx->stream));
+    VP_HIP(hipMemcpy(p->map, map, sizeof(double) * m32.size(), hipMemcpyHostToDevice));
+    VP_HIP(hipMemcpy(p->map32, m32.data(), sizeof(float) * m32.size(), hipMemcpyHostToDevice));
+    return VP_OK;
+}
+
+vp_status vp_alloc_get(vp_problem* p, int32_t* n_h)
+{
+    if (!p || !n_h) return fail(VP_ERR_INVALID_ARG, "problem and n_h are required");
+    VP_HIP(hipStreamSynchronize(p->ctx->stream));
+    VP_HIP(hipMemcpy(n_h, p->n_h, sizeof(int32_t) * p->n_hc, hipMemcpyDeviceToHost));
+    return VP_OK;
+}
+
+vp_status vp_alloc_set(vp_problem* p, const int32_t* n_h)
+{
+    if (!p || !n_h) return fail(VP_ERR_INVALID_ARG, "problem and n_h are required");
+    int64_t tot = 0;
+    for (int64_t h = 0; h < p->n_hc; ++h) {
+        if (n_h[h] < 2) return fail(VP_ERR_INVALID_ARG, "n_h[%lld] = %d < 2", (long long)h, n_h[h]);
+        tot += n_h[h];
+    }
+    if (tot > (int64_t)1 << 40) return fail(VP_ERR_INVALID_ARG, "allocation too large");
+    VP_HIP(hipStreamSynchronize(p->ctx->stream));
+    VP_HIP(hipMemcpy(p->n_h, n_h, sizeof(int32_t) * p->n_hc, hipMemcpyHostToDevice));
+    return VP_OK;
+}
+
+vp_status vp_iteration_get(vp_problem* p, int32_t* it)
+{
+    if (!p || !it) return fail(VP_ERR_INVALID_ARG, "problem and it are required");
+    *it = p->it;
+    return VP_OK;
+}
+
+vp_status vp_iteration_set(vp_problem* p, int32_t it)
+{
+    if (!p || it < 0) return fail(VP_ERR_INVALID_ARG, "problem is NULL or it < 0");
+    p->it = it;
+    return VP_OK;
+}
+
+vp_status vp_accum_get(vp_problem* p, double* S1, double* S2, double* H, double* W)
+{
+    if (!p) return fail(VP_ERR_INVALID_ARG, "problem is NULL");
+    VP_HIP(hipStreamSynchronize(p->ctx->stream));
+    const size_t nb = (size_t)p->P.dim * p->P.n_g;
+    if (S1) VP_HIP(hipMemcpy(S1, p->S1, sizeof(double) * p->n_hc, hipMemcpyDeviceToHost));
+    if (S2) VP_HIP(hipMemcpy(S2, p->S2, sizeof(double) * p->n_hc, hipMemcpyDeviceToHost));
+    if (H) VP_HIP(hipMemcpy(H, p->H, sizeof(double) * nb, hipMemcpyDeviceToHost));
+    if (W) VP_HIP(hipMemcpy(W, p->W, sizeof(double) * nb, hipMemcpyDeviceToHost));
+    return VP_OK;
+}
+
+struct StateHeader {
+    uint32_t magic, version;
+    int32_t dim, n_g;
+    int64_t n_hc;
+    int32_t it, slot;
+    int64_t n_evals;
+    uint64_t ties;
+};
+
+vp_status vp_state_export(vp_problem* p, void* buf, size_t* size)
+{
+    if (!p || !size) return fail(VP_ERR_INVALID_ARG, "problem and size are required");
+    const size_t nm = (size_t)p->P.dim * (p->P.n_g + 1);
+    const size_t need = sizeof(StateHeader) + nm * sizeof(double) + (size_t)p->n_hc * sizeof(int32_t) +
+                        2 * (size_t)p->slot * sizeof(double);
+    if (!buf) {
+        *size = need;
+        return VP_OK;
+    }
+    if (*size < need) return fail(VP_ERR_INVALID_ARG, "buffer of %zu bytes, need %zu", *size, need);
+    VP_HIP(hipStreamSynchronize(p->ctx->stream));
+    DevState st;
+    VP_HIP(hipMemcpy(&st, p->st, sizeof st, hipMemcpyDeviceToHost));
+    StateHeader hd = {kStateMagic, 1, p->P.dim, p->P.n_g, p->n_hc, p->it, p->slot, st.n_evals, st.ties};
+    char* b = (char*)buf;
+    memcpy(b, &hd, sizeof hd);
+    b += sizeof hd;
+    VP_HIP(hipMemcpy(b, p->map, nm * sizeof(double), hipMemcpyDeviceToHost));
+    b += nm * sizeof(double);
+    VP_HIP(hipMemcpy(b, p->n_h, (size_t)p->n_hc * sizeof(int32_t), hipMemcpyDeviceToHost));
+    b += (size_t)p->n_hc * sizeof(int32_t);
+    if (p->slot > 0) {
+        VP_HIP(hipMemcpy(b, p->hist_I, (size_t)p->slot * sizeof(double), hipMemcpyDeviceToHost));
+        b += (size_t)p->slot * sizeof(double);
+        VP_HIP(hipMemcpy(b, p->hist_V, (size_t)p->slot * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    *size = need;
+    return VP_OK;
+}
+
+vp_status vp_state_import(vp_problem* p, const void* buf, size_t size)
+{
+    if (!p || !buf) return fail(VP_ERR_INVALID_ARG, "problem and buf are required");
+    StateHeader hd;
+    if (size < sizeof hd) return fail(VP_ERR_INVALID_ARG, "state blob too small");
+    memcpy(&hd, buf, sizeof hd);
+    if (hd.magic != kStateMagic || hd.version != 1) return fail(VP_ERR_INVALID_ARG, "not a state blob");
+    if (hd.dim != p->P.dim || hd.n_g != p->P.n_g || hd.n_hc != p->n_hc)
+        return fail(VP_ERR_INVALID_ARG, "state shape (dim %d, n_g %d, n_hc %lld) does not match the problem",
+                    hd.dim, hd.n_g, (long long)hd.n_hc);
+    if (hd.slot < 0 || hd.slot > kMaxHistory || hd.it < 0) return fail(VP_ERR_INVALID_ARG, "bad iteration counters");
+    const size_t nm = (size_t)p->P.dim * (p->P.n_g + 1);
+    const size_t need = sizeof hd + nm * sizeof(double) + (size_t)p->n_hc * sizeof(int32_t) +
+                        2 * (size_t)hd.slot * sizeof(double);
+    if (size != need) return fail(VP_ERR_INVALID_ARG, "state blob of %zu bytes, expected %zu", size, need);
+    const char* b = (const char*)buf + sizeof hd;
+    vp_status s = vp_map_set(p, (const double*)b);
+    if (s != VP_OK) return s;
+    b += nm * sizeof(double);
+    s = vp_alloc_set(p, (const int32_t*)b);
+    if (s != VP_OK) return s;
+    b += (size_t)p->n_hc * sizeof(int32_t);
+    if (hd.slot > 0) {
+        VP_HIP(hipMemcpy(p->hist_I, b, (size_t)hd.slot * sizeof(double), hipMemcpyHostToDevice));
+        b += (size_t)hd.slot * sizeof(double);
+        VP_HIP(hipMemcpy(p->hist_V, b, (size_t)hd.slot * sizeof(double), hipMemcpyHostToDevice));
+    }
+    DevState st;
+    VP_HIP(hipMemcpy(&st, p->st, sizeof st, hipMemcpyDeviceToHost));
+    st.n_evals = hd.n_evals;
+    st.ties = hd.ties;
+    st.n_iter_done = hd.slot;
+    VP_HIP(hipMemcpy(p->st, &st, sizeof st, hipMemcpyHostToDevice));
+    p->it = hd.it;
+    p->slot = hd.slot;
+    return VP_OK;
+}
+
+vp_status vp_profile_enable(vp_problem* p, int32_t on)
+{
+    if (!p) return fail(VP_ERR_INVALID_ARG, "problem is NULL");
+    vp_status s = drain_events(p);
+    if (s != VP_OK) return s;
+    p->prof = on != 0;
+    p->t_sample_ms = p->t_iter_ms = 0.0;
+    p->n_sample = p->n_iter = 0;
+    return VP_OK;
+}
+
+vp_status vp_kernel_time(vp_problem* p, int32_t which, double* total_ms, int64_t* launches)
+{
+    if (!p || which < 0 || which > 1) return fail(VP_ERR_INVALID_ARG, "problem is NULL or which not in 0..1");
+    vp_status s = drain_events(p);
+    if (s != VP_OK) return s;
+    if (total_ms) *total_ms = which == 0 ? p->t_sample_ms : p->t_iter_ms;
+    if (launches) *launches = which == 0 ? p->n_sample : p->n_iter;
+    return VP_OK;
+}
+
+vp_status vp_integrate(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, vp_result* out)
+{
+    if (!out) return fail(VP_ERR_INVALID_ARG, "out is NULL");
+    vp_problem* p = nullptr;
+    vp_status s = vp_problem_create(ctx, P, f, &p);
+    if (s != VP_OK) return s;
+    s = vp_iterate(p, P->n_iter);
+    if (s == VP_OK) s = vp_result_get(p, out, nullptr, nullptr, 0);
+    vp_problem_destroy(p);
+    return s;
+}
+
+}  // extern "C"

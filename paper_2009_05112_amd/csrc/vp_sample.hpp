@@ -1,0 +1,702 @@
+// vp_sample.hpp -- the fused per-sample kernel of one vegas+ iteration.
+//
+// One launch draws every sample of the iteration, maps it through the vegas
+// map, evaluates J f, and accumulates (a) the per-hypercube sums of J f and
+// (J f)^2 (Sec. 3, step 2) and (b) the per-axis, per-increment training data
+// of the map (Sec. 2.3 and 2.4).  Nothing per sample touches HBM.
+//
+// Work decomposition.  The samples of an iteration are numbered in hypercube
+// order, s = offs[h] + j (offs is the exclusive scan of n_h).  The launch is
+// persistent: every wave owns one contiguous, equal share of the sample range
+// and walks it in tiles of 64 * chunk samples, each lane taking `chunk`
+// consecutive samples.  A lane finds the hypercube of its first sample with a
+// wave-cooperative search over 64 offsets at a time, then walks forward.
+// Runs of samples of one hypercube are summed in registers; runs that cross
+// lane boundaries are joined by a segmented scan across the wave (a fixed
+// shuffle tree, so the result does not depend on timing), and runs that cross
+// wave boundaries are handed to a fix-up kernel as edge records.  Every
+// hypercube's S1, S2 is therefore written exactly once, deterministically.
+//
+// Training data are privatised per workgroup in LDS (one workgroup per CU
+// holds all D * N_g bins) and written out once per workgroup; a second
+// kernel reduces the per-workgroup partials in a fixed order.
+#pragma once
+
+#include "vp_internal.hpp"
+
+namespace vp {
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies of counter words 0 and 2, with the high halves xored
+// into words 1 and 3 and the round key, the key advanced by two Weyl
+// constants between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t* out)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ int64_t shfl64(int64_t v, int src)
+{
+    int lo = __shfl((int)(uint32_t)(uint64_t)v, src);
+    int hi = __shfl((int)(uint32_t)((uint64_t)v >> 32), src);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+// Largest h with offs[h] <= s over the whole array (wave-uniform s):
+// a 64-ary search, one coalesced load per level.
+__device__ __forceinline__ int64_t find_hypercube(const int64_t* __restrict__ offs, int64_t n_hc,
+                                                  int64_t s, int lane)
+{
+    int64_t lo = 0, hi = n_hc;  // offs[lo] <= s < offs[hi]
+    while (hi - lo > 64) {
+        const int64_t step = (hi - lo) / 64;
+        const int64_t p = lo + (int64_t)(lane + 1) * step;
+        const bool le = (p < hi) && (offs[p] <= s);
+        const int c = __popcll(__ballot(le));
+        const int64_t nlo = lo + (int64_t)c * step;
+        const int64_t nhi = (c < 64) ? lo + (int64_t)(c + 1) * step : hi;
+        lo = nlo;
+        hi = nhi < hi ? nhi : hi;
+    }
+    const int64_t p = lo + 1 + lane;
+    const bool le = (p < hi) && (offs[p] <= s);
+    return lo + __popcll(__ballot(le));
+}
+
+// Per-lane hypercube of s (s >= offs[base] for every active lane): windows of
+// 64 consecutive offsets, binary-searched with lane shuffles.
+__device__ __forceinline__ int64_t locate(const int64_t* __restrict__ offs, int64_t n_hc,
+                                          int64_t base, int64_t s, bool active, int lane)
+{
+    int64_t res = base;
+    bool done = !active;
+    for (;;) {
+        const int64_t p = base + 1 + lane;
+        const int64_t bnd = (p <= n_hc) ? offs[p] : INT64_MAX;
+        int pos = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const int64_t b = shfl64(bnd, pos + step - 1);
+            if (b <= s) pos += step;
+        }
+        const int64_t last = shfl64(bnd, 63);
+        if (!done && last > s) {
+            res = base + pos;
+            done = true;
+        }
+        if (__all(done)) break;
+        base += 64;
+    }
+    return res;
+}
+
+// ---------------------------------------------------------------- run sums
+// Sums of J f and (J f)^2 over a run of samples of one hypercube.
+struct AccD {
+    double a, b;
+    __device__ void zero() { a = 0.0; b = 0.0; }
+    __device__ void add(double v)
+    {
+        a = a + v;
+        b = b + v * v;
+    }
+    // this := prev (+) this, prev's samples first
+    __device__ void join_after(const AccD& prev)
+    {
+        a = prev.a + a;
+        b = prev.b + b;
+    }
+    __device__ double sa() const { return a; }
+    __device__ double sb() const { return b; }
+    __device__ AccD shfl_up(int d) const
+    {
+        AccD r;
+        r.a = __shfl_up(a, d);
+        r.b = __shfl_up(b, d);
+        return r;
+    }
+    __device__ AccD bcast(int src) const
+    {
+        AccD r;
+        r.a = __shfl(a, src);
+        r.b = __shfl(b, src);
+        return r;
+    }
+};
+
+// Neumaier's compensated summation in single precision.
+__device__ __forceinline__ void neumaier_add(float& s, float& c, float v)
+{
+    const float t = s + v;
+    if (fabsf(s) >= fabsf(v)) c += (s - t) + v;
+    else c += (v - t) + s;
+    s = t;
+}
+
+struct AccN {
+    float as, ac, bs, bc;
+    __device__ void zero() { as = ac = bs = bc = 0.0f; }
+    __device__ void addf(float v)
+    {
+        neumaier_add(as, ac, v);
+        neumaier_add(bs, bc, v * v);
+    }
+    __device__ void join_after(const AccN& prev)
+    {
+        float s = prev.as, c = prev.ac;
+        neumaier_add(s, c, as);
+        ac = c + ac;
+        as = s;
+        s = prev.bs;
+        c = prev.bc;
+        neumaier_add(s, c, bs);
+        bc = c + bc;
+        bs = s;
+    }
+    __device__ double sa() const { return (double)as + (double)ac; }
+    __device__ double sb() const { return (double)bs + (double)bc; }
+    __device__ AccN shfl_up(int d) const
+    {
+        AccN r;
+        r.as = __shfl_up(as, d);
+        r.ac = __shfl_up(ac, d);
+        r.bs = __shfl_up(bs, d);
+        r.bc = __shfl_up(bc, d);
+        return r;
+    }
+    __device__ AccN bcast(int src) const
+    {
+        AccN r;
+        r.as = __shfl(as, src);
+        r.ac = __shfl(ac, src);
+        r.bs = __shfl(bs, src);
+        r.bc = __shfl(bc, src);
+        return r;
+    }
+};
+
+template <int PREC>
+struct AccOf {
+    typedef AccD type;
+};
+template <>
+struct AccOf<P_FP32_NEUMAIER> {
+    typedef AccN type;
+};
+
+// Exact rounding error of an LDS atomic add: the atomic returns the old value,
+// the stored sum is fl(old + x), and TwoSum recovers old + x - fl(old + x).
+__device__ __forceinline__ void lds_add_compensated(float* pair, float x)
+{
+    const float old = atomicAdd(pair, x);
+    const float s = old + x;
+    const float bp = s - old;
+    const float err = (old - (s - bp)) + (x - bp);
+    if (err != 0.0f) atomicAdd(pair + 1, err);
+}
+
+// ---------------------------------------------------------------- integrands
+// Per-axis accumulation followed by a finish step, in the same operation
+// order as the problem statement defines each integrand.
+template <int D, typename T>
+struct FState {
+    T q[kMaxTerms];
+    T lin;
+    T t[D];
+};
+
+template <int D>
+__device__ __forceinline__ void f_axis(const IntegrandDev* __restrict__ f, int kind, int K, int mu,
+                                       double x, FState<D, double>& st)
+{
+    if (kind == K_GAUSS_MIX || kind == K_EXP_ABS || kind == K_BALLS) {
+#pragma unroll
+        for (int k = 0; k < kMaxTerms; ++k) {
+            if (k < K) {
+                const double tt = x - f->centers[k * D + mu];
+                st.q[k] = fma(tt, tt, st.q[k]);
+            }
+        }
+    } else if (kind == K_CORR_GAUSS) {
+        st.t[mu] = x - f->centers[mu];
+    } else if (kind == K_AFFINE) {
+        st.lin = fma(f->centers[mu + 1], x, st.lin);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ double f_finish(const IntegrandDev* __restrict__ f, int kind, int K,
+                                           FState<D, double>& st)
+{
+    double acc = 0.0;
+    switch (kind) {
+    case K_GAUSS_MIX:
+#pragma unroll
+        for (int k = 0; k < kMaxTerms; ++k)
+            if (k < K) acc = fma(f->amps[k], exp(-(f->coefs[k] * st.q[k])), acc);
+        return f->scale * acc;
+    case K_EXP_ABS:
+#pragma unroll
+        for (int k = 0; k < kMaxTerms; ++k)
+            if (k < K) acc = fma(f->amps[k], exp(-(f->coefs[k] * sqrt(st.q[k]))), acc);
+        return f->scale * acc;
+    case K_BALLS:
+#pragma unroll
+        for (int k = 0; k < kMaxTerms; ++k)
+            if (k < K && st.q[k] < f->rad2[k]) acc = acc + f->amps[k];
+        return f->scale * acc;
+    case K_CORR_GAUSS: {
+        double q = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            double z = 0.0;
+#pragma unroll
+            for (int e = d; e < D; ++e) z = fma(f->chol[d * D + e], st.t[e], z);
+            q = fma(z, z, q);
+        }
+        return f->scale * exp(-0.5 * q);
+    }
+    case K_CONST:
+        return f->scale;
+    case K_AFFINE:
+        return f->scale * st.lin;
+    default:
+        return __builtin_nan("");
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void f_axis32(const IntegrandDev* __restrict__ f, int kind, int K, int mu,
+                                         float x, FState<D, float>& st)
+{
+    if (kind == K_GAUSS_MIX || kind == K_EXP_ABS || kind == K_BALLS) {
+#pragma unroll
+        for (int k = 0; k < kMaxTerms; ++k) {
+            if (k < K) {
+                const float tt = x - f->centers32[k * D + mu];
+                st.q[k] = fmaf(tt, tt, st.q[k]);
+            }
+        }
+    } else if (kind == K_CORR_GAUSS) {
+        st.t[mu] = x - f->centers32[mu];
+    } else if (kind == K_AFFINE) {
+        st.lin = fmaf(f->centers32[mu + 1], x, st.lin);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ float f_finish32(const IntegrandDev* __restrict__ f, int kind, int K,
+                                            FState<D, float>& st)
+{
+    float acc = 0.0f;
+    switch (kind) {
+    case K_GAUSS_MIX:
+#pragma unroll
+        for (int k = 0; k < kMaxTerms; ++k)
+            if (k < K) acc = fmaf(f->amps32[k], expf(-(f->coefs32[k] * st.q[k])), acc);
+        return f->scale32 * acc;
+    case K_EXP_ABS:
+#pragma unroll
+        for (int k = 0; k < kMaxTerms; ++k)
+            if (k < K) acc = fmaf(f->amps32[k], expf(-(f->coefs32[k] * sqrtf(st.q[k]))), acc);
+        return f->scale32 * acc;
+    case K_BALLS:
+#pragma unroll
+        for (int k = 0; k < kMaxTerms; ++k)
+            if (k < K && st.q[k] < f->rad2_32[k]) acc = acc + f->amps32[k];
+        return f->scale32 * acc;
+    case K_CORR_GAUSS: {
+        float q = 0.0f;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            float z = 0.0f;
+#pragma unroll
+            for (int e = d; e < D; ++e) z = fmaf(f->chol32[d * D + e], st.t[e], z);
+            q = fmaf(z, z, q);
+        }
+        return f->scale32 * expf(-0.5f * q);
+    }
+    case K_CONST:
+        return f->scale32;
+    case K_AFFINE:
+        return f->scale32 * st.lin;
+    default:
+        return __builtin_nanf("");
+    }
+}
+
+// ---------------------------------------------------------------- one sample
+// Stratified y in hypercube k (Sec. 3): y^mu = (k_mu + u) / N_st, so
+// t = y N_g = (k_mu + u) R; vegas map (Sec. 2.2, Eqs. y and jac):
+// i = floor(t) (clamped to N_g - 1), delta = t - i (clamped to 1),
+// x = x_i + Delta x_i delta, J = prod_mu N_g Delta x_i.
+// FP64: u from 53 bits -- the high word of axis mu is word mu of the
+// stream, its low word is word D + mu.
+template <int D, bool MAPLDS>
+__device__ __forceinline__ double sample_fp64(const SampleArgs& a, const double* __restrict__ map,
+                                              uint32_t j, uint32_t h, const int32_t* k,
+                                              int32_t* idx, int kind, int K)
+{
+    constexpr int NB = (2 * D + 3) / 4;
+    uint32_t w[4 * NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) philox4x32_10(j, h, a.it, (uint32_t)b, a.key0, a.key1, &w[4 * b]);
+    const int n_g = a.n_g;
+    FState<D, double> st;
+#pragma unroll
+    for (int kk = 0; kk < kMaxTerms; ++kk) st.q[kk] = 0.0;
+    st.lin = (kind == K_AFFINE) ? a.f->centers[0] : 0.0;
+    double jac = 1.0;
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        const double hi = (double)(w[mu] >> 5);
+        const double lo = (double)(w[D + mu] >> 6);
+        const double u = fma(hi, 0x1p-27, lo * 0x1p-53);  // exact: a 53-bit integer times 2^-53
+        const double t = ((double)k[mu] + u) * a.R;
+        int i = (int)t;
+        i = i < n_g - 1 ? i : n_g - 1;
+        double delta = t - (double)i;
+        delta = delta < 1.0 ? delta : 1.0;
+        const double* xm = map + mu * (n_g + 1);
+        const double x0 = xm[i];
+        const double dx = xm[i + 1] - x0;
+        const double x = fma(dx, delta, x0);
+        jac = jac * ((double)n_g * dx);
+        idx[mu] = i;
+        f_axis<D>(a.f, kind, K, mu, x, st);
+    }
+    return jac * f_finish<D>(a.f, kind, K, st);
+}
+
+// FP32 split: u = (w >> 8) 2^-24 from the high word of each axis alone.
+template <int D, bool MAPLDS>
+__device__ __forceinline__ float sample_fp32(const SampleArgs& a, const float* __restrict__ map,
+                                             uint32_t j, uint32_t h, const int32_t* k, int32_t* idx,
+                                             int kind, int K)
+{
+    constexpr int NB = (D + 3) / 4;
+    uint32_t w[4 * NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) philox4x32_10(j, h, a.it, (uint32_t)b, a.key0, a.key1, &w[4 * b]);
+    const int n_g = a.n_g;
+    FState<D, float> st;
+#pragma unroll
+    for (int kk = 0; kk < kMaxTerms; ++kk) st.q[kk] = 0.0f;
+    st.lin = (kind == K_AFFINE) ? a.f->centers32[0] : 0.0f;
+    float jac = 1.0f;
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        const float u = (float)(w[mu] >> 8) * 0x1p-24f;
+        const float t = ((float)k[mu] + u) * a.R32;
+        int i = (int)t;
+        i = i < n_g - 1 ? i : n_g - 1;
+        float delta = t - (float)i;
+        delta = delta < 1.0f ? delta : 1.0f;
+        const float* xm = map + mu * (n_g + 1);
+        const float x0 = xm[i];
+        const float dx = xm[i + 1] - x0;
+        const float x = fmaf(dx, delta, x0);
+        jac = jac * ((float)n_g * dx);
+        idx[mu] = i;
+        f_axis32<D>(a.f, kind, K, mu, x, st);
+    }
+    return jac * f_finish32<D>(a.f, kind, K, st);
+}
+
+// ---------------------------------------------------------------- the kernel
+template <int D, int PREC, bool MAPLDS>
+__global__ __launch_bounds__(sample_block(PREC)) void k_sample(SampleArgs a)
+{
+    typedef typename AccOf<PREC>::type Acc;
+    typedef typename std::conditional<PREC == P_FP64, double, float>::type MapT;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+
+    const int n_g = a.n_g;
+    const int nbins = D * n_g;
+    const size_t hist_bytes = a.hist_lds ? (size_t)nbins * 16 : 0;
+    double* lds_hist = reinterpret_cast<double*>(lds_raw);
+    float* lds_histf = reinterpret_cast<float*>(lds_raw);
+    MapT* lds_map = reinterpret_cast<MapT*>(lds_raw + hist_bytes);
+    const MapT* gmap;
+    if constexpr (PREC == P_FP64) gmap = a.map;
+    else gmap = a.map32;
+
+    if (a.hist_lds)
+        for (int i = threadIdx.x; i < 2 * nbins; i += blockDim.x) lds_hist[i] = 0.0;
+    if constexpr (MAPLDS)
+        for (int i = threadIdx.x; i < D * (n_g + 1); i += blockDim.x) lds_map[i] = gmap[i];
+    __syncthreads();
+    const MapT* map;
+    if constexpr (MAPLDS) map = lds_map;
+    else map = gmap;
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int waves_per_block = blockDim.x / kWave;
+    const int64_t wave = (int64_t)blockIdx.x * waves_per_block + (threadIdx.x / kWave);
+    const int64_t n_waves = (int64_t)gridDim.x * waves_per_block;
+    const int64_t* __restrict__ offs = a.offs;
+    const int64_t n_hc = a.n_hc;
+    const int64_t n_tot = offs[n_hc];
+    const int64_t s_a = n_tot * wave / n_waves;
+    const int64_t s_b = n_tot * (wave + 1) / n_waves;
+    const int C = a.chunk;
+    const int kind = a.f->kind;
+    const int K = a.f->n_terms;
+    const uint32_t n_st = (uint32_t)a.n_st;
+    const bool literal = (a.hist_mode != 0);
+    unsigned long long bad = 0;
+
+    if (s_a < s_b) {
+        const int64_t h_a = find_hypercube(offs, n_hc, s_a, lane);
+        int64_t h_cur = h_a;
+        Acc carry;
+        carry.zero();
+        bool carry_ext = true;   // the run reaching the next lane is the wave's first hypercube
+        bool carry_live = true;  // an unfinished run reaches the next lane
+        int64_t h_open = h_a;
+
+        for (int64_t s0 = s_a; s0 < s_b; s0 += (int64_t)kWave * C) {
+            const int64_t s_l = s0 + (int64_t)lane * C;
+            const bool active = s_l < s_b;
+            const int64_t e_l = active ? (s_l + C < s_b ? s_l + C : s_b) : s_l;
+            int64_t h = locate(offs, n_hc, h_cur, s_l, active, lane);
+
+            Acc run, headacc;
+            run.zero();
+            headacc.zero();
+            bool in_head = true, head_closed = false, open_end = false;
+            const int64_t head_h = h;
+            int64_t h_end = h;
+            if (active) {
+                int64_t o_cur = offs[h], o_next = offs[h + 1];
+                int32_t k[D];
+                {
+                    uint32_t r = (uint32_t)h;
+#pragma unroll
+                    for (int m = D - 1; m >= 0; --m) {
+                        k[m] = (int32_t)(r % n_st);
+                        r /= n_st;
+                    }
+                }
+                double inv_n = 1.0 / (double)(o_next - o_cur);
+                float inv_n32 = 1.0f / (float)(o_next - o_cur);
+                for (int64_t s = s_l; s < e_l; ++s) {
+                    if (s == o_next) {
+                        if (in_head) {
+                            headacc = run;
+                            head_closed = true;
+                            in_head = false;
+                        } else {
+                            a.S1[h] = run.sa();
+                            a.S2[h] = run.sb();
+                        }
+                        run.zero();
+                        ++h;
+                        o_cur = o_next;
+                        o_next = offs[h + 1];
+                        inv_n = 1.0 / (double)(o_next - o_cur);
+                        inv_n32 = 1.0f / (float)(o_next - o_cur);
+#pragma unroll
+                        for (int m = D - 1; m >= 0; --m) {
+                            if (++k[m] < (int32_t)n_st) break;
+                            k[m] = 0;
+                        }
+                    }
+                    const uint32_t j = (uint32_t)(s - o_cur);
+                    int32_t idx[D];
+                    if constexpr (PREC == P_FP64) {
+                        const double v = sample_fp64<D, MAPLDS>(a, map, j, (uint32_t)h, k, idx, kind, K);
+                        run.add(v);
+                        if (!isfinite(v)) ++bad;
+                        const double v2 = v * v;
+                        const double hh = literal ? v2 : v2 * inv_n;
+                        const double hw = literal ? 1.0 : inv_n;
+#pragma unroll
+                        for (int mu = 0; mu < D; ++mu) {
+                            const int bin = mu * n_g + idx[mu];
+                            if (a.hist_lds) {
+                                atomicAdd(&lds_hist[2 * bin], hh);
+                                atomicAdd(&lds_hist[2 * bin + 1], hw);
+                            } else {
+                                atomicAdd(&a.hist_glob[2 * bin], hh);
+                                atomicAdd(&a.hist_glob[2 * bin + 1], hw);
+                            }
+                        }
+                    } else if constexpr (PREC == P_FP32_ACC64) {
+                        const float v32 = sample_fp32<D, MAPLDS>(a, map, j, (uint32_t)h, k, idx, kind, K);
+                        const double v = (double)v32;
+                        run.add(v);
+                        if (!isfinite(v32)) ++bad;
+                        const double v2 = v * v;
+                        const double hh = literal ? v2 : v2 * inv_n;
+                        const double hw = literal ? 1.0 : inv_n;
+#pragma unroll
+                        for (int mu = 0; mu < D; ++mu) {
+                            const int bin = mu * n_g + idx[mu];
+                            if (a.hist_lds) {
+                                atomicAdd(&lds_hist[2 * bin], hh);
+                                atomicAdd(&lds_hist[2 * bin + 1], hw);
+                            } else {
+                                atomicAdd(&a.hist_glob[2 * bin], hh);
+                                atomicAdd(&a.hist_glob[2 * bin + 1], hw);
+                            }
+                        }
+                    } else {
+                        const float v32 = sample_fp32<D, MAPLDS>(a, map, j, (uint32_t)h, k, idx, kind, K);
+                        run.addf(v32);
+                        if (!isfinite(v32)) ++bad;
+                        const float v2 = v32 * v32;
+                        const float hh = literal ? v2 : v2 * inv_n32;
+                        const float hw = literal ? 1.0f : inv_n32;
+#pragma unroll
+                        for (int mu = 0; mu < D; ++mu) {
+                            const int bin = mu * n_g + idx[mu];
+                            lds_add_compensated(&lds_histf[4 * bin], hh);
+                            lds_add_compensated(&lds_histf[4 * bin + 2], hw);
+                        }
+                    }
+                }
+                if (e_l == o_next) {
+                    // the run ends exactly at the end of this lane's samples
+                    if (in_head) {
+                        headacc = run;
+                        head_closed = true;
+                        in_head = false;
+                    } else {
+                        a.S1[h] = run.sa();
+                        a.S2[h] = run.sb();
+                    }
+                    run.zero();
+                    h_end = h + 1;
+                } else {
+                    open_end = true;
+                    h_end = h;
+                }
+            }
+
+            // Segmented scan of the runs that cross lane boundaries.  Lane l maps
+            // the carry reaching it to the carry leaving it: a lane whose first
+            // run never closes (pass-through) adds its sums to the carry; any
+            // other lane starts a new carry from its open last run (or zero).
+            // Inactive lanes are the identity.
+            bool A = !active || !head_closed;
+            Acc B = run;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const bool Ap = __shfl_up((int)A, d) != 0;
+                const Acc Bp = B.shfl_up(d);
+                if (lane >= d) {
+                    if (A) B.join_after(Bp);
+                    A = A && Ap;
+                }
+            }
+            // exclusive prefix for this lane
+            bool Ax = __shfl_up((int)A, 1) != 0;
+            Acc Bx = B.shfl_up(1);
+            if (lane == 0) {
+                Ax = true;
+                Bx.zero();
+            }
+            if (active && head_closed) {
+                Acc cin = Bx;
+                if (Ax) cin.join_after(carry);
+                const bool ext = Ax && carry_ext;
+                Acc tot = headacc;
+                tot.join_after(cin);
+                if (ext) {
+                    EdgeRec r;
+                    r.h = head_h;
+                    r.s1 = tot.sa();
+                    r.s2 = tot.sb();
+                    a.edges[2 * wave] = r;
+                } else {
+                    a.S1[head_h] = tot.sa();
+                    a.S2[head_h] = tot.sb();
+                }
+            }
+            // carry into the next tile: lane 63's inclusive map applied to the carry
+            const bool A63 = __shfl((int)A, kWave - 1) != 0;
+            Acc B63 = B.bcast(kWave - 1);
+            if (A63) B63.join_after(carry);
+            carry = B63;
+            carry_ext = A63 && carry_ext;
+            // the last active lane decides whether a run is still open, and where
+            const int64_t rem = (s_b - 1 - s0) / C;
+            const int last_active = rem < kWave - 1 ? (int)rem : kWave - 1;
+            const bool live_own = active && (!head_closed || open_end);
+            carry_live = __shfl((int)live_own, last_active) != 0;
+            h_open = shfl64(h_end, last_active);
+            h_cur = shfl64(h_end, kWave - 1);
+        }
+        if (lane == 0) {
+            EdgeRec empty;
+            empty.h = -1;
+            empty.s1 = 0.0;
+            empty.s2 = 0.0;
+            if (carry_live) {
+                EdgeRec r;
+                r.s1 = carry.sa();
+                r.s2 = carry.sb();
+                if (carry_ext) {
+                    r.h = h_a;
+                    a.edges[2 * wave] = r;
+                    a.edges[2 * wave + 1] = empty;
+                } else {
+                    r.h = h_open;
+                    a.edges[2 * wave + 1] = r;
+                }
+            } else {
+                a.edges[2 * wave + 1] = empty;
+            }
+        }
+    } else if (lane == 0) {
+        EdgeRec empty;
+        empty.h = -1;
+        empty.s1 = 0.0;
+        empty.s2 = 0.0;
+        a.edges[2 * wave] = empty;
+        a.edges[2 * wave + 1] = empty;
+    }
+
+    // non-finite samples: one atomic per wave
+    for (int d = kWave / 2; d >= 1; d >>= 1) bad += __shfl_down(bad, d);
+    if (lane == 0 && bad) atomicAdd(a.nonfinite, bad);
+
+    __syncthreads();
+    if (a.hist_lds) {
+        double* out = a.hist_part + (size_t)blockIdx.x * 2 * nbins;
+        if constexpr (PREC == P_FP32_NEUMAIER) {
+            for (int i = threadIdx.x; i < 2 * nbins; i += blockDim.x)
+                out[i] = (double)lds_histf[2 * i] + (double)lds_histf[2 * i + 1];
+        } else {
+            for (int i = threadIdx.x; i < 2 * nbins; i += blockDim.x) out[i] = lds_hist[i];
+        }
+    }
+}
+
+template <int D, int PREC, bool MAPLDS>
+void launch_sample(const SampleArgs& a, int grid, int block, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_sample<D, PREC, MAPLDS>), dim3(grid), dim3(block), lds, s, a);
+}
+
+}  // namespace vp
