@@ -60,7 +60,20 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=list(SLOTS_PER_SAMPLE))
     ap.add_argument("--n-ev", type=int, default=100_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a buffer of this many MiB on the GPU (a plain copy kernel of known "
+                         "size, the reference for the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the method's per-iteration "
               "state is sharded across GPUs only in the design notes, not built", file=sys.stderr)

@@ -701,11 +701,12 @@ int or_refine_axis(const or_params* p, const double* H, const double* W, double*
     if (p->alpha == 0.0 || NG < 2) return 0;
     double* d = work;
     double* c = work + NG;
-    double s = 0.0;
+    or_ksum ks = {0.0, 0.0};
     for (int32_t i = 0; i < NG; ++i) {
         d[i] = (W[i] > 0.0) ? H[i] / W[i] : 0.0;
-        s = s + d[i];
+        or_kadd(&ks, d[i]);
     }
+    const double s = or_kval(&ks);
     if (!(s > 0.0)) return 0;
     /* smoothing, then normalisation */
     c[0] = (7.0 * d[0] + d[1]) / 8.0;
@@ -713,12 +714,13 @@ int or_refine_axis(const or_params* p, const double* H, const double* W, double*
     c[NG - 1] = (d[NG - 2] + 7.0 * d[NG - 1]) / 8.0;
     for (int32_t i = 0; i < NG; ++i) c[i] = c[i] / s;
     /* compression */
-    double csum = 0.0;
+    or_ksum kc = {0.0, 0.0};
     for (int32_t i = 0; i < NG; ++i) {
         double di = c[i];
         c[i] = (di == 0.0) ? 0.0 : pow((1.0 - di) / (-log(di)), p->alpha);
-        csum = csum + c[i];
+        or_kadd(&kc, c[i]);
     }
+    const double csum = or_kval(&kc);
     /* regrid; with nothing to share out (the compressed sum underflowed or is
      * not finite) step 1's delta d is not positive and the axis is kept */
     const double delta_d = csum / (double)NG;
@@ -748,11 +750,12 @@ int or_refine_stages(const or_params* p, const double* H, const double* W, doubl
 {
     const int32_t NG = p->n_g;
     if (NG < 2) return 0;
-    double s = 0.0;
+    or_ksum ks = {0.0, 0.0};
     for (int32_t i = 0; i < NG; ++i) {
         d_raw[i] = (W[i] > 0.0) ? H[i] / W[i] : 0.0;
-        s = s + d_raw[i];
+        or_kadd(&ks, d_raw[i]);
     }
+    const double s = or_kval(&ks);
     if (!(s > 0.0)) return 0;
     const double* d = d_raw;
     double* c = d_smooth;

@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvegasp.so")
-SOURCES = ["vp_runtime.hip", "vp_aux.hip", "vp_sample_fp64.hip", "vp_sample_fp32acc.hip",
-           "vp_sample_fp32neu.hip"]
+SOURCES = ["vp_runtime.hip", "vp_aux.hip", "vp_sample_fp64_gauss.hip", "vp_sample_fp64_corr.hip",
+           "vp_sample_fp64_generic.hip", "vp_sample_fp32acc.hip", "vp_sample_fp32neu.hip"]
 ARCH = os.environ.get("VEGASP_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -30,7 +30,8 @@ def _hipcc():
 
 def _compile(src):
     out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", out]
+    extra = ["-Rpass-analysis=kernel-resource-usage"] if os.environ.get("VEGASP_RESOURCE_USAGE") else []
+    cmd = [_hipcc()] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:

@@ -66,9 +66,11 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_local(const int32_t* __rest
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-// Exclusive scan of the block totals by one block; writes N_tot.
+// Exclusive scan of the block totals by one block.  Afterwards the sample
+// offset of hypercube h is loc[h] + bsum[h / kScanTile] (see gofs), and the
+// entry for h = n_hc holds N_tot, the samples drawn this iteration.
 __global__ __launch_bounds__(kScanBlock) void k_scan_top(int64_t* __restrict__ bsum, int64_t nb,
-                                                         int64_t* __restrict__ offs, int64_t n_hc)
+                                                         int64_t* __restrict__ loc, int64_t n_hc)
 {
     const int64_t per = (nb + kScanBlock - 1) / kScanBlock;
     const int64_t b0 = (int64_t)threadIdx.x * per;
@@ -84,13 +86,11 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_top(int64_t* __restrict__ b
             run += x;
         }
     }
-    if (threadIdx.x == 0) offs[n_hc] = total;
-}
-
-__global__ void k_scan_add(int64_t* __restrict__ offs, int64_t n_hc, const int64_t* __restrict__ bsum)
-{
-    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (h < n_hc) offs[h] += bsum[h / kScanTile];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bsum[nb] = total;
+        loc[n_hc] = total - bsum[n_hc / kScanTile];
+    }
 }
 
 // ---------------------------------------------------------------- edge fix-up
@@ -127,8 +127,17 @@ __global__ void k_hist_reduce(const double* __restrict__ part, int n_part, int64
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * nbins;
          i += (int64_t)gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int p = 0; p < n_part; ++p) s = s + part[(int64_t)p * 2 * nbins + i];
+        // four interleaved chains keep four loads in flight; fixed order
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int p = 0;
+        for (; p + 3 < n_part; p += 4) {
+            a0 = a0 + part[(int64_t)(p + 0) * 2 * nbins + i];
+            a1 = a1 + part[(int64_t)(p + 1) * 2 * nbins + i];
+            a2 = a2 + part[(int64_t)(p + 2) * 2 * nbins + i];
+            a3 = a3 + part[(int64_t)(p + 3) * 2 * nbins + i];
+        }
+        for (; p < n_part; ++p) a0 = a0 + part[(int64_t)p * 2 * nbins + i];
+        const double s = (a0 + a1) + (a2 + a3);
         if (i & 1) W[i >> 1] = s;
         else H[i >> 1] = s;
     }
@@ -177,7 +186,8 @@ __global__ __launch_bounds__(kRedBlock) void k_est_partial(const int32_t* __rest
                                                            const double* __restrict__ S1,
                                                            const double* __restrict__ S2,
                                                            int64_t n_hc, double omega, double omega2,
-                                                           double beta, double* __restrict__ part)
+                                                           double beta, double* __restrict__ part,
+                                                           double* __restrict__ dh)
 {
     double I = 0.0, V = 0.0, Sd = 0.0;
     for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < n_hc;
@@ -185,6 +195,7 @@ __global__ __launch_bounds__(kRedBlock) void k_est_partial(const int32_t* __rest
         double m, var, d;
         const int32_t n = n_h[h];
         hypercube_terms(S1[h], S2[h], n, omega, omega2, beta, &m, &var, &d);
+        dh[h] = d;
         I = I + m;
         V = V + var / ((double)n - 1.0);
         Sd = Sd + d;
@@ -213,25 +224,46 @@ __global__ __launch_bounds__(kRedBlock) void k_est_partial(const int32_t* __rest
     }
 }
 
-// One thread: totals over the partials in block order, the iteration's
+// Totals over the partials (one block, fixed tree order), the iteration's
 // record, and the combination over iterations n_discard..it (Sec. 2.5).
-__global__ void k_est_final(const double* __restrict__ part, int n_part, DevState* st,
-                            double* __restrict__ hist_I, double* __restrict__ hist_V,
-                            const int64_t* __restrict__ offs, int64_t n_hc, int32_t it_slot,
-                            int32_t n_discard)
+__global__ __launch_bounds__(kRedBlock) void k_est_final(const double* __restrict__ part, int n_part,
+                                                         DevState* st, double* __restrict__ hist_I,
+                                                         double* __restrict__ hist_V,
+                                                         const int64_t* __restrict__ loc,
+                                                         const int64_t* __restrict__ bbase, int64_t n_hc,
+                                                         int32_t it_slot, int32_t n_discard)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a = 0.0, b = 0.0, c = 0.0;
+    const int per = (n_part + kRedBlock - 1) / kRedBlock;
+    const int p0 = threadIdx.x * per;
+    for (int p = p0; p < p0 + per && p < n_part; ++p) {
+        a = a + part[3 * p + 0];
+        b = b + part[3 * p + 1];
+        c = c + part[3 * p + 2];
+    }
+    __shared__ double red[3][kRedBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    if (lane == 0) {
+        red[0][w] = a;
+        red[1][w] = b;
+        red[2][w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     double I = 0.0, V = 0.0, Sd = 0.0;
-    for (int p = 0; p < n_part; ++p) {
-        I = I + part[3 * p + 0];
-        V = V + part[3 * p + 1];
-        Sd = Sd + part[3 * p + 2];
+    for (int i = 0; i < kRedBlock / kWave; ++i) {
+        I = I + red[0][i];
+        V = V + red[1][i];
+        Sd = Sd + red[2][i];
     }
     st->sumd = Sd;
     hist_I[it_slot] = I;
     hist_V[it_slot] = V;
     st->n_iter_done = it_slot + 1;
-    st->n_evals += offs[n_hc];
+    st->n_evals += loc[n_hc] + bbase[n_hc / kScanTile];
     const int first = n_discard < 0 ? 0 : n_discard;
     const int n = it_slot + 1;
     const int cnt = n - first;
@@ -277,9 +309,7 @@ __global__ void k_est_final(const double* __restrict__ part, int n_part, DevStat
 // Sec. 3 steps 3-4: n_h = max(2, floor(N_ev d_h / sum d)), or floor(.) + 2.
 // Near-ties (within 1e-9 relative of an integer that decides n_h) are counted.
 __global__ __launch_bounds__(kRedBlock) void k_realloc(int32_t* __restrict__ n_h,
-                                                       const double* __restrict__ S1,
-                                                       const double* __restrict__ S2, int64_t n_hc,
-                                                       double omega, double omega2, double beta,
+                                                       const double* __restrict__ dh, int64_t n_hc,
                                                        double n_ev, int32_t plus2,
                                                        const DevState* __restrict__ st,
                                                        unsigned long long* __restrict__ ties)
@@ -290,9 +320,7 @@ __global__ __launch_bounds__(kRedBlock) void k_realloc(int32_t* __restrict__ n_h
     const double first_visible = plus2 ? 1.0 : 3.0;
     for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < n_hc;
          h += (int64_t)gridDim.x * blockDim.x) {
-        double m, var, d;
-        hypercube_terms(S1[h], S2[h], n_h[h], omega, omega2, beta, &m, &var, &d);
-        const double q = (n_ev * d) / sumd;
+        const double q = (n_ev * dh[h]) / sumd;
         const double fl = floor(q);
         const double r = rint(q);
         const double tol = 1e-9 * (q > 1.0 ? q : 1.0);
@@ -308,11 +336,61 @@ __global__ __launch_bounds__(kRedBlock) void k_realloc(int32_t* __restrict__ n_h
 }
 
 // ---------------------------------------------------------------- refinement
+// Double-double arithmetic (Dekker / Knuth error-free sums) for sums and
+// prefix sums of non-negative terms: the refinement's sums are taken to
+// within about one rounding of the exact value.
+struct DD {
+    double hi, lo;
+};
+
+__device__ __forceinline__ DD dd_from(double a) { return DD{a, 0.0}; }
+
+__device__ __forceinline__ DD dd_add(DD a, DD b)
+{
+    const double s = a.hi + b.hi;
+    const double bp = s - a.hi;
+    const double e = (a.hi - (s - bp)) + (b.hi - bp);
+    const double lo = e + (a.lo + b.lo);
+    const double r = s + lo;
+    return DD{r, lo - (r - s)};
+}
+
+__device__ __forceinline__ bool dd_ge(DD a, DD b) { return a.hi > b.hi || (a.hi == b.hi && a.lo >= b.lo); }
+
+// a - b rounded to double
+__device__ __forceinline__ double dd_sub_to_d(DD a, DD b)
+{
+    const double s = a.hi - b.hi;
+    const double bp = s - a.hi;
+    const double e = (a.hi - (s - bp)) + (-b.hi - bp);
+    return s + (e + (a.lo - b.lo));
+}
+
+// Block-wide sum of per-thread double-doubles (fixed tree order); every
+// thread receives the total.
+__device__ DD block_dd_sum(DD v, DD* scratch)
+{
+    scratch[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = kRefineBlock / 2; d >= 1; d >>= 1) {
+        if ((int)threadIdx.x < d) scratch[threadIdx.x] = dd_add(scratch[threadIdx.x], scratch[threadIdx.x + d]);
+        __syncthreads();
+    }
+    const DD t = scratch[0];
+    __syncthreads();
+    return t;
+}
+
 // One workgroup per axis (Sec. 2.3): d_i = H_i / W_i (0 without samples);
-// smoothing (7,1)/8, (1,6,1)/8, (1,7)/8 and division by the raw sum;
-// compression ((1 - d) / ln(1/d))^alpha (0 at d = 0); regrid so that every
-// new increment holds an equal share of the compressed d.  The two running
-// sums and the regrid walk are sequential, in increment order.
+// smoothing (7,1)/8, (1,6,1)/8, (1,7)/8 and division by sum d_i; compression
+// ((1 - d) / ln(1/d))^alpha (0 at d = 0); then the regrid that gives every new
+// increment an equal share delta_d = sum c / N_g of the compressed data.  The
+// regrid walk (add old increments until the running sum reaches delta_d, take
+// delta_d off, interpolate inside the last increment) puts new point i in the
+// first old increment j where the prefix sum C_j = c_0 + ... + c_{j-1}
+// reaches i delta_d, at the fraction (C_j - i delta_d) / c_{j-1} from its top;
+// here every new point finds its increment by binary search over the prefix
+// sums, kept in double-double so they carry no accumulated rounding.
 __global__ __launch_bounds__(kRefineBlock) void k_refine(double* __restrict__ map,
                                                          float* __restrict__ map32,
                                                          const double* __restrict__ H,
@@ -320,73 +398,108 @@ __global__ __launch_bounds__(kRefineBlock) void k_refine(double* __restrict__ ma
                                                          double alpha)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    double* x = reinterpret_cast<double*>(lds_raw);  // [n_g + 1]
-    double* c = x + (n_g + 1);                        // [n_g]
-    double* y = c + n_g;                              // [n_g + 1]
-    __shared__ double s_sum;
+    double* x = reinterpret_cast<double*>(lds_raw);  // [n_g + 1] old grid
+    double* c = x + (n_g + 1);                        // [n_g]     d, then compressed d
+    double* A = c + n_g;                              // [n_g + 1] smoothed d, then prefix hi
+    double* Bv = A + (n_g + 1);                       // [n_g + 1] prefix lo
+    __shared__ DD scratch[kRefineBlock];
     const int mu = blockIdx.x;
+    const int tid = threadIdx.x;
     double* xm = map + (int64_t)mu * (n_g + 1);
     float* xm32 = map32 + (int64_t)mu * (n_g + 1);
     const double* Hm = H + (int64_t)mu * n_g;
     const double* Wm = W + (int64_t)mu * n_g;
     if (alpha == 0.0 || n_g < 2) return;
 
-    for (int i = threadIdx.x; i <= n_g; i += blockDim.x) x[i] = xm[i];
-    for (int i = threadIdx.x; i < n_g; i += blockDim.x) {
+    for (int i = tid; i <= n_g; i += kRefineBlock) x[i] = xm[i];
+    DD part = dd_from(0.0);
+    for (int i = tid; i < n_g; i += kRefineBlock) {
         const double w = Wm[i];
-        c[i] = (w > 0.0) ? Hm[i] / w : 0.0;
+        const double d = (w > 0.0) ? Hm[i] / w : 0.0;
+        c[i] = d;
+        part = dd_add(part, dd_from(d));
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n_g; ++i) s = s + c[i];
-        s_sum = s;
-    }
-    __syncthreads();
-    const double s = s_sum;
+    const DD sd = block_dd_sum(part, scratch);
+    const double s = sd.hi + sd.lo;
     if (!(s > 0.0)) return;
-    // smoothing and normalisation into y
-    for (int i = threadIdx.x; i < n_g; i += blockDim.x) {
+    for (int i = tid; i < n_g; i += kRefineBlock) {
         double v;
         if (i == 0) v = (7.0 * c[0] + c[1]) / 8.0;
         else if (i == n_g - 1) v = (c[n_g - 2] + 7.0 * c[n_g - 1]) / 8.0;
         else v = (c[i - 1] + 6.0 * c[i] + c[i + 1]) / 8.0;
-        y[i] = v / s;
+        A[i] = v / s;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n_g; i += blockDim.x) {
-        const double di = y[i];
+    // compression, and this thread's contiguous chunk of the prefix sums
+    const int per = (n_g + kRefineBlock - 1) / kRefineBlock;
+    const int j0 = tid * per;
+    const int j1 = (j0 + per < n_g) ? j0 + per : n_g;
+    for (int i = j0; i < j1; ++i) {
+        const double di = A[i];
         c[i] = (di == 0.0) ? 0.0 : pow((1.0 - di) / (-log(di)), alpha);
     }
+    DD tot = dd_from(0.0);
+    for (int i = j0; i < j1; ++i) tot = dd_add(tot, dd_from(c[i]));
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double csum = 0.0;
-        for (int i = 0; i < n_g; ++i) csum = csum + c[i];
-        const double delta_d = csum / (double)n_g;
-        y[0] = x[0];
-        y[n_g] = x[n_g];
-        if (!(delta_d > 0.0)) {
-            // nothing to share out (underflow or non-finite data): keep the axis
-            for (int i = 1; i < n_g; ++i) y[i] = x[i];
+    // exclusive scan of the chunk totals (Hillis-Steele over the block)
+    scratch[tid] = tot;
+    __syncthreads();
+    for (int d = 1; d < kRefineBlock; d <<= 1) {
+        const DD prev = (tid >= d) ? scratch[tid - d] : dd_from(0.0);
+        __syncthreads();
+        if (tid >= d) scratch[tid] = dd_add(prev, scratch[tid]);
+        __syncthreads();
+    }
+    DD run = (tid > 0) ? scratch[tid - 1] : dd_from(0.0);
+    const DD csum = scratch[kRefineBlock - 1];
+    __syncthreads();
+    // prefix sums C_j (j = 0..n_g) into (A, Bv)
+    if (tid == 0) {
+        A[0] = 0.0;
+        Bv[0] = 0.0;
+    }
+    for (int i = j0; i < j1; ++i) {
+        run = dd_add(run, dd_from(c[i]));
+        A[i + 1] = run.hi;
+        Bv[i + 1] = run.lo;
+    }
+    __syncthreads();
+    const double delta_d = (csum.hi + csum.lo) / (double)n_g;
+    if (!(delta_d > 0.0)) return;  // nothing to share out: keep the axis
+    for (int i = 1 + tid; i < n_g; i += kRefineBlock) {
+        // target i * delta_d exactly as a double-double
+        const double th = (double)i * delta_d;
+        const DD T = DD{th, fma((double)i, delta_d, -th)};
+        int lo = 1, hi = n_g + 1;  // smallest j in [1, n_g] with C_j >= T, or n_g + 1
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (dd_ge(DD{A[mid], Bv[mid]}, T)) hi = mid;
+            else lo = mid + 1;
+        }
+        double xn;
+        if (lo > n_g) {
+            xn = x[n_g];
         } else {
-        int j = 0;
-        double acc = 0.0;
-        for (int i = 1; i < n_g; ++i) {
-            while (acc < delta_d && j < n_g) {
-                acc = acc + c[j];
-                j = j + 1;
-            }
-            acc = acc - delta_d;
-            const double frac_left = (acc > 0.0) ? acc / c[j - 1] : 0.0;
-            y[i] = x[j] - frac_left * (x[j] - x[j - 1]);
+            const double S = dd_sub_to_d(DD{A[lo], Bv[lo]}, T);
+            const double frac_left = (S > 0.0) ? S / c[lo - 1] : 0.0;
+            xn = x[lo] - frac_left * (x[lo] - x[lo - 1]);
         }
-        }
+        xm[i] = xn;
+        xm32[i] = (float)xn;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i <= n_g; i += blockDim.x) {
-        xm[i] = y[i];
-        xm32[i] = (float)y[i];
+}
+
+void launch_refine(double* map, float* map32, const double* H, const double* W, int dim, int n_g,
+                   double alpha, hipStream_t s)
+{
+    const size_t lds = (size_t)(4 * n_g + 3) * sizeof(double);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void*)k_refine, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)((4 * kMaxNg + 3) * sizeof(double)));
+        attr_set = true;
     }
+    hipLaunchKernelGGL(k_refine, dim3(dim), dim3(kRefineBlock), lds, s, map, map32, H, W, n_g, alpha);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -395,8 +508,6 @@ void launch_scan(const int32_t* n_h, int64_t n_hc, int64_t* offs, int64_t* bsum,
     const int64_t nb = (n_hc + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kScanBlock), 0, s, n_h, n_hc, offs, bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, bsum, nb, offs, n_hc);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n_hc + 255) / 256)), dim3(256), 0, s, offs, n_hc,
-                       (const int64_t*)bsum);
 }
 
 void launch_edge_fixup(const EdgeRec* e, int64_t n_rec, double* S1, double* S2, hipStream_t s)
@@ -436,31 +547,23 @@ int est_grid(int64_t n_hc)
 }
 
 void launch_estimate(const int32_t* n_h, const double* S1, const double* S2, int64_t n_hc,
-                     double omega, double omega2, double beta, double* part, DevState* st,
-                     double* hist_I, double* hist_V, const int64_t* offs, int32_t it_slot,
-                     int32_t n_discard, hipStream_t s)
+                     double omega, double omega2, double beta, double* part, double* dh, DevState* st,
+                     double* hist_I, double* hist_V, const int64_t* loc, const int64_t* bbase,
+                     int32_t it_slot, int32_t n_discard, hipStream_t s)
 {
     const int g = est_grid(n_hc);
     hipLaunchKernelGGL(k_est_partial, dim3(g), dim3(kRedBlock), 0, s, n_h, S1, S2, n_hc, omega, omega2,
-                       beta, part);
-    hipLaunchKernelGGL(k_est_final, dim3(1), dim3(64), 0, s, (const double*)part, g, st, hist_I, hist_V,
-                       offs, n_hc, it_slot, n_discard);
+                       beta, part, dh);
+    hipLaunchKernelGGL(k_est_final, dim3(1), dim3(kRedBlock), 0, s, (const double*)part, g, st, hist_I,
+                       hist_V, loc, bbase, n_hc, it_slot, n_discard);
 }
 
-void launch_realloc(int32_t* n_h, const double* S1, const double* S2, int64_t n_hc, double omega,
-                    double omega2, double beta, double n_ev, int32_t plus2, const DevState* st,
-                    unsigned long long* ties, hipStream_t s)
+void launch_realloc(int32_t* n_h, const double* dh, int64_t n_hc, double n_ev, int32_t plus2,
+                    const DevState* st, unsigned long long* ties, hipStream_t s)
 {
     const int g = est_grid(n_hc);
-    hipLaunchKernelGGL(k_realloc, dim3(g), dim3(kRedBlock), 0, s, n_h, S1, S2, n_hc, omega, omega2,
-                       beta, n_ev, plus2, st, ties);
+    hipLaunchKernelGGL(k_realloc, dim3(g), dim3(kRedBlock), 0, s, n_h, dh, n_hc, n_ev, plus2, st, ties);
 }
 
-void launch_refine(double* map, float* map32, const double* H, const double* W, int dim, int n_g,
-                   double alpha, hipStream_t s)
-{
-    const size_t lds = (size_t)(3 * n_g + 2) * sizeof(double);
-    hipLaunchKernelGGL(k_refine, dim3(dim), dim3(kRefineBlock), lds, s, map, map32, H, W, n_g, alpha);
-}
 
 }  // namespace vp

@@ -11,12 +11,23 @@ constexpr int kMaxTerms = 4;
 constexpr int kMaxDim = 24;       // FP64 sampling path
 constexpr int kMaxDimSplit = 16;  // FP32 sampling paths
 constexpr int kMaxNg = 4096;      // refinement keeps one axis in LDS
-// Sampling workgroup size: the FP64 body needs ~180 VGPRs (two waves per
-// SIMD), the FP32 bodies fit four waves per SIMD.
-constexpr int sample_block(int prec) { return prec == 0 ? 512 : 1024; }
 
 enum Prec { P_FP64 = 0, P_FP32_ACC64 = 1, P_FP32_NEUMAIER = 2 };
 enum Kind { K_GAUSS_MIX = 1, K_CORR_GAUSS = 2, K_EXP_ABS = 3, K_CONST = 4, K_AFFINE = 5, K_BALLS = 6 };
+
+// Sampling workgroup size (one workgroup per CU holds the LDS training data):
+// the largest of 1024 / 768 / 512 threads whose register budget (128 / 168 /
+// 256 VGPRs) holds the kernel body without spilling, i.e. four, three or two
+// waves per SIMD.
+constexpr int sample_block(int prec, int kind, int dim)
+{
+    if (prec == 0) {
+        if (kind != K_GAUSS_MIX) return 512;
+        return dim <= 8 ? 1024 : (dim <= 12 ? 768 : 512);
+    }
+    return dim <= 13 ? 1024 : 768;
+}
+
 
 // Integrand coefficients, in device memory; every lane reads the same
 // addresses, so the compiler turns the reads into scalar loads.
@@ -43,10 +54,21 @@ struct EdgeRec {
     double s1, s2;
 };
 
+// Sample offsets are kept as offsets within blocks of kOffsTile hypercubes
+// plus one base per block: offset(h) = loc[h] + base[h / kOffsTile]; the
+// entry for h = n_hc is N_tot.
+constexpr int kOffsTile = 4096;
+__device__ __forceinline__ int64_t gofs(const int64_t* __restrict__ loc, const int64_t* __restrict__ base,
+                                        int64_t h)
+{
+    return loc[h] + base[h / kOffsTile];
+}
+
 struct SampleArgs {
     const double* map;      // [dim][n_g + 1]
     const float* map32;     // FP32 copy (split paths)
-    const int64_t* offs;    // [n_hc + 1] exclusive scan of n_h; offs[n_hc] = N_tot
+    const int64_t* offs;    // [n_hc + 1] offsets within blocks (see gofs)
+    const int64_t* obase;   // per-block bases
     double* S1;             // [n_hc]
     double* S2;             // [n_hc]
     double* hist_part;      // [grid][dim * n_g][2] per-workgroup training data (LDS path)
@@ -70,11 +92,17 @@ typedef int (*SampleOccupancy)(int block, size_t lds);
 struct SampleEntry {
     SampleLauncher launch;
     SampleOccupancy occupancy;  // resident workgroups per CU at this block size and LDS
+    int block;                  // workgroup size the kernel is built for
 };
 
-SampleEntry sample_entry_fp64(int dim, bool map_lds);
-SampleEntry sample_entry_fp32acc(int dim, bool map_lds);
-SampleEntry sample_entry_fp32neu(int dim, bool map_lds);
+// Specialised kernel for (precision, integrand kind, dim, map in LDS), or an
+// entry with launch == nullptr when none is built.  kind 0: generic kernel.
+SampleEntry sample_entry(int prec, int kind, int dim, bool map_lds);
+SampleEntry sample_entry_fp64_gauss(int dim, bool map_lds);
+SampleEntry sample_entry_fp64_corr(int dim, bool map_lds);
+SampleEntry sample_entry_fp64_generic(int dim, bool map_lds);
+SampleEntry sample_entry_fp32acc(int kind, int dim, bool map_lds);
+SampleEntry sample_entry_fp32neu(int kind, int dim, bool map_lds);
 
 // sampling kernels' LDS needs (bytes) for histogram and map
 inline size_t hist_lds_bytes(int dim, int n_g) { return (size_t)dim * n_g * 2 * sizeof(double); }

@@ -64,10 +64,10 @@ struct vp_ctx {
 static void ctx_release(vp_ctx* c)
 {
     if (--c->refs > 0) return;
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     if (c->own_stream) {
-        hipStreamSynchronize(c->stream);
-        hipStreamDestroy(c->stream);
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipStreamDestroy(c->stream);
     }
     delete c;
 }
@@ -91,6 +91,7 @@ struct vp_problem {
     int64_t* bsum = nullptr;
     double* S1 = nullptr;
     double* S2 = nullptr;
+    double* dh = nullptr;
     double* H = nullptr;
     double* W = nullptr;
     double* hist_part = nullptr;
@@ -115,6 +116,21 @@ struct vp_problem {
 };
 
 // ---------------------------------------------------------------- helpers
+SampleEntry vp::sample_entry(int prec, int kind, int dim, bool map_lds)
+{
+    SampleEntry e = {nullptr, nullptr, 0};
+    if (prec == P_FP64) {
+        if (kind == K_GAUSS_MIX) e = sample_entry_fp64_gauss(dim, map_lds);
+        else if (kind == K_CORR_GAUSS) e = sample_entry_fp64_corr(dim, map_lds);
+        if (!e.launch) e = sample_entry_fp64_generic(dim, map_lds);
+    } else if (prec == P_FP32_ACC64) {
+        e = sample_entry_fp32acc(kind, dim, map_lds);
+    } else if (prec == P_FP32_NEUMAIER) {
+        e = sample_entry_fp32neu(kind, dim, map_lds);
+    }
+    return e;
+}
+
 static int32_t nst_rule(int32_t dim, int64_t n_ev)
 {
     // largest n >= 1 with 4 n^dim <= n_ev (Sec. 3, Eq. Nst_vegasp)
@@ -230,25 +246,26 @@ static void free_problem(vp_problem* p)
 {
     if (!p) return;
     vp_ctx* ctx = p->ctx;
-    hipFree(p->f_d);
-    hipFree(p->map);
-    hipFree(p->map32);
-    hipFree(p->n_h);
-    hipFree(p->offs);
-    hipFree(p->bsum);
-    hipFree(p->S1);
-    hipFree(p->S2);
-    hipFree(p->H);
-    hipFree(p->W);
-    hipFree(p->hist_part);
-    hipFree(p->hist_glob);
-    hipFree(p->edges);
-    hipFree(p->est_part);
-    hipFree(p->hist_I);
-    hipFree(p->hist_V);
-    hipFree(p->st);
-    for (auto e : p->ev_pending) hipEventDestroy(e);
-    for (auto e : p->ev_free) hipEventDestroy(e);
+    (void)hipFree(p->f_d);
+    (void)hipFree(p->map);
+    (void)hipFree(p->map32);
+    (void)hipFree(p->n_h);
+    (void)hipFree(p->offs);
+    (void)hipFree(p->bsum);
+    (void)hipFree(p->S1);
+    (void)hipFree(p->S2);
+    (void)hipFree(p->dh);
+    (void)hipFree(p->H);
+    (void)hipFree(p->W);
+    (void)hipFree(p->hist_part);
+    (void)hipFree(p->hist_glob);
+    (void)hipFree(p->edges);
+    (void)hipFree(p->est_part);
+    (void)hipFree(p->hist_I);
+    (void)hipFree(p->hist_V);
+    (void)hipFree(p->st);
+    for (auto e : p->ev_pending) (void)hipEventDestroy(e);
+    for (auto e : p->ev_free) (void)hipEventDestroy(e);
     delete p;
     if (ctx) ctx_release(ctx);
 }
@@ -261,7 +278,7 @@ static hipEvent_t take_event(vp_problem* p)
         return e;
     }
     hipEvent_t e = nullptr;
-    hipEventCreate(&e);
+    (void)hipEventCreate(&e);
     return e;
 }
 
@@ -324,8 +341,8 @@ vp_status vp_ctx_create(int device, void* hip_stream, vp_ctx** out)
         c->stream = (hipStream_t)hip_stream;
     }
     int cu = 0, lds = 0;
-    hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device);
-    hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device);
+    (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
     c->n_cu = cu > 0 ? cu : 1;
     c->lds_max = lds > 0 ? (size_t)lds : 65536;
     *out = c;
@@ -381,7 +398,6 @@ vp_status vp_problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand*
 
     // sampling launch shape
     const int prec = P->precision;
-    p->block = sample_block(prec);
     const size_t hb = hist_lds_bytes(D, NG), mb = map_lds_bytes(prec, D, NG);
     p->hist_lds = hb <= ctx->lds_max ? 1 : 0;
     if (prec == VP_FP32_NEUMAIER && !p->hist_lds) {
@@ -389,14 +405,17 @@ vp_status vp_problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand*
         return fail(VP_ERR_INVALID_ARG, "compensated sums need dim * n_g * 16 <= %zu bytes of LDS", ctx->lds_max);
     }
     p->map_lds = (p->hist_lds ? hb : 0) + mb <= ctx->lds_max ? 1 : 0;
-    p->lds = (p->hist_lds ? hb : 0) + (p->map_lds ? mb : 0);
-    p->entry = prec == VP_FP64 ? sample_entry_fp64(D, p->map_lds)
-             : prec == VP_FP32_ACC64 ? sample_entry_fp32acc(D, p->map_lds)
-                                     : sample_entry_fp32neu(D, p->map_lds);
+    p->entry = sample_entry(prec, f->kind, D, p->map_lds != 0);
+    if (!p->entry.launch && p->map_lds) {
+        p->map_lds = 0;
+        p->entry = sample_entry(prec, f->kind, D, false);
+    }
     if (!p->entry.launch) {
         free_problem(p);
         return fail(VP_ERR_INVALID_ARG, "no sampling kernel for dim %d", D);
     }
+    p->block = p->entry.block;
+    p->lds = (p->hist_lds ? hb : 0) + (p->map_lds ? mb : 0);
     const char* env_chunk = getenv("VEGASP_CHUNK");
     p->chunk = env_chunk ? std::max(1, atoi(env_chunk)) : 8;
     int occ = p->entry.occupancy(p->block, p->lds);
@@ -422,6 +441,7 @@ vp_status vp_problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand*
     VP_ALLOC(p->bsum, scan_blocks(nhc) + 1);
     VP_ALLOC(p->S1, nhc);
     VP_ALLOC(p->S2, nhc);
+    VP_ALLOC(p->dh, nhc);
     VP_ALLOC(p->H, nbins);
     VP_ALLOC(p->W, nbins);
     if (p->hist_lds) VP_ALLOC(p->hist_part, (int64_t)p->grid * 2 * nbins);
@@ -475,8 +495,8 @@ vp_status vp_problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand*
 vp_status vp_problem_destroy(vp_problem* p)
 {
     if (!p) return VP_OK;
-    hipSetDevice(p->ctx->device);
-    hipStreamSynchronize(p->ctx->stream);
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipStreamSynchronize(p->ctx->stream);
     free_problem(p);
     return VP_OK;
 }
@@ -515,6 +535,7 @@ vp_status vp_iterate(vp_problem* p, int32_t n_iter)
         a.map = p->map;
         a.map32 = p->map32;
         a.offs = p->offs;
+        a.obase = p->bsum;
         a.S1 = p->S1;
         a.S2 = p->S2;
         a.hist_part = p->hist_part;
@@ -542,11 +563,10 @@ vp_status vp_iterate(vp_problem* p, int32_t n_iter)
         if (p->hist_lds) launch_hist_reduce(p->hist_part, p->grid, nbins, p->H, p->W, s);
         else launch_hist_reduce(p->hist_glob, 1, nbins, p->H, p->W, s);
         // 3. iteration estimate and combination
-        launch_estimate(p->n_h, p->S1, p->S2, p->n_hc, p->omega, p->omega2, P.beta, p->est_part, p->st,
-                        p->hist_I, p->hist_V, p->offs, p->slot, P.n_discard, s);
+        launch_estimate(p->n_h, p->S1, p->S2, p->n_hc, p->omega, p->omega2, P.beta, p->est_part, p->dh,
+                        p->st, p->hist_I, p->hist_V, p->offs, p->bsum, p->slot, P.n_discard, s);
         // 4. reallocation and 5. refinement, both for the next iteration
-        launch_realloc(p->n_h, p->S1, p->S2, p->n_hc, p->omega, p->omega2, P.beta, (double)P.n_ev,
-                       P.realloc_plus2, p->st, &p->st->ties, s);
+        launch_realloc(p->n_h, p->dh, p->n_hc, (double)P.n_ev, P.realloc_plus2, p->st, &p->st->ties, s);
         launch_refine(p->map, p->map32, p->H, p->W, D, NG, P.alpha, s);
         VP_HIP(hipGetLastError());
         if (p->prof) {

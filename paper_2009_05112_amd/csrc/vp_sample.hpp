@@ -6,7 +6,7 @@
 // of the map (Sec. 2.3 and 2.4).  Nothing per sample touches HBM.
 //
 // Work decomposition.  The samples of an iteration are numbered in hypercube
-// order, s = offs[h] + j (offs is the exclusive scan of n_h).  The launch is
+// order, s = offset(h) + j (the exclusive scan of n_h).  The launch is
 // persistent: every wave owns one contiguous, equal share of the sample range
 // and walks it in tiles of 64 * chunk samples, each lane taking `chunk`
 // consecutive samples.  A lane finds the hypercube of its first sample with a
@@ -63,14 +63,15 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src)
 
 // Largest h with offs[h] <= s over the whole array (wave-uniform s):
 // a 64-ary search, one coalesced load per level.
-__device__ __forceinline__ int64_t find_hypercube(const int64_t* __restrict__ offs, int64_t n_hc,
+__device__ __forceinline__ int64_t find_hypercube(const int64_t* __restrict__ offs,
+                                                  const int64_t* __restrict__ ob, int64_t n_hc,
                                                   int64_t s, int lane)
 {
     int64_t lo = 0, hi = n_hc;  // offs[lo] <= s < offs[hi]
     while (hi - lo > 64) {
         const int64_t step = (hi - lo) / 64;
         const int64_t p = lo + (int64_t)(lane + 1) * step;
-        const bool le = (p < hi) && (offs[p] <= s);
+        const bool le = (p < hi) && (gofs(offs, ob, p) <= s);
         const int c = __popcll(__ballot(le));
         const int64_t nlo = lo + (int64_t)c * step;
         const int64_t nhi = (c < 64) ? lo + (int64_t)(c + 1) * step : hi;
@@ -78,20 +79,21 @@ __device__ __forceinline__ int64_t find_hypercube(const int64_t* __restrict__ of
         hi = nhi < hi ? nhi : hi;
     }
     const int64_t p = lo + 1 + lane;
-    const bool le = (p < hi) && (offs[p] <= s);
+    const bool le = (p < hi) && (gofs(offs, ob, p) <= s);
     return lo + __popcll(__ballot(le));
 }
 
 // Per-lane hypercube of s (s >= offs[base] for every active lane): windows of
 // 64 consecutive offsets, binary-searched with lane shuffles.
-__device__ __forceinline__ int64_t locate(const int64_t* __restrict__ offs, int64_t n_hc,
+__device__ __forceinline__ int64_t locate(const int64_t* __restrict__ offs,
+                                          const int64_t* __restrict__ ob, int64_t n_hc,
                                           int64_t base, int64_t s, bool active, int lane)
 {
     int64_t res = base;
     bool done = !active;
     for (;;) {
         const int64_t p = base + 1 + lane;
-        const int64_t bnd = (p <= n_hc) ? offs[p] : INT64_MAX;
+        const int64_t bnd = (p <= n_hc) ? gofs(offs, ob, p) : INT64_MAX;
         int pos = 0;
 #pragma unroll
         for (int step = 32; step >= 1; step >>= 1) {
@@ -344,6 +346,49 @@ __device__ __forceinline__ float f_finish32(const IntegrandDev* __restrict__ f, 
     }
 }
 
+// ---------------------------------------------------------------- map access
+// The map of one axis is x[mu][0..N_g]; a sample needs the pair (x_i, x_{i+1}).
+// From LDS: two adjacent reads.  From global memory: one 16-byte (FP64) or
+// 8-byte (FP32) buffer load with a 32-bit offset from a wave-uniform buffer
+// resource (bounds-checked by the hardware: reads past the map return zero).
+typedef int vp_v4i __attribute__((ext_vector_type(4)));
+typedef int vp_v2i __attribute__((ext_vector_type(2)));
+constexpr int kBufferWord3 = 0x00020000;  // raw buffer, gfx9 family
+
+template <bool LDS>
+struct MapPair64 {
+    const double* lds;
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ __forceinline__ void get(uint32_t pos, double& x0, double& x1) const
+    {
+        if constexpr (LDS) {
+            x0 = lds[pos];
+            x1 = lds[pos + 1];
+        } else {
+            const vp_v4i v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, pos * 8u, 0, 0);
+            x0 = __builtin_bit_cast(double, (vp_v2i){v.x, v.y});
+            x1 = __builtin_bit_cast(double, (vp_v2i){v.z, v.w});
+        }
+    }
+};
+
+template <bool LDS>
+struct MapPair32 {
+    const float* lds;
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ __forceinline__ void get(uint32_t pos, float& x0, float& x1) const
+    {
+        if constexpr (LDS) {
+            x0 = lds[pos];
+            x1 = lds[pos + 1];
+        } else {
+            const vp_v2i v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, pos * 4u, 0, 0);
+            x0 = __builtin_bit_cast(float, v.x);
+            x1 = __builtin_bit_cast(float, v.y);
+        }
+    }
+};
+
 // ---------------------------------------------------------------- one sample
 // Stratified y in hypercube k (Sec. 3): y^mu = (k_mu + u) / N_st, so
 // t = y N_g = (k_mu + u) R; vegas map (Sec. 2.2, Eqs. y and jac):
@@ -352,51 +397,64 @@ __device__ __forceinline__ float f_finish32(const IntegrandDev* __restrict__ f, 
 // FP64: u from 53 bits -- the high word of axis mu is word mu of the
 // stream, its low word is word D + mu.
 template <int D, bool MAPLDS>
-__device__ __forceinline__ double sample_fp64(const SampleArgs& a, const double* __restrict__ map,
+__device__ __forceinline__ double sample_fp64(const SampleArgs& a, const MapPair64<MAPLDS>& map,
                                               uint32_t j, uint32_t h, const int32_t* k,
                                               int32_t* idx, int kind, int K)
 {
-    constexpr int NB = (2 * D + 3) / 4;
-    uint32_t w[4 * NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) philox4x32_10(j, h, a.it, (uint32_t)b, a.key0, a.key1, &w[4 * b]);
+    // Axes are processed in groups of four: group g takes its high words from
+    // block g and its low words from the block(s) holding words D+4g..D+4g+3,
+    // each block generated right before its first use so that only a few
+    // words are live at a time.
+    constexpr int NG4 = (D + 3) / 4;
     const int n_g = a.n_g;
     FState<D, double> st;
 #pragma unroll
     for (int kk = 0; kk < kMaxTerms; ++kk) st.q[kk] = 0.0;
     st.lin = (kind == K_AFFINE) ? a.f->centers[0] : 0.0;
     double jac = 1.0;
+    uint32_t lo_blk[4];
+    int lo_have = -1;  // index of the block held in lo_blk
 #pragma unroll
-    for (int mu = 0; mu < D; ++mu) {
-        const double hi = (double)(w[mu] >> 5);
-        const double lo = (double)(w[D + mu] >> 6);
-        const double u = fma(hi, 0x1p-27, lo * 0x1p-53);  // exact: a 53-bit integer times 2^-53
-        const double t = ((double)k[mu] + u) * a.R;
-        int i = (int)t;
-        i = i < n_g - 1 ? i : n_g - 1;
-        double delta = t - (double)i;
-        delta = delta < 1.0 ? delta : 1.0;
-        const double* xm = map + mu * (n_g + 1);
-        const double x0 = xm[i];
-        const double dx = xm[i + 1] - x0;
-        const double x = fma(dx, delta, x0);
-        jac = jac * ((double)n_g * dx);
-        idx[mu] = i;
-        f_axis<D>(a.f, kind, K, mu, x, st);
+    for (int g = 0; g < NG4; ++g) {
+        uint32_t hi_blk[4];
+        philox4x32_10(j, h, a.it, (uint32_t)g, a.key0, a.key1, hi_blk);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int mu = 4 * g + r;
+            if (mu >= D) break;
+            const int lw = D + mu;
+            const int lb = lw / 4;
+            if (lb != lo_have) {
+                philox4x32_10(j, h, a.it, (uint32_t)lb, a.key0, a.key1, lo_blk);
+                lo_have = lb;
+            }
+            const double hi = (double)(hi_blk[r] >> 5);
+            const double lo = (double)(lo_blk[lw % 4] >> 6);
+            const double u = fma(hi, 0x1p-27, lo * 0x1p-53);  // exact: a 53-bit integer times 2^-53
+            const double t = ((double)k[mu] + u) * a.R;
+            int i = (int)t;
+            i = i < n_g - 1 ? i : n_g - 1;
+            double delta = t - (double)i;
+            delta = delta < 1.0 ? delta : 1.0;
+            double x0, x1;
+            map.get((uint32_t)(mu * (n_g + 1) + i), x0, x1);
+            const double dx = x1 - x0;
+            const double x = fma(dx, delta, x0);
+            jac = jac * ((double)n_g * dx);
+            idx[mu] = i;
+            f_axis<D>(a.f, kind, K, mu, x, st);
+        }
     }
     return jac * f_finish<D>(a.f, kind, K, st);
 }
 
 // FP32 split: u = (w >> 8) 2^-24 from the high word of each axis alone.
 template <int D, bool MAPLDS>
-__device__ __forceinline__ float sample_fp32(const SampleArgs& a, const float* __restrict__ map,
+__device__ __forceinline__ float sample_fp32(const SampleArgs& a, const MapPair32<MAPLDS>& map,
                                              uint32_t j, uint32_t h, const int32_t* k, int32_t* idx,
                                              int kind, int K)
 {
-    constexpr int NB = (D + 3) / 4;
-    uint32_t w[4 * NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) philox4x32_10(j, h, a.it, (uint32_t)b, a.key0, a.key1, &w[4 * b]);
+    constexpr int NG4 = (D + 3) / 4;
     const int n_g = a.n_g;
     FState<D, float> st;
 #pragma unroll
@@ -404,27 +462,36 @@ __device__ __forceinline__ float sample_fp32(const SampleArgs& a, const float* _
     st.lin = (kind == K_AFFINE) ? a.f->centers32[0] : 0.0f;
     float jac = 1.0f;
 #pragma unroll
-    for (int mu = 0; mu < D; ++mu) {
-        const float u = (float)(w[mu] >> 8) * 0x1p-24f;
-        const float t = ((float)k[mu] + u) * a.R32;
-        int i = (int)t;
-        i = i < n_g - 1 ? i : n_g - 1;
-        float delta = t - (float)i;
-        delta = delta < 1.0f ? delta : 1.0f;
-        const float* xm = map + mu * (n_g + 1);
-        const float x0 = xm[i];
-        const float dx = xm[i + 1] - x0;
-        const float x = fmaf(dx, delta, x0);
-        jac = jac * ((float)n_g * dx);
-        idx[mu] = i;
-        f_axis32<D>(a.f, kind, K, mu, x, st);
+    for (int g = 0; g < NG4; ++g) {
+        uint32_t w[4];
+        philox4x32_10(j, h, a.it, (uint32_t)g, a.key0, a.key1, w);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int mu = 4 * g + r;
+            if (mu >= D) break;
+            const float u = (float)(w[r] >> 8) * 0x1p-24f;
+            const float t = ((float)k[mu] + u) * a.R32;
+            int i = (int)t;
+            i = i < n_g - 1 ? i : n_g - 1;
+            float delta = t - (float)i;
+            delta = delta < 1.0f ? delta : 1.0f;
+            float x0, x1;
+            map.get((uint32_t)(mu * (n_g + 1) + i), x0, x1);
+            const float dx = x1 - x0;
+            const float x = fmaf(dx, delta, x0);
+            jac = jac * ((float)n_g * dx);
+            idx[mu] = i;
+            f_axis32<D>(a.f, kind, K, mu, x, st);
+        }
     }
     return jac * f_finish32<D>(a.f, kind, K, st);
 }
 
 // ---------------------------------------------------------------- the kernel
-template <int D, int PREC, bool MAPLDS>
-__global__ __launch_bounds__(sample_block(PREC)) void k_sample(SampleArgs a)
+// KIND fixes the integrand at compile time (K_GAUSS_MIX, K_CORR_GAUSS), or is
+// 0 for the generic kernel that dispatches on the integrand's kind at run time.
+template <int D, int PREC, bool MAPLDS, int KIND>
+__global__ __launch_bounds__(sample_block(PREC, KIND, D)) void k_sample(SampleArgs a)
 {
     typedef typename AccOf<PREC>::type Acc;
     typedef typename std::conditional<PREC == P_FP64, double, float>::type MapT;
@@ -445,28 +512,31 @@ __global__ __launch_bounds__(sample_block(PREC)) void k_sample(SampleArgs a)
     if constexpr (MAPLDS)
         for (int i = threadIdx.x; i < D * (n_g + 1); i += blockDim.x) lds_map[i] = gmap[i];
     __syncthreads();
-    const MapT* map;
-    if constexpr (MAPLDS) map = lds_map;
-    else map = gmap;
+    typedef typename std::conditional<PREC == P_FP64, MapPair64<MAPLDS>, MapPair32<MAPLDS>>::type MapAcc;
+    MapAcc map;
+    map.lds = lds_map;
+    map.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)gmap, (short)0,
+                                                 (int)((size_t)D * (n_g + 1) * sizeof(MapT)), kBufferWord3);
 
     const int lane = threadIdx.x & (kWave - 1);
     const int waves_per_block = blockDim.x / kWave;
     const int64_t wave = (int64_t)blockIdx.x * waves_per_block + (threadIdx.x / kWave);
     const int64_t n_waves = (int64_t)gridDim.x * waves_per_block;
     const int64_t* __restrict__ offs = a.offs;
+    const int64_t* __restrict__ ob = a.obase;
     const int64_t n_hc = a.n_hc;
-    const int64_t n_tot = offs[n_hc];
+    const int64_t n_tot = gofs(offs, ob, n_hc);
     const int64_t s_a = n_tot * wave / n_waves;
     const int64_t s_b = n_tot * (wave + 1) / n_waves;
     const int C = a.chunk;
-    const int kind = a.f->kind;
+    const int kind = KIND ? KIND : a.f->kind;
     const int K = a.f->n_terms;
     const uint32_t n_st = (uint32_t)a.n_st;
     const bool literal = (a.hist_mode != 0);
-    unsigned long long bad = 0;
+    uint32_t bad = 0;
 
     if (s_a < s_b) {
-        const int64_t h_a = find_hypercube(offs, n_hc, s_a, lane);
+        const int64_t h_a = find_hypercube(offs, ob, n_hc, s_a, lane);
         int64_t h_cur = h_a;
         Acc carry;
         carry.zero();
@@ -478,7 +548,7 @@ __global__ __launch_bounds__(sample_block(PREC)) void k_sample(SampleArgs a)
             const int64_t s_l = s0 + (int64_t)lane * C;
             const bool active = s_l < s_b;
             const int64_t e_l = active ? (s_l + C < s_b ? s_l + C : s_b) : s_l;
-            int64_t h = locate(offs, n_hc, h_cur, s_l, active, lane);
+            int64_t h = locate(offs, ob, n_hc, h_cur, s_l, active, lane);
 
             Acc run, headacc;
             run.zero();
@@ -487,44 +557,53 @@ __global__ __launch_bounds__(sample_block(PREC)) void k_sample(SampleArgs a)
             const int64_t head_h = h;
             int64_t h_end = h;
             if (active) {
-                int64_t o_cur = offs[h], o_next = offs[h + 1];
+                // Walk state in 32 bits: sample positions relative to the wave's
+                // first sample s_a (N_tot < 2^32), the index j within the current
+                // hypercube, and the hypercube itself (N_hc < 2^31).
+                const int64_t o_cur0 = gofs(offs, ob, h);
+                uint32_t hh32 = (uint32_t)h;
+                uint32_t next = (uint32_t)(gofs(offs, ob, h + 1) - s_a);
+                uint32_t j = (uint32_t)(s_l - o_cur0);
+                const uint32_t s_end = (uint32_t)(e_l - s_a);
                 int32_t k[D];
                 {
-                    uint32_t r = (uint32_t)h;
+                    uint32_t r = hh32;
 #pragma unroll
                     for (int m = D - 1; m >= 0; --m) {
                         k[m] = (int32_t)(r % n_st);
                         r /= n_st;
                     }
                 }
-                double inv_n = 1.0 / (double)(o_next - o_cur);
-                float inv_n32 = 1.0f / (float)(o_next - o_cur);
-                for (int64_t s = s_l; s < e_l; ++s) {
-                    if (s == o_next) {
+                uint32_t n_cur = (uint32_t)(gofs(offs, ob, h + 1) - o_cur0);
+                double inv_n = 1.0 / (double)n_cur;
+                float inv_n32 = 1.0f / (float)n_cur;
+                for (uint32_t s = (uint32_t)(s_l - s_a); s < s_end; ++s, ++j) {
+                    if (s == next) {
                         if (in_head) {
                             headacc = run;
                             head_closed = true;
                             in_head = false;
                         } else {
-                            a.S1[h] = run.sa();
-                            a.S2[h] = run.sb();
+                            a.S1[hh32] = run.sa();
+                            a.S2[hh32] = run.sb();
                         }
                         run.zero();
-                        ++h;
-                        o_cur = o_next;
-                        o_next = offs[h + 1];
-                        inv_n = 1.0 / (double)(o_next - o_cur);
-                        inv_n32 = 1.0f / (float)(o_next - o_cur);
+                        ++hh32;
+                        j = 0;
+                        const uint32_t nn = (uint32_t)(gofs(offs, ob, (int64_t)hh32 + 1) - s_a);
+                        n_cur = nn - next;
+                        next = nn;
+                        inv_n = 1.0 / (double)n_cur;
+                        inv_n32 = 1.0f / (float)n_cur;
 #pragma unroll
                         for (int m = D - 1; m >= 0; --m) {
                             if (++k[m] < (int32_t)n_st) break;
                             k[m] = 0;
                         }
                     }
-                    const uint32_t j = (uint32_t)(s - o_cur);
                     int32_t idx[D];
                     if constexpr (PREC == P_FP64) {
-                        const double v = sample_fp64<D, MAPLDS>(a, map, j, (uint32_t)h, k, idx, kind, K);
+                        const double v = sample_fp64<D, MAPLDS>(a, map, j, hh32, k, idx, kind, K);
                         run.add(v);
                         if (!isfinite(v)) ++bad;
                         const double v2 = v * v;
@@ -542,7 +621,7 @@ __global__ __launch_bounds__(sample_block(PREC)) void k_sample(SampleArgs a)
                             }
                         }
                     } else if constexpr (PREC == P_FP32_ACC64) {
-                        const float v32 = sample_fp32<D, MAPLDS>(a, map, j, (uint32_t)h, k, idx, kind, K);
+                        const float v32 = sample_fp32<D, MAPLDS>(a, map, j, hh32, k, idx, kind, K);
                         const double v = (double)v32;
                         run.add(v);
                         if (!isfinite(v32)) ++bad;
@@ -561,7 +640,7 @@ __global__ __launch_bounds__(sample_block(PREC)) void k_sample(SampleArgs a)
                             }
                         }
                     } else {
-                        const float v32 = sample_fp32<D, MAPLDS>(a, map, j, (uint32_t)h, k, idx, kind, K);
+                        const float v32 = sample_fp32<D, MAPLDS>(a, map, j, hh32, k, idx, kind, K);
                         run.addf(v32);
                         if (!isfinite(v32)) ++bad;
                         const float v2 = v32 * v32;
@@ -575,21 +654,21 @@ __global__ __launch_bounds__(sample_block(PREC)) void k_sample(SampleArgs a)
                         }
                     }
                 }
-                if (e_l == o_next) {
+                if (s_end == next) {
                     // the run ends exactly at the end of this lane's samples
                     if (in_head) {
                         headacc = run;
                         head_closed = true;
                         in_head = false;
                     } else {
-                        a.S1[h] = run.sa();
-                        a.S2[h] = run.sb();
+                        a.S1[hh32] = run.sa();
+                        a.S2[hh32] = run.sb();
                     }
                     run.zero();
-                    h_end = h + 1;
+                    h_end = (int64_t)hh32 + 1;
                 } else {
                     open_end = true;
-                    h_end = h;
+                    h_end = (int64_t)hh32;
                 }
             }
 
@@ -679,7 +758,7 @@ __global__ __launch_bounds__(sample_block(PREC)) void k_sample(SampleArgs a)
 
     // non-finite samples: one atomic per wave
     for (int d = kWave / 2; d >= 1; d >>= 1) bad += __shfl_down(bad, d);
-    if (lane == 0 && bad) atomicAdd(a.nonfinite, bad);
+    if (lane == 0 && bad) atomicAdd(a.nonfinite, (unsigned long long)bad);
 
     __syncthreads();
     if (a.hist_lds) {
@@ -693,10 +772,32 @@ __global__ __launch_bounds__(sample_block(PREC)) void k_sample(SampleArgs a)
     }
 }
 
-template <int D, int PREC, bool MAPLDS>
+template <int D, int PREC, bool MAPLDS, int KIND>
 void launch_sample(const SampleArgs& a, int grid, int block, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sample<D, PREC, MAPLDS>), dim3(grid), dim3(block), lds, s, a);
+    hipLaunchKernelGGL((k_sample<D, PREC, MAPLDS, KIND>), dim3(grid), dim3(block), lds, s, a);
+}
+
+template <int D, int PREC, bool MAPLDS, int KIND>
+int sample_occupancy(int block, size_t lds)
+{
+    int n = 0;
+    (void)hipFuncSetAttribute((const void*)k_sample<D, PREC, MAPLDS, KIND>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sample<D, PREC, MAPLDS, KIND>, block, lds) !=
+        hipSuccess)
+        return 0;
+    return n;
+}
+
+template <int D, int PREC, bool MAPLDS, int KIND>
+SampleEntry make_entry()
+{
+    SampleEntry e;
+    e.launch = launch_sample<D, PREC, MAPLDS, KIND>;
+    e.occupancy = sample_occupancy<D, PREC, MAPLDS, KIND>;
+    e.block = sample_block(PREC, KIND, D);
+    return e;
 }
 
 }  // namespace vp

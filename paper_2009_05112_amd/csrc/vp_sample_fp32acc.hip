@@ -1,92 +1,51 @@
-// vp_sample_fp32acc.hip -- instantiations of the fused sampling kernel, single-precision map and integrand with double sums, D = 1..16.
+// vp_sample_fp32acc.hip -- instantiations of the fused sampling kernel: single-precision map and integrand, double sums, D = 1..16.
 #include "vp_sample.hpp"
 
 namespace vp {
 
-namespace {
-template <int D, bool MAPLDS>
-int occ(int block, size_t lds)
+SampleEntry sample_entry_fp32acc(int kind, int dim, bool map_lds)
 {
-    int n = 0;
-    (void)hipFuncSetAttribute((const void*)k_sample<D, P_FP32_ACC64, MAPLDS>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sample<D, P_FP32_ACC64, MAPLDS>, block, lds) !=
-        hipSuccess)
-        return 0;
-    return n;
-}
-}  // namespace
-
-SampleEntry sample_entry_fp32acc(int dim, bool map_lds)
-{
-    SampleEntry e = {nullptr, nullptr};
-    switch (dim) {
-    case 1:
-        e.launch = map_lds ? launch_sample<1, P_FP32_ACC64, true> : launch_sample<1, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<1, true> : occ<1, false>;
-        break;
-    case 2:
-        e.launch = map_lds ? launch_sample<2, P_FP32_ACC64, true> : launch_sample<2, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<2, true> : occ<2, false>;
-        break;
-    case 3:
-        e.launch = map_lds ? launch_sample<3, P_FP32_ACC64, true> : launch_sample<3, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<3, true> : occ<3, false>;
-        break;
-    case 4:
-        e.launch = map_lds ? launch_sample<4, P_FP32_ACC64, true> : launch_sample<4, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<4, true> : occ<4, false>;
-        break;
-    case 5:
-        e.launch = map_lds ? launch_sample<5, P_FP32_ACC64, true> : launch_sample<5, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<5, true> : occ<5, false>;
-        break;
-    case 6:
-        e.launch = map_lds ? launch_sample<6, P_FP32_ACC64, true> : launch_sample<6, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<6, true> : occ<6, false>;
-        break;
-    case 7:
-        e.launch = map_lds ? launch_sample<7, P_FP32_ACC64, true> : launch_sample<7, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<7, true> : occ<7, false>;
-        break;
-    case 8:
-        e.launch = map_lds ? launch_sample<8, P_FP32_ACC64, true> : launch_sample<8, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<8, true> : occ<8, false>;
-        break;
-    case 9:
-        e.launch = map_lds ? launch_sample<9, P_FP32_ACC64, true> : launch_sample<9, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<9, true> : occ<9, false>;
-        break;
-    case 10:
-        e.launch = map_lds ? launch_sample<10, P_FP32_ACC64, true> : launch_sample<10, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<10, true> : occ<10, false>;
-        break;
-    case 11:
-        e.launch = map_lds ? launch_sample<11, P_FP32_ACC64, true> : launch_sample<11, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<11, true> : occ<11, false>;
-        break;
-    case 12:
-        e.launch = map_lds ? launch_sample<12, P_FP32_ACC64, true> : launch_sample<12, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<12, true> : occ<12, false>;
-        break;
-    case 13:
-        e.launch = map_lds ? launch_sample<13, P_FP32_ACC64, true> : launch_sample<13, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<13, true> : occ<13, false>;
-        break;
-    case 14:
-        e.launch = map_lds ? launch_sample<14, P_FP32_ACC64, true> : launch_sample<14, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<14, true> : occ<14, false>;
-        break;
-    case 15:
-        e.launch = map_lds ? launch_sample<15, P_FP32_ACC64, true> : launch_sample<15, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<15, true> : occ<15, false>;
-        break;
-    case 16:
-        e.launch = map_lds ? launch_sample<16, P_FP32_ACC64, true> : launch_sample<16, P_FP32_ACC64, false>;
-        e.occupancy = map_lds ? occ<16, true> : occ<16, false>;
-        break;
-    default:
-        break;
+    SampleEntry e = {nullptr, nullptr, 0};
+    if (kind == K_GAUSS_MIX) {
+        switch (dim) {
+        case 1: e = map_lds ? make_entry<1, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<1, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 2: e = map_lds ? make_entry<2, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<2, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 3: e = map_lds ? make_entry<3, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<3, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 4: e = map_lds ? make_entry<4, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<4, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 5: e = map_lds ? make_entry<5, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<5, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 6: e = map_lds ? make_entry<6, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<6, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 7: e = map_lds ? make_entry<7, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<7, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 8: e = map_lds ? make_entry<8, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<8, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 9: e = map_lds ? make_entry<9, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<9, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 10: e = map_lds ? make_entry<10, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<10, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 11: e = map_lds ? make_entry<11, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<11, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 12: e = map_lds ? make_entry<12, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<12, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 13: e = map_lds ? make_entry<13, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<13, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 14: e = map_lds ? make_entry<14, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<14, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 15: e = map_lds ? make_entry<15, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<15, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        case 16: e = map_lds ? make_entry<16, P_FP32_ACC64, true, K_GAUSS_MIX>() : make_entry<16, P_FP32_ACC64, false, K_GAUSS_MIX>(); break;
+        default: break;
+        }
+    } else {
+        switch (dim) {
+        case 1: if (!map_lds) e = make_entry<1, P_FP32_ACC64, false, 0>(); break;
+        case 2: if (!map_lds) e = make_entry<2, P_FP32_ACC64, false, 0>(); break;
+        case 3: if (!map_lds) e = make_entry<3, P_FP32_ACC64, false, 0>(); break;
+        case 4: if (!map_lds) e = make_entry<4, P_FP32_ACC64, false, 0>(); break;
+        case 5: if (!map_lds) e = make_entry<5, P_FP32_ACC64, false, 0>(); break;
+        case 6: if (!map_lds) e = make_entry<6, P_FP32_ACC64, false, 0>(); break;
+        case 7: if (!map_lds) e = make_entry<7, P_FP32_ACC64, false, 0>(); break;
+        case 8: if (!map_lds) e = make_entry<8, P_FP32_ACC64, false, 0>(); break;
+        case 9: if (!map_lds) e = make_entry<9, P_FP32_ACC64, false, 0>(); break;
+        case 10: if (!map_lds) e = make_entry<10, P_FP32_ACC64, false, 0>(); break;
+        case 11: if (!map_lds) e = make_entry<11, P_FP32_ACC64, false, 0>(); break;
+        case 12: if (!map_lds) e = make_entry<12, P_FP32_ACC64, false, 0>(); break;
+        case 13: if (!map_lds) e = make_entry<13, P_FP32_ACC64, false, 0>(); break;
+        case 14: if (!map_lds) e = make_entry<14, P_FP32_ACC64, false, 0>(); break;
+        case 15: if (!map_lds) e = make_entry<15, P_FP32_ACC64, false, 0>(); break;
+        case 16: if (!map_lds) e = make_entry<16, P_FP32_ACC64, false, 0>(); break;
+        default: break;
+        }
     }
     return e;
 }
