@@ -120,8 +120,8 @@ __global__ void k_edge_fixup(const EdgeRec* __restrict__ e, int64_t n_rec, doubl
 }
 
 // ---------------------------------------------------------------- training data
-// Sum of the per-workgroup partials in workgroup order; splits the
-// interleaved (numerator, weight) pairs into H and W.
+// Sum of the per-workgroup partials in workgroup order; each partial holds the
+// numerator plane H[nbins] followed by the weight plane W[nbins].
 __global__ void k_hist_reduce(const double* __restrict__ part, int n_part, int64_t nbins,
                               double* __restrict__ H, double* __restrict__ W)
 {
@@ -138,8 +138,8 @@ __global__ void k_hist_reduce(const double* __restrict__ part, int n_part, int64
         }
         for (; p < n_part; ++p) a0 = a0 + part[(int64_t)p * 2 * nbins + i];
         const double s = (a0 + a1) + (a2 + a3);
-        if (i & 1) W[i >> 1] = s;
-        else H[i >> 1] = s;
+        if (i >= nbins) W[i - nbins] = s;
+        else H[i] = s;
     }
 }
 

@@ -25,7 +25,7 @@ constexpr int sample_block(int prec, int kind, int dim)
         if (kind != K_GAUSS_MIX) return 512;
         return dim <= 8 ? 1024 : (dim <= 12 ? 768 : 512);
     }
-    return dim <= 13 ? 1024 : 768;
+    return dim <= 12 ? 1024 : 768;
 }
 
 
@@ -71,8 +71,8 @@ struct SampleArgs {
     const int64_t* obase;   // per-block bases
     double* S1;             // [n_hc]
     double* S2;             // [n_hc]
-    double* hist_part;      // [grid][dim * n_g][2] per-workgroup training data (LDS path)
-    double* hist_glob;      // [dim * n_g][2] (global-atomic path, zeroed before launch)
+    double* hist_part;      // [grid][2][dim * n_g] per-workgroup training data (LDS path)
+    double* hist_glob;      // [2][dim * n_g] (global-atomic path, zeroed before launch)
     EdgeRec* edges;         // [2 * n_waves]
     unsigned long long* nonfinite;
     const IntegrandDev* f;

@@ -18,8 +18,10 @@
 // hypercube's S1, S2 is therefore written exactly once, deterministically.
 //
 // Training data are privatised per workgroup in LDS (one workgroup per CU
-// holds all D * N_g bins) and written out once per workgroup; a second
-// kernel reduces the per-workgroup partials in a fixed order.
+// holds all D * N_g bins, numerators and weights in separate planes so the
+// 8-byte atomics of a wave spread over every LDS bank) and written out once
+// per workgroup; a second kernel reduces the per-workgroup partials in a
+// fixed order.
 #pragma once
 
 #include "vp_internal.hpp"
@@ -38,8 +40,9 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        // three-way xors as single CDNA4 bitop3 instructions (truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -207,13 +210,13 @@ struct AccOf<P_FP32_NEUMAIER> {
 
 // Exact rounding error of an LDS atomic add: the atomic returns the old value,
 // the stored sum is fl(old + x), and TwoSum recovers old + x - fl(old + x).
-__device__ __forceinline__ void lds_add_compensated(float* pair, float x)
+__device__ __forceinline__ void lds_add_compensated(float* sum, float* comp, float x)
 {
-    const float old = atomicAdd(pair, x);
+    const float old = atomicAdd(sum, x);
     const float s = old + x;
     const float bp = s - old;
     const float err = (old - (s - bp)) + (x - bp);
-    if (err != 0.0f) atomicAdd(pair + 1, err);
+    if (err != 0.0f) atomicAdd(comp, err);
 }
 
 // ---------------------------------------------------------------- integrands
@@ -351,8 +354,6 @@ __device__ __forceinline__ float f_finish32(const IntegrandDev* __restrict__ f, 
 // From LDS: two adjacent reads.  From global memory: one 16-byte (FP64) or
 // 8-byte (FP32) buffer load with a 32-bit offset from a wave-uniform buffer
 // resource (bounds-checked by the hardware: reads past the map return zero).
-typedef int vp_v4i __attribute__((ext_vector_type(4)));
-typedef int vp_v2i __attribute__((ext_vector_type(2)));
 constexpr int kBufferWord3 = 0x00020000;  // raw buffer, gfx9 family
 
 template <bool LDS>
@@ -365,9 +366,9 @@ struct MapPair64 {
             x0 = lds[pos];
             x1 = lds[pos + 1];
         } else {
-            const vp_v4i v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, pos * 8u, 0, 0);
-            x0 = __builtin_bit_cast(double, (vp_v2i){v.x, v.y});
-            x1 = __builtin_bit_cast(double, (vp_v2i){v.z, v.w});
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, pos * 8u, 0, 0);
+            x0 = __builtin_bit_cast(double, ((uint64_t)(uint32_t)v[1] << 32) | (uint32_t)v[0]);
+            x1 = __builtin_bit_cast(double, ((uint64_t)(uint32_t)v[3] << 32) | (uint32_t)v[2]);
         }
     }
 };
@@ -382,9 +383,9 @@ struct MapPair32 {
             x0 = lds[pos];
             x1 = lds[pos + 1];
         } else {
-            const vp_v2i v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, pos * 4u, 0, 0);
-            x0 = __builtin_bit_cast(float, v.x);
-            x1 = __builtin_bit_cast(float, v.y);
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, pos * 4u, 0, 0);
+            x0 = __builtin_bit_cast(float, (uint32_t)v[0]);
+            x1 = __builtin_bit_cast(float, (uint32_t)v[1]);
         }
     }
 };
@@ -613,11 +614,11 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D)) void k_sample(SampleAr
                         for (int mu = 0; mu < D; ++mu) {
                             const int bin = mu * n_g + idx[mu];
                             if (a.hist_lds) {
-                                atomicAdd(&lds_hist[2 * bin], hh);
-                                atomicAdd(&lds_hist[2 * bin + 1], hw);
+                                atomicAdd(&lds_hist[bin], hh);
+                                atomicAdd(&lds_hist[nbins + bin], hw);
                             } else {
-                                atomicAdd(&a.hist_glob[2 * bin], hh);
-                                atomicAdd(&a.hist_glob[2 * bin + 1], hw);
+                                atomicAdd(&a.hist_glob[bin], hh);
+                                atomicAdd(&a.hist_glob[nbins + bin], hw);
                             }
                         }
                     } else if constexpr (PREC == P_FP32_ACC64) {
@@ -632,11 +633,11 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D)) void k_sample(SampleAr
                         for (int mu = 0; mu < D; ++mu) {
                             const int bin = mu * n_g + idx[mu];
                             if (a.hist_lds) {
-                                atomicAdd(&lds_hist[2 * bin], hh);
-                                atomicAdd(&lds_hist[2 * bin + 1], hw);
+                                atomicAdd(&lds_hist[bin], hh);
+                                atomicAdd(&lds_hist[nbins + bin], hw);
                             } else {
-                                atomicAdd(&a.hist_glob[2 * bin], hh);
-                                atomicAdd(&a.hist_glob[2 * bin + 1], hw);
+                                atomicAdd(&a.hist_glob[bin], hh);
+                                atomicAdd(&a.hist_glob[nbins + bin], hw);
                             }
                         }
                     } else {
@@ -649,8 +650,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D)) void k_sample(SampleAr
 #pragma unroll
                         for (int mu = 0; mu < D; ++mu) {
                             const int bin = mu * n_g + idx[mu];
-                            lds_add_compensated(&lds_histf[4 * bin], hh);
-                            lds_add_compensated(&lds_histf[4 * bin + 2], hw);
+                            lds_add_compensated(&lds_histf[bin], &lds_histf[nbins + bin], hh);
+                            lds_add_compensated(&lds_histf[2 * nbins + bin], &lds_histf[3 * nbins + bin], hw);
                         }
                     }
                 }
@@ -764,8 +765,10 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D)) void k_sample(SampleAr
     if (a.hist_lds) {
         double* out = a.hist_part + (size_t)blockIdx.x * 2 * nbins;
         if constexpr (PREC == P_FP32_NEUMAIER) {
-            for (int i = threadIdx.x; i < 2 * nbins; i += blockDim.x)
-                out[i] = (double)lds_histf[2 * i] + (double)lds_histf[2 * i + 1];
+            for (int i = threadIdx.x; i < nbins; i += blockDim.x) {
+                out[i] = (double)lds_histf[i] + (double)lds_histf[nbins + i];
+                out[nbins + i] = (double)lds_histf[2 * nbins + i] + (double)lds_histf[3 * nbins + i];
+            }
         } else {
             for (int i = threadIdx.x; i < 2 * nbins; i += blockDim.x) out[i] = lds_hist[i];
         }

@@ -34,9 +34,12 @@ def variance_scale(n_hc, n_h, S2):
 
 
 def step_and_compare(gp: B.Problem, op: oracle.Problem, rtol=RTOL64, rtol_hist=RTOL64,
-                     exact_counts=False, check_map=True, check_alloc=True):
+                     exact_counts=False, check_map=True, check_alloc=True, floor=0.0):
     """Run one GPU iteration from its current state, run the oracle from the
-    same (map, n_h, it), compare every output.  Returns the oracle's outputs."""
+    same (map, n_h, it), compare every output.  Returns the oracle's outputs.
+    floor: per-hypercube sums are compared up to an absolute floor of
+    floor * max|sum| (single-precision paths: values near the FP32 underflow
+    threshold are flushed on the GPU and carry no weight in any result)."""
     fmap = gp.map()
     n_h = gp.alloc()
     it = gp.it
@@ -44,8 +47,10 @@ def step_and_compare(gp: B.Problem, op: oracle.Problem, rtol=RTOL64, rtol_hist=R
     acc = gp.accum()
     res = gp.result(allow_nonfinite=True)
     o = op.sample_range(fmap, n_h, it)
-    assert_close(acc["S1"], o["S1"], rtol, what="S1")
-    assert_close(acc["S2"], o["S2"], rtol, what="S2")
+    sc1 = np.maximum(np.abs(acc["S1"]), np.abs(o["S1"]))
+    sc2 = np.maximum(np.abs(acc["S2"]), np.abs(o["S2"]))
+    assert_close(acc["S1"], o["S1"], rtol, scale=np.maximum(sc1, floor * sc1.max() / rtol), what="S1")
+    assert_close(acc["S2"], o["S2"], rtol, scale=np.maximum(sc2, floor * sc2.max() / rtol), what="S2")
     for m in range(fmap.shape[0]):
         if exact_counts:
             np.testing.assert_array_equal(acc["W"][m], o["W"][m])
