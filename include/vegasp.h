@@ -108,7 +108,7 @@ enum { VP_HIST_WEIGHTED = 0, VP_HIST_LITERAL = 1 };
 /* The problem statement (Sec. 2 and 3): dimension, samples per iteration
  * N_ev, map increments N_g per axis, damping alpha (map, Sec. 2.3) and beta
  * (allocation, Sec. 3 Eq. dh), iteration count, integration box.
- *  dim 1..24 (split precisions: 1..16); n_ev 4 .. 2^31-1; n_g 1 .. 65535;
+ *  dim 1..24 (split precisions: 1..16); n_ev 4 .. 2^31-1; n_g 1 .. 4096;
  *  alpha >= 0; beta >= 0; lower/upper: host arrays of dim or NULL for [0,1].
  *  n_st: stratifications per axis, 0 for the rule of Sec. 3 Eq. Nst_vegasp
  *        (largest n with 4 n^dim <= n_ev); a user value must keep
@@ -203,6 +203,69 @@ vp_status vp_kernel_time(vp_problem* p, int32_t which, double* total_ms, int64_t
  * destroy (synchronising). */
 vp_status vp_integrate(vp_ctx* ctx, const vp_params* params, const vp_integrand* f,
                        vp_result* out);
+
+/* ---------------------------------------------------------------- serving
+ * A server integrates many independent requests on one GPU with continuous
+ * batching (not in the paper; the per-request computation is exactly the
+ * iteration above).  A scheduler thread admits submitted requests while the
+ * device-memory budget and the slot count allow, keeps every admitted
+ * request's state (map, allocation, sums, history) resident, and runs one
+ * batched step at a time: every kernel of one iteration is launched once for
+ * all active requests (sampling once per kernel instantiation).  A request
+ * that arrives while others run is admitted at the next step boundary;
+ * finished requests are retired at once, freeing memory for the queue.
+ * With an unchanged set of active requests a step is replayed from a
+ * captured HIP graph.  Each request computes exactly what vp_integrate
+ * computes for it (the sampling grid is sized per request, independent of
+ * the mix), up to the order of floating-point sums.
+ *
+ * mem_budget_bytes: device bytes all active requests may hold (0: 3/4 of
+ * the device's free memory).  max_slots: most requests active at once.
+ * flags: VP_SERVER_NO_GRAPH launches every step directly.
+ * The server uses its own stream on the context's device. */
+enum { VP_SERVER_NO_GRAPH = 1 };
+
+typedef struct {
+    int64_t steps;          /* batched steps run */
+    int64_t completed;      /* requests finished */
+    int64_t cancelled;
+    int64_t failed;
+    int64_t samples;        /* samples drawn by finished requests */
+    int64_t graph_launches; /* steps replayed from a captured graph */
+    int64_t graph_captures;
+    int32_t active;
+    int32_t pending;
+    int32_t peak_active;
+    int32_t pad;
+    int64_t mem_in_use;
+    int64_t mem_peak;
+} vp_server_stats;
+
+vp_status vp_server_create(vp_ctx* ctx, size_t mem_budget_bytes, int32_t max_slots, int32_t flags,
+                           vp_server** out);
+/* Thread-safe.  Copies params and integrand; fails with VP_ERR_INVALID_ARG
+ * as vp_problem_create would, or VP_ERR_OOM when the request alone exceeds
+ * the budget.  *ticket identifies the request. */
+vp_status vp_server_submit(vp_server* s, const vp_params* params, const vp_integrand* f, uint64_t* ticket);
+/* Thread-safe.  Device bytes the request would hold while admitted (the
+ * figure the memory budget is charged), without submitting it. */
+vp_status vp_server_request_bytes(vp_server* s, const vp_params* params, const vp_integrand* f, size_t* bytes);
+/* Thread-safe.  VP_OK with the result once finished, VP_ERR_NOT_READY
+ * before, VP_ERR_CANCELLED after a cancellation; a request that failed on
+ * the device returns its error. */
+vp_status vp_server_poll(vp_server* s, uint64_t ticket, vp_result* out);
+/* Thread-safe; blocks until the request has finished (or was cancelled). */
+vp_status vp_server_wait(vp_server* s, uint64_t ticket, vp_result* out);
+/* Thread-safe.  Seconds on the server's monotonic clock (0 at creation):
+ * submission, admission (-1 if not yet) and completion (-1 if not yet). */
+vp_status vp_server_times(vp_server* s, uint64_t ticket, double* t_submit, double* t_admit, double* t_finish);
+vp_status vp_server_now(vp_server* s, double* t);
+/* Thread-safe.  A pending request is dropped; an active one is retired at
+ * the next step boundary. */
+vp_status vp_server_cancel(vp_server* s, uint64_t ticket);
+vp_status vp_server_stats_get(vp_server* s, vp_server_stats* out);
+/* Cancels what is left, stops the scheduler and frees everything. */
+vp_status vp_server_destroy(vp_server* s);
 
 #ifdef __cplusplus
 }

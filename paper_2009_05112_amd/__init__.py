@@ -9,7 +9,7 @@ from . import workloads  # noqa: F401  (seeded inputs; no method arithmetic)
 
 def __getattr__(name):
     # the binding loads libvegasp.so on first use and raises if it is missing
-    if name in ("Context", "Problem", "integrate", "VegaspError", "lib", "declared_symbols"):
+    if name in ("Context", "Problem", "Server", "integrate", "VegaspError", "lib", "declared_symbols"):
         from . import _binding
         return getattr(_binding, name)
     raise AttributeError(name)

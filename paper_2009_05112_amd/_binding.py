@@ -51,6 +51,16 @@ class vp_result(C.Structure):
                 ("n_nonfinite", C.c_int64)]
 
 
+class vp_server_stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("completed", C.c_int64), ("cancelled", C.c_int64),
+                ("failed", C.c_int64), ("samples", C.c_int64), ("graph_launches", C.c_int64),
+                ("graph_captures", C.c_int64), ("active", C.c_int32), ("pending", C.c_int32),
+                ("peak_active", C.c_int32), ("pad", C.c_int32), ("mem_in_use", C.c_int64),
+                ("mem_peak", C.c_int64)]
+
+
+VP_SERVER_NO_GRAPH = 1
+
 _lib = None
 
 
@@ -89,6 +99,18 @@ def lib():
             "vp_profile_enable": ([vp, C.c_int32], C.c_int),
             "vp_kernel_time": ([vp, C.c_int32, dp, C.POINTER(C.c_int64)], C.c_int),
             "vp_integrate": ([vp, C.POINTER(vp_params), C.POINTER(vp_integrand), C.POINTER(vp_result)], C.c_int),
+            "vp_server_create": ([vp, C.c_size_t, C.c_int32, C.c_int32, C.POINTER(vp)], C.c_int),
+            "vp_server_submit": ([vp, C.POINTER(vp_params), C.POINTER(vp_integrand), C.POINTER(C.c_uint64)],
+                                 C.c_int),
+            "vp_server_request_bytes": ([vp, C.POINTER(vp_params), C.POINTER(vp_integrand),
+                                         C.POINTER(C.c_size_t)], C.c_int),
+            "vp_server_poll": ([vp, C.c_uint64, C.POINTER(vp_result)], C.c_int),
+            "vp_server_wait": ([vp, C.c_uint64, C.POINTER(vp_result)], C.c_int),
+            "vp_server_times": ([vp, C.c_uint64, dp, dp, dp], C.c_int),
+            "vp_server_now": ([vp, dp], C.c_int),
+            "vp_server_cancel": ([vp, C.c_uint64], C.c_int),
+            "vp_server_stats_get": ([vp, C.POINTER(vp_server_stats)], C.c_int),
+            "vp_server_destroy": ([vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -275,6 +297,82 @@ def integrate(ctx: Context, params, integrand):
     check(lib().vp_integrate(ctx.h, C.byref(pp), C.byref(fi), C.byref(r)), "vp_integrate")
     return {"mean": r.mean, "sdev": r.sdev, "chi2": r.chi2, "dof": r.dof, "n_evals": r.n_evals,
             "n_iter_done": r.n_iter_done, "ties": r.n_near_ties}
+
+
+def _result_dict(r):
+    return {"mean": r.mean, "sdev": r.sdev, "chi2": r.chi2, "dof": r.dof, "n_evals": r.n_evals,
+            "n_iter_done": r.n_iter_done, "ties": r.n_near_ties, "nonfinite": r.n_nonfinite}
+
+
+class Server:
+    """Continuous-batching server (vp_server): submit integrations from any
+    thread, the library's scheduler runs all admitted ones in batched steps."""
+
+    def __init__(self, ctx: Context, mem_budget: int = 0, max_slots: int = 256, graphs: bool = True):
+        self.ctx = ctx
+        self.h = C.c_void_p()
+        flags = 0 if graphs else VP_SERVER_NO_GRAPH
+        check(lib().vp_server_create(ctx.h, int(mem_budget), int(max_slots), flags, C.byref(self.h)),
+              "vp_server_create")
+
+    def submit(self, params, integrand) -> int:
+        pp, fi, keep = marshal(params, integrand)
+        t = C.c_uint64()
+        check(lib().vp_server_submit(self.h, C.byref(pp), C.byref(fi), C.byref(t)), "vp_server_submit")
+        return t.value
+
+    def request_bytes(self, params, integrand) -> int:
+        pp, fi, keep = marshal(params, integrand)
+        n = C.c_size_t()
+        check(lib().vp_server_request_bytes(self.h, C.byref(pp), C.byref(fi), C.byref(n)),
+              "vp_server_request_bytes")
+        return n.value
+
+    def poll(self, ticket: int):
+        """The result once finished, None while it runs."""
+        r = vp_result()
+        st = lib().vp_server_poll(self.h, ticket, C.byref(r))
+        if st == VP_ERR_NOT_READY:
+            return None
+        check(st, "vp_server_poll")
+        return _result_dict(r)
+
+    def wait(self, ticket: int):
+        r = vp_result()
+        check(lib().vp_server_wait(self.h, ticket, C.byref(r)), "vp_server_wait")
+        return _result_dict(r)
+
+    def times(self, ticket: int):
+        """(submitted, admitted, finished) in seconds on the server's clock."""
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        check(lib().vp_server_times(self.h, ticket, C.byref(a), C.byref(b), C.byref(c)), "vp_server_times")
+        return a.value, b.value, c.value
+
+    def now(self) -> float:
+        t = C.c_double()
+        check(lib().vp_server_now(self.h, C.byref(t)))
+        return t.value
+
+    def cancel(self, ticket: int):
+        check(lib().vp_server_cancel(self.h, ticket), "vp_server_cancel")
+
+    def stats(self):
+        st = vp_server_stats()
+        check(lib().vp_server_stats_get(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in vp_server_stats._fields_ if k != "pad"}
+
+    def close(self):
+        if self.h:
+            lib().vp_server_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def declared_symbols() -> list:

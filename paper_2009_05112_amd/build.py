@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvegasp.so")
-SOURCES = ["vp_runtime.hip", "vp_aux.hip", "vp_sample_fp64_gauss.hip", "vp_sample_fp64_corr.hip",
+SOURCES = ["vp_runtime.hip", "vp_server.hip", "vp_aux.hip", "vp_sample_fp64_gauss.hip", "vp_sample_fp64_corr.hip",
            "vp_sample_fp64_generic.hip", "vp_sample_fp32acc.hip", "vp_sample_fp32neu.hip"]
 ARCH = os.environ.get("VEGASP_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -42,11 +42,14 @@ __device__ int64_t block_excl_scan(int64_t v, int64_t* total)
 // ---------------------------------------------------------------- allocation scan
 // Sample offsets of every hypercube: offs[h] = sum_{h' < h} n_h', and
 // offs[n_hc] = N_tot (the samples actually drawn this iteration, Sec. 3).
-__global__ __launch_bounds__(kScanBlock) void k_scan_local(const int32_t* __restrict__ n_h,
-                                                           int64_t n_hc, int64_t* __restrict__ offs,
-                                                           int64_t* __restrict__ bsum)
+__global__ __launch_bounds__(kScanBlock) void k_scan_local(LaunchSet L)
 {
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    VP_REQ_PROLOGUE(L);
+    const int32_t* __restrict__ n_h = q.n_h;
+    const int64_t n_hc = q.n_hc;
+    int64_t* __restrict__ offs = q.offs;
+    int64_t* __restrict__ bsum = q.bsum;
+    const int64_t base = (int64_t)bid * kScanTile + (int64_t)threadIdx.x * kScanPer;
     int64_t v[kScanPer];
     int64_t t = 0;
 #pragma unroll
@@ -63,15 +66,19 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_local(const int32_t* __rest
         if (h < n_hc) offs[h] = run;
         run += v[i];
     }
-    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+    if (threadIdx.x == 0) bsum[bid] = total;
 }
 
 // Exclusive scan of the block totals by one block.  Afterwards the sample
 // offset of hypercube h is loc[h] + bsum[h / kScanTile] (see gofs), and the
 // entry for h = n_hc holds N_tot, the samples drawn this iteration.
-__global__ __launch_bounds__(kScanBlock) void k_scan_top(int64_t* __restrict__ bsum, int64_t nb,
-                                                         int64_t* __restrict__ loc, int64_t n_hc)
+__global__ __launch_bounds__(kScanBlock) void k_scan_top(LaunchSet L)
 {
+    VP_REQ_PROLOGUE(L);
+    int64_t* __restrict__ bsum = q.bsum;
+    int64_t* __restrict__ loc = q.offs;
+    const int64_t n_hc = q.n_hc;
+    const int64_t nb = (n_hc + kScanTile - 1) / kScanTile;
     const int64_t per = (nb + kScanBlock - 1) / kScanBlock;
     const int64_t b0 = (int64_t)threadIdx.x * per;
     int64_t t = 0;
@@ -96,11 +103,14 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_top(int64_t* __restrict__ b
 // ---------------------------------------------------------------- edge fix-up
 // Records arrive sorted by hypercube (wave order); each run of records of
 // one hypercube is summed in record order by the thread holding its first.
-__global__ void k_edge_fixup(const EdgeRec* __restrict__ e, int64_t n_rec, double* __restrict__ S1,
-                             double* __restrict__ S2)
+__global__ void k_edge_fixup(LaunchSet L)
 {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rec;
-         r += (int64_t)gridDim.x * blockDim.x) {
+    VP_REQ_PROLOGUE(L);
+    const EdgeRec* __restrict__ e = q.edges;
+    const int64_t n_rec = 2 * q.n_waves;
+    double* __restrict__ S1 = q.S1;
+    double* __restrict__ S2 = q.S2;
+    for (int64_t r = (int64_t)bid * blockDim.x + threadIdx.x; r < n_rec; r += (int64_t)nblk * blockDim.x) {
         const int64_t h = e[r].h;
         if (h < 0) continue;
         int64_t p = r - 1;
@@ -122,11 +132,15 @@ __global__ void k_edge_fixup(const EdgeRec* __restrict__ e, int64_t n_rec, doubl
 // ---------------------------------------------------------------- training data
 // Sum of the per-workgroup partials in workgroup order; each partial holds the
 // numerator plane H[nbins] followed by the weight plane W[nbins].
-__global__ void k_hist_reduce(const double* __restrict__ part, int n_part, int64_t nbins,
-                              double* __restrict__ H, double* __restrict__ W)
+__global__ void k_hist_reduce(LaunchSet L)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * nbins;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    VP_REQ_PROLOGUE(L);
+    const double* __restrict__ part = q.hist_lds ? q.hist_part : q.hist_glob;
+    const int n_part = q.hist_lds ? q.grid : 1;
+    const int64_t nbins = (int64_t)q.dim * q.n_g;
+    double* __restrict__ H = q.H;
+    double* __restrict__ W = q.W;
+    for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < 2 * nbins; i += (int64_t)nblk * blockDim.x) {
         // four interleaved chains keep four loads in flight; fixed order
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         int p = 0;
@@ -141,6 +155,17 @@ __global__ void k_hist_reduce(const double* __restrict__ part, int n_part, int64
         if (i >= nbins) W[i - nbins] = s;
         else H[i] = s;
     }
+}
+
+// Clears the global training-data bins of requests that accumulate them with
+// global atomics (a fill kernel, so the step can be captured in a graph).
+__global__ void k_hist_zero(LaunchSet L)
+{
+    VP_REQ_PROLOGUE(L);
+    if (q.hist_lds) return;
+    const int64_t n = 2 * (int64_t)q.dim * q.n_g;
+    for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n; i += (int64_t)nblk * blockDim.x)
+        q.hist_glob[i] = 0.0;
 }
 
 __global__ void k_fill_f64(double* __restrict__ x, int64_t n, double v)
@@ -182,16 +207,18 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_est_partial(const int32_t* __restrict__ n_h,
-                                                           const double* __restrict__ S1,
-                                                           const double* __restrict__ S2,
-                                                           int64_t n_hc, double omega, double omega2,
-                                                           double beta, double* __restrict__ part,
-                                                           double* __restrict__ dh)
+__global__ __launch_bounds__(kRedBlock) void k_est_partial(LaunchSet L)
 {
+    VP_REQ_PROLOGUE(L);
+    const int32_t* __restrict__ n_h = q.n_h;
+    const double* __restrict__ S1 = q.S1;
+    const double* __restrict__ S2 = q.S2;
+    const int64_t n_hc = q.n_hc;
+    const double omega = q.omega, omega2 = q.omega2, beta = q.beta;
+    double* __restrict__ part = q.est_part;
+    double* __restrict__ dh = q.dh;
     double I = 0.0, V = 0.0, Sd = 0.0;
-    for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < n_hc;
-         h += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t h = (int64_t)bid * blockDim.x + threadIdx.x; h < n_hc; h += (int64_t)nblk * blockDim.x) {
         double m, var, d;
         const int32_t n = n_h[h];
         hypercube_terms(S1[h], S2[h], n, omega, omega2, beta, &m, &var, &d);
@@ -218,21 +245,27 @@ __global__ __launch_bounds__(kRedBlock) void k_est_partial(const int32_t* __rest
             b = b + red[1][i];
             c = c + red[2][i];
         }
-        part[3 * blockIdx.x + 0] = a;
-        part[3 * blockIdx.x + 1] = b;
-        part[3 * blockIdx.x + 2] = c;
+        part[3 * bid + 0] = a;
+        part[3 * bid + 1] = b;
+        part[3 * bid + 2] = c;
     }
 }
 
 // Totals over the partials (one block, fixed tree order), the iteration's
 // record, and the combination over iterations n_discard..it (Sec. 2.5).
-__global__ __launch_bounds__(kRedBlock) void k_est_final(const double* __restrict__ part, int n_part,
-                                                         DevState* st, double* __restrict__ hist_I,
-                                                         double* __restrict__ hist_V,
-                                                         const int64_t* __restrict__ loc,
-                                                         const int64_t* __restrict__ bbase, int64_t n_hc,
-                                                         int32_t it_slot, int32_t n_discard)
+__global__ __launch_bounds__(kRedBlock) void k_est_final(LaunchSet L)
 {
+    VP_REQ_PROLOGUE(L);
+    const double* __restrict__ part = q.est_part;
+    const int n_part = q.est_blocks;
+    DevState* st = q.st;
+    double* __restrict__ hist_I = q.hist_I;
+    double* __restrict__ hist_V = q.hist_V;
+    const int64_t* __restrict__ loc = q.offs;
+    const int64_t* __restrict__ bbase = q.bsum;
+    const int64_t n_hc = q.n_hc;
+    const int32_t it_slot = q.slot;
+    const int32_t n_discard = q.n_discard;
     double a = 0.0, b = 0.0, c = 0.0;
     const int per = (n_part + kRedBlock - 1) / kRedBlock;
     const int p0 = threadIdx.x * per;
@@ -308,23 +341,26 @@ __global__ __launch_bounds__(kRedBlock) void k_est_final(const double* __restric
 // ---------------------------------------------------------------- reallocation
 // Sec. 3 steps 3-4: n_h = max(2, floor(N_ev d_h / sum d)), or floor(.) + 2.
 // Near-ties (within 1e-9 relative of an integer that decides n_h) are counted.
-__global__ __launch_bounds__(kRedBlock) void k_realloc(int32_t* __restrict__ n_h,
-                                                       const double* __restrict__ dh, int64_t n_hc,
-                                                       double n_ev, int32_t plus2,
-                                                       const DevState* __restrict__ st,
-                                                       unsigned long long* __restrict__ ties)
+__global__ __launch_bounds__(kRedBlock) void k_realloc(LaunchSet L)
 {
+    VP_REQ_PROLOGUE(L);
+    int32_t* __restrict__ n_h = q.n_h;
+    const double* __restrict__ dh = q.dh;
+    const int64_t n_hc = q.n_hc;
+    const double n_ev = q.n_ev;
+    const int32_t plus2 = q.plus2;
+    const DevState* __restrict__ st = q.st;
+    unsigned long long* __restrict__ ties = &q.st->ties;
     const double sumd = st->sumd;
     if (!(sumd > 0.0)) return;
     unsigned long long nt = 0;
     const double first_visible = plus2 ? 1.0 : 3.0;
-    for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < n_hc;
-         h += (int64_t)gridDim.x * blockDim.x) {
-        const double q = (n_ev * dh[h]) / sumd;
-        const double fl = floor(q);
-        const double r = rint(q);
-        const double tol = 1e-9 * (q > 1.0 ? q : 1.0);
-        if (r >= first_visible && fabs(q - r) <= tol) ++nt;
+    for (int64_t h = (int64_t)bid * blockDim.x + threadIdx.x; h < n_hc; h += (int64_t)nblk * blockDim.x) {
+        const double qv = (n_ev * dh[h]) / sumd;
+        const double fl = floor(qv);
+        const double r = rint(qv);
+        const double tol = 1e-9 * (qv > 1.0 ? qv : 1.0);
+        if (r >= first_visible && fabs(qv - r) <= tol) ++nt;
         int64_t n = (int64_t)fl;
         if (plus2) n = n + 2;
         else if (n < 2) n = 2;
@@ -391,19 +427,22 @@ __device__ DD block_dd_sum(DD v, DD* scratch)
 // reaches i delta_d, at the fraction (C_j - i delta_d) / c_{j-1} from its top;
 // here every new point finds its increment by binary search over the prefix
 // sums, kept in double-double so they carry no accumulated rounding.
-__global__ __launch_bounds__(kRefineBlock) void k_refine(double* __restrict__ map,
-                                                         float* __restrict__ map32,
-                                                         const double* __restrict__ H,
-                                                         const double* __restrict__ W, int n_g,
-                                                         double alpha)
+__global__ __launch_bounds__(kRefineBlock) void k_refine(LaunchSet L)
 {
+    VP_REQ_PROLOGUE(L);
+    double* __restrict__ map = q.map;
+    float* __restrict__ map32 = q.map32;
+    const double* __restrict__ H = q.H;
+    const double* __restrict__ W = q.W;
+    const int n_g = q.n_g;
+    const double alpha = q.alpha;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     double* x = reinterpret_cast<double*>(lds_raw);  // [n_g + 1] old grid
     double* c = x + (n_g + 1);                        // [n_g]     d, then compressed d
     double* A = c + n_g;                              // [n_g + 1] smoothed d, then prefix hi
     double* Bv = A + (n_g + 1);                       // [n_g + 1] prefix lo
     __shared__ DD scratch[kRefineBlock];
-    const int mu = blockIdx.x;
+    const int mu = bid;
     const int tid = threadIdx.x;
     double* xm = map + (int64_t)mu * (n_g + 1);
     float* xm32 = map32 + (int64_t)mu * (n_g + 1);
@@ -489,38 +528,46 @@ __global__ __launch_bounds__(kRefineBlock) void k_refine(double* __restrict__ ma
     }
 }
 
-void launch_refine(double* map, float* map32, const double* H, const double* W, int dim, int n_g,
-                   double alpha, hipStream_t s)
+// ---------------------------------------------------------------- advance
+// End of an iteration: the next iteration's Philox counter and history slot.
+__global__ void k_advance(LaunchSet L)
 {
-    const size_t lds = (size_t)(4 * n_g + 3) * sizeof(double);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void*)k_refine, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)((4 * kMaxNg + 3) * sizeof(double)));
-        attr_set = true;
+    VP_REQ_PROLOGUE(L);
+    if (threadIdx.x == 0) {
+        q.s.it += 1;
+        q.slot += 1;
     }
-    hipLaunchKernelGGL(k_refine, dim3(dim), dim3(kRefineBlock), lds, s, map, map32, H, W, n_g, alpha);
 }
 
 // ---------------------------------------------------------------- launchers
-void launch_scan(const int32_t* n_h, int64_t n_hc, int64_t* offs, int64_t* bsum, hipStream_t s)
+static void launch(void (*k)(LaunchSet), const LaunchSet& L, int blocks, int threads, size_t lds,
+                   hipStream_t s)
 {
-    const int64_t nb = (n_hc + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kScanBlock), 0, s, n_h, n_hc, offs, bsum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, bsum, nb, offs, n_hc);
+    if (blocks > 0) hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, s, L);
 }
 
-void launch_edge_fixup(const EdgeRec* e, int64_t n_rec, double* S1, double* S2, hipStream_t s)
+hipError_t aux_init()
 {
-    const int64_t g = (n_rec + 255) / 256;
-    hipLaunchKernelGGL(k_edge_fixup, dim3((unsigned)(g > 0 ? g : 1)), dim3(256), 0, s, e, n_rec, S1, S2);
+    return hipFuncSetAttribute((const void*)k_refine, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)((4 * kMaxNg + 3) * sizeof(double)));
 }
 
-void launch_hist_reduce(const double* part, int n_part, int64_t nbins, double* H, double* W,
-                        hipStream_t s)
+void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin, hipEvent_t sample_end)
 {
-    const int64_t g = (2 * nbins + 255) / 256;
-    hipLaunchKernelGGL(k_hist_reduce, dim3((unsigned)g), dim3(256), 0, s, part, n_part, nbins, H, W);
+    launch(k_scan_local, P.scan_local, P.n_scan_local, kScanBlock, 0, s);
+    launch(k_scan_top, P.one, P.n_one, kScanBlock, 0, s);
+    launch(k_hist_zero, P.hist, P.n_hist, 256, 0, s);
+    if (sample_begin) (void)hipEventRecord(sample_begin, s);
+    for (int g = 0; g < P.n_groups; ++g)
+        P.groups[g].entry.launch(P.groups[g].L, P.groups[g].blocks, P.groups[g].entry.block, P.groups[g].lds, s);
+    if (sample_end) (void)hipEventRecord(sample_end, s);
+    launch(k_edge_fixup, P.fixup, P.n_fixup, 256, 0, s);
+    launch(k_hist_reduce, P.hist, P.n_hist, 256, 0, s);
+    launch(k_est_partial, P.est, P.n_est, kRedBlock, 0, s);
+    launch(k_est_final, P.one, P.n_one, kRedBlock, 0, s);
+    launch(k_realloc, P.est, P.n_est, kRedBlock, 0, s);
+    launch(k_refine, P.refine, P.n_refine, kRefineBlock, (size_t)(4 * P.max_ng + 3) * sizeof(double), s);
+    launch(k_advance, P.one, P.n_one, 64, 0, s);
 }
 
 void launch_fill_f64(double* x, int64_t n, double v, hipStream_t s)
@@ -545,25 +592,5 @@ int est_grid(int64_t n_hc)
     if (g > kRedMaxGrid) g = kRedMaxGrid;
     return (int)(g < 1 ? 1 : g);
 }
-
-void launch_estimate(const int32_t* n_h, const double* S1, const double* S2, int64_t n_hc,
-                     double omega, double omega2, double beta, double* part, double* dh, DevState* st,
-                     double* hist_I, double* hist_V, const int64_t* loc, const int64_t* bbase,
-                     int32_t it_slot, int32_t n_discard, hipStream_t s)
-{
-    const int g = est_grid(n_hc);
-    hipLaunchKernelGGL(k_est_partial, dim3(g), dim3(kRedBlock), 0, s, n_h, S1, S2, n_hc, omega, omega2,
-                       beta, part, dh);
-    hipLaunchKernelGGL(k_est_final, dim3(1), dim3(kRedBlock), 0, s, (const double*)part, g, st, hist_I,
-                       hist_V, loc, bbase, n_hc, it_slot, n_discard);
-}
-
-void launch_realloc(int32_t* n_h, const double* dh, int64_t n_hc, double n_ev, int32_t plus2,
-                    const DevState* st, unsigned long long* ties, hipStream_t s)
-{
-    const int g = est_grid(n_hc);
-    hipLaunchKernelGGL(k_realloc, dim3(g), dim3(kRedBlock), 0, s, n_h, dh, n_hc, n_ev, plus2, st, ties);
-}
-
 
 }  // namespace vp

@@ -24,21 +24,37 @@ struct DevState {
     unsigned long long nonfinite;
 };
 
-void launch_scan(const int32_t* n_h, int64_t n_hc, int64_t* offs, int64_t* bsum, hipStream_t s);
 inline int64_t scan_blocks(int64_t n_hc) { return (n_hc + kScanTile - 1) / kScanTile; }
-void launch_edge_fixup(const EdgeRec* e, int64_t n_rec, double* S1, double* S2, hipStream_t s);
-void launch_hist_reduce(const double* part, int n_part, int64_t nbins, double* H, double* W,
-                        hipStream_t s);
 void launch_fill_f64(double* x, int64_t n, double v, hipStream_t s);
 void launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s);
 int est_grid(int64_t n_hc);
-void launch_estimate(const int32_t* n_h, const double* S1, const double* S2, int64_t n_hc,
-                     double omega, double omega2, double beta, double* part, double* dh, DevState* st,
-                     double* hist_I, double* hist_V, const int64_t* loc, const int64_t* bbase,
-                     int32_t it_slot, int32_t n_discard, hipStream_t s);
-void launch_realloc(int32_t* n_h, const double* dh, int64_t n_hc, double n_ev, int32_t plus2,
-                    const DevState* st, unsigned long long* ties, hipStream_t s);
-void launch_refine(double* map, float* map32, const double* H, const double* W, int dim, int n_g,
-                   double alpha, hipStream_t s);
+
+constexpr int kMaxGroups = 64;
+
+// Sampling launch of one group of requests sharing a kernel instantiation.
+struct SampleGroup {
+    SampleEntry entry;
+    LaunchSet L;
+    int blocks;
+    size_t lds;
+};
+
+// Every launch of one batched iteration over a set of requests: the launch
+// sets share the request table and differ in their workgroup counts.
+struct IterPlan {
+    LaunchSet scan_local, one, hist, fixup, est, refine;
+    int n_scan_local, n_one, n_hist, n_fixup, n_est, n_refine;
+    SampleGroup groups[kMaxGroups];
+    int n_groups;
+    int max_ng;
+};
+
+// Enqueues one iteration of every request of the plan; when given, the two
+// events bracket the sampling launches.
+// One-time per-device set-up of the auxiliary kernels (dynamic LDS limits);
+// done when a context is created, so enqueue_iteration makes no such call and
+// can be captured into a graph.
+hipError_t aux_init();
+void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin, hipEvent_t sample_end);
 
 }  // namespace vp

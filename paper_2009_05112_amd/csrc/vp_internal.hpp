@@ -19,11 +19,12 @@ enum Kind { K_GAUSS_MIX = 1, K_CORR_GAUSS = 2, K_EXP_ABS = 3, K_CONST = 4, K_AFF
 // the largest of 1024 / 768 / 512 threads whose register budget (128 / 168 /
 // 256 VGPRs) holds the kernel body without spilling, i.e. four, three or two
 // waves per SIMD.
-constexpr int sample_block(int prec, int kind, int dim)
+constexpr int sample_block(int prec, int kind, int dim, bool map_lds)
 {
     if (prec == 0) {
         if (kind != K_GAUSS_MIX) return 512;
-        return dim <= 8 ? 1024 : (dim <= 12 ? 768 : 512);
+        if (dim == 8) return map_lds ? 768 : 1024;
+        return dim < 8 ? 1024 : (dim <= 12 ? 768 : 512);
     }
     return dim <= 12 ? 1024 : 768;
 }
@@ -87,7 +88,69 @@ struct SampleArgs {
     int32_t chunk;          // samples per lane per tile
 };
 
-typedef void (*SampleLauncher)(const SampleArgs& a, int grid, int block, size_t lds, hipStream_t s);
+// Scalars every iteration kernel may need about one request (the single
+// problem of the library's problem calls is a batch of one request).
+struct DevState;
+struct ReqArgs {
+    SampleArgs s;           // sampling kernel; s.it is advanced on the device
+    int32_t* n_h;
+    int64_t* offs;
+    int64_t* bsum;
+    double* S1;
+    double* S2;
+    double* dh;
+    double* H;
+    double* W;
+    double* hist_part;
+    double* hist_glob;
+    EdgeRec* edges;
+    double* est_part;
+    double* hist_I;
+    double* hist_V;
+    DevState* st;
+    double* map;
+    float* map32;
+    int64_t n_hc;
+    int64_t n_waves;
+    int32_t dim, n_g;
+    double omega, omega2, alpha, beta, n_ev;
+    int32_t plus2, n_discard;
+    int32_t slot;           // history slot of the current iteration (advanced on the device)
+    int32_t grid;           // sampling workgroups
+    int32_t est_blocks;     // workgroups of the estimate and reallocation passes
+    int32_t hist_lds;
+    int32_t done_flag;      // set on the device when the last iteration of a served request ends
+    int32_t n_iter_target;  // iterations of a served request (0: unbounded)
+};
+
+// One batched launch over n requests: request r's argument record is
+// *reqs[r] (device pointers) and it owns workgroups [bbase[r], bbase[r + 1]).
+struct LaunchSet {
+    ReqArgs* const* reqs;
+    const int32_t* bbase;
+    int32_t n;
+};
+
+__device__ __forceinline__ int find_req(const int32_t* __restrict__ bbase, int n, int b)
+{
+    int lo = 0, hi = n - 1;  // largest r with bbase[r] <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bbase[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+#define VP_REQ_PROLOGUE(L)                                             \
+    const int req_r_ = find_req((L).bbase, (L).n, (int)blockIdx.x);    \
+    ReqArgs& q = *(L).reqs[req_r_];                                    \
+    const int bid = (int)blockIdx.x - (L).bbase[req_r_];               \
+    const int nblk = (L).bbase[req_r_ + 1] - (L).bbase[req_r_];        \
+    (void)bid;                                                         \
+    (void)nblk
+
+typedef void (*SampleLauncher)(const LaunchSet& L, int grid, int block, size_t lds, hipStream_t s);
 typedef int (*SampleOccupancy)(int block, size_t lds);
 struct SampleEntry {
     SampleLauncher launch;

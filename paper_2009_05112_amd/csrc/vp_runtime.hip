@@ -16,17 +16,15 @@
 #include <string>
 #include <vector>
 
-#include "../../include/vegasp.h"
-#include "vp_aux.hpp"
-#include "vp_internal.hpp"
+#include "vp_state.hpp"
 
 using namespace vp;
 
 namespace {
-
 thread_local std::string g_err;
+}
 
-vp_status fail(vp_status s, const char* fmt, ...)
+vp_status vp::fail(vp_status s, const char* fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -36,6 +34,8 @@ vp_status fail(vp_status s, const char* fmt, ...)
     g_err = buf;
     return s;
 }
+
+namespace {
 
 #define VP_HIP(call)                                                                            \
     do {                                                                                        \
@@ -49,71 +49,6 @@ constexpr int kMaxHistory = 65536;
 constexpr uint32_t kStateMagic = 0x56504C53u;  // "SLPV"
 
 }  // namespace
-
-// A context lives until its handle and every problem created on it are
-// destroyed, whatever the order of the destroy calls.
-struct vp_ctx {
-    int device;
-    hipStream_t stream;
-    bool own_stream;
-    int n_cu;
-    size_t lds_max;
-    int refs;
-};
-
-static void ctx_release(vp_ctx* c)
-{
-    if (--c->refs > 0) return;
-    (void)hipSetDevice(c->device);
-    if (c->own_stream) {
-        (void)hipStreamSynchronize(c->stream);
-        (void)hipStreamDestroy(c->stream);
-    }
-    delete c;
-}
-
-struct vp_problem {
-    vp_ctx* ctx;
-    vp_params P;
-    std::vector<double> lower, upper;
-    IntegrandDev fh;
-    int32_t n_st;
-    int64_t n_hc;
-    double omega, omega2, R;
-    int32_t it;  // iteration index of the next iteration
-    int32_t slot;  // history slot of the next iteration
-    // device state
-    IntegrandDev* f_d = nullptr;
-    double* map = nullptr;
-    float* map32 = nullptr;
-    int32_t* n_h = nullptr;
-    int64_t* offs = nullptr;
-    int64_t* bsum = nullptr;
-    double* S1 = nullptr;
-    double* S2 = nullptr;
-    double* dh = nullptr;
-    double* H = nullptr;
-    double* W = nullptr;
-    double* hist_part = nullptr;
-    double* hist_glob = nullptr;
-    EdgeRec* edges = nullptr;
-    double* est_part = nullptr;
-    double* hist_I = nullptr;
-    double* hist_V = nullptr;
-    DevState* st = nullptr;
-    // sampling launch
-    SampleEntry entry;
-    int block, grid, chunk;
-    int hist_lds, map_lds;
-    size_t lds;
-    int64_t n_waves;
-    // profiling
-    bool prof = false;
-    std::vector<hipEvent_t> ev_pending;  // pairs: k1 start, k1 end, it start, it end
-    std::vector<hipEvent_t> ev_free;
-    double t_sample_ms = 0.0, t_iter_ms = 0.0;
-    int64_t n_sample = 0, n_iter = 0;
-};
 
 // ---------------------------------------------------------------- helpers
 SampleEntry vp::sample_entry(int prec, int kind, int dim, bool map_lds)
@@ -158,7 +93,7 @@ static bool pow_le(int64_t n, int dim, int64_t mult, int64_t limit)
     return acc <= limit;
 }
 
-static vp_status validate(const vp_params* P, const vp_integrand* f)
+vp_status vp::validate(const vp_params* P, const vp_integrand* f)
 {
     if (!P || !f) return fail(VP_ERR_INVALID_ARG, "params and integrand are required");
     const int maxd = P->precision == VP_FP64 ? kMaxDim : kMaxDimSplit;
@@ -242,7 +177,7 @@ static hipError_t dalloc(T** p, size_t n)
     return hipMalloc((void**)p, sizeof(T) * (n ? n : 1));
 }
 
-static void free_problem(vp_problem* p)
+void vp::problem_free(vp_problem* p)
 {
     if (!p) return;
     vp_ctx* ctx = p->ctx;
@@ -264,6 +199,7 @@ static void free_problem(vp_problem* p)
     (void)hipFree(p->hist_I);
     (void)hipFree(p->hist_V);
     (void)hipFree(p->st);
+    (void)hipFree(p->d_req);
     for (auto e : p->ev_pending) (void)hipEventDestroy(e);
     for (auto e : p->ev_free) (void)hipEventDestroy(e);
     delete p;
@@ -299,6 +235,82 @@ static vp_status drain_events(vp_problem* p)
     return VP_OK;
 }
 
+// Argument record of a problem for the batched kernels.
+static void fill_req(vp_problem* p)
+{
+    const vp_params& P = p->P;
+    ReqArgs& q = p->req;
+    memset(&q, 0, sizeof q);
+    SampleArgs& a = q.s;
+    a.map = p->map;
+    a.map32 = p->map32;
+    a.offs = p->offs;
+    a.obase = p->bsum;
+    a.S1 = p->S1;
+    a.S2 = p->S2;
+    a.hist_part = p->hist_part;
+    a.hist_glob = p->hist_glob;
+    a.edges = p->edges;
+    a.nonfinite = &p->st->nonfinite;
+    a.f = p->f_d;
+    a.n_hc = p->n_hc;
+    a.n_g = P.n_g;
+    a.n_st = p->n_st;
+    a.R = p->R;
+    a.R32 = (float)P.n_g / (float)p->n_st;
+    a.key0 = (uint32_t)(P.seed & 0xffffffffu);
+    a.key1 = (uint32_t)(P.seed >> 32);
+    a.it = (uint32_t)p->it;
+    a.hist_mode = P.hist_mode;
+    a.hist_lds = p->hist_lds;
+    a.map_lds = p->map_lds;
+    a.chunk = p->chunk;
+    q.n_h = p->n_h;
+    q.offs = p->offs;
+    q.bsum = p->bsum;
+    q.S1 = p->S1;
+    q.S2 = p->S2;
+    q.dh = p->dh;
+    q.H = p->H;
+    q.W = p->W;
+    q.hist_part = p->hist_part;
+    q.hist_glob = p->hist_glob;
+    q.edges = p->edges;
+    q.est_part = p->est_part;
+    q.hist_I = p->hist_I;
+    q.hist_V = p->hist_V;
+    q.st = p->st;
+    q.map = p->map;
+    q.map32 = p->map32;
+    q.n_hc = p->n_hc;
+    q.n_waves = p->n_waves;
+    q.dim = P.dim;
+    q.n_g = P.n_g;
+    q.omega = p->omega;
+    q.omega2 = p->omega2;
+    q.alpha = P.alpha;
+    q.beta = P.beta;
+    q.n_ev = (double)P.n_ev;
+    q.plus2 = P.realloc_plus2;
+    q.n_discard = P.n_discard;
+    q.slot = p->slot;
+    q.grid = p->grid;
+    q.est_blocks = est_grid(p->n_hc);
+    q.hist_lds = p->hist_lds;
+}
+
+// Writes the device copies of the iteration counters.
+static hipError_t push_counters(vp_problem* p)
+{
+    uint32_t it = (uint32_t)p->it;
+    int32_t slot = p->slot;
+    hipError_t e = hipMemcpy((char*)p->d_req + offsetof(ReqArgs, s) + offsetof(SampleArgs, it), &it,
+                             sizeof it, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy((char*)p->d_req + offsetof(ReqArgs, slot), &slot, sizeof slot, hipMemcpyHostToDevice);
+    return e;
+}
+
 // ---------------------------------------------------------------- C ABI
 extern "C" {
 
@@ -327,6 +339,7 @@ vp_status vp_ctx_create(int device, void* hip_stream, vp_ctx** out)
     VP_HIP(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(VP_ERR_INVALID_ARG, "device %d not in 0..%d", device, n - 1);
     VP_HIP(hipSetDevice(device));
+    VP_HIP(aux_init());
     vp_ctx* c = new vp_ctx();
     c->device = device;
     c->refs = 1;
@@ -364,11 +377,86 @@ vp_status vp_ctx_info(vp_ctx* c, int32_t* n_cu, int64_t* lds)
     return VP_OK;
 }
 
-vp_status vp_problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, vp_problem** out)
+}  // extern "C"
+
+// Derived sizes and the sampling launch shape of a problem.
+struct Shape {
+    int32_t n_st;
+    int64_t n_hc;
+    int hist_lds, map_lds;
+    SampleEntry entry;
+    int block, chunk, grid;
+    size_t lds;
+    int64_t n_waves;
+    int32_t hist_cap;
+};
+
+static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
+                               Shape* sh)
+{
+    const int D = P->dim, NG = P->n_g;
+    sh->n_st = P->n_st > 0 ? P->n_st : nst_rule(D, P->n_ev);
+    int64_t nhc = 1;
+    for (int d = 0; d < D; ++d) nhc *= sh->n_st;
+    sh->n_hc = nhc;
+    const int prec = P->precision;
+    const size_t hb = hist_lds_bytes(D, NG), mb = map_lds_bytes(prec, D, NG);
+    sh->hist_lds = hb <= ctx->lds_max ? 1 : 0;
+    if (prec == VP_FP32_NEUMAIER && !sh->hist_lds)
+        return fail(VP_ERR_INVALID_ARG, "compensated sums need dim * n_g * 16 <= %zu bytes of LDS", ctx->lds_max);
+    sh->map_lds = (sh->hist_lds ? hb : 0) + mb <= ctx->lds_max ? 1 : 0;
+    sh->entry = sample_entry(prec, f->kind, D, sh->map_lds != 0);
+    if (!sh->entry.launch && sh->map_lds) {
+        sh->map_lds = 0;
+        sh->entry = sample_entry(prec, f->kind, D, false);
+    }
+    if (!sh->entry.launch) return fail(VP_ERR_INVALID_ARG, "no sampling kernel for dim %d", D);
+    sh->block = sh->entry.block;
+    sh->lds = (sh->hist_lds ? hb : 0) + (sh->map_lds ? mb : 0);
+    sh->chunk = 8;
+    int occ = sh->entry.occupancy(sh->block, sh->lds);
+    if (occ < 1) occ = 1;
+    const int64_t n_tot_max = P->n_ev + 2 * nhc;
+    const int64_t waves_per_block = sh->block / kWave;
+    const int64_t useful_waves = std::max<int64_t>(1, n_tot_max / ((int64_t)kWave * sh->chunk));
+    int64_t grid = (int64_t)ctx->n_cu * occ;
+    grid = std::min<int64_t>(grid, (useful_waves + waves_per_block - 1) / waves_per_block);
+    if (samples_per_wg > 0) grid = std::min<int64_t>(grid, (n_tot_max + samples_per_wg - 1) / samples_per_wg);
+    sh->grid = (int)std::max<int64_t>(1, grid);
+    sh->n_waves = (int64_t)sh->grid * waves_per_block;
+    sh->hist_cap = samples_per_wg > 0 ? std::max<int32_t>(1, P->n_iter) : kMaxHistory;
+    return VP_OK;
+}
+
+vp_status vp::problem_bytes(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
+                            size_t* bytes)
+{
+    vp_status s = validate(P, f);
+    if (s != VP_OK) return s;
+    Shape sh;
+    s = compute_shape(ctx, P, f, samples_per_wg, &sh);
+    if (s != VP_OK) return s;
+    const int64_t D = P->dim, NG = P->n_g, nhc = sh.n_hc, nbins = D * NG;
+    size_t b = sizeof(IntegrandDev) + sizeof(DevState) + sizeof(ReqArgs) + 4096;
+    b += (size_t)D * (NG + 1) * 12;
+    b += (size_t)nhc * (4 + 8 + 8 + 8 + 8) + 8 + (size_t)(scan_blocks(nhc) + 1) * 8;
+    b += (size_t)nbins * 16;
+    b += sh.hist_lds ? (size_t)sh.grid * 2 * nbins * 8 : (size_t)2 * nbins * 8;
+    b += (size_t)2 * sh.n_waves * sizeof(EdgeRec) + (size_t)3 * est_grid(nhc) * 8 + (size_t)sh.hist_cap * 16;
+    *bytes = b;
+    return VP_OK;
+}
+
+
+vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
+                             vp_problem** out)
 {
     if (!ctx || !out) return fail(VP_ERR_INVALID_ARG, "ctx and out are required");
     *out = nullptr;
     vp_status s = validate(P, f);
+    if (s != VP_OK) return s;
+    Shape sh;
+    s = compute_shape(ctx, P, f, samples_per_wg, &sh);
     if (s != VP_OK) return s;
     VP_HIP(hipSetDevice(ctx->device));
     vp_problem* p = new vp_problem();
@@ -386,47 +474,23 @@ vp_status vp_problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand*
     p->P.lower = p->lower.data();
     p->P.upper = p->upper.data();
     fill_integrand(p->fh, f);
-    p->n_st = P->n_st > 0 ? P->n_st : nst_rule(D, P->n_ev);
-    int64_t nhc = 1;
-    for (int d = 0; d < D; ++d) nhc *= p->n_st;
+    p->n_st = sh.n_st;
+    const int64_t nhc = sh.n_hc;
     p->n_hc = nhc;
     p->omega = 1.0 / (double)nhc;
     p->omega2 = p->omega * p->omega;
     p->R = (double)NG / (double)p->n_st;
     p->it = 0;
     p->slot = 0;
-
-    // sampling launch shape
-    const int prec = P->precision;
-    const size_t hb = hist_lds_bytes(D, NG), mb = map_lds_bytes(prec, D, NG);
-    p->hist_lds = hb <= ctx->lds_max ? 1 : 0;
-    if (prec == VP_FP32_NEUMAIER && !p->hist_lds) {
-        free_problem(p);
-        return fail(VP_ERR_INVALID_ARG, "compensated sums need dim * n_g * 16 <= %zu bytes of LDS", ctx->lds_max);
-    }
-    p->map_lds = (p->hist_lds ? hb : 0) + mb <= ctx->lds_max ? 1 : 0;
-    p->entry = sample_entry(prec, f->kind, D, p->map_lds != 0);
-    if (!p->entry.launch && p->map_lds) {
-        p->map_lds = 0;
-        p->entry = sample_entry(prec, f->kind, D, false);
-    }
-    if (!p->entry.launch) {
-        free_problem(p);
-        return fail(VP_ERR_INVALID_ARG, "no sampling kernel for dim %d", D);
-    }
-    p->block = p->entry.block;
-    p->lds = (p->hist_lds ? hb : 0) + (p->map_lds ? mb : 0);
-    const char* env_chunk = getenv("VEGASP_CHUNK");
-    p->chunk = env_chunk ? std::max(1, atoi(env_chunk)) : 8;
-    int occ = p->entry.occupancy(p->block, p->lds);
-    if (occ < 1) occ = 1;
-    const int64_t n_tot_max = P->n_ev + 2 * nhc;
-    const int64_t waves_per_block = p->block / kWave;
-    const int64_t useful_waves = std::max<int64_t>(1, n_tot_max / ((int64_t)kWave * p->chunk));
-    int64_t grid = (int64_t)ctx->n_cu * occ;
-    grid = std::min<int64_t>(grid, (useful_waves + waves_per_block - 1) / waves_per_block);
-    p->grid = (int)std::max<int64_t>(1, grid);
-    p->n_waves = (int64_t)p->grid * waves_per_block;
+    p->hist_lds = sh.hist_lds;
+    p->map_lds = sh.map_lds;
+    p->entry = sh.entry;
+    p->block = sh.block;
+    p->lds = sh.lds;
+    p->chunk = sh.chunk;
+    p->grid = sh.grid;
+    p->n_waves = sh.n_waves;
+    p->hist_cap = sh.hist_cap;
 
     // device state
     const int64_t nbins = (int64_t)D * NG;
@@ -448,12 +512,13 @@ vp_status vp_problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand*
     if (!p->hist_lds) VP_ALLOC(p->hist_glob, 2 * nbins);
     VP_ALLOC(p->edges, 2 * p->n_waves);
     VP_ALLOC(p->est_part, 3 * (int64_t)est_grid(nhc));
-    VP_ALLOC(p->hist_I, kMaxHistory);
-    VP_ALLOC(p->hist_V, kMaxHistory);
+    VP_ALLOC(p->hist_I, p->hist_cap);
+    VP_ALLOC(p->hist_V, p->hist_cap);
     VP_ALLOC(p->st, 1);
+    VP_ALLOC(p->d_req, 1);
 #undef VP_ALLOC
     if (e != hipSuccess) {
-        free_problem(p);
+        problem_free(p);
         return fail(e == hipErrorOutOfMemory ? VP_ERR_OOM : VP_ERR_DEVICE, "allocating problem state: %s",
                     hipGetErrorString(e));
     }
@@ -484,12 +549,27 @@ vp_status vp_problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand*
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(sm);
+    if (e == hipSuccess) {
+        fill_req(p);
+        e = hipMemcpy(p->d_req, &p->req, sizeof(ReqArgs), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) {
+        std::vector<PlanReq> pr = {{&p->req, p->d_req, p->entry, p->lds}};
+        e = p->planner.build(pr, &p->plan);
+    }
     if (e != hipSuccess) {
-        free_problem(p);
+        problem_free(p);
         return fail(VP_ERR_DEVICE, "initialising problem state: %s", hipGetErrorString(e));
     }
     *out = p;
     return VP_OK;
+}
+
+extern "C" {
+
+vp_status vp_problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, vp_problem** out)
+{
+    return problem_create(ctx, P, f, 0, out);
 }
 
 vp_status vp_problem_destroy(vp_problem* p)
@@ -497,7 +577,7 @@ vp_status vp_problem_destroy(vp_problem* p)
     if (!p) return VP_OK;
     (void)hipSetDevice(p->ctx->device);
     (void)hipStreamSynchronize(p->ctx->stream);
-    free_problem(p);
+    problem_free(p);
     return VP_OK;
 }
 
@@ -512,70 +592,23 @@ vp_status vp_problem_info(vp_problem* p, int32_t* n_st, int64_t* n_hc)
 vp_status vp_iterate(vp_problem* p, int32_t n_iter)
 {
     if (!p || n_iter < 0) return fail(VP_ERR_INVALID_ARG, "problem is NULL or n_iter < 0");
-    if (p->slot + n_iter > kMaxHistory) return fail(VP_ERR_STATE, "more than %d iterations", kMaxHistory);
+    if (p->slot + n_iter > p->hist_cap) return fail(VP_ERR_STATE, "more than %d iterations", p->hist_cap);
     VP_HIP(hipSetDevice(p->ctx->device));
     hipStream_t s = p->ctx->stream;
-    const vp_params& P = p->P;
-    const int D = P.dim, NG = P.n_g;
-    const int64_t nbins = (int64_t)D * NG;
     for (int32_t r = 0; r < n_iter; ++r) {
-        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
         if (p->prof) {
-            e0 = take_event(p);
-            e1 = take_event(p);
-            e2 = take_event(p);
-            e3 = take_event(p);
+            hipEvent_t e0 = take_event(p), e1 = take_event(p), e2 = take_event(p), e3 = take_event(p);
             VP_HIP(hipEventRecord(e2, s));
-        }
-        // 1. sample offsets and N_tot
-        launch_scan(p->n_h, p->n_hc, p->offs, p->bsum, s);
-        if (!p->hist_lds) launch_fill_f64(p->hist_glob, 2 * nbins, 0.0, s);
-        // 2. fused sampling, map, integrand, sums and training data
-        SampleArgs a;
-        a.map = p->map;
-        a.map32 = p->map32;
-        a.offs = p->offs;
-        a.obase = p->bsum;
-        a.S1 = p->S1;
-        a.S2 = p->S2;
-        a.hist_part = p->hist_part;
-        a.hist_glob = p->hist_glob;
-        a.edges = p->edges;
-        a.nonfinite = &p->st->nonfinite;
-        a.f = p->f_d;
-        a.n_hc = p->n_hc;
-        a.n_g = NG;
-        a.n_st = p->n_st;
-        a.R = p->R;
-        a.R32 = (float)NG / (float)p->n_st;
-        a.key0 = (uint32_t)(P.seed & 0xffffffffu);
-        a.key1 = (uint32_t)(P.seed >> 32);
-        a.it = (uint32_t)p->it;
-        a.hist_mode = P.hist_mode;
-        a.hist_lds = p->hist_lds;
-        a.map_lds = p->map_lds;
-        a.chunk = p->chunk;
-        if (p->prof) VP_HIP(hipEventRecord(e0, s));
-        p->entry.launch(a, p->grid, p->block, p->lds, s);
-        if (p->prof) VP_HIP(hipEventRecord(e1, s));
-        VP_HIP(hipGetLastError());
-        launch_edge_fixup(p->edges, 2 * p->n_waves, p->S1, p->S2, s);
-        if (p->hist_lds) launch_hist_reduce(p->hist_part, p->grid, nbins, p->H, p->W, s);
-        else launch_hist_reduce(p->hist_glob, 1, nbins, p->H, p->W, s);
-        // 3. iteration estimate and combination
-        launch_estimate(p->n_h, p->S1, p->S2, p->n_hc, p->omega, p->omega2, P.beta, p->est_part, p->dh,
-                        p->st, p->hist_I, p->hist_V, p->offs, p->bsum, p->slot, P.n_discard, s);
-        // 4. reallocation and 5. refinement, both for the next iteration
-        launch_realloc(p->n_h, p->dh, p->n_hc, (double)P.n_ev, P.realloc_plus2, p->st, &p->st->ties, s);
-        launch_refine(p->map, p->map32, p->H, p->W, D, NG, P.alpha, s);
-        VP_HIP(hipGetLastError());
-        if (p->prof) {
+            enqueue_iteration(p->plan, s, e0, e1);
             VP_HIP(hipEventRecord(e3, s));
             p->ev_pending.push_back(e0);
             p->ev_pending.push_back(e1);
             p->ev_pending.push_back(e2);
             p->ev_pending.push_back(e3);
+        } else {
+            enqueue_iteration(p->plan, s, nullptr, nullptr);
         }
+        VP_HIP(hipGetLastError());
         p->it += 1;
         p->slot += 1;
     }
@@ -669,7 +702,9 @@ vp_status vp_iteration_get(vp_problem* p, int32_t* it)
 vp_status vp_iteration_set(vp_problem* p, int32_t it)
 {
     if (!p || it < 0) return fail(VP_ERR_INVALID_ARG, "problem is NULL or it < 0");
+    VP_HIP(hipStreamSynchronize(p->ctx->stream));
     p->it = it;
+    VP_HIP(push_counters(p));
     return VP_OK;
 }
 
@@ -735,7 +770,7 @@ vp_status vp_state_import(vp_problem* p, const void* buf, size_t size)
     if (hd.dim != p->P.dim || hd.n_g != p->P.n_g || hd.n_hc != p->n_hc)
         return fail(VP_ERR_INVALID_ARG, "state shape (dim %d, n_g %d, n_hc %lld) does not match the problem",
                     hd.dim, hd.n_g, (long long)hd.n_hc);
-    if (hd.slot < 0 || hd.slot > kMaxHistory || hd.it < 0) return fail(VP_ERR_INVALID_ARG, "bad iteration counters");
+    if (hd.slot < 0 || hd.slot > p->hist_cap || hd.it < 0) return fail(VP_ERR_INVALID_ARG, "bad iteration counters");
     const size_t nm = (size_t)p->P.dim * (p->P.n_g + 1);
     const size_t need = sizeof hd + nm * sizeof(double) + (size_t)p->n_hc * sizeof(int32_t) +
                         2 * (size_t)hd.slot * sizeof(double);
@@ -760,6 +795,7 @@ vp_status vp_state_import(vp_problem* p, const void* buf, size_t size)
     VP_HIP(hipMemcpy(p->st, &st, sizeof st, hipMemcpyHostToDevice));
     p->it = hd.it;
     p->slot = hd.slot;
+    VP_HIP(push_counters(p));
     return VP_OK;
 }
 

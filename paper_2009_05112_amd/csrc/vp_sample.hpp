@@ -492,8 +492,10 @@ __device__ __forceinline__ float sample_fp32(const SampleArgs& a, const MapPair3
 // KIND fixes the integrand at compile time (K_GAUSS_MIX, K_CORR_GAUSS), or is
 // 0 for the generic kernel that dispatches on the integrand's kind at run time.
 template <int D, int PREC, bool MAPLDS, int KIND>
-__global__ __launch_bounds__(sample_block(PREC, KIND, D)) void k_sample(SampleArgs a)
+__global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(LaunchSet L)
 {
+    VP_REQ_PROLOGUE(L);
+    const SampleArgs a = q.s;
     typedef typename AccOf<PREC>::type Acc;
     typedef typename std::conditional<PREC == P_FP64, double, float>::type MapT;
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -521,8 +523,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D)) void k_sample(SampleAr
 
     const int lane = threadIdx.x & (kWave - 1);
     const int waves_per_block = blockDim.x / kWave;
-    const int64_t wave = (int64_t)blockIdx.x * waves_per_block + (threadIdx.x / kWave);
-    const int64_t n_waves = (int64_t)gridDim.x * waves_per_block;
+    const int64_t wave = (int64_t)bid * waves_per_block + (threadIdx.x / kWave);
+    const int64_t n_waves = (int64_t)nblk * waves_per_block;
     const int64_t* __restrict__ offs = a.offs;
     const int64_t* __restrict__ ob = a.obase;
     const int64_t n_hc = a.n_hc;
@@ -763,7 +765,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D)) void k_sample(SampleAr
 
     __syncthreads();
     if (a.hist_lds) {
-        double* out = a.hist_part + (size_t)blockIdx.x * 2 * nbins;
+        double* out = a.hist_part + (size_t)bid * 2 * nbins;
         if constexpr (PREC == P_FP32_NEUMAIER) {
             for (int i = threadIdx.x; i < nbins; i += blockDim.x) {
                 out[i] = (double)lds_histf[i] + (double)lds_histf[nbins + i];
@@ -776,9 +778,9 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D)) void k_sample(SampleAr
 }
 
 template <int D, int PREC, bool MAPLDS, int KIND>
-void launch_sample(const SampleArgs& a, int grid, int block, size_t lds, hipStream_t s)
+void launch_sample(const LaunchSet& L, int grid, int block, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sample<D, PREC, MAPLDS, KIND>), dim3(grid), dim3(block), lds, s, a);
+    hipLaunchKernelGGL((k_sample<D, PREC, MAPLDS, KIND>), dim3(grid), dim3(block), lds, s, L);
 }
 
 template <int D, int PREC, bool MAPLDS, int KIND>
@@ -799,7 +801,7 @@ SampleEntry make_entry()
     SampleEntry e;
     e.launch = launch_sample<D, PREC, MAPLDS, KIND>;
     e.occupancy = sample_occupancy<D, PREC, MAPLDS, KIND>;
-    e.block = sample_block(PREC, KIND, D);
+    e.block = sample_block(PREC, KIND, D, MAPLDS);
     return e;
 }
 

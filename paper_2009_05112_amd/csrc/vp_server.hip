@@ -1,0 +1,452 @@
+// vp_server.hip -- continuous-batching server for many vegas+ integrations.
+//
+// The scheduler thread owns the GPU work.  Each loop turn:
+//  1. admits queued requests in arrival order while the device-memory budget
+//     and the slot count allow (a request's footprint is known before it is
+//     created), creating their device state on the server's stream;
+//  2. if the set of active requests changed, builds the batched iteration
+//     plan (one launch per kernel for all requests, one sampling launch per
+//     kernel instantiation) and drops the captured graph;
+//  3. runs one step -- one iteration of every active request -- replaying the
+//     step's captured HIP graph when the set is unchanged (the per-request
+//     Philox iteration and history slot live in device memory and are
+//     advanced by the step itself, so a replay is the next iteration);
+//  4. retires requests that reached their iteration count (or were
+//     cancelled): copies their result, frees their memory, wakes waiters.
+// Requests submitted while a step runs are admitted at the next turn, so the
+// GPU work of new and old requests overlaps in the same launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "vp_state.hpp"
+
+using namespace vp;
+
+namespace {
+
+// Sampling workgroups of a served request hold about this many samples, so a
+// step of many small requests does not pay per-workgroup LDS set-up and
+// flush for nearly empty workgroups.
+constexpr int64_t kServeSamplesPerWG = 65536;
+
+enum ReqState { R_PENDING = 0, R_ACTIVE = 1, R_DONE = 2, R_CANCELLED = 3, R_FAILED = 4 };
+
+struct ServedReq {
+    uint64_t ticket = 0;
+    vp_params P;
+    std::vector<double> lower, upper;
+    vp_integrand f;
+    std::vector<double> centers, coefs, amps, chol;
+    size_t bytes = 0;
+    int state = R_PENDING;
+    bool cancel = false;
+    double t_submit = -1, t_admit = -1, t_finish = -1;
+    vp_problem* prob = nullptr;
+    int iters_left = 0;
+    vp_result res;
+    vp_status status = VP_OK;
+    std::string err;
+};
+
+}  // namespace
+
+struct vp_server {
+    vp_ctx* ctx = nullptr;  // own stream on the caller's device
+    size_t budget = 0;
+    int max_slots = 0;
+    bool graphs = true;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<ServedReq*> pending;
+    std::vector<ServedReq*> active;  // scheduler thread only
+    std::unordered_map<uint64_t, ServedReq*> all;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread th;
+    size_t mem_used = 0, mem_peak = 0;
+    vp_server_stats st;
+    PlanBuilder planner;
+    IterPlan plan;
+    bool plan_valid = false;
+    hipGraphExec_t gexec = nullptr;
+    std::chrono::steady_clock::time_point t0;
+
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+static void copy_request(ServedReq* r, const vp_params* P, const vp_integrand* f)
+{
+    r->P = *P;
+    if (P->lower) {
+        r->lower.assign(P->lower, P->lower + P->dim);
+        r->upper.assign(P->upper, P->upper + P->dim);
+        r->P.lower = r->lower.data();
+        r->P.upper = r->upper.data();
+    }
+    r->f = *f;
+    const int D = f->dim, K = f->n_terms;
+    auto cp = [](std::vector<double>& dst, const double* src, size_t n) -> const double* {
+        if (!src) return nullptr;
+        dst.assign(src, src + n);
+        return dst.data();
+    };
+    size_t nc = 0;
+    if (f->kind == VP_F_GAUSS_MIX || f->kind == VP_F_EXP_ABS || f->kind == VP_F_BALLS) nc = (size_t)K * D;
+    else if (f->kind == VP_F_CORR_GAUSS) nc = D;
+    else if (f->kind == VP_F_AFFINE) nc = D + 1;
+    r->f.centers = cp(r->centers, f->centers, nc);
+    const size_t nk = (f->kind == VP_F_GAUSS_MIX || f->kind == VP_F_EXP_ABS || f->kind == VP_F_BALLS) ? K : 0;
+    r->f.coefs = cp(r->coefs, f->coefs, nk);
+    r->f.amps = cp(r->amps, f->amps, nk);
+    r->f.chol = f->kind == VP_F_CORR_GAUSS ? cp(r->chol, f->chol, (size_t)D * D) : nullptr;
+}
+
+static void drop_graph(vp_server* s)
+{
+    if (s->gexec) {
+        (void)hipGraphExecDestroy(s->gexec);
+        s->gexec = nullptr;
+    }
+}
+
+// Enqueues one step; returns false on a device error.
+static bool run_step(vp_server* s)
+{
+    hipStream_t st = s->ctx->stream;
+    if (s->graphs) {
+        if (!s->gexec) {
+            hipGraph_t g = nullptr;
+            if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+            enqueue_iteration(s->plan, st, nullptr, nullptr);
+            if (hipStreamEndCapture(st, &g) != hipSuccess) return false;
+            hipError_t e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                s->gexec = nullptr;
+                return false;
+            }
+            s->st.graph_captures += 1;
+        }
+        if (hipGraphLaunch(s->gexec, st) != hipSuccess) return false;
+        s->st.graph_launches += 1;
+    } else {
+        enqueue_iteration(s->plan, st, nullptr, nullptr);
+        if (hipGetLastError() != hipSuccess) return false;
+    }
+    return hipStreamSynchronize(st) == hipSuccess;
+}
+
+static void retire(vp_server* s, ServedReq* r, int state)
+{
+    if (r->prob) {
+        problem_free(r->prob);
+        r->prob = nullptr;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->mem_used -= r->bytes;
+    r->state = state;
+    r->t_finish = s->now();
+    if (state == R_DONE) {
+        s->st.completed += 1;
+        s->st.samples += r->res.n_evals;
+    } else if (state == R_CANCELLED) {
+        s->st.cancelled += 1;
+    } else {
+        s->st.failed += 1;
+    }
+    s->cv_done.notify_all();
+}
+
+static void scheduler(vp_server* s)
+{
+    (void)hipSetDevice(s->ctx->device);
+    for (;;) {
+        std::vector<ServedReq*> admit;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            for (;;) {
+                while (!s->pending.empty() && (int)(s->active.size() + admit.size()) < s->max_slots) {
+                    ServedReq* r = s->pending.front();
+                    if (r->cancel) {
+                        s->pending.pop_front();
+                        r->state = R_CANCELLED;
+                        r->t_finish = s->now();
+                        s->st.cancelled += 1;
+                        s->cv_done.notify_all();
+                        continue;
+                    }
+                    if (s->mem_used + r->bytes > s->budget) break;  // wait for memory
+                    s->pending.pop_front();
+                    s->mem_used += r->bytes;
+                    s->mem_peak = std::max(s->mem_peak, s->mem_used);
+                    r->state = R_ACTIVE;
+                    r->t_admit = s->now();
+                    admit.push_back(r);
+                }
+                if (!s->active.empty() || !admit.empty()) break;
+                if (s->stop) return;
+                s->cv_work.wait(lk);
+            }
+        }
+        bool changed = false;
+        for (ServedReq* r : admit) {
+            vp_status st = problem_create(s->ctx, &r->P, &r->f, kServeSamplesPerWG, &r->prob);
+            if (st != VP_OK) {
+                r->status = st;
+                r->err = vp_last_error();
+                retire(s, r, R_FAILED);
+                continue;
+            }
+            r->iters_left = r->P.n_iter;
+            s->active.push_back(r);
+            changed = true;
+        }
+        // cancellations of active requests, and requests with nothing to do
+        for (size_t i = 0; i < s->active.size();) {
+            ServedReq* r = s->active[i];
+            bool cancel;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                cancel = r->cancel;
+            }
+            if (cancel || r->iters_left <= 0) {
+                if (!cancel) r->status = vp_result_get(r->prob, &r->res, nullptr, nullptr, 0);
+                s->active.erase(s->active.begin() + i);
+                retire(s, r, cancel ? R_CANCELLED : R_DONE);
+                changed = true;
+            } else {
+                ++i;
+            }
+        }
+        if (s->active.empty()) continue;
+        if (changed || !s->plan_valid) {
+            std::vector<PlanReq> pr;
+            pr.reserve(s->active.size());
+            for (ServedReq* r : s->active) pr.push_back({&r->prob->req, r->prob->d_req, r->prob->entry, r->prob->lds});
+            drop_graph(s);
+            s->plan_valid = s->planner.build(pr, &s->plan) == hipSuccess;
+            if (!s->plan_valid) {
+                for (ServedReq* r : s->active) {
+                    r->status = VP_ERR_DEVICE;
+                    r->err = "building the batched plan failed";
+                    retire(s, r, R_FAILED);
+                }
+                s->active.clear();
+                continue;
+            }
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->st.peak_active = std::max<int32_t>(s->st.peak_active, (int32_t)s->active.size());
+        }
+        const bool ok = run_step(s);
+        s->st.steps += 1;
+        for (size_t i = 0; i < s->active.size();) {
+            ServedReq* r = s->active[i];
+            if (!ok) {
+                r->status = VP_ERR_DEVICE;
+                r->err = "device error during a batched step";
+                s->active.erase(s->active.begin() + i);
+                retire(s, r, R_FAILED);
+                continue;
+            }
+            r->prob->it += 1;
+            r->prob->slot += 1;
+            r->iters_left -= 1;
+            if (r->iters_left <= 0) {
+                r->status = vp_result_get(r->prob, &r->res, nullptr, nullptr, 0);
+                if (r->status != VP_OK) r->err = vp_last_error();
+                s->active.erase(s->active.begin() + i);
+                retire(s, r, r->status == VP_OK || r->status == VP_ERR_NUMERIC ? R_DONE : R_FAILED);
+                s->plan_valid = false;
+                continue;
+            }
+            ++i;
+        }
+        if (!ok) s->plan_valid = false;
+    }
+}
+
+extern "C" {
+
+vp_status vp_server_create(vp_ctx* ctx, size_t mem_budget_bytes, int32_t max_slots, int32_t flags,
+                           vp_server** out)
+{
+    if (!ctx || !out || max_slots < 1) return fail(VP_ERR_INVALID_ARG, "ctx, out and max_slots >= 1 are required");
+    *out = nullptr;
+    vp_ctx* own = nullptr;
+    vp_status st = vp_ctx_create(ctx->device, nullptr, &own);
+    if (st != VP_OK) return st;
+    if (mem_budget_bytes == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            vp_ctx_destroy(own);
+            return fail(VP_ERR_DEVICE, "hipMemGetInfo failed");
+        }
+        mem_budget_bytes = fr / 4 * 3;
+    }
+    vp_server* s = new vp_server();
+    s->ctx = own;
+    s->budget = mem_budget_bytes;
+    s->max_slots = max_slots;
+    s->graphs = (flags & VP_SERVER_NO_GRAPH) == 0;
+    memset(&s->st, 0, sizeof s->st);
+    s->t0 = std::chrono::steady_clock::now();
+    s->th = std::thread(scheduler, s);
+    *out = s;
+    return VP_OK;
+}
+
+vp_status vp_server_submit(vp_server* s, const vp_params* P, const vp_integrand* f, uint64_t* ticket)
+{
+    if (!s || !ticket) return fail(VP_ERR_INVALID_ARG, "server and ticket are required");
+    vp_status st = validate(P, f);
+    if (st != VP_OK) return st;
+    size_t bytes = 0;
+    st = problem_bytes(s->ctx, P, f, kServeSamplesPerWG, &bytes);
+    if (st != VP_OK) return st;
+    if (bytes > s->budget)
+        return fail(VP_ERR_OOM, "request needs %zu device bytes, the budget is %zu", bytes, s->budget);
+    ServedReq* r = new ServedReq();
+    copy_request(r, P, f);
+    r->bytes = bytes;
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->ticket = s->next_ticket++;
+    r->t_submit = s->now();
+    s->all[r->ticket] = r;
+    s->pending.push_back(r);
+    s->cv_work.notify_one();
+    *ticket = r->ticket;
+    return VP_OK;
+}
+
+vp_status vp_server_request_bytes(vp_server* s, const vp_params* P, const vp_integrand* f, size_t* bytes)
+{
+    if (!s || !bytes) return fail(VP_ERR_INVALID_ARG, "server and bytes are required");
+    vp_status st = validate(P, f);
+    if (st != VP_OK) return st;
+    return problem_bytes(s->ctx, P, f, kServeSamplesPerWG, bytes);
+}
+
+static vp_status result_of(ServedReq* r, vp_result* out)
+{
+    if (r->state == R_CANCELLED) return fail(VP_ERR_CANCELLED, "request %llu was cancelled", (unsigned long long)r->ticket);
+    if (r->state == R_FAILED) return fail(r->status, "request %llu failed: %s", (unsigned long long)r->ticket, r->err.c_str());
+    if (r->state != R_DONE) return fail(VP_ERR_NOT_READY, "request %llu is not finished", (unsigned long long)r->ticket);
+    if (out) *out = r->res;
+    if (r->status != VP_OK) return fail(r->status, "request %llu: %s", (unsigned long long)r->ticket, r->err.c_str());
+    return VP_OK;
+}
+
+vp_status vp_server_poll(vp_server* s, uint64_t ticket, vp_result* out)
+{
+    if (!s) return fail(VP_ERR_INVALID_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(VP_ERR_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    return result_of(it->second, out);
+}
+
+vp_status vp_server_wait(vp_server* s, uint64_t ticket, vp_result* out)
+{
+    if (!s) return fail(VP_ERR_INVALID_ARG, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(VP_ERR_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    ServedReq* r = it->second;
+    s->cv_done.wait(lk, [&] { return r->state >= R_DONE; });
+    return result_of(r, out);
+}
+
+vp_status vp_server_times(vp_server* s, uint64_t ticket, double* t_submit, double* t_admit, double* t_finish)
+{
+    if (!s) return fail(VP_ERR_INVALID_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(VP_ERR_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    if (t_submit) *t_submit = it->second->t_submit;
+    if (t_admit) *t_admit = it->second->t_admit;
+    if (t_finish) *t_finish = it->second->t_finish;
+    return VP_OK;
+}
+
+vp_status vp_server_now(vp_server* s, double* t)
+{
+    if (!s || !t) return fail(VP_ERR_INVALID_ARG, "server and t are required");
+    *t = s->now();
+    return VP_OK;
+}
+
+vp_status vp_server_cancel(vp_server* s, uint64_t ticket)
+{
+    if (!s) return fail(VP_ERR_INVALID_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(VP_ERR_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    ServedReq* r = it->second;
+    if (r->state >= R_DONE) return VP_OK;
+    r->cancel = true;
+    if (r->state == R_PENDING) {
+        auto pit = std::find(s->pending.begin(), s->pending.end(), r);
+        if (pit != s->pending.end()) s->pending.erase(pit);
+        r->state = R_CANCELLED;
+        r->t_finish = s->now();
+        s->st.cancelled += 1;
+        s->cv_done.notify_all();
+    }
+    s->cv_work.notify_one();
+    return VP_OK;
+}
+
+vp_status vp_server_stats_get(vp_server* s, vp_server_stats* out)
+{
+    if (!s || !out) return fail(VP_ERR_INVALID_ARG, "server and out are required");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->st;
+    out->pending = (int32_t)s->pending.size();
+    int32_t act = 0;
+    for (auto& kv : s->all)
+        if (kv.second->state == R_ACTIVE) ++act;
+    out->active = act;
+    out->mem_in_use = (int64_t)s->mem_used;
+    out->mem_peak = (int64_t)s->mem_peak;
+    return VP_OK;
+}
+
+vp_status vp_server_destroy(vp_server* s)
+{
+    if (!s) return VP_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto& kv : s->all)
+            if (kv.second->state < R_DONE) kv.second->cancel = true;
+        for (ServedReq* r : s->pending) {
+            r->state = R_CANCELLED;
+            r->t_finish = s->now();
+        }
+        s->pending.clear();
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->th.joinable()) s->th.join();
+    drop_graph(s);
+    for (auto& kv : s->all) {
+        if (kv.second->prob) problem_free(kv.second->prob);
+        delete kv.second;
+    }
+    vp_ctx_destroy(s->ctx);
+    delete s;
+    return VP_OK;
+}
+
+}  // extern "C"

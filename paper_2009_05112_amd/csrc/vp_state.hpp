@@ -1,0 +1,107 @@
+// vp_state.hpp -- host-side objects of the library (context, problem) and
+// the internal calls the serving loop shares with the problem calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/vegasp.h"
+#include "vp_aux.hpp"
+#include "vp_internal.hpp"
+#include "vp_plan.hpp"
+
+using vp::DevState;
+using vp::EdgeRec;
+using vp::IntegrandDev;
+using vp::IterPlan;
+using vp::PlanBuilder;
+using vp::ReqArgs;
+using vp::SampleEntry;
+
+// A context lives until its handle and every problem created on it are
+// destroyed, whatever the order of the destroy calls.
+struct vp_ctx {
+    int device;
+    hipStream_t stream;
+    bool own_stream;
+    int n_cu;
+    size_t lds_max;
+    int refs;
+};
+
+inline void ctx_release(vp_ctx* c)
+{
+    if (--c->refs > 0) return;
+    (void)hipSetDevice(c->device);
+    if (c->own_stream) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipStreamDestroy(c->stream);
+    }
+    delete c;
+}
+
+struct vp_problem {
+    vp_ctx* ctx;
+    vp_params P;
+    std::vector<double> lower, upper;
+    IntegrandDev fh;
+    int32_t n_st;
+    int64_t n_hc;
+    double omega, omega2, R;
+    int32_t it;  // iteration index of the next iteration
+    int32_t slot;  // history slot of the next iteration
+    // device state
+    IntegrandDev* f_d = nullptr;
+    double* map = nullptr;
+    float* map32 = nullptr;
+    int32_t* n_h = nullptr;
+    int64_t* offs = nullptr;
+    int64_t* bsum = nullptr;
+    double* S1 = nullptr;
+    double* S2 = nullptr;
+    double* dh = nullptr;
+    double* H = nullptr;
+    double* W = nullptr;
+    double* hist_part = nullptr;
+    double* hist_glob = nullptr;
+    EdgeRec* edges = nullptr;
+    double* est_part = nullptr;
+    double* hist_I = nullptr;
+    double* hist_V = nullptr;
+    DevState* st = nullptr;
+    ReqArgs req;                 // host copy of the argument record
+    ReqArgs* d_req = nullptr;    // device table of one record
+    PlanBuilder planner;
+    IterPlan plan;
+    // sampling launch
+    SampleEntry entry;
+    int block, grid, chunk;
+    int hist_lds, map_lds;
+    size_t lds;
+    int64_t n_waves;
+    int32_t hist_cap;            // capacity of the estimate history
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pending;  // pairs: k1 start, k1 end, it start, it end
+    std::vector<hipEvent_t> ev_free;
+    double t_sample_ms = 0.0, t_iter_ms = 0.0;
+    int64_t n_sample = 0, n_iter = 0;
+};
+
+
+namespace vp {
+
+vp_status fail(vp_status s, const char* fmt, ...);
+vp_status validate(const vp_params* P, const vp_integrand* f);
+// samples_per_wg > 0 sizes the sampling grid to about that many samples per
+// workgroup (serving: many requests share the GPU); 0 fills the GPU.
+vp_status problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
+                         vp_problem** out);
+// Device bytes problem_create would allocate for these parameters.
+vp_status problem_bytes(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
+                        size_t* bytes);
+void problem_free(vp_problem* p);
+
+}  // namespace vp

@@ -1,0 +1,214 @@
+"""Serving loop: continuous batching of many integrations on one GPU.
+
+Each request's result depends only on its own parameters: the sampling grid
+of a served request is sized from the request alone, and every batched
+kernel maps a workgroup to exactly one request.  So a request gives the same
+bits alone and in any mix, submitted at once or arriving while others run,
+replayed from a captured graph or launched directly.  Against the
+single-problem path (vp_integrate) the workgroup split differs, so the sums
+are added in another order: those agree to rounding.
+"""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2009_05112_amd import _binding as B
+from paper_2009_05112_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("mean", "sdev", "chi2", "dof", "n_evals", "n_iter_done", "ties")
+
+
+def small_mix():
+    """Gaussian mixtures of the served-batch shape at small N_ev, correlated
+    Gaussians of the stream shape, and the two split precisions."""
+    reqs = [(r.params, r.integrand) for r in
+            W.served_batch(n_req=10, seed=3, nev_log=(3.5, 4.7), n_iter=4, n_g=500)]
+    for r in W.served_stream(n_req=4, rate=0.0, seed=5, nev_log=(4.0, 4.5), it_range=(2, 4), n_g=300):
+        reqs.append((r.params, r.integrand))
+    p, f = W.cfg_diag_d8(n_ev=60_000, precision="fp32_acc64")
+    reqs.append((p.with_(n_iter=3, seed=77), f))
+    p, f = W.cfg_diag_d8(n_ev=40_000, precision="fp32_neumaier")
+    reqs.append((p.with_(n_iter=3, seed=78, hist_mode="literal"), f))
+    return reqs
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def mix():
+    return small_mix()
+
+
+@pytest.fixture(scope="module")
+def alone(ctx, mix):
+    """Each request run alone on a server (submitted after the previous one
+    finished)."""
+    s = B.Server(ctx)
+    out = []
+    for p, f in mix:
+        print(f"alone: D={p.dim} n_ev={p.n_ev} n_iter={p.n_iter} {f.kind} {p.precision}", flush=True)
+        out.append(s.wait(s.submit(p, f)))
+    st = s.stats()
+    s.close()
+    assert st["completed"] == len(mix) and st["peak_active"] == 1
+    return out
+
+
+def same(a, b, what):
+    for k in FIELDS:
+        assert a[k] == b[k], f"{what}: {k} {a[k]!r} != {b[k]!r}"
+
+
+def test_mix_at_once_equals_alone(ctx, mix, alone):
+    s = B.Server(ctx)
+    tickets = [s.submit(p, f) for p, f in mix]
+    res = [s.wait(t) for t in tickets]
+    st = s.stats()
+    s.close()
+    assert st["peak_active"] > 1
+    for i, (a, r) in enumerate(zip(alone, res)):
+        same(a, r, f"request {i}")
+
+
+def test_staggered_arrivals_equal_alone(ctx, mix, alone):
+    """Requests arrive from another thread while earlier ones are on the GPU."""
+    s = B.Server(ctx)
+    tickets = [None] * len(mix)
+    rng = np.random.default_rng(11)
+    delays = rng.exponential(0.002, size=len(mix))
+
+    def producer():
+        for i, (p, f) in enumerate(mix):
+            time.sleep(delays[i])
+            tickets[i] = s.submit(p, f)
+
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    res = [s.wait(t) for t in tickets]
+    st = s.stats()
+    s.close()
+    assert st["completed"] == len(mix)
+    for i, (a, r) in enumerate(zip(alone, res)):
+        same(a, r, f"request {i}")
+
+
+def test_eager_steps_equal_graph_replays(ctx, mix, alone):
+    s = B.Server(ctx, graphs=False)
+    res = [s.wait(t) for t in [s.submit(p, f) for p, f in mix]]
+    st = s.stats()
+    s.close()
+    assert st["graph_launches"] == 0
+    for i, (a, r) in enumerate(zip(alone, res)):
+        same(a, r, f"request {i}")
+
+
+def test_graphs_are_replayed(ctx):
+    """Same-length requests submitted together run as one unchanged set: one
+    capture, then replays."""
+    s = B.Server(ctx)
+    reqs = W.served_batch(n_req=6, seed=9, nev_log=(4.0, 4.5), n_iter=8, n_g=200)
+    ts = [s.submit(r.params, r.integrand) for r in reqs]
+    # all six are admitted together unless the scheduler woke between submits
+    for t in ts:
+        s.wait(t)
+    st = s.stats()
+    s.close()
+    assert st["graph_launches"] == st["steps"]
+    assert st["graph_captures"] < st["steps"]
+
+
+def test_served_equals_single_problem_path(ctx, mix):
+    """Against vp_integrate: the same samples, sums in another order."""
+    s = B.Server(ctx)
+    res = [s.wait(t) for t in [s.submit(p, f) for p, f in mix]]
+    s.close()
+    for i, ((p, f), r) in enumerate(zip(mix, res)):
+        ref = B.integrate(ctx, p, f)
+        assert r["n_evals"] == ref["n_evals"], i
+        assert r["n_iter_done"] == ref["n_iter_done"] == p.n_iter
+        rtol = 1e-9 if p.precision == "fp64" else 1e-5
+        assert abs(r["mean"] - ref["mean"]) <= rtol * abs(ref["mean"]) + 1e-300, i
+        assert abs(r["sdev"] - ref["sdev"]) <= rtol * 10 * abs(ref["sdev"]) + 1e-300, i
+
+
+def test_admission_respects_memory_budget(ctx, mix, alone):
+    s0 = B.Server(ctx)
+    sizes = [s0.request_bytes(p, f) for p, f in mix]
+    s0.close()
+    budget = 2 * max(sizes)
+    s = B.Server(ctx, mem_budget=budget)
+    res = [s.wait(t) for t in [s.submit(p, f) for p, f in mix]]
+    st = s.stats()
+    s.close()
+    assert st["mem_peak"] <= budget
+    assert st["completed"] == len(mix)
+    assert st["mem_in_use"] == 0
+    for i, (a, r) in enumerate(zip(alone, res)):
+        same(a, r, f"request {i}")
+
+
+def test_slot_limit(ctx, mix, alone):
+    s = B.Server(ctx, max_slots=2)
+    res = [s.wait(t) for t in [s.submit(p, f) for p, f in mix]]
+    st = s.stats()
+    s.close()
+    assert st["peak_active"] <= 2
+    for i, (a, r) in enumerate(zip(alone, res)):
+        same(a, r, f"request {i}")
+
+
+def test_request_over_budget_is_refused(ctx):
+    s = B.Server(ctx, mem_budget=1 << 20)
+    p, f = W.cfg_diag_d8(n_ev=10_000_000)
+    with pytest.raises(B.VegaspError) as e:
+        s.submit(p, f)
+    assert e.value.status == B.VP_ERR_OOM
+    with pytest.raises(B.VegaspError) as e:
+        s.submit(p.with_(dim=0), f)
+    assert e.value.status == B.VP_ERR_INVALID_ARG
+    s.close()
+
+
+def test_cancel_active_and_pending(ctx):
+    s = B.Server(ctx, max_slots=1)
+    p, f = W.cfg_diag_d8(n_ev=200_000)
+    long_p = p.with_(n_iter=100_000)
+    t_long = s.submit(long_p, f)
+    t_wait = s.submit(p.with_(n_iter=2), f)
+    s.cancel(t_wait)
+    with pytest.raises(B.VegaspError) as e:
+        s.wait(t_wait)
+    assert e.value.status == B.VP_ERR_CANCELLED
+    time.sleep(0.05)
+    assert s.poll(t_long) is None
+    s.cancel(t_long)
+    with pytest.raises(B.VegaspError) as e:
+        s.wait(t_long)
+    assert e.value.status == B.VP_ERR_CANCELLED
+    st = s.stats()
+    assert st["cancelled"] == 2 and st["mem_in_use"] == 0
+    # the server keeps serving after cancellations
+    r = s.wait(s.submit(p.with_(n_iter=2), f))
+    assert r["n_iter_done"] == 2
+    sub, adm, fin = s.times(t_long)
+    assert 0 <= sub <= adm <= fin
+    s.close()
+
+
+def test_destroy_with_work_in_flight(ctx):
+    s = B.Server(ctx)
+    p, f = W.cfg_diag_d8(n_ev=200_000)
+    for i in range(4):
+        s.submit(p.with_(n_iter=100_000, seed=i), f)
+    time.sleep(0.05)
+    s.close()

@@ -71,3 +71,14 @@ def test_split_error_vs_fp64_oracle(ctx, prec):
           f"({dev / abs(ro['mean']):.2e} relative); sigma ratio {rs['sdev'] / ro['sdev']:.6f}")
     assert dev <= 0.1 * ro["sdev"]
     assert abs(rs["sdev"] / ro["sdev"] - 1.0) < 0.01
+
+
+def test_split_map_in_global_memory(ctx):
+    """N_g = 1200 at D=8: the single-precision map no longer fits in LDS next
+    to the training data and is read through buffer loads."""
+    p, f = W.cfg_diag_d8(n_ev=500_000, precision="fp32_acc64")
+    p = p.with_(n_g=1200)
+    gp = B.Problem(ctx, p, f)
+    op = oracle.Problem(p, f, n_st=gp.n_st)
+    for _ in range(3):
+        step_and_compare(gp, op, rtol=RTOL32, rtol_hist=RTOL32, floor=FLOOR32)

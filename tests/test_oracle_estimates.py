@@ -251,3 +251,18 @@ def test_precision_split_tracks_fp64(orc):
     a, n = out["fp32_acc64"], out["fp32_neumaier"]
     np.testing.assert_allclose(n["S1"], a["S1"], rtol=1e-6, atol=1e-12 * np.abs(a["S1"]).max())
     np.testing.assert_allclose(n["H"], a["H"], rtol=1e-5, atol=1e-9 * a["H"].max())
+
+
+def test_weighted_training_data_equal_printed_formula_at_uniform_allocation(orc):
+    # Sec. 2.3 prints d_i = (1/n_i) sum J^2 f^2; with every n_h equal the
+    # weighted form sum(v^2/n_h)/sum(1/n_h) reduces to it exactly.
+    p = W.Params(dim=3, n_ev=20_000, n_g=40, seed=3)
+    f = W.gauss_single(3, coef=20.0)
+    pw = orc.Problem(p, f)
+    pl = orc.Problem(p.with_(hist_mode="literal"), f)
+    fmap, n_h = pw.map_init(), pw.alloc_init()
+    a = pw.sample_range(fmap, n_h, 0)
+    b = pl.sample_range(fmap, n_h, 0)
+    dw = np.where(a["W"] > 0, a["H"] / np.where(a["W"] > 0, a["W"], 1), 0)
+    dl = np.where(b["W"] > 0, b["H"] / np.where(b["W"] > 0, b["W"], 1), 0)
+    np.testing.assert_allclose(dw, dl, rtol=1e-12, atol=0)
