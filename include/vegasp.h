@@ -215,9 +215,11 @@ vp_status vp_integrate(vp_ctx* ctx, const vp_params* params, const vp_integrand*
  * that arrives while others run is admitted at the next step boundary;
  * finished requests are retired at once, freeing memory for the queue.
  * With an unchanged set of active requests a step is replayed from a
- * captured HIP graph.  Each request computes exactly what vp_integrate
- * computes for it (the sampling grid is sized per request, independent of
- * the mix), up to the order of floating-point sums.
+ * captured HIP graph.  Each request computes what vp_integrate computes for
+ * it, up to the order of floating-point sums: its sampling grid is sized
+ * from the request alone, so its samples, counts and increment indices do
+ * not depend on the mix; the order of the LDS-atomic additions into the
+ * increment histograms is not fixed by the hardware, in or out of a mix.
  *
  * mem_budget_bytes: device bytes all active requests may hold (0: 3/4 of
  * the device's free memory).  max_slots: most requests active at once.

@@ -666,7 +666,7 @@ int64_t or_realloc(const or_params* p, const double* S1, const double* S2, const
     }
     const double nev = (double)p->n_ev;
     for (int64_t h = 0; h < nhc; ++h) {
-        const double q = (nev * dh[h]) / sum;
+        const double q = nev * (dh[h] / sum);
         double fl = floor(q);
         double r = nearbyint(q);
         double tol = 1e-9 * (q > 1.0 ? q : 1.0);

@@ -356,7 +356,7 @@ __global__ __launch_bounds__(kRedBlock) void k_realloc(LaunchSet L)
     unsigned long long nt = 0;
     const double first_visible = plus2 ? 1.0 : 3.0;
     for (int64_t h = (int64_t)bid * blockDim.x + threadIdx.x; h < n_hc; h += (int64_t)nblk * blockDim.x) {
-        const double qv = (n_ev * dh[h]) / sumd;
+        const double qv = n_ev * (dh[h] / sumd);
         const double fl = floor(qv);
         const double r = rint(qv);
         const double tol = 1e-9 * (qv > 1.0 ? qv : 1.0);

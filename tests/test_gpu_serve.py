@@ -1,12 +1,16 @@
 """Serving loop: continuous batching of many integrations on one GPU.
 
-Each request's result depends only on its own parameters: the sampling grid
+Each request's work depends only on its own parameters: the sampling grid
 of a served request is sized from the request alone, and every batched
-kernel maps a workgroup to exactly one request.  So a request gives the same
-bits alone and in any mix, submitted at once or arriving while others run,
-replayed from a captured graph or launched directly.  Against the
-single-problem path (vp_integrate) the workgroup split differs, so the sums
-are added in another order: those agree to rounding.
+kernel maps a workgroup to exactly one request.  So a request draws the same
+samples, hypercube counts and increment indices alone and in any mix,
+submitted at once or arriving while others run, replayed from a captured
+graph or launched directly; the integer results agree exactly.  The one
+source of difference is the order in which the waves of a workgroup add into
+the shared increment histograms (LDS atomics), which the hardware does not
+fix, so the refined map -- and through it the next iterations' estimates --
+agree to rounding: within 1e-12 relative, the FP64 parity bound.  Against the
+single-problem path (vp_integrate) the workgroup split also differs.
 """
 import threading
 import time
@@ -19,7 +23,8 @@ from paper_2009_05112_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-FIELDS = ("mean", "sdev", "chi2", "dof", "n_evals", "n_iter_done", "ties")
+EXACT = ("dof", "n_evals", "n_iter_done", "ties")
+RTOL = {"mean": 1e-12, "sdev": 1e-12, "chi2": 1e-9}
 
 
 def small_mix():
@@ -64,8 +69,13 @@ def alone(ctx, mix):
 
 
 def same(a, b, what):
-    for k in FIELDS:
+    for k in EXACT:
         assert a[k] == b[k], f"{what}: {k} {a[k]!r} != {b[k]!r}"
+    for k, rtol in RTOL.items():
+        if np.isnan(a[k]) and np.isnan(b[k]):  # chi2 of a result with a zero variance
+            continue
+        assert abs(a[k] - b[k]) <= rtol * abs(b[k]) + 1e-300 + (1e-12 if k == "chi2" else 0.0), \
+            f"{what}: {k} {a[k]!r} vs {b[k]!r}"
 
 
 def test_mix_at_once_equals_alone(ctx, mix, alone):
@@ -128,17 +138,27 @@ def test_graphs_are_replayed(ctx):
 
 
 def test_served_equals_single_problem_path(ctx, mix):
-    """Against vp_integrate: the same samples, sums in another order."""
+    """Against vp_integrate: the same samples, sums in another order.  Where
+    either run met a near-tie of the allocation rule (floor of N_ev d_h / sum d
+    within rounding of an integer), the two orders may take different sample
+    counts from then on; those runs agree within their error estimates."""
     s = B.Server(ctx)
     res = [s.wait(t) for t in [s.submit(p, f) for p, f in mix]]
     s.close()
+    n_tight = 0
     for i, ((p, f), r) in enumerate(zip(mix, res)):
         ref = B.integrate(ctx, p, f)
-        assert r["n_evals"] == ref["n_evals"], i
         assert r["n_iter_done"] == ref["n_iter_done"] == p.n_iter
+        if r["ties"] or ref["ties"]:
+            tol = 5 * np.hypot(r["sdev"], ref["sdev"]) + 1e-300
+            assert abs(r["mean"] - ref["mean"]) <= tol, i
+            continue
+        n_tight += 1
+        assert r["n_evals"] == ref["n_evals"], i
         rtol = 1e-9 if p.precision == "fp64" else 1e-5
         assert abs(r["mean"] - ref["mean"]) <= rtol * abs(ref["mean"]) + 1e-300, i
         assert abs(r["sdev"] - ref["sdev"]) <= rtol * 10 * abs(ref["sdev"]) + 1e-300, i
+    assert n_tight >= len(mix) // 2
 
 
 def test_admission_respects_memory_budget(ctx, mix, alone):

@@ -179,6 +179,20 @@ def test_beta_zero_is_uniform_and_plus2(orc):
     assert np.all(same == 5)
 
 
+@pytest.mark.parametrize("n_ev", [6084, 24700, 65_535])
+def test_single_hypercube_keeps_every_sample(orc, n_ev):
+    """With one hypercube d_h equals its own sum, so the allocation is N_ev for
+    any sigma: the rule must not lose a sample to rounding."""
+    p = W.Params(dim=14, n_ev=n_ev, n_g=10, beta=0.75)
+    pr = orc.Problem(p, W.const(14))
+    assert pr.n_hc == 1
+    rng = np.random.default_rng(n_ev)
+    for sig in np.exp(rng.uniform(-30, 5, size=200)):
+        S1, S2 = _sums_for_sigma(orc, pr, np.array([sig]), np.array([float(n_ev)]))
+        new, _ = pr.realloc(S1, S2, np.array([n_ev], np.int32))
+        assert new[0] == n_ev, sig
+
+
 # ---------------------------------------------------------------- combination
 def test_combination_fixtures(orc):
     g = json.load(open(os.path.join(GOLD, "combine_cases.json")))
