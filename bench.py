@@ -7,6 +7,20 @@ alpha=0.5, beta=0.75.  The value is integrand samples per second (samples
 actually drawn, sum of n_h) over the timed steps, with all state resident in
 HBM.  Prints one JSON line.
 
+Beside it, outside the timed steps:
+  precision_split  the same workload with FP32 map and integrand (FP64 or
+                   compensated-FP32 accumulation): samples/s and estimates;
+  serving.batch    a batch of Gaussian-mixture requests (D 2..16, N_ev
+                   log-uniform 1e4..1e6, 10 iterations, N_g=500) all submitted
+                   at once to the continuous-batching server, against the plain
+                   path (vp_integrate, one request after another): makespan,
+                   samples/s and p50/p99 latency;
+  serving.stream   Poisson arrivals of correlated-Gaussian requests (D 3..21,
+                   N_ev log-uniform 1e5..1e7, 5..20 iterations, N_g=1000) at a
+                   fixed rate, served live; the plain path is a first-come
+                   first-served queue whose service times are measured one by
+                   one.
+
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision fp64]
 """
 import argparse
@@ -24,7 +38,9 @@ PEAK_VALU_SLOTS = 256 * 64 * 2.4e9  # lane-slots per second: 256 CUs x 64 lanes 
 # with three Gaussian terms (derivation in the design notes): Philox blocks
 # x 10 rounds x (2 wide multiplies at 4 slots + 2 three-way xors), the
 # uniform-to-increment arithmetic, the map, the integrand and the sums.
-SLOTS_PER_SAMPLE = {"fp64": 700.0, "fp32_acc64": 380.0, "fp32_neumaier": 420.0}
+# The compensated FP32 sums take 4 slots per addition instead of 1 for the two
+# per-hypercube sums and the 2D training-data values.
+SLOTS_PER_SAMPLE = {"fp64": 656.0, "fp32_acc64": 413.0, "fp32_neumaier": 413.0 + 3 * (2 + 2 * 8)}
 
 
 def cpu_baseline(p, f, budget_s=12.0):
@@ -52,6 +68,135 @@ def cpu_baseline(p, f, budget_s=12.0):
                       f"({samples} samples, {dt:.1f} s, single thread)"}
 
 
+def pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x, dtype=float), q)) if len(x) else None
+
+
+def lat_summary(lat):
+    return {"p50_s": pct(lat, 50), "p99_s": pct(lat, 99), "mean_s": sum(lat) / max(len(lat), 1)}
+
+
+def run_split(B, W, ctx, n_ev, steps):
+    """FP64 and the two split precisions on the headline workload."""
+    out = {}
+    for prec in ("fp64", "fp32_acc64", "fp32_neumaier"):
+        p, f = W.cfg_diag_d8(n_ev=n_ev, precision=prec)
+        gp = B.Problem(ctx, p.with_(n_iter=steps + 2), f)
+        gp.iterate(2)
+        r0 = gp.result()
+        gp.sync()
+        t0 = time.perf_counter()
+        gp.iterate(steps)
+        gp.sync()
+        dt = time.perf_counter() - t0
+        r1 = gp.result()
+        gp.close()
+        out[prec] = {"samples_per_s": (r1["n_evals"] - r0["n_evals"]) / dt, "mean": r1["mean"],
+                     "sdev": r1["sdev"], "pull_vs_exact": (r1["mean"] - 1.0) / r1["sdev"]}
+    ref = out["fp64"]
+    for prec in ("fp32_acc64", "fp32_neumaier"):
+        o = out[prec]
+        o["speedup_vs_fp64"] = o["samples_per_s"] / ref["samples_per_s"]
+        o["diff_vs_fp64_in_sdev"] = (o["mean"] - ref["mean"]) / ref["sdev"]
+    return out
+
+
+def run_plain(B, ctx, reqs):
+    """vp_integrate one request after another; per-request service times."""
+    svc, res = [], []
+    for r in reqs:
+        t0 = time.perf_counter()
+        res.append(B.integrate(ctx, r.params, r.integrand))
+        svc.append(time.perf_counter() - t0)
+    return svc, res
+
+
+def agreement(served, plain):
+    """Largest |served - plain| over requests, in units of the plain sdev."""
+    worst = 0.0
+    for a, b in zip(served, plain):
+        if b["sdev"] > 0:
+            worst = max(worst, abs(a["mean"] - b["mean"]) / b["sdev"])
+    return worst
+
+
+def run_batch(B, W, ctx, n_req):
+    reqs = W.served_batch(n_req=n_req)
+    srv = B.Server(ctx, max_slots=n_req)
+    t0 = srv.now()
+    tickets = [srv.submit(r.params, r.integrand) for r in reqs]
+    served = [srv.wait(t) for t in tickets]
+    times = [srv.times(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    makespan = max(t[2] for t in times) - t0
+    lat = [t[2] - t[0] for t in times]
+    samples = sum(r["n_evals"] for r in served)
+    svc, plain = run_plain(B, ctx, reqs)
+    import numpy as np
+    plain_lat = list(np.cumsum(svc))  # all submitted at time 0, served in order
+    return {
+        "workload": f"{n_req} Gaussian-mixture requests, D 2..16, N_ev 1e4..1e6 log-uniform, 1-4 terms, "
+                    "10 iterations, N_g=500, fp64, all submitted at t=0",
+        "samples": samples,
+        "served": {"makespan_s": makespan, "samples_per_s": samples / makespan, **lat_summary(lat),
+                   "steps": st["steps"], "graph_launches": st["graph_launches"],
+                   "peak_active": st["peak_active"], "mem_peak_bytes": st["mem_peak"]},
+        "plain": {"makespan_s": float(sum(svc)), "samples_per_s": samples / sum(svc), **lat_summary(plain_lat)},
+        "max_diff_in_sdev": agreement(served, plain),
+    }
+
+
+def run_stream(B, W, ctx, n_req, load):
+    import numpy as np
+    reqs = W.served_stream(n_req=n_req, rate=1.0)
+    unit = np.array([r.arrival for r in reqs])  # arrivals at rate 1
+    svc, plain = run_plain(B, ctx, reqs)
+    rate = load / float(np.mean(svc))  # requests/s at which the plain path is `load` busy
+    arr = unit / rate
+    # plain: first come, first served, one at a time
+    fin, t = [], 0.0
+    for a, s_ in zip(arr, svc):
+        t = max(t, a) + s_
+        fin.append(t)
+    plain_lat = [f - a for f, a in zip(fin, arr)]
+    srv = B.Server(ctx, max_slots=n_req)
+    tickets = [None] * n_req
+
+    def producer():
+        t0 = time.perf_counter()
+        for i, r in enumerate(reqs):
+            d = arr[i] - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            tickets[i] = srv.submit(r.params, r.integrand)
+
+    import threading
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    served = [srv.wait(t) for t in tickets]
+    times = [srv.times(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    lat = [t[2] - t[0] for t in times]
+    samples = sum(r["n_evals"] for r in served)
+    span = max(t[2] for t in times) - min(t[0] for t in times)
+    return {
+        "workload": f"{n_req} correlated-Gaussian requests (cond 100, scale 0.05), D 3..21, N_ev 1e5..1e7 "
+                    f"log-uniform, 5-20 iterations, N_g=1000, fp64; Poisson arrivals at {rate:.1f}/s "
+                    f"(plain path {100 * load:.0f}% busy)",
+        "rate_per_s": rate,
+        "samples": samples,
+        "served": {"span_s": span, "samples_per_s": samples / span, **lat_summary(lat),
+                   "steps": st["steps"], "graph_launches": st["graph_launches"],
+                   "peak_active": st["peak_active"], "mem_peak_bytes": st["mem_peak"]},
+        "plain": {"busy_s": float(sum(svc)), "samples_per_s": samples / float(sum(svc)), **lat_summary(plain_lat)},
+        "max_diff_in_sdev": agreement(served, plain),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +205,10 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=list(SLOTS_PER_SAMPLE))
     ap.add_argument("--n-ev", type=int, default=100_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the precision split and serving sections")
+    ap.add_argument("--batch", type=int, default=4096, help="requests in the served batch")
+    ap.add_argument("--stream", type=int, default=300, help="requests in the Poisson stream")
+    ap.add_argument("--load", type=float, default=0.8, help="plain-path utilisation that sets the stream rate")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a buffer of this many MiB on the GPU (a plain copy kernel of known "
                          "size, the reference for the HBM byte counters) and exit")
@@ -127,6 +276,19 @@ def main():
                      "exact": 1.0},
     }
     gp.close()
+    if not args.no_extra:
+        print("precision split ...", file=sys.stderr, flush=True)
+        line["precision_split"] = run_split(B, W, ctx, args.n_ev, 10)
+        print("served batch ...", file=sys.stderr, flush=True)
+        batch = run_batch(B, W, ctx, args.batch)
+        print("served stream ...", file=sys.stderr, flush=True)
+        stream = run_stream(B, W, ctx, args.stream, args.load)
+        line["serving"] = {"batch": batch, "stream": stream}
+        line["latency"] = {"batch_p50_s": batch["served"]["p50_s"], "batch_p99_s": batch["served"]["p99_s"],
+                           "batch_plain_p50_s": batch["plain"]["p50_s"], "batch_plain_p99_s": batch["plain"]["p99_s"],
+                           "stream_p50_s": stream["served"]["p50_s"], "stream_p99_s": stream["served"]["p99_s"],
+                           "stream_plain_p50_s": stream["plain"]["p50_s"],
+                           "stream_plain_p99_s": stream["plain"]["p99_s"]}
     ctx.close()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, f)

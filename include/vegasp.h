@@ -178,7 +178,7 @@ vp_status vp_result_get(vp_problem* p, vp_result* out, double* I_j, double* V_j,
 vp_status vp_map_get(vp_problem* p, double* map);
 vp_status vp_map_set(vp_problem* p, const double* map);       /* must be non-decreasing */
 vp_status vp_alloc_get(vp_problem* p, int32_t* n_h);
-vp_status vp_alloc_set(vp_problem* p, const int32_t* n_h);    /* every n_h >= 2 */
+vp_status vp_alloc_set(vp_problem* p, const int32_t* n_h);    /* every n_h >= 2, sum <= n_ev + 2 n_hc */
 /* Iteration index used by the next iteration's Philox counters. */
 vp_status vp_iteration_get(vp_problem* p, int32_t* it);
 vp_status vp_iteration_set(vp_problem* p, int32_t it);

@@ -101,31 +101,132 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_top(LaunchSet L)
 }
 
 // ---------------------------------------------------------------- edge fix-up
-// Records arrive sorted by hypercube (wave order); each run of records of
-// one hypercube is summed in record order by the thread holding its first.
-__global__ void k_edge_fixup(LaunchSet L)
+// Hypercubes whose samples span several waves leave one partial per wave as
+// edge records (h = -1: no record), sorted by h in wave order.  One workgroup
+// per request sums every run of equal h: each thread summarises a contiguous
+// slice of records, a fixed-shape scan over the slices gives each thread the
+// run reaching it from the left, and the thread holding a run's last record
+// writes S1[h], S2[h].  The summation order depends only on the records'
+// positions, never on timing.
+struct RunSum {
+    int64_t hf, hl;  // first and last hypercube of the slice
+    double a, b;     // sums of the slice's last run
+    int has;         // the slice holds a record
+    int single;      // every record of the slice has the same h
+};
+
+__device__ __forceinline__ RunSum run_combine(const RunSum& x, const RunSum& y)
+{
+    if (!y.has) return x;
+    if (!x.has) return y;
+    RunSum r;
+    r.has = 1;
+    r.hf = x.hf;
+    r.hl = y.hl;
+    if (y.single && y.hf == x.hl) {
+        r.a = x.a + y.a;
+        r.b = x.b + y.b;
+        r.single = x.single;
+    } else {
+        r.a = y.a;
+        r.b = y.b;
+        r.single = 0;
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(kFixBlock) void k_edge_fixup(LaunchSet L)
 {
     VP_REQ_PROLOGUE(L);
+    __shared__ RunSum sh[kFixBlock];
+    __shared__ int64_t nxt_h[kFixBlock];
+    __shared__ int nxt_has[kFixBlock];
     const EdgeRec* __restrict__ e = q.edges;
     const int64_t n_rec = 2 * q.n_waves;
-    double* __restrict__ S1 = q.S1;
-    double* __restrict__ S2 = q.S2;
-    for (int64_t r = (int64_t)bid * blockDim.x + threadIdx.x; r < n_rec; r += (int64_t)nblk * blockDim.x) {
+    const int t = threadIdx.x;
+    const int64_t per = (n_rec + kFixBlock - 1) / kFixBlock;
+    const int64_t r0 = min(n_rec, (int64_t)t * per), r1 = min(n_rec, r0 + per);
+    RunSum mine;
+    mine.has = 0;
+    mine.single = 1;
+    mine.hf = mine.hl = -1;
+    mine.a = mine.b = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
         const int64_t h = e[r].h;
         if (h < 0) continue;
-        int64_t p = r - 1;
-        while (p >= 0 && e[p].h < 0) --p;
-        if (p >= 0 && e[p].h == h) continue;
-        double a = e[r].s1, b = e[r].s2;
-        for (int64_t q = r + 1; q < n_rec; ++q) {
-            const int64_t hq = e[q].h;
-            if (hq < 0) continue;
-            if (hq != h) break;
-            a = a + e[q].s1;
-            b = b + e[q].s2;
+        if (!mine.has) {
+            mine.has = 1;
+            mine.hf = mine.hl = h;
+            mine.a = e[r].s1;
+            mine.b = e[r].s2;
+        } else if (h == mine.hl) {
+            mine.a = mine.a + e[r].s1;
+            mine.b = mine.b + e[r].s2;
+        } else {
+            mine.hl = h;
+            mine.a = e[r].s1;
+            mine.b = e[r].s2;
+            mine.single = 0;
         }
-        S1[h] = a;
-        S2[h] = b;
+    }
+    // inclusive scan from the left, and the first record to the right
+    sh[t] = mine;
+    nxt_has[t] = mine.has;
+    nxt_h[t] = mine.hf;
+    __syncthreads();
+    for (int d = 1; d < kFixBlock; d <<= 1) {
+        RunSum v = sh[t];
+        if (t >= d) v = run_combine(sh[t - d], v);
+        int hv = nxt_has[t];
+        int64_t hh = nxt_h[t];
+        if (!hv && t + d < kFixBlock) {
+            hv = nxt_has[t + d];
+            hh = nxt_h[t + d];
+        }
+        __syncthreads();
+        sh[t] = v;
+        nxt_has[t] = hv;
+        nxt_h[t] = hh;
+        __syncthreads();
+    }
+    if (!mine.has) return;
+    RunSum carry;
+    carry.has = 0;
+    if (t > 0) carry = sh[t - 1];
+    const int next_has = t + 1 < kFixBlock ? nxt_has[t + 1] : 0;
+    const int64_t next_h = t + 1 < kFixBlock ? nxt_h[t + 1] : -1;
+    double* __restrict__ S1 = q.S1;
+    double* __restrict__ S2 = q.S2;
+    bool open = false;
+    int64_t ch = -1;
+    double ca = 0.0, cb = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const int64_t h = e[r].h;
+        if (h < 0) continue;
+        if (!open) {
+            open = true;
+            ch = h;
+            if (carry.has && carry.hl == h) {
+                ca = carry.a + e[r].s1;
+                cb = carry.b + e[r].s2;
+            } else {
+                ca = e[r].s1;
+                cb = e[r].s2;
+            }
+        } else if (h == ch) {
+            ca = ca + e[r].s1;
+            cb = cb + e[r].s2;
+        } else {
+            S1[ch] = ca;
+            S2[ch] = cb;
+            ch = h;
+            ca = e[r].s1;
+            cb = e[r].s2;
+        }
+    }
+    if (open && !(next_has && next_h == ch)) {
+        S1[ch] = ca;
+        S2[ch] = cb;
     }
 }
 
@@ -135,13 +236,15 @@ __global__ void k_edge_fixup(LaunchSet L)
 __global__ void k_hist_reduce(LaunchSet L)
 {
     VP_REQ_PROLOGUE(L);
-    const double* __restrict__ part = q.hist_lds ? q.hist_part : q.hist_glob;
-    const int n_part = q.hist_lds ? q.grid : 1;
+    const double* __restrict__ part = q.hist_part;
     const int64_t nbins = (int64_t)q.dim * q.n_g;
+    const int64_t lbins = (int64_t)q.hist_axes * q.n_g;
     double* __restrict__ H = q.H;
     double* __restrict__ W = q.W;
     for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < 2 * nbins; i += (int64_t)nblk * blockDim.x) {
         // four interleaved chains keep four loads in flight; fixed order
+        const int64_t j = i < nbins ? i : i - nbins;
+        const int n_part = j < lbins ? q.grid : q.rec_chunks;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         int p = 0;
         for (; p + 3 < n_part; p += 4) {
@@ -157,15 +260,52 @@ __global__ void k_hist_reduce(LaunchSet L)
     }
 }
 
-// Clears the global training-data bins of requests that accumulate them with
-// global atomics (a fill kernel, so the step can be captured in a graph).
-__global__ void k_hist_zero(LaunchSet L)
+// Training data from per-sample records, for the axes the sampling kernel
+// could not privatise in LDS (D * N_g bins too many).  Workgroup (chunk c,
+// slice l) bins the records of sample positions
+// [c N / chunks, (c + 1) N / chunks) for the axes of slice l into
+// LDS -- numerator and weight planes of rec_axes * n_g bins -- and writes them
+// to partial c, which k_hist_reduce sums over chunks.  The weight is 1/n_h
+// (1 for the literal form), as the sampling kernel computes it.
+__global__ __launch_bounds__(kRecBlock) void k_hist_records(LaunchSet L)
 {
     VP_REQ_PROLOGUE(L);
-    if (q.hist_lds) return;
-    const int64_t n = 2 * (int64_t)q.dim * q.n_g;
-    for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n; i += (int64_t)nblk * blockDim.x)
-        q.hist_glob[i] = 0.0;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    double* lh = reinterpret_cast<double*>(lds_raw);
+    const int n_g = q.n_g;
+    const int c = bid / q.rec_slices;
+    const int l = bid - c * q.rec_slices;
+    const int a0 = q.hist_axes + l * q.rec_axes;
+    const int a1 = min(q.dim, a0 + q.rec_axes);
+    const int nb = (a1 - a0) * n_g;
+    double* lw = lh + nb;
+    for (int i = threadIdx.x; i < 2 * nb; i += blockDim.x) lh[i] = 0.0;
+    __syncthreads();
+    const SampleArgs& a = q.s;
+    const int64_t n_tot = gofs(a.offs, a.obase, q.n_hc);
+    const int64_t p0 = n_tot * c / q.rec_chunks;
+    const int64_t p1 = n_tot * (c + 1) / q.rec_chunks;
+    const bool literal = a.hist_mode != 0;
+    const double* __restrict__ rh = a.rec_h;
+    const uint32_t* __restrict__ rn = a.rec_n;
+    const uint16_t* __restrict__ rb = a.rec_bin;
+    const int64_t stride = a.rec_stride;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const double hh = rh[p];
+        const double hw = literal ? 1.0 : 1.0 / (double)rn[p];
+        for (int mu = a0; mu < a1; ++mu) {
+            const int bin = (mu - a0) * n_g + (int)rb[(mu - q.hist_axes) * stride + p];
+            atomicAdd(&lh[bin], hh);
+            atomicAdd(&lw[bin], hw);
+        }
+    }
+    __syncthreads();
+    const int64_t nbins = (int64_t)q.dim * n_g;
+    double* out = q.hist_part + (int64_t)c * 2 * nbins + (int64_t)a0 * n_g;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        out[i] = lh[i];
+        out[nbins + i] = lw[i];
+    }
 }
 
 __global__ void k_fill_f64(double* __restrict__ x, int64_t n, double v)
@@ -546,22 +686,26 @@ static void launch(void (*k)(LaunchSet), const LaunchSet& L, int blocks, int thr
     if (blocks > 0) hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, s, L);
 }
 
-hipError_t aux_init()
+hipError_t aux_init(size_t lds_max)
 {
-    return hipFuncSetAttribute((const void*)k_refine, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)((4 * kMaxNg + 3) * sizeof(double)));
+    hipError_t e = hipFuncSetAttribute((const void*)k_refine, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)((4 * kMaxNg + 3) * sizeof(double)));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_hist_records, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds_max);
+    return e;
 }
 
 void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin, hipEvent_t sample_end)
 {
     launch(k_scan_local, P.scan_local, P.n_scan_local, kScanBlock, 0, s);
     launch(k_scan_top, P.one, P.n_one, kScanBlock, 0, s);
-    launch(k_hist_zero, P.hist, P.n_hist, 256, 0, s);
     if (sample_begin) (void)hipEventRecord(sample_begin, s);
     for (int g = 0; g < P.n_groups; ++g)
         P.groups[g].entry.launch(P.groups[g].L, P.groups[g].blocks, P.groups[g].entry.block, P.groups[g].lds, s);
     if (sample_end) (void)hipEventRecord(sample_end, s);
-    launch(k_edge_fixup, P.fixup, P.n_fixup, 256, 0, s);
+    launch(k_hist_records, P.rec, P.n_rec, kRecBlock, P.rec_lds, s);
+    launch(k_edge_fixup, P.fixup, P.n_fixup, kFixBlock, 0, s);
     launch(k_hist_reduce, P.hist, P.n_hist, 256, 0, s);
     launch(k_est_partial, P.est, P.n_est, kRedBlock, 0, s);
     launch(k_est_final, P.one, P.n_one, kRedBlock, 0, s);

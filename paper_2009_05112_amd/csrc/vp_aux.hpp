@@ -12,6 +12,7 @@ static_assert(kScanTile == kOffsTile, "scan tile and offset blocks must agree");
 constexpr int kRedBlock = 256;
 constexpr int kRedMaxGrid = 16384;
 constexpr int kRefineBlock = 256;
+constexpr int kFixBlock = 1024;  // edge fix-up: one workgroup per request
 
 // Device-resident scalars of one problem.
 struct DevState {
@@ -42,19 +43,20 @@ struct SampleGroup {
 // Every launch of one batched iteration over a set of requests: the launch
 // sets share the request table and differ in their workgroup counts.
 struct IterPlan {
-    LaunchSet scan_local, one, hist, fixup, est, refine;
-    int n_scan_local, n_one, n_hist, n_fixup, n_est, n_refine;
+    LaunchSet scan_local, one, hist, rec, fixup, est, refine;
+    int n_scan_local, n_one, n_hist, n_rec, n_fixup, n_est, n_refine;
+    size_t rec_lds;  // dynamic LDS of the records-to-histogram pass
     SampleGroup groups[kMaxGroups];
     int n_groups;
     int max_ng;
 };
 
+// One-time per-device set-up of the auxiliary kernels (dynamic LDS limits,
+// lds_max: the device's LDS per workgroup); done when a context is created,
+// so enqueue_iteration makes no such call and can be captured into a graph.
+hipError_t aux_init(size_t lds_max);
 // Enqueues one iteration of every request of the plan; when given, the two
 // events bracket the sampling launches.
-// One-time per-device set-up of the auxiliary kernels (dynamic LDS limits);
-// done when a context is created, so enqueue_iteration makes no such call and
-// can be captured into a graph.
-hipError_t aux_init();
 void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin, hipEvent_t sample_end);
 
 }  // namespace vp

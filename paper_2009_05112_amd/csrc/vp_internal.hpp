@@ -72,8 +72,14 @@ struct SampleArgs {
     const int64_t* obase;   // per-block bases
     double* S1;             // [n_hc]
     double* S2;             // [n_hc]
-    double* hist_part;      // [grid][2][dim * n_g] per-workgroup training data (LDS path)
-    double* hist_glob;      // [2][dim * n_g] (global-atomic path, zeroed before launch)
+    double* hist_part;      // [n_part][2][dim * n_g] per-workgroup training data
+    // training records for the axes not privatised in LDS (dim * n_g too large),
+    // per sample position: the value added to the numerator, the sample's n_h,
+    // and the increment index of each such axis ([dim - hist_axes][rec_stride])
+    double* rec_h;
+    uint32_t* rec_n;
+    uint16_t* rec_bin;
+    int64_t rec_stride;
     EdgeRec* edges;         // [2 * n_waves]
     unsigned long long* nonfinite;
     const IntegrandDev* f;
@@ -83,7 +89,7 @@ struct SampleArgs {
     float R32;
     uint32_t key0, key1, it;
     int32_t hist_mode;      // 0 weighted, 1 literal
-    int32_t hist_lds;       // 1: privatised in LDS; 0: global atomics
+    int32_t hist_axes;      // training data of axes [0, hist_axes) privatised in LDS
     int32_t map_lds;        // 1: map staged in LDS
     int32_t chunk;          // samples per lane per tile
 };
@@ -101,8 +107,8 @@ struct ReqArgs {
     double* dh;
     double* H;
     double* W;
-    double* hist_part;
-    double* hist_glob;
+    double* hist_part;      // [n_part][2][dim * n_g]: bins of LDS axes have grid partials,
+                            // bins of record axes have rec_chunks partials
     EdgeRec* edges;
     double* est_part;
     double* hist_I;
@@ -118,9 +124,10 @@ struct ReqArgs {
     int32_t slot;           // history slot of the current iteration (advanced on the device)
     int32_t grid;           // sampling workgroups
     int32_t est_blocks;     // workgroups of the estimate and reallocation passes
-    int32_t hist_lds;
-    int32_t done_flag;      // set on the device when the last iteration of a served request ends
-    int32_t n_iter_target;  // iterations of a served request (0: unbounded)
+    int32_t hist_axes;      // axes privatised in the sampling kernel's LDS (the rest: records)
+    int32_t rec_chunks;     // records: sample chunks, each one partial
+    int32_t rec_slices;     // records: axis slices per chunk
+    int32_t rec_axes;       // records: axes per slice (the last may hold fewer)
 };
 
 // One batched launch over n requests: request r's argument record is
@@ -169,6 +176,8 @@ SampleEntry sample_entry_fp32neu(int kind, int dim, bool map_lds);
 
 // sampling kernels' LDS needs (bytes) for histogram and map
 inline size_t hist_lds_bytes(int dim, int n_g) { return (size_t)dim * n_g * 2 * sizeof(double); }
+// Workgroup size of the records-to-histogram pass.
+constexpr int kRecBlock = 1024;
 inline size_t map_lds_bytes(int prec, int dim, int n_g)
 {
     return (size_t)dim * (n_g + 1) * (prec == P_FP64 ? sizeof(double) : sizeof(float));

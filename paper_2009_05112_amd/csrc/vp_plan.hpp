@@ -63,11 +63,13 @@ public:
             *total = acc;
             return p;
         };
-        int n_scan = 0, n_one = 0, n_hist = 0, n_fix = 0, n_est = 0, n_ref = 0;
+        int n_scan = 0, n_one = 0, n_hist = 0, n_rec = 0, n_fix = 0, n_est = 0, n_ref = 0;
         Pending ps = add_set([](const ReqArgs& q) { return (int)scan_blocks(q.n_hc); }, &n_scan);
         Pending po = add_set([](const ReqArgs&) { return 1; }, &n_one);
         Pending ph = add_set([](const ReqArgs& q) { return (int)((2LL * q.dim * q.n_g + 255) / 256); }, &n_hist);
-        Pending pf = add_set([](const ReqArgs& q) { return (int)((2 * q.n_waves + 255) / 256); }, &n_fix);
+        Pending prc = add_set(
+            [](const ReqArgs& q) { return q.hist_axes < q.dim ? q.rec_chunks * q.rec_slices : 0; }, &n_rec);
+        Pending pf = add_set([](const ReqArgs&) { return 1; }, &n_fix);
         Pending pe = add_set([](const ReqArgs& q) { return q.est_blocks; }, &n_est);
         Pending pr = add_set([](const ReqArgs& q) { return q.dim; }, &n_ref);
         // sampling groups: requests with the same kernel instantiation
@@ -122,18 +124,26 @@ public:
         out->scan_local = mk(ps);
         out->one = mk(po);
         out->hist = mk(ph);
+        out->rec = mk(prc);
         out->fixup = mk(pf);
         out->est = mk(pe);
         out->refine = mk(pr);
         out->n_scan_local = n_scan;
         out->n_one = n_one;
         out->n_hist = n_hist;
+        out->n_rec = n_rec;
         out->n_fixup = n_fix;
         out->n_est = n_est;
         out->n_refine = n_ref;
         out->n_groups = (int)keys.size();
         out->max_ng = 1;
-        for (int r = 0; r < n; ++r) out->max_ng = std::max(out->max_ng, reqs[r].host->n_g);
+        out->rec_lds = 0;
+        for (int r = 0; r < n; ++r) {
+            const ReqArgs& q = *reqs[r].host;
+            out->max_ng = std::max(out->max_ng, q.n_g);
+            if (q.hist_axes < q.dim)
+                out->rec_lds = std::max(out->rec_lds, (size_t)2 * q.rec_axes * q.n_g * sizeof(double));
+        }
         for (size_t g = 0; g < keys.size(); ++g) {
             out->groups[g].entry = reqs[members[g][0]].entry;
             out->groups[g].L = mk(pg[g]);

@@ -171,35 +171,11 @@ static void fill_integrand(IntegrandDev& d, const vp_integrand* f)
     for (int i = 0; i < kMaxDim * kMaxDim; ++i) d.chol32[i] = (float)d.chol[i];
 }
 
-template <typename T>
-static hipError_t dalloc(T** p, size_t n)
-{
-    return hipMalloc((void**)p, sizeof(T) * (n ? n : 1));
-}
-
 void vp::problem_free(vp_problem* p)
 {
     if (!p) return;
     vp_ctx* ctx = p->ctx;
-    (void)hipFree(p->f_d);
-    (void)hipFree(p->map);
-    (void)hipFree(p->map32);
-    (void)hipFree(p->n_h);
-    (void)hipFree(p->offs);
-    (void)hipFree(p->bsum);
-    (void)hipFree(p->S1);
-    (void)hipFree(p->S2);
-    (void)hipFree(p->dh);
-    (void)hipFree(p->H);
-    (void)hipFree(p->W);
-    (void)hipFree(p->hist_part);
-    (void)hipFree(p->hist_glob);
-    (void)hipFree(p->edges);
-    (void)hipFree(p->est_part);
-    (void)hipFree(p->hist_I);
-    (void)hipFree(p->hist_V);
-    (void)hipFree(p->st);
-    (void)hipFree(p->d_req);
+    (void)hipFree(p->arena);
     for (auto e : p->ev_pending) (void)hipEventDestroy(e);
     for (auto e : p->ev_free) (void)hipEventDestroy(e);
     delete p;
@@ -249,7 +225,10 @@ static void fill_req(vp_problem* p)
     a.S1 = p->S1;
     a.S2 = p->S2;
     a.hist_part = p->hist_part;
-    a.hist_glob = p->hist_glob;
+    a.rec_h = p->rec_h;
+    a.rec_n = p->rec_n;
+    a.rec_bin = p->rec_bin;
+    a.rec_stride = p->rec_stride;
     a.edges = p->edges;
     a.nonfinite = &p->st->nonfinite;
     a.f = p->f_d;
@@ -262,7 +241,7 @@ static void fill_req(vp_problem* p)
     a.key1 = (uint32_t)(P.seed >> 32);
     a.it = (uint32_t)p->it;
     a.hist_mode = P.hist_mode;
-    a.hist_lds = p->hist_lds;
+    a.hist_axes = p->hist_axes;
     a.map_lds = p->map_lds;
     a.chunk = p->chunk;
     q.n_h = p->n_h;
@@ -274,7 +253,6 @@ static void fill_req(vp_problem* p)
     q.H = p->H;
     q.W = p->W;
     q.hist_part = p->hist_part;
-    q.hist_glob = p->hist_glob;
     q.edges = p->edges;
     q.est_part = p->est_part;
     q.hist_I = p->hist_I;
@@ -296,7 +274,10 @@ static void fill_req(vp_problem* p)
     q.slot = p->slot;
     q.grid = p->grid;
     q.est_blocks = est_grid(p->n_hc);
-    q.hist_lds = p->hist_lds;
+    q.hist_axes = p->hist_axes;
+    q.rec_chunks = p->rec_chunks;
+    q.rec_slices = p->rec_slices;
+    q.rec_axes = p->rec_axes;
 }
 
 // Writes the device copies of the iteration counters.
@@ -339,7 +320,6 @@ vp_status vp_ctx_create(int device, void* hip_stream, vp_ctx** out)
     VP_HIP(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(VP_ERR_INVALID_ARG, "device %d not in 0..%d", device, n - 1);
     VP_HIP(hipSetDevice(device));
-    VP_HIP(aux_init());
     vp_ctx* c = new vp_ctx();
     c->device = device;
     c->refs = 1;
@@ -358,6 +338,14 @@ vp_status vp_ctx_create(int device, void* hip_stream, vp_ctx** out)
     (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
     c->n_cu = cu > 0 ? cu : 1;
     c->lds_max = lds > 0 ? (size_t)lds : 65536;
+    {
+        hipError_t e = aux_init(c->lds_max);
+        if (e != hipSuccess) {
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            delete c;
+            return fail(VP_ERR_DEVICE, "configuring kernels: %s", hipGetErrorString(e));
+        }
+    }
     *out = c;
     return VP_OK;
 }
@@ -383,12 +371,14 @@ vp_status vp_ctx_info(vp_ctx* c, int32_t* n_cu, int64_t* lds)
 struct Shape {
     int32_t n_st;
     int64_t n_hc;
-    int hist_lds, map_lds;
+    int hist_axes, map_lds;
     SampleEntry entry;
     int block, chunk, grid;
     size_t lds;
     int64_t n_waves;
     int32_t hist_cap;
+    int64_t rec_stride;  // records path: sample positions held (0: LDS path)
+    int32_t rec_chunks, rec_slices, rec_axes;
 };
 
 static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
@@ -400,11 +390,13 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     for (int d = 0; d < D; ++d) nhc *= sh->n_st;
     sh->n_hc = nhc;
     const int prec = P->precision;
-    const size_t hb = hist_lds_bytes(D, NG), mb = map_lds_bytes(prec, D, NG);
-    sh->hist_lds = hb <= ctx->lds_max ? 1 : 0;
-    if (prec == VP_FP32_NEUMAIER && !sh->hist_lds)
+    // training data: as many axes as fit privatised in LDS, the rest as records
+    const int fit = std::max<int>(1, (int)(ctx->lds_max / (2 * sizeof(double) * (size_t)NG)));
+    sh->hist_axes = std::min(D, fit);
+    if (prec == VP_FP32_NEUMAIER && sh->hist_axes < D)
         return fail(VP_ERR_INVALID_ARG, "compensated sums need dim * n_g * 16 <= %zu bytes of LDS", ctx->lds_max);
-    sh->map_lds = (sh->hist_lds ? hb : 0) + mb <= ctx->lds_max ? 1 : 0;
+    const size_t hb = hist_lds_bytes(sh->hist_axes, NG), mb = map_lds_bytes(prec, D, NG);
+    sh->map_lds = hb + mb <= ctx->lds_max ? 1 : 0;
     sh->entry = sample_entry(prec, f->kind, D, sh->map_lds != 0);
     if (!sh->entry.launch && sh->map_lds) {
         sh->map_lds = 0;
@@ -412,7 +404,7 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     }
     if (!sh->entry.launch) return fail(VP_ERR_INVALID_ARG, "no sampling kernel for dim %d", D);
     sh->block = sh->entry.block;
-    sh->lds = (sh->hist_lds ? hb : 0) + (sh->map_lds ? mb : 0);
+    sh->lds = hb + (sh->map_lds ? mb : 0);
     sh->chunk = 8;
     int occ = sh->entry.occupancy(sh->block, sh->lds);
     if (occ < 1) occ = 1;
@@ -425,7 +417,64 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     sh->grid = (int)std::max<int64_t>(1, grid);
     sh->n_waves = (int64_t)sh->grid * waves_per_block;
     sh->hist_cap = samples_per_wg > 0 ? std::max<int32_t>(1, P->n_iter) : kMaxHistory;
+    sh->rec_stride = 0;
+    sh->rec_chunks = sh->rec_slices = sh->rec_axes = 0;
+    if (sh->hist_axes < D) {
+        // axis slices of the remaining axes whose two planes fit in LDS,
+        // balanced; chunks of at least 64 Ki samples, about two workgroups per
+        // CU over all slices
+        const int rem = D - sh->hist_axes;
+        sh->rec_slices = (rem + fit - 1) / fit;
+        sh->rec_axes = (rem + sh->rec_slices - 1) / sh->rec_slices;
+        const int64_t want = (2 * (int64_t)ctx->n_cu + sh->rec_slices - 1) / sh->rec_slices;
+        sh->rec_chunks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(want, (n_tot_max + 65535) / 65536));
+        sh->rec_stride = n_tot_max;
+    }
     return VP_OK;
+}
+
+// Byte offsets of a problem's device buffers inside its one allocation.  The
+// records the host writes at creation (integrand, scalars, argument record,
+// map) come first, so one copy initialises them.
+struct Layout {
+    size_t f_d, st, d_req, map, map32, head_end;
+    size_t n_h, offs, bsum, S1, S2, dh, H, W, hist, edges, est_part, hist_I, hist_V, rec_h, rec_n, rec_bin, total;
+};
+
+static Layout layout_of(const vp_params* P, const Shape& sh)
+{
+    const int64_t D = P->dim, NG = P->n_g, nhc = sh.n_hc, nbins = D * NG;
+    Layout L;
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = at;
+        at += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    L.f_d = take(sizeof(IntegrandDev));
+    L.st = take(sizeof(DevState));
+    L.d_req = take(sizeof(ReqArgs));
+    L.map = take((size_t)D * (NG + 1) * sizeof(double));
+    L.map32 = take((size_t)D * (NG + 1) * sizeof(float));
+    L.head_end = at;
+    L.n_h = take((size_t)nhc * sizeof(int32_t));
+    L.offs = take((size_t)(nhc + 1) * sizeof(int64_t));
+    L.bsum = take((size_t)(scan_blocks(nhc) + 1) * sizeof(int64_t));
+    L.S1 = take((size_t)nhc * sizeof(double));
+    L.S2 = take((size_t)nhc * sizeof(double));
+    L.dh = take((size_t)nhc * sizeof(double));
+    L.H = take((size_t)nbins * sizeof(double));
+    L.W = take((size_t)nbins * sizeof(double));
+    L.hist = take((size_t)std::max(sh.grid, sh.rec_chunks) * 2 * nbins * sizeof(double));
+    L.edges = take((size_t)2 * sh.n_waves * sizeof(EdgeRec));
+    L.est_part = take((size_t)3 * est_grid(nhc) * sizeof(double));
+    L.hist_I = take((size_t)sh.hist_cap * sizeof(double));
+    L.hist_V = take((size_t)sh.hist_cap * sizeof(double));
+    L.rec_h = take((size_t)sh.rec_stride * sizeof(double));
+    L.rec_n = take((size_t)sh.rec_stride * sizeof(uint32_t));
+    L.rec_bin = take((size_t)sh.rec_stride * (D - sh.hist_axes) * sizeof(uint16_t));
+    L.total = at;
+    return L;
 }
 
 vp_status vp::problem_bytes(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
@@ -436,13 +485,7 @@ vp_status vp::problem_bytes(vp_ctx* ctx, const vp_params* P, const vp_integrand*
     Shape sh;
     s = compute_shape(ctx, P, f, samples_per_wg, &sh);
     if (s != VP_OK) return s;
-    const int64_t D = P->dim, NG = P->n_g, nhc = sh.n_hc, nbins = D * NG;
-    size_t b = sizeof(IntegrandDev) + sizeof(DevState) + sizeof(ReqArgs) + 4096;
-    b += (size_t)D * (NG + 1) * 12;
-    b += (size_t)nhc * (4 + 8 + 8 + 8 + 8) + 8 + (size_t)(scan_blocks(nhc) + 1) * 8;
-    b += (size_t)nbins * 16;
-    b += sh.hist_lds ? (size_t)sh.grid * 2 * nbins * 8 : (size_t)2 * nbins * 8;
-    b += (size_t)2 * sh.n_waves * sizeof(EdgeRec) + (size_t)3 * est_grid(nhc) * 8 + (size_t)sh.hist_cap * 16;
+    const size_t b = layout_of(P, sh).total;
     *bytes = b;
     return VP_OK;
 }
@@ -482,7 +525,7 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
     p->R = (double)NG / (double)p->n_st;
     p->it = 0;
     p->slot = 0;
-    p->hist_lds = sh.hist_lds;
+    p->hist_axes = sh.hist_axes;
     p->map_lds = sh.map_lds;
     p->entry = sh.entry;
     p->block = sh.block;
@@ -492,36 +535,43 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
     p->n_waves = sh.n_waves;
     p->hist_cap = sh.hist_cap;
 
-    // device state
+    // device state: one allocation per problem
     const int64_t nbins = (int64_t)D * NG;
-    hipError_t e = hipSuccess;
-#define VP_ALLOC(ptr, n)                                                                    \
-    if (e == hipSuccess) e = dalloc(&(ptr), (size_t)(n));
-    VP_ALLOC(p->f_d, 1);
-    VP_ALLOC(p->map, (int64_t)D * (NG + 1));
-    VP_ALLOC(p->map32, (int64_t)D * (NG + 1));
-    VP_ALLOC(p->n_h, nhc);
-    VP_ALLOC(p->offs, nhc + 1);
-    VP_ALLOC(p->bsum, scan_blocks(nhc) + 1);
-    VP_ALLOC(p->S1, nhc);
-    VP_ALLOC(p->S2, nhc);
-    VP_ALLOC(p->dh, nhc);
-    VP_ALLOC(p->H, nbins);
-    VP_ALLOC(p->W, nbins);
-    if (p->hist_lds) VP_ALLOC(p->hist_part, (int64_t)p->grid * 2 * nbins);
-    if (!p->hist_lds) VP_ALLOC(p->hist_glob, 2 * nbins);
-    VP_ALLOC(p->edges, 2 * p->n_waves);
-    VP_ALLOC(p->est_part, 3 * (int64_t)est_grid(nhc));
-    VP_ALLOC(p->hist_I, p->hist_cap);
-    VP_ALLOC(p->hist_V, p->hist_cap);
-    VP_ALLOC(p->st, 1);
-    VP_ALLOC(p->d_req, 1);
-#undef VP_ALLOC
+    const Layout lay = layout_of(P, sh);
+    hipError_t e = hipMalloc((void**)&p->arena, lay.total);
     if (e != hipSuccess) {
+        p->arena = nullptr;
         problem_free(p);
-        return fail(e == hipErrorOutOfMemory ? VP_ERR_OOM : VP_ERR_DEVICE, "allocating problem state: %s",
-                    hipGetErrorString(e));
+        return fail(e == hipErrorOutOfMemory ? VP_ERR_OOM : VP_ERR_DEVICE, "allocating %zu bytes of problem state: %s",
+                    lay.total, hipGetErrorString(e));
     }
+    p->arena_bytes = lay.total;
+    char* base = p->arena;
+    p->f_d = (IntegrandDev*)(base + lay.f_d);
+    p->st = (DevState*)(base + lay.st);
+    p->d_req = (ReqArgs*)(base + lay.d_req);
+    p->map = (double*)(base + lay.map);
+    p->map32 = (float*)(base + lay.map32);
+    p->n_h = (int32_t*)(base + lay.n_h);
+    p->offs = (int64_t*)(base + lay.offs);
+    p->bsum = (int64_t*)(base + lay.bsum);
+    p->S1 = (double*)(base + lay.S1);
+    p->S2 = (double*)(base + lay.S2);
+    p->dh = (double*)(base + lay.dh);
+    p->H = (double*)(base + lay.H);
+    p->W = (double*)(base + lay.W);
+    p->hist_part = (double*)(base + lay.hist);
+    p->rec_stride = sh.rec_stride;
+    p->rec_chunks = sh.rec_chunks;
+    p->rec_slices = sh.rec_slices;
+    p->rec_axes = sh.rec_axes;
+    p->rec_h = sh.rec_stride ? (double*)(base + lay.rec_h) : nullptr;
+    p->rec_n = sh.rec_stride ? (uint32_t*)(base + lay.rec_n) : nullptr;
+    p->rec_bin = sh.rec_stride ? (uint16_t*)(base + lay.rec_bin) : nullptr;
+    p->edges = (EdgeRec*)(base + lay.edges);
+    p->est_part = (double*)(base + lay.est_part);
+    p->hist_I = (double*)(base + lay.hist_I);
+    p->hist_V = (double*)(base + lay.hist_V);
     // initial map (Sec. 2.3: start from a uniform grid), uniform allocation
     std::vector<double> m((size_t)D * (NG + 1));
     std::vector<float> m32(m.size());
@@ -531,15 +581,18 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
         m[(size_t)d * (NG + 1) + NG] = b;
     }
     for (size_t i = 0; i < m.size(); ++i) m32[i] = (float)m[i];
-    DevState st0;
-    memset(&st0, 0, sizeof st0);
+    // the head of the allocation (integrand, scalars, argument record, map)
+    // is staged on the host and copied at once
+    std::vector<char> head(lay.head_end, 0);
+    memcpy(head.data() + lay.f_d, &p->fh, sizeof(IntegrandDev));
+    fill_req(p);
+    memcpy(head.data() + lay.d_req, &p->req, sizeof(ReqArgs));
+    memcpy(head.data() + lay.map, m.data(), m.size() * sizeof(double));
+    memcpy(head.data() + lay.map32, m32.data(), m32.size() * sizeof(float));
     hipStream_t sm = ctx->stream;
     int64_t n0 = P->n_ev / nhc;
     if (n0 < 2) n0 = 2;
-    e = hipMemcpyAsync(p->f_d, &p->fh, sizeof(IntegrandDev), hipMemcpyHostToDevice, sm);
-    if (e == hipSuccess) e = hipMemcpyAsync(p->map, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice, sm);
-    if (e == hipSuccess) e = hipMemcpyAsync(p->map32, m32.data(), m32.size() * sizeof(float), hipMemcpyHostToDevice, sm);
-    if (e == hipSuccess) e = hipMemcpyAsync(p->st, &st0, sizeof st0, hipMemcpyHostToDevice, sm);
+    e = hipMemcpyAsync(p->arena, head.data(), head.size(), hipMemcpyHostToDevice, sm);
     if (e == hipSuccess) {
         launch_fill_i32(p->n_h, nhc, (int32_t)n0, sm);
         launch_fill_f64(p->H, nbins, 0.0, sm);
@@ -549,14 +602,6 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(sm);
-    if (e == hipSuccess) {
-        fill_req(p);
-        e = hipMemcpy(p->d_req, &p->req, sizeof(ReqArgs), hipMemcpyHostToDevice);
-    }
-    if (e == hipSuccess) {
-        std::vector<PlanReq> pr = {{&p->req, p->d_req, p->entry, p->lds}};
-        e = p->planner.build(pr, &p->plan);
-    }
     if (e != hipSuccess) {
         problem_free(p);
         return fail(VP_ERR_DEVICE, "initialising problem state: %s", hipGetErrorString(e));
@@ -595,6 +640,11 @@ vp_status vp_iterate(vp_problem* p, int32_t n_iter)
     if (p->slot + n_iter > p->hist_cap) return fail(VP_ERR_STATE, "more than %d iterations", p->hist_cap);
     VP_HIP(hipSetDevice(p->ctx->device));
     hipStream_t s = p->ctx->stream;
+    if (!p->plan_built) {
+        std::vector<PlanReq> pr = {{&p->req, p->d_req, p->entry, p->lds}};
+        VP_HIP(p->planner.build(pr, &p->plan));
+        p->plan_built = true;
+    }
     for (int32_t r = 0; r < n_iter; ++r) {
         if (p->prof) {
             hipEvent_t e0 = take_event(p), e1 = take_event(p), e2 = take_event(p), e3 = take_event(p);
@@ -686,7 +736,12 @@ vp_status vp_alloc_set(vp_problem* p, const int32_t* n_h)
         if (n_h[h] < 2) return fail(VP_ERR_INVALID_ARG, "n_h[%lld] = %d < 2", (long long)h, n_h[h]);
         tot += n_h[h];
     }
-    if (tot > (int64_t)1 << 40) return fail(VP_ERR_INVALID_ARG, "allocation too large");
+    // the reallocation rule never exceeds N_ev + 2 N_hc; the sampling grid and
+    // the training-record buffers are sized for that
+    const int64_t cap = p->P.n_ev + 2 * p->n_hc;
+    if (tot > cap)
+        return fail(VP_ERR_INVALID_ARG, "allocation of %lld samples exceeds n_ev + 2 n_hc = %lld", (long long)tot,
+                    (long long)cap);
     VP_HIP(hipStreamSynchronize(p->ctx->stream));
     VP_HIP(hipMemcpy(p->n_h, n_h, sizeof(int32_t) * p->n_hc, hipMemcpyHostToDevice));
     return VP_OK;

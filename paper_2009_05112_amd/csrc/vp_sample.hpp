@@ -491,6 +491,32 @@ __device__ __forceinline__ float sample_fp32(const SampleArgs& a, const MapPair3
 // ---------------------------------------------------------------- the kernel
 // KIND fixes the integrand at compile time (K_GAUSS_MIX, K_CORR_GAUSS), or is
 // 0 for the generic kernel that dispatches on the integrand's kind at run time.
+// Training data of one sample: atomics into the LDS bins of the privatised
+// axes, and for the other axes a record at the sample's position -- the
+// numerator value, n_h and those axes' increment indices (k_hist_records bins
+// them).
+template <int D>
+__device__ __forceinline__ void put_training(const SampleArgs& a, double* lds_hist, int lbins, int n_g, int64_t pos,
+                                             double hh, double hw, uint32_t n, const int32_t* idx)
+{
+    const int ha = a.hist_axes;
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        if (mu < ha) {
+            const int bin = mu * n_g + idx[mu];
+            atomicAdd(&lds_hist[bin], hh);
+            atomicAdd(&lds_hist[lbins + bin], hw);
+        }
+    }
+    if (ha < D) {
+        a.rec_h[pos] = hh;
+        a.rec_n[pos] = n;
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu)
+            if (mu >= ha) a.rec_bin[(mu - ha) * a.rec_stride + pos] = (uint16_t)idx[mu];
+    }
+}
+
 template <int D, int PREC, bool MAPLDS, int KIND>
 __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(LaunchSet L)
 {
@@ -502,7 +528,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
 
     const int n_g = a.n_g;
     const int nbins = D * n_g;
-    const size_t hist_bytes = a.hist_lds ? (size_t)nbins * 16 : 0;
+    const int lbins = a.hist_axes * n_g;  // bins per LDS plane
+    const size_t hist_bytes = (size_t)lbins * 16;
     double* lds_hist = reinterpret_cast<double*>(lds_raw);
     float* lds_histf = reinterpret_cast<float*>(lds_raw);
     MapT* lds_map = reinterpret_cast<MapT*>(lds_raw + hist_bytes);
@@ -510,8 +537,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
     if constexpr (PREC == P_FP64) gmap = a.map;
     else gmap = a.map32;
 
-    if (a.hist_lds)
-        for (int i = threadIdx.x; i < 2 * nbins; i += blockDim.x) lds_hist[i] = 0.0;
+    for (int i = threadIdx.x; i < 2 * lbins; i += blockDim.x) lds_hist[i] = 0.0;
     if constexpr (MAPLDS)
         for (int i = threadIdx.x; i < D * (n_g + 1); i += blockDim.x) lds_map[i] = gmap[i];
     __syncthreads();
@@ -612,17 +638,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         const double v2 = v * v;
                         const double hh = literal ? v2 : v2 * inv_n;
                         const double hw = literal ? 1.0 : inv_n;
-#pragma unroll
-                        for (int mu = 0; mu < D; ++mu) {
-                            const int bin = mu * n_g + idx[mu];
-                            if (a.hist_lds) {
-                                atomicAdd(&lds_hist[bin], hh);
-                                atomicAdd(&lds_hist[nbins + bin], hw);
-                            } else {
-                                atomicAdd(&a.hist_glob[bin], hh);
-                                atomicAdd(&a.hist_glob[nbins + bin], hw);
-                            }
-                        }
+                        put_training<D>(a, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
                     } else if constexpr (PREC == P_FP32_ACC64) {
                         const float v32 = sample_fp32<D, MAPLDS>(a, map, j, hh32, k, idx, kind, K);
                         const double v = (double)v32;
@@ -631,17 +647,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         const double v2 = v * v;
                         const double hh = literal ? v2 : v2 * inv_n;
                         const double hw = literal ? 1.0 : inv_n;
-#pragma unroll
-                        for (int mu = 0; mu < D; ++mu) {
-                            const int bin = mu * n_g + idx[mu];
-                            if (a.hist_lds) {
-                                atomicAdd(&lds_hist[bin], hh);
-                                atomicAdd(&lds_hist[nbins + bin], hw);
-                            } else {
-                                atomicAdd(&a.hist_glob[bin], hh);
-                                atomicAdd(&a.hist_glob[nbins + bin], hw);
-                            }
-                        }
+                        put_training<D>(a, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
                     } else {
                         const float v32 = sample_fp32<D, MAPLDS>(a, map, j, hh32, k, idx, kind, K);
                         run.addf(v32);
@@ -652,8 +658,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
 #pragma unroll
                         for (int mu = 0; mu < D; ++mu) {
                             const int bin = mu * n_g + idx[mu];
-                            lds_add_compensated(&lds_histf[bin], &lds_histf[nbins + bin], hh);
-                            lds_add_compensated(&lds_histf[2 * nbins + bin], &lds_histf[3 * nbins + bin], hw);
+                            lds_add_compensated(&lds_histf[bin], &lds_histf[lbins + bin], hh);
+                            lds_add_compensated(&lds_histf[2 * lbins + bin], &lds_histf[3 * lbins + bin], hw);
                         }
                     }
                 }
@@ -764,15 +770,18 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
     if (lane == 0 && bad) atomicAdd(a.nonfinite, (unsigned long long)bad);
 
     __syncthreads();
-    if (a.hist_lds) {
+    {
         double* out = a.hist_part + (size_t)bid * 2 * nbins;
         if constexpr (PREC == P_FP32_NEUMAIER) {
-            for (int i = threadIdx.x; i < nbins; i += blockDim.x) {
-                out[i] = (double)lds_histf[i] + (double)lds_histf[nbins + i];
-                out[nbins + i] = (double)lds_histf[2 * nbins + i] + (double)lds_histf[3 * nbins + i];
+            for (int i = threadIdx.x; i < lbins; i += blockDim.x) {
+                out[i] = (double)lds_histf[i] + (double)lds_histf[lbins + i];
+                out[nbins + i] = (double)lds_histf[2 * lbins + i] + (double)lds_histf[3 * lbins + i];
             }
         } else {
-            for (int i = threadIdx.x; i < 2 * nbins; i += blockDim.x) out[i] = lds_hist[i];
+            for (int i = threadIdx.x; i < lbins; i += blockDim.x) {
+                out[i] = lds_hist[i];
+                out[nbins + i] = lds_hist[lbins + i];
+            }
         }
     }
 }

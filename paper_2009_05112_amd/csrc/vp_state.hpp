@@ -52,7 +52,9 @@ struct vp_problem {
     double omega, omega2, R;
     int32_t it;  // iteration index of the next iteration
     int32_t slot;  // history slot of the next iteration
-    // device state
+    // device state: every buffer lives in one allocation
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
     IntegrandDev* f_d = nullptr;
     double* map = nullptr;
     float* map32 = nullptr;
@@ -65,7 +67,11 @@ struct vp_problem {
     double* H = nullptr;
     double* W = nullptr;
     double* hist_part = nullptr;
-    double* hist_glob = nullptr;
+    double* rec_h = nullptr;
+    uint32_t* rec_n = nullptr;
+    uint16_t* rec_bin = nullptr;
+    int64_t rec_stride = 0;
+    int32_t rec_chunks = 0, rec_slices = 0, rec_axes = 0;
     EdgeRec* edges = nullptr;
     double* est_part = nullptr;
     double* hist_I = nullptr;
@@ -73,12 +79,13 @@ struct vp_problem {
     DevState* st = nullptr;
     ReqArgs req;                 // host copy of the argument record
     ReqArgs* d_req = nullptr;    // device table of one record
-    PlanBuilder planner;
+    PlanBuilder planner;         // single-problem plan, built on the first vp_iterate
     IterPlan plan;
+    bool plan_built = false;
     // sampling launch
     SampleEntry entry;
     int block, grid, chunk;
-    int hist_lds, map_lds;
+    int hist_axes, map_lds;
     size_t lds;
     int64_t n_waves;
     int32_t hist_cap;            // capacity of the estimate history

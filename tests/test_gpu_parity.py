@@ -114,14 +114,25 @@ def test_integrand_kinds_and_dims(ctx, dim, kind):
         step_and_compare(gp, op)
 
 
-def test_global_histogram_path(ctx):
-    """dim * N_g too large for LDS: training data through global atomics."""
-    rng = np.random.default_rng(3)
-    f = W.corr_gauss(rng, 21, s_max=0.2, cond=10.0)
-    p = W.Params(dim=21, n_ev=300_000, n_g=1000, n_iter=2, seed=5)
+@pytest.mark.parametrize("dim,n_ev,n_g,prec,hist", [
+    (21, 300_000, 1000, "fp64", "weighted"),     # 3 slices of 7 axes, 5 chunks
+    (11, 700_000, 1000, "fp64", "literal"),      # 2 slices (6 + 5 axes), counts exact
+    (4, 200_000, 4096, "fp64", "weighted"),      # N_g at its maximum: 2 slices of 2 axes
+    (21, 5_000, 1000, "fp64", "weighted"),       # one hypercube, one chunk
+    (12, 400_000, 1000, "fp32_acc64", "weighted"),
+])
+def test_training_records_path(ctx, dim, n_ev, n_g, prec, hist):
+    """dim * N_g too large for LDS: the sampler writes per-sample training
+    records, binned per axis slice in a second pass."""
+    rng = np.random.default_rng(dim)
+    f = W.corr_gauss(rng, dim, s_max=0.2, cond=10.0)
+    p = W.Params(dim=dim, n_ev=n_ev, n_g=n_g, n_iter=2, seed=5, precision=prec, hist_mode=hist)
     gp, op = _pair(ctx, p, f)
     for _ in range(2):
-        step_and_compare(gp, op)
+        if prec == "fp64":
+            step_and_compare(gp, op, exact_counts=(hist == "literal"))
+        else:
+            step_and_compare(gp, op, rtol=2e-6, rtol_hist=2e-6, floor=1e-12)
 
 
 def test_single_hypercube_spans_every_wave(ctx):
@@ -205,6 +216,10 @@ def test_invalid_arguments(ctx):
     gp = B.Problem(ctx, W.Params(dim=2, n_ev=100, n_g=10), f)
     with pytest.raises(B.VegaspError):
         gp.set_alloc(np.ones(gp.n_hc, dtype=np.int32))
+    too_many = np.full(gp.n_hc, 2, dtype=np.int32)
+    too_many[0] = 100 + 2 * gp.n_hc  # beyond n_ev + 2 n_hc: the buffers are sized for that bound
+    with pytest.raises(B.VegaspError):
+        gp.set_alloc(too_many)
     m = gp.map()
     m[0, 3] = m[0, 5]
     m[0, 4] = 0.0
