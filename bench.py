@@ -142,7 +142,9 @@ def run_batch(B, W, ctx, n_req):
         "samples": samples,
         "served": {"makespan_s": makespan, "samples_per_s": samples / makespan, **lat_summary(lat),
                    "steps": st["steps"], "graph_launches": st["graph_launches"],
-                   "peak_active": st["peak_active"], "mem_peak_bytes": st["mem_peak"]},
+                   "graph_captures": st["graph_captures"], "peak_active": st["peak_active"],
+                   "mem_peak_bytes": st["mem_peak"],
+                   "scheduler_s": {k: st[k] for k in ("t_admit", "t_plan", "t_step", "t_retire")}},
         "plain": {"makespan_s": float(sum(svc)), "samples_per_s": samples / sum(svc), **lat_summary(plain_lat)},
         "max_diff_in_sdev": agreement(served, plain),
     }
@@ -191,7 +193,9 @@ def run_stream(B, W, ctx, n_req, load):
         "samples": samples,
         "served": {"span_s": span, "samples_per_s": samples / span, **lat_summary(lat),
                    "steps": st["steps"], "graph_launches": st["graph_launches"],
-                   "peak_active": st["peak_active"], "mem_peak_bytes": st["mem_peak"]},
+                   "graph_captures": st["graph_captures"], "peak_active": st["peak_active"],
+                   "mem_peak_bytes": st["mem_peak"],
+                   "scheduler_s": {k: st[k] for k in ("t_admit", "t_plan", "t_step", "t_retire")}},
         "plain": {"busy_s": float(sum(svc)), "samples_per_s": samples / float(sum(svc)), **lat_summary(plain_lat)},
         "max_diff_in_sdev": agreement(served, plain),
     }
@@ -206,6 +210,8 @@ def main():
     ap.add_argument("--n-ev", type=int, default=100_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the precision split and serving sections")
+    ap.add_argument("--sections", default="split,batch,stream",
+                    help="extra sections to run after the headline steps (comma list of split, batch, stream)")
     ap.add_argument("--batch", type=int, default=4096, help="requests in the served batch")
     ap.add_argument("--stream", type=int, default=300, help="requests in the Poisson stream")
     ap.add_argument("--load", type=float, default=0.8, help="plain-path utilisation that sets the stream rate")
@@ -276,19 +282,24 @@ def main():
                      "exact": 1.0},
     }
     gp.close()
-    if not args.no_extra:
+    sections = set() if args.no_extra else set(x for x in args.sections.split(",") if x)
+    if "split" in sections:
         print("precision split ...", file=sys.stderr, flush=True)
         line["precision_split"] = run_split(B, W, ctx, args.n_ev, 10)
+    serving, latency = {}, {}
+    if "batch" in sections:
         print("served batch ...", file=sys.stderr, flush=True)
-        batch = run_batch(B, W, ctx, args.batch)
+        serving["batch"] = b = run_batch(B, W, ctx, args.batch)
+        latency.update({"batch_p50_s": b["served"]["p50_s"], "batch_p99_s": b["served"]["p99_s"],
+                        "batch_plain_p50_s": b["plain"]["p50_s"], "batch_plain_p99_s": b["plain"]["p99_s"]})
+    if "stream" in sections:
         print("served stream ...", file=sys.stderr, flush=True)
-        stream = run_stream(B, W, ctx, args.stream, args.load)
-        line["serving"] = {"batch": batch, "stream": stream}
-        line["latency"] = {"batch_p50_s": batch["served"]["p50_s"], "batch_p99_s": batch["served"]["p99_s"],
-                           "batch_plain_p50_s": batch["plain"]["p50_s"], "batch_plain_p99_s": batch["plain"]["p99_s"],
-                           "stream_p50_s": stream["served"]["p50_s"], "stream_p99_s": stream["served"]["p99_s"],
-                           "stream_plain_p50_s": stream["plain"]["p50_s"],
-                           "stream_plain_p99_s": stream["plain"]["p99_s"]}
+        serving["stream"] = t = run_stream(B, W, ctx, args.stream, args.load)
+        latency.update({"stream_p50_s": t["served"]["p50_s"], "stream_p99_s": t["served"]["p99_s"],
+                        "stream_plain_p50_s": t["plain"]["p50_s"], "stream_plain_p99_s": t["plain"]["p99_s"]})
+    if serving:
+        line["serving"] = serving
+        line["latency"] = latency
     ctx.close()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, f)

@@ -241,6 +241,10 @@ typedef struct {
     int32_t pad;
     int64_t mem_in_use;
     int64_t mem_peak;
+    /* seconds spent by the scheduler: admitting (creating device state),
+     * building plans and capturing graphs, running steps on the GPU
+     * (enqueue to completion), and retiring (results, freeing) */
+    double t_admit, t_plan, t_step, t_retire;
 } vp_server_stats;
 
 vp_status vp_server_create(vp_ctx* ctx, size_t mem_budget_bytes, int32_t max_slots, int32_t flags,

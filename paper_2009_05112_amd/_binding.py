@@ -56,7 +56,8 @@ class vp_server_stats(C.Structure):
                 ("failed", C.c_int64), ("samples", C.c_int64), ("graph_launches", C.c_int64),
                 ("graph_captures", C.c_int64), ("active", C.c_int32), ("pending", C.c_int32),
                 ("peak_active", C.c_int32), ("pad", C.c_int32), ("mem_in_use", C.c_int64),
-                ("mem_peak", C.c_int64)]
+                ("mem_peak", C.c_int64), ("t_admit", C.c_double), ("t_plan", C.c_double),
+                ("t_step", C.c_double), ("t_retire", C.c_double)]
 
 
 VP_SERVER_NO_GRAPH = 1

@@ -308,6 +308,49 @@ __global__ __launch_bounds__(kRecBlock) void k_hist_records(LaunchSet L)
     }
 }
 
+__global__ void k_init(InitArgs a)
+{
+    const int64_t nm = (int64_t)a.dim * (a.n_g + 1);
+    const int64_t n = max(nm, max(a.n_hc, a.nbins));
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < nm) {
+            const int d = (int)(i / (a.n_g + 1)), k = (int)(i - (int64_t)d * (a.n_g + 1));
+            const double lo = a.bounds[d], hi = a.bounds[a.dim + d];
+            const double v = k == a.n_g ? hi : lo + (hi - lo) * ((double)k / (double)a.n_g);
+            a.map[i] = v;
+            a.map32[i] = (float)v;
+        }
+        if (i < a.n_hc) {
+            a.n_h[i] = a.n0;
+            a.S1[i] = 0.0;
+            a.S2[i] = 0.0;
+        }
+        if (i < a.nbins) {
+            a.H[i] = 0.0;
+            a.W[i] = 0.0;
+        }
+    }
+}
+
+void launch_init(const InitArgs& a, hipStream_t s)
+{
+    const int64_t nm = (int64_t)a.dim * (a.n_g + 1);
+    const int64_t n = std::max(nm, std::max(a.n_hc, a.nbins));
+    const int64_t g = std::min<int64_t>(4096, std::max<int64_t>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(k_init, dim3((unsigned)g), dim3(256), 0, s, a);
+}
+
+__global__ void k_gather_states(DevState* const* states, int n, DevState* out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = *states[i];
+}
+
+void launch_gather_states(DevState* const* states, int n, DevState* out, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_gather_states, dim3((n + 255) / 256), dim3(256), 0, s, states, n, out);
+}
+
 __global__ void k_fill_f64(double* __restrict__ x, int64_t n, double v)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;

@@ -26,6 +26,21 @@ struct DevState {
 };
 
 inline int64_t scan_blocks(int64_t n_hc) { return (n_hc + kScanTile - 1) / kScanTile; }
+
+// Initial device state of a problem: the uniform map over [lower, upper]
+// (FP64 and its FP32 copy), the uniform allocation n0, zero sums.
+struct InitArgs {
+    const double* bounds;  // [2][dim]: lower, upper
+    double* map;
+    float* map32;
+    int32_t* n_h;
+    double *S1, *S2, *H, *W;
+    int64_t n_hc, nbins;
+    int32_t dim, n_g, n0;
+};
+void launch_init(const InitArgs& a, hipStream_t s);
+// Copies the estimate scalars of n problems into host-visible memory.
+void launch_gather_states(DevState* const* states, int n, DevState* out, hipStream_t s);
 void launch_fill_f64(double* x, int64_t n, double v, hipStream_t s);
 void launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s);
 int est_grid(int64_t n_hc);

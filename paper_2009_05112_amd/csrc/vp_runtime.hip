@@ -13,6 +13,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -175,7 +178,14 @@ void vp::problem_free(vp_problem* p)
 {
     if (!p) return;
     vp_ctx* ctx = p->ctx;
-    (void)hipFree(p->arena);
+    if (p->pool) {
+        // before any iteration ran, the initial copy from the staging image
+        // may still be queued
+        if (p->slot == 0 && !p->staging.empty()) (void)hipStreamSynchronize(ctx->stream);
+        p->pool->release(p->arena);
+    } else {
+        (void)hipFree(p->arena);
+    }
     for (auto e : p->ev_pending) (void)hipEventDestroy(e);
     for (auto e : p->ev_free) (void)hipEventDestroy(e);
     delete p;
@@ -381,6 +391,21 @@ struct Shape {
     int32_t rec_chunks, rec_slices, rec_axes;
 };
 
+// Resident sampling workgroups per CU; the query (and the kernel attribute it
+// sets) is made once per device, kernel, block size and LDS size.
+static int cached_occupancy(int device, const SampleEntry& e, int block, size_t lds)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, void*, int, size_t>, int> cache;
+    const auto key = std::make_tuple(device, (void*)e.launch, block, lds);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    const int occ = e.occupancy(block, lds);
+    cache[key] = occ;
+    return occ;
+}
+
 static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
                                Shape* sh)
 {
@@ -406,7 +431,7 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     sh->block = sh->entry.block;
     sh->lds = hb + (sh->map_lds ? mb : 0);
     sh->chunk = 8;
-    int occ = sh->entry.occupancy(sh->block, sh->lds);
+    int occ = cached_occupancy(ctx->device, sh->entry, sh->block, sh->lds);
     if (occ < 1) occ = 1;
     const int64_t n_tot_max = P->n_ev + 2 * nhc;
     const int64_t waves_per_block = sh->block / kWave;
@@ -435,9 +460,9 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
 
 // Byte offsets of a problem's device buffers inside its one allocation.  The
 // records the host writes at creation (integrand, scalars, argument record,
-// map) come first, so one copy initialises them.
+// map bounds) come first, so one copy initialises them.
 struct Layout {
-    size_t f_d, st, d_req, map, map32, head_end;
+    size_t f_d, st, d_req, bounds, head_end, map, map32;
     size_t n_h, offs, bsum, S1, S2, dh, H, W, hist, edges, est_part, hist_I, hist_V, rec_h, rec_n, rec_bin, total;
 };
 
@@ -454,9 +479,10 @@ static Layout layout_of(const vp_params* P, const Shape& sh)
     L.f_d = take(sizeof(IntegrandDev));
     L.st = take(sizeof(DevState));
     L.d_req = take(sizeof(ReqArgs));
+    L.bounds = take((size_t)2 * D * sizeof(double));
+    L.head_end = at;
     L.map = take((size_t)D * (NG + 1) * sizeof(double));
     L.map32 = take((size_t)D * (NG + 1) * sizeof(float));
-    L.head_end = at;
     L.n_h = take((size_t)nhc * sizeof(int32_t));
     L.offs = take((size_t)(nhc + 1) * sizeof(int64_t));
     L.bsum = take((size_t)(scan_blocks(nhc) + 1) * sizeof(int64_t));
@@ -492,7 +518,7 @@ vp_status vp::problem_bytes(vp_ctx* ctx, const vp_params* P, const vp_integrand*
 
 
 vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
-                             vp_problem** out)
+                             DevicePool* pool, vp_problem** out)
 {
     if (!ctx || !out) return fail(VP_ERR_INVALID_ARG, "ctx and out are required");
     *out = nullptr;
@@ -538,7 +564,14 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
     // device state: one allocation per problem
     const int64_t nbins = (int64_t)D * NG;
     const Layout lay = layout_of(P, sh);
-    hipError_t e = hipMalloc((void**)&p->arena, lay.total);
+    hipError_t e = hipSuccess;
+    if (pool) {
+        p->arena = pool->alloc(lay.total);
+        if (p->arena) p->pool = pool;
+        else e = hipErrorOutOfMemory;
+    } else {
+        e = hipMalloc((void**)&p->arena, lay.total);
+    }
     if (e != hipSuccess) {
         p->arena = nullptr;
         problem_free(p);
@@ -572,36 +605,43 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
     p->est_part = (double*)(base + lay.est_part);
     p->hist_I = (double*)(base + lay.hist_I);
     p->hist_V = (double*)(base + lay.hist_V);
-    // initial map (Sec. 2.3: start from a uniform grid), uniform allocation
-    std::vector<double> m((size_t)D * (NG + 1));
-    std::vector<float> m32(m.size());
-    for (int d = 0; d < D; ++d) {
-        const double a = p->lower[d], b = p->upper[d];
-        for (int i = 0; i < NG; ++i) m[(size_t)d * (NG + 1) + i] = a + (b - a) * ((double)i / (double)NG);
-        m[(size_t)d * (NG + 1) + NG] = b;
-    }
-    for (size_t i = 0; i < m.size(); ++i) m32[i] = (float)m[i];
-    // the head of the allocation (integrand, scalars, argument record, map)
-    // is staged on the host and copied at once
-    std::vector<char> head(lay.head_end, 0);
+    // the head of the allocation (integrand, scalars, argument record, map
+    // bounds) is staged on the host and copied at once; the initial map
+    // (Sec. 2.3: a uniform grid), the uniform allocation and the zero sums are
+    // written by one kernel
+    std::vector<char>& head = p->staging;
+    head.assign(lay.head_end, 0);
     memcpy(head.data() + lay.f_d, &p->fh, sizeof(IntegrandDev));
     fill_req(p);
     memcpy(head.data() + lay.d_req, &p->req, sizeof(ReqArgs));
-    memcpy(head.data() + lay.map, m.data(), m.size() * sizeof(double));
-    memcpy(head.data() + lay.map32, m32.data(), m32.size() * sizeof(float));
+    memcpy(head.data() + lay.bounds, p->lower.data(), D * sizeof(double));
+    memcpy(head.data() + lay.bounds + D * sizeof(double), p->upper.data(), D * sizeof(double));
     hipStream_t sm = ctx->stream;
     int64_t n0 = P->n_ev / nhc;
     if (n0 < 2) n0 = 2;
     e = hipMemcpyAsync(p->arena, head.data(), head.size(), hipMemcpyHostToDevice, sm);
     if (e == hipSuccess) {
-        launch_fill_i32(p->n_h, nhc, (int32_t)n0, sm);
-        launch_fill_f64(p->H, nbins, 0.0, sm);
-        launch_fill_f64(p->W, nbins, 0.0, sm);
-        launch_fill_f64(p->S1, nhc, 0.0, sm);
-        launch_fill_f64(p->S2, nhc, 0.0, sm);
+        InitArgs ia;
+        ia.bounds = (const double*)(base + lay.bounds);
+        ia.map = p->map;
+        ia.map32 = p->map32;
+        ia.n_h = p->n_h;
+        ia.S1 = p->S1;
+        ia.S2 = p->S2;
+        ia.H = p->H;
+        ia.W = p->W;
+        ia.n_hc = nhc;
+        ia.nbins = nbins;
+        ia.dim = D;
+        ia.n_g = NG;
+        ia.n0 = (int32_t)n0;
+        launch_init(ia, sm);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(sm);
+    // stream-ordered creation leaves the initialisation queued before the
+    // request's first kernels on the same stream (the staging copy lives in
+    // the problem until it is freed)
+    if (e == hipSuccess && !pool) e = hipStreamSynchronize(sm);
     if (e != hipSuccess) {
         problem_free(p);
         return fail(VP_ERR_DEVICE, "initialising problem state: %s", hipGetErrorString(e));
@@ -610,11 +650,25 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
     return VP_OK;
 }
 
+vp_status vp::result_from_state(const DevState& st, vp_result* out)
+{
+    out->mean = st.mean;
+    out->sdev = st.sdev;
+    out->chi2 = st.chi2;
+    out->dof = st.dof;
+    out->n_iter_done = st.n_iter_done;
+    out->n_evals = st.n_evals;
+    out->n_near_ties = (int64_t)st.ties;
+    out->n_nonfinite = (int64_t)st.nonfinite;
+    if (st.nonfinite) return fail(VP_ERR_NUMERIC, "%llu non-finite integrand values", st.nonfinite);
+    return VP_OK;
+}
+
 extern "C" {
 
 vp_status vp_problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, vp_problem** out)
 {
-    return problem_create(ctx, P, f, 0, out);
+    return problem_create(ctx, P, f, 0, nullptr, out);
 }
 
 vp_status vp_problem_destroy(vp_problem* p)
@@ -678,19 +732,10 @@ vp_status vp_result_get(vp_problem* p, vp_result* out, double* I_j, double* V_j,
     VP_HIP(hipStreamSynchronize(p->ctx->stream));
     DevState st;
     VP_HIP(hipMemcpy(&st, p->st, sizeof st, hipMemcpyDeviceToHost));
-    out->mean = st.mean;
-    out->sdev = st.sdev;
-    out->chi2 = st.chi2;
-    out->dof = st.dof;
-    out->n_iter_done = st.n_iter_done;
-    out->n_evals = st.n_evals;
-    out->n_near_ties = (int64_t)st.ties;
-    out->n_nonfinite = (int64_t)st.nonfinite;
     const int32_t n = std::min<int32_t>(cap, st.n_iter_done);
     if (I_j && n > 0) VP_HIP(hipMemcpy(I_j, p->hist_I, sizeof(double) * n, hipMemcpyDeviceToHost));
     if (V_j && n > 0) VP_HIP(hipMemcpy(V_j, p->hist_V, sizeof(double) * n, hipMemcpyDeviceToHost));
-    if (st.nonfinite) return fail(VP_ERR_NUMERIC, "%llu non-finite integrand values", st.nonfinite);
-    return VP_OK;
+    return result_from_state(st, out);
 }
 
 vp_status vp_map_get(vp_problem* p, double* map)

@@ -33,10 +33,10 @@ using namespace vp;
 
 namespace {
 
-// Sampling workgroups of a served request hold about this many samples, so a
-// step of many small requests does not pay per-workgroup LDS set-up and
-// flush for nearly empty workgroups.
-constexpr int64_t kServeSamplesPerWG = 65536;
+// Sampling workgroups of a served request hold about this many samples: small
+// requests still spread over many CUs (a step's launches are short), while
+// the per-workgroup LDS set-up and flush stay a few percent of the work.
+constexpr int64_t kServeSamplesPerWG = 8192;
 
 enum ReqState { R_PENDING = 0, R_ACTIVE = 1, R_DONE = 2, R_CANCELLED = 3, R_FAILED = 4 };
 
@@ -73,12 +73,29 @@ struct vp_server {
     bool stop = false;
     std::thread th;
     size_t mem_used = 0, mem_peak = 0;
-    vp_server_stats st;
+    vp_server_stats st;  // guarded by mu
+    struct {
+        int64_t steps = 0, graph_launches = 0, graph_captures = 0;
+        double t_admit = 0, t_plan = 0, t_step = 0, t_retire = 0;
+    } ss;  // the scheduler's own counters, published into st under mu
     PlanBuilder planner;
     IterPlan plan;
+    DevicePool pool;  // device memory of admitted requests
     bool plan_valid = false;
+    int64_t plan_steps = 0;  // steps run with the current plan
     hipGraphExec_t gexec = nullptr;
     std::chrono::steady_clock::time_point t0;
+    // gather of finished requests' estimates: pointers and results, host
+    // (pinned) and device copies, max_slots entries each
+    DevState** h_ptrs = nullptr;
+    DevState* h_out = nullptr;
+    DevState** d_ptrs = nullptr;
+    DevState* d_out = nullptr;
+
+    double tsec(std::chrono::steady_clock::time_point a) const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
+    }
 
     double now() const
     {
@@ -113,6 +130,18 @@ static void copy_request(ServedReq* r, const vp_params* P, const vp_integrand* f
     r->f.chol = f->kind == VP_F_CORR_GAUSS ? cp(r->chol, f->chol, (size_t)D * D) : nullptr;
 }
 
+static void free_gather(vp_server* s)
+{
+    (void)hipHostFree(s->h_ptrs);
+    (void)hipHostFree(s->h_out);
+    (void)hipFree(s->d_ptrs);
+    (void)hipFree(s->d_out);
+    s->h_ptrs = nullptr;
+    s->h_out = nullptr;
+    s->d_ptrs = nullptr;
+    s->d_out = nullptr;
+}
+
 static void drop_graph(vp_server* s)
 {
     if (s->gexec) {
@@ -121,12 +150,15 @@ static void drop_graph(vp_server* s)
     }
 }
 
-// Enqueues one step; returns false on a device error.
+// Runs one step and waits for it; returns false on a device error.  A plan is
+// launched directly on its first step and captured into a graph on its
+// second, so sets of requests that change every step pay no capture.
 static bool run_step(vp_server* s)
 {
     hipStream_t st = s->ctx->stream;
-    if (s->graphs) {
+    if (s->graphs && s->plan_steps >= 1) {
         if (!s->gexec) {
+            const auto t0 = std::chrono::steady_clock::now();
             hipGraph_t g = nullptr;
             if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
             enqueue_iteration(s->plan, st, nullptr, nullptr);
@@ -137,15 +169,24 @@ static bool run_step(vp_server* s)
                 s->gexec = nullptr;
                 return false;
             }
-            s->st.graph_captures += 1;
+            s->ss.graph_captures += 1;
+            s->ss.t_plan += s->tsec(t0);
         }
+        const auto t0 = std::chrono::steady_clock::now();
         if (hipGraphLaunch(s->gexec, st) != hipSuccess) return false;
-        s->st.graph_launches += 1;
-    } else {
-        enqueue_iteration(s->plan, st, nullptr, nullptr);
-        if (hipGetLastError() != hipSuccess) return false;
+        s->ss.graph_launches += 1;
+        const bool ok = hipStreamSynchronize(st) == hipSuccess;
+        s->ss.t_step += s->tsec(t0);
+        s->plan_steps += 1;
+        return ok;
     }
-    return hipStreamSynchronize(st) == hipSuccess;
+    const auto t0 = std::chrono::steady_clock::now();
+    enqueue_iteration(s->plan, st, nullptr, nullptr);
+    if (hipGetLastError() != hipSuccess) return false;
+    const bool ok = hipStreamSynchronize(st) == hipSuccess;
+    s->ss.t_step += s->tsec(t0);
+    s->plan_steps += 1;
+    return ok;
 }
 
 static void retire(vp_server* s, ServedReq* r, int state)
@@ -201,8 +242,9 @@ static void scheduler(vp_server* s)
             }
         }
         bool changed = false;
+        const auto t_adm = std::chrono::steady_clock::now();
         for (ServedReq* r : admit) {
-            vp_status st = problem_create(s->ctx, &r->P, &r->f, kServeSamplesPerWG, &r->prob);
+            vp_status st = problem_create(s->ctx, &r->P, &r->f, kServeSamplesPerWG, &s->pool, &r->prob);
             if (st != VP_OK) {
                 r->status = st;
                 r->err = vp_last_error();
@@ -213,6 +255,7 @@ static void scheduler(vp_server* s)
             s->active.push_back(r);
             changed = true;
         }
+        if (!admit.empty()) s->ss.t_admit += s->tsec(t_adm);
         // cancellations of active requests, and requests with nothing to do
         for (size_t i = 0; i < s->active.size();) {
             ServedReq* r = s->active[i];
@@ -232,11 +275,14 @@ static void scheduler(vp_server* s)
         }
         if (s->active.empty()) continue;
         if (changed || !s->plan_valid) {
+            const auto t_pl = std::chrono::steady_clock::now();
             std::vector<PlanReq> pr;
             pr.reserve(s->active.size());
             for (ServedReq* r : s->active) pr.push_back({&r->prob->req, r->prob->d_req, r->prob->entry, r->prob->lds});
             drop_graph(s);
+            s->plan_steps = 0;
             s->plan_valid = s->planner.build(pr, &s->plan) == hipSuccess;
+            s->ss.t_plan += s->tsec(t_pl);
             if (!s->plan_valid) {
                 for (ServedReq* r : s->active) {
                     r->status = VP_ERR_DEVICE;
@@ -250,30 +296,60 @@ static void scheduler(vp_server* s)
             s->st.peak_active = std::max<int32_t>(s->st.peak_active, (int32_t)s->active.size());
         }
         const bool ok = run_step(s);
-        s->st.steps += 1;
-        for (size_t i = 0; i < s->active.size();) {
-            ServedReq* r = s->active[i];
+        s->ss.steps += 1;
+        const auto t_ret = std::chrono::steady_clock::now();
+        std::vector<ServedReq*> keep, fin;
+        keep.reserve(s->active.size());
+        for (ServedReq* r : s->active) {
             if (!ok) {
                 r->status = VP_ERR_DEVICE;
                 r->err = "device error during a batched step";
-                s->active.erase(s->active.begin() + i);
                 retire(s, r, R_FAILED);
                 continue;
             }
             r->prob->it += 1;
             r->prob->slot += 1;
             r->iters_left -= 1;
-            if (r->iters_left <= 0) {
-                r->status = vp_result_get(r->prob, &r->res, nullptr, nullptr, 0);
-                if (r->status != VP_OK) r->err = vp_last_error();
-                s->active.erase(s->active.begin() + i);
-                retire(s, r, r->status == VP_OK || r->status == VP_ERR_NUMERIC ? R_DONE : R_FAILED);
-                s->plan_valid = false;
-                continue;
+            (r->iters_left <= 0 ? fin : keep).push_back(r);
+        }
+        s->active.swap(keep);
+        if (!fin.empty()) {
+            // the estimates of every finished request in one gather and copy
+            const int n = (int)fin.size();
+            for (int i = 0; i < n; ++i) s->h_ptrs[i] = fin[i]->prob->st;
+            hipStream_t st = s->ctx->stream;
+            bool got = hipMemcpyAsync(s->d_ptrs, s->h_ptrs, n * sizeof(DevState*), hipMemcpyHostToDevice, st) ==
+                       hipSuccess;
+            if (got) {
+                launch_gather_states(s->d_ptrs, n, s->d_out, st);
+                got = hipGetLastError() == hipSuccess &&
+                      hipMemcpyAsync(s->h_out, s->d_out, n * sizeof(DevState), hipMemcpyDeviceToHost, st) ==
+                          hipSuccess &&
+                      hipStreamSynchronize(st) == hipSuccess;
             }
-            ++i;
+            for (int i = 0; i < n; ++i) {
+                ServedReq* r = fin[i];
+                if (got) {
+                    r->status = result_from_state(s->h_out[i], &r->res);
+                    if (r->status != VP_OK) r->err = vp_last_error();
+                } else {
+                    r->status = VP_ERR_DEVICE;
+                    r->err = "reading the estimates failed";
+                }
+                retire(s, r, r->status == VP_OK || r->status == VP_ERR_NUMERIC ? R_DONE : R_FAILED);
+            }
+            s->plan_valid = false;
         }
         if (!ok) s->plan_valid = false;
+        s->ss.t_retire += s->tsec(t_ret);
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->st.steps = s->ss.steps;
+        s->st.graph_launches = s->ss.graph_launches;
+        s->st.graph_captures = s->ss.graph_captures;
+        s->st.t_admit = s->ss.t_admit;
+        s->st.t_plan = s->ss.t_plan;
+        s->st.t_step = s->ss.t_step;
+        s->st.t_retire = s->ss.t_retire;
     }
 }
 
@@ -297,7 +373,18 @@ vp_status vp_server_create(vp_ctx* ctx, size_t mem_budget_bytes, int32_t max_slo
     }
     vp_server* s = new vp_server();
     s->ctx = own;
+    if (hipHostMalloc((void**)&s->h_ptrs, sizeof(DevState*) * max_slots, 0) != hipSuccess ||
+        hipHostMalloc((void**)&s->h_out, sizeof(DevState) * max_slots, 0) != hipSuccess ||
+        hipMalloc((void**)&s->d_ptrs, sizeof(DevState*) * max_slots) != hipSuccess ||
+        hipMalloc((void**)&s->d_out, sizeof(DevState) * max_slots) != hipSuccess) {
+        free_gather(s);
+        vp_ctx_destroy(own);
+        delete s;
+        return fail(VP_ERR_OOM, "allocating the server's result buffers");
+    }
     s->budget = mem_budget_bytes;
+    // slabs of at most 1 GiB and a quarter of the budget
+    s->pool.set_slab_bytes(std::min<size_t>(size_t(1) << 30, mem_budget_bytes / 4));
     s->max_slots = max_slots;
     s->graphs = (flags & VP_SERVER_NO_GRAPH) == 0;
     memset(&s->st, 0, sizeof s->st);
@@ -444,6 +531,9 @@ vp_status vp_server_destroy(vp_server* s)
         if (kv.second->prob) problem_free(kv.second->prob);
         delete kv.second;
     }
+    (void)hipStreamSynchronize(s->ctx->stream);
+    s->pool.release_all();
+    free_gather(s);
     vp_ctx_destroy(s->ctx);
     delete s;
     return VP_OK;

@@ -11,6 +11,7 @@
 #include "vp_aux.hpp"
 #include "vp_internal.hpp"
 #include "vp_plan.hpp"
+#include "vp_pool.hpp"
 
 using vp::DevState;
 using vp::EdgeRec;
@@ -55,6 +56,8 @@ struct vp_problem {
     // device state: every buffer lives in one allocation
     char* arena = nullptr;
     size_t arena_bytes = 0;
+    vp::DevicePool* pool = nullptr;  // owner of the allocation, or none (own hipMalloc)
+    std::vector<char> staging;  // host image of the allocation's head (initial copy)
     IntegrandDev* f_d = nullptr;
     double* map = nullptr;
     float* map32 = nullptr;
@@ -104,11 +107,17 @@ vp_status fail(vp_status s, const char* fmt, ...);
 vp_status validate(const vp_params* P, const vp_integrand* f);
 // samples_per_wg > 0 sizes the sampling grid to about that many samples per
 // workgroup (serving: many requests share the GPU); 0 fills the GPU.
+// pool: the state is carved from the pool (a server's) instead of its own
+// hipMalloc, and its initialisation is queued on the context's stream without
+// waiting for it.
 vp_status problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
-                         vp_problem** out);
+                         DevicePool* pool, vp_problem** out);
 // Device bytes problem_create would allocate for these parameters.
 vp_status problem_bytes(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
                         size_t* bytes);
 void problem_free(vp_problem* p);
+// The caller's view of a problem's estimate scalars; VP_ERR_NUMERIC (result
+// still filled) when non-finite integrand values were seen.
+vp_status result_from_state(const DevState& st, vp_result* out);
 
 }  // namespace vp

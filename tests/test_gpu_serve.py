@@ -123,8 +123,9 @@ def test_eager_steps_equal_graph_replays(ctx, mix, alone):
 
 
 def test_graphs_are_replayed(ctx):
-    """Same-length requests submitted together run as one unchanged set: one
-    capture, then replays."""
+    """Same-length requests submitted together run as one unchanged set: the
+    set's first step is launched directly, the second captured, the rest
+    replayed."""
     s = B.Server(ctx)
     reqs = W.served_batch(n_req=6, seed=9, nev_log=(4.0, 4.5), n_iter=8, n_g=200)
     ts = [s.submit(r.params, r.integrand) for r in reqs]
@@ -133,8 +134,8 @@ def test_graphs_are_replayed(ctx):
         s.wait(t)
     st = s.stats()
     s.close()
-    assert st["graph_launches"] == st["steps"]
-    assert st["graph_captures"] < st["steps"]
+    assert st["graph_launches"] > st["graph_captures"] >= 1
+    assert st["graph_launches"] < st["steps"]
 
 
 def test_served_equals_single_problem_path(ctx, mix):
