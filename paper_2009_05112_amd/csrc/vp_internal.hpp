@@ -77,9 +77,9 @@ struct SampleArgs {
     // per sample position: the value added to the numerator, the sample's n_h,
     // and the increment index of each such axis ([dim - hist_axes][rec_stride])
     double* rec_h;
-    uint32_t* rec_n;
-    uint16_t* rec_bin;
-    int64_t rec_stride;
+    uint32_t* rec_n;        // = rec_h + rec_stride (as bytes: 8 rec_stride further)
+    uint16_t* rec_bin;      // = rec_n + rec_stride
+    int64_t rec_stride;     // a multiple of 64
     EdgeRec* edges;         // [2 * n_waves]
     unsigned long long* nonfinite;
     const IntegrandDev* f;
@@ -165,14 +165,14 @@ struct SampleEntry {
     int block;                  // workgroup size the kernel is built for
 };
 
-// Specialised kernel for (precision, integrand kind, dim, map in LDS), or an
-// entry with launch == nullptr when none is built.  kind 0: generic kernel.
-SampleEntry sample_entry(int prec, int kind, int dim, bool map_lds);
-SampleEntry sample_entry_fp64_gauss(int dim, bool map_lds);
-SampleEntry sample_entry_fp64_corr(int dim, bool map_lds);
-SampleEntry sample_entry_fp64_generic(int dim, bool map_lds);
-SampleEntry sample_entry_fp32acc(int kind, int dim, bool map_lds);
-SampleEntry sample_entry_fp32neu(int kind, int dim, bool map_lds);
+// Specialised kernel for (precision, integrand kind, dim, map in LDS,
+// training records), or an entry with launch == nullptr when none is built.
+SampleEntry sample_entry(int prec, int kind, int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp64_gauss(int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp64_corr(int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp64_generic(int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp32acc(int kind, int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp32neu(int kind, int dim, bool map_lds, bool rec);
 
 // sampling kernels' LDS needs (bytes) for histogram and map
 inline size_t hist_lds_bytes(int dim, int n_g) { return (size_t)dim * n_g * 2 * sizeof(double); }
@@ -181,6 +181,24 @@ constexpr int kRecBlock = 1024;
 inline size_t map_lds_bytes(int prec, int dim, int n_g)
 {
     return (size_t)dim * (n_g + 1) * (prec == P_FP64 ? sizeof(double) : sizeof(float));
+}
+
+// Integrand constants the sampling kernel stages in LDS after the training
+// data and the map: elements (double on the FP64 path, float otherwise).
+constexpr int kFcHead = 16;
+__host__ __device__ constexpr int fc_count(int kind, int dim)
+{
+    return kFcHead + 4 * dim + (kind == K_CORR_GAUSS ? dim * dim : 0);
+}
+__host__ __device__ constexpr size_t fc_lds_bytes(int prec, int kind, int dim)
+{
+    return (size_t)fc_count(kind, dim) * (prec == P_FP64 ? sizeof(double) : sizeof(float));
+}
+// Byte offset of the constants: after the training data and (when staged)
+// the map, rounded up to 16 bytes.
+__host__ __device__ constexpr size_t fc_lds_offset(size_t hist_bytes, bool map_lds, int prec, int dim, int n_g)
+{
+    return (hist_bytes + (map_lds ? (size_t)dim * (n_g + 1) * (prec == P_FP64 ? 8 : 4) : 0) + 15) / 16 * 16;
 }
 
 }  // namespace vp

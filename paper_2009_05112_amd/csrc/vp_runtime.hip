@@ -54,17 +54,17 @@ constexpr uint32_t kStateMagic = 0x56504C53u;  // "SLPV"
 }  // namespace
 
 // ---------------------------------------------------------------- helpers
-SampleEntry vp::sample_entry(int prec, int kind, int dim, bool map_lds)
+SampleEntry vp::sample_entry(int prec, int kind, int dim, bool map_lds, bool rec)
 {
     SampleEntry e = {nullptr, nullptr, 0};
     if (prec == P_FP64) {
-        if (kind == K_GAUSS_MIX) e = sample_entry_fp64_gauss(dim, map_lds);
-        else if (kind == K_CORR_GAUSS) e = sample_entry_fp64_corr(dim, map_lds);
-        if (!e.launch) e = sample_entry_fp64_generic(dim, map_lds);
+        if (kind == K_GAUSS_MIX) e = sample_entry_fp64_gauss(dim, map_lds, rec);
+        else if (kind == K_CORR_GAUSS) e = sample_entry_fp64_corr(dim, map_lds, rec);
+        if (!e.launch) e = sample_entry_fp64_generic(dim, map_lds, rec);
     } else if (prec == P_FP32_ACC64) {
-        e = sample_entry_fp32acc(kind, dim, map_lds);
+        e = sample_entry_fp32acc(kind, dim, map_lds, rec);
     } else if (prec == P_FP32_NEUMAIER) {
-        e = sample_entry_fp32neu(kind, dim, map_lds);
+        e = sample_entry_fp32neu(kind, dim, map_lds, rec);
     }
     return e;
 }
@@ -415,21 +415,25 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     for (int d = 0; d < D; ++d) nhc *= sh->n_st;
     sh->n_hc = nhc;
     const int prec = P->precision;
-    // training data: as many axes as fit privatised in LDS, the rest as records
-    const int fit = std::max<int>(1, (int)(ctx->lds_max / (2 * sizeof(double) * (size_t)NG)));
+    // training data: as many axes as fit privatised in LDS beside the
+    // integrand constants, the rest as records
+    const size_t fcb = fc_lds_bytes(prec, f->kind, D) + 16;
+    const int fit = std::max<int>(1, (int)((ctx->lds_max - fcb) / (2 * sizeof(double) * (size_t)NG)));
     sh->hist_axes = std::min(D, fit);
     if (prec == VP_FP32_NEUMAIER && sh->hist_axes < D)
         return fail(VP_ERR_INVALID_ARG, "compensated sums need dim * n_g * 16 <= %zu bytes of LDS", ctx->lds_max);
     const size_t hb = hist_lds_bytes(sh->hist_axes, NG), mb = map_lds_bytes(prec, D, NG);
-    sh->map_lds = hb + mb <= ctx->lds_max ? 1 : 0;
-    sh->entry = sample_entry(prec, f->kind, D, sh->map_lds != 0);
+    sh->map_lds = hb + mb + fcb <= ctx->lds_max ? 1 : 0;
+    const bool rec = sh->hist_axes < D;
+    if (rec) sh->map_lds = 0;
+    sh->entry = sample_entry(prec, f->kind, D, sh->map_lds != 0, rec);
     if (!sh->entry.launch && sh->map_lds) {
         sh->map_lds = 0;
-        sh->entry = sample_entry(prec, f->kind, D, false);
+        sh->entry = sample_entry(prec, f->kind, D, false, rec);
     }
     if (!sh->entry.launch) return fail(VP_ERR_INVALID_ARG, "no sampling kernel for dim %d", D);
     sh->block = sh->entry.block;
-    sh->lds = hb + (sh->map_lds ? mb : 0);
+    sh->lds = fc_lds_offset(hb, sh->map_lds != 0, prec, D, NG) + fc_lds_bytes(prec, f->kind, D);
     sh->chunk = 8;
     int occ = cached_occupancy(ctx->device, sh->entry, sh->block, sh->lds);
     if (occ < 1) occ = 1;
@@ -453,7 +457,9 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
         sh->rec_axes = (rem + sh->rec_slices - 1) / sh->rec_slices;
         const int64_t want = (2 * (int64_t)ctx->n_cu + sh->rec_slices - 1) / sh->rec_slices;
         sh->rec_chunks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(want, (n_tot_max + 65535) / 65536));
-        sh->rec_stride = n_tot_max;
+        // a multiple of 64, so that the three record arrays (8-, 4- and 2-byte
+        // elements) follow each other exactly at 256-byte boundaries
+        sh->rec_stride = (n_tot_max + 63) / 64 * 64;
     }
     return VP_OK;
 }
@@ -496,6 +502,8 @@ static Layout layout_of(const vp_params* P, const Shape& sh)
     L.est_part = take((size_t)3 * est_grid(nhc) * sizeof(double));
     L.hist_I = take((size_t)sh.hist_cap * sizeof(double));
     L.hist_V = take((size_t)sh.hist_cap * sizeof(double));
+    // records: values, counts and bins contiguous (the sampling kernel derives
+    // the second and third array from the first)
     L.rec_h = take((size_t)sh.rec_stride * sizeof(double));
     L.rec_n = take((size_t)sh.rec_stride * sizeof(uint32_t));
     L.rec_bin = take((size_t)sh.rec_stride * (D - sh.hist_axes) * sizeof(uint16_t));

@@ -229,123 +229,111 @@ struct FState {
     T t[D];
 };
 
-template <int D>
-__device__ __forceinline__ void f_axis(const IntegrandDev* __restrict__ f, int kind, int K, int mu,
-                                       double x, FState<D, double>& st)
+// Integrand constants staged in LDS once per workgroup (reading them from
+// LDS costs no VALU slot, while keeping the K*D centres and the Cholesky
+// factor in scalar registers spills).  Layout, in units of T (double on the
+// FP64 path, float on the split paths):
+//   [0] scale, [1] affine constant, [4..7] coefs, [8..11] amps, [12..15] radii^2,
+//   [16 + 4 mu + k] centre k of axis mu (the four terms of an axis adjacent),
+//   [16 + 4 D + d D + e] Cholesky factor (correlated Gaussian only).
+
+template <typename T>
+__device__ __forceinline__ T fc_value(const IntegrandDev* __restrict__ f, int kind, int D, int i)
 {
+    constexpr bool F64 = sizeof(T) == 8;
+    if (i < kFcHead) {
+        if (i == 0) return F64 ? (T)f->scale : (T)f->scale32;
+        if (i == 1) return kind == K_AFFINE ? (F64 ? (T)f->centers[0] : (T)f->centers32[0]) : (T)0;
+        if (i < 4) return (T)0;
+        const int k = i & 3;
+        if (i < 8) return F64 ? (T)f->coefs[k] : (T)f->coefs32[k];
+        if (i < 12) return F64 ? (T)f->amps[k] : (T)f->amps32[k];
+        return F64 ? (T)f->rad2[k] : (T)f->rad2_32[k];
+    }
+    i -= kFcHead;
+    if (i < 4 * D) {
+        const int mu = i >> 2, k = i & 3;
+        if (kind == K_GAUSS_MIX || kind == K_EXP_ABS || kind == K_BALLS)
+            return k < f->n_terms ? (F64 ? (T)f->centers[k * D + mu] : (T)f->centers32[k * D + mu]) : (T)0;
+        if (kind == K_CORR_GAUSS) return k == 0 ? (F64 ? (T)f->centers[mu] : (T)f->centers32[mu]) : (T)0;
+        if (kind == K_AFFINE) return k == 0 ? (F64 ? (T)f->centers[mu + 1] : (T)f->centers32[mu + 1]) : (T)0;
+        return (T)0;
+    }
+    i -= 4 * D;
+    return F64 ? (T)f->chol[i] : (T)f->chol32[i];
+}
+
+__device__ __forceinline__ double vexp(double x) { return exp(x); }
+__device__ __forceinline__ float vexp(float x) { return expf(x); }
+__device__ __forceinline__ double vsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float vsqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double vfma(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float vfma(float a, float b, float c) { return fmaf(a, b, c); }
+
+template <int D, typename T>
+__device__ __forceinline__ void f_axis(const T* __restrict__ fc, int kind, int K, int mu, T x, FState<D, T>& st)
+{
+    const T* c = fc + kFcHead + 4 * mu;
     if (kind == K_GAUSS_MIX || kind == K_EXP_ABS || kind == K_BALLS) {
+        T cv[kMaxTerms];
+#pragma unroll
+        for (int k = 0; k < kMaxTerms; ++k) cv[k] = c[k];
 #pragma unroll
         for (int k = 0; k < kMaxTerms; ++k) {
             if (k < K) {
-                const double tt = x - f->centers[k * D + mu];
-                st.q[k] = fma(tt, tt, st.q[k]);
+                const T tt = x - cv[k];
+                st.q[k] = vfma(tt, tt, st.q[k]);
             }
         }
     } else if (kind == K_CORR_GAUSS) {
-        st.t[mu] = x - f->centers[mu];
+        st.t[mu] = x - c[0];
     } else if (kind == K_AFFINE) {
-        st.lin = fma(f->centers[mu + 1], x, st.lin);
+        st.lin = vfma(c[0], x, st.lin);
     }
 }
 
-template <int D>
-__device__ __forceinline__ double f_finish(const IntegrandDev* __restrict__ f, int kind, int K,
-                                           FState<D, double>& st)
+template <int D, typename T>
+__device__ __forceinline__ T f_finish(const T* __restrict__ fc, int kind, int K, FState<D, T>& st)
 {
-    double acc = 0.0;
+    const T scale = fc[0];
+    const T* coefs = fc + 4;
+    const T* amps = fc + 8;
+    const T* rad2 = fc + 12;
+    T acc = (T)0;
     switch (kind) {
     case K_GAUSS_MIX:
 #pragma unroll
         for (int k = 0; k < kMaxTerms; ++k)
-            if (k < K) acc = fma(f->amps[k], exp(-(f->coefs[k] * st.q[k])), acc);
-        return f->scale * acc;
+            if (k < K) acc = vfma(amps[k], vexp(-(coefs[k] * st.q[k])), acc);
+        return scale * acc;
     case K_EXP_ABS:
 #pragma unroll
         for (int k = 0; k < kMaxTerms; ++k)
-            if (k < K) acc = fma(f->amps[k], exp(-(f->coefs[k] * sqrt(st.q[k]))), acc);
-        return f->scale * acc;
+            if (k < K) acc = vfma(amps[k], vexp(-(coefs[k] * vsqrt(st.q[k]))), acc);
+        return scale * acc;
     case K_BALLS:
 #pragma unroll
         for (int k = 0; k < kMaxTerms; ++k)
-            if (k < K && st.q[k] < f->rad2[k]) acc = acc + f->amps[k];
-        return f->scale * acc;
+            if (k < K && st.q[k] < rad2[k]) acc = acc + amps[k];
+        return scale * acc;
     case K_CORR_GAUSS: {
-        double q = 0.0;
+        const T* chol = fc + kFcHead + 4 * D;
+        T q = (T)0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            double z = 0.0;
+            T z = (T)0;
 #pragma unroll
-            for (int e = d; e < D; ++e) z = fma(f->chol[d * D + e], st.t[e], z);
-            q = fma(z, z, q);
+            for (int e = d; e < D; ++e) z = vfma(chol[d * D + e], st.t[e], z);
+            q = vfma(z, z, q);
         }
-        return f->scale * exp(-0.5 * q);
+        return scale * vexp((T)(-0.5) * q);
     }
     case K_CONST:
-        return f->scale;
+        return scale;
     case K_AFFINE:
-        return f->scale * st.lin;
+        return scale * st.lin;
     default:
-        return __builtin_nan("");
-    }
-}
-
-template <int D>
-__device__ __forceinline__ void f_axis32(const IntegrandDev* __restrict__ f, int kind, int K, int mu,
-                                         float x, FState<D, float>& st)
-{
-    if (kind == K_GAUSS_MIX || kind == K_EXP_ABS || kind == K_BALLS) {
-#pragma unroll
-        for (int k = 0; k < kMaxTerms; ++k) {
-            if (k < K) {
-                const float tt = x - f->centers32[k * D + mu];
-                st.q[k] = fmaf(tt, tt, st.q[k]);
-            }
-        }
-    } else if (kind == K_CORR_GAUSS) {
-        st.t[mu] = x - f->centers32[mu];
-    } else if (kind == K_AFFINE) {
-        st.lin = fmaf(f->centers32[mu + 1], x, st.lin);
-    }
-}
-
-template <int D>
-__device__ __forceinline__ float f_finish32(const IntegrandDev* __restrict__ f, int kind, int K,
-                                            FState<D, float>& st)
-{
-    float acc = 0.0f;
-    switch (kind) {
-    case K_GAUSS_MIX:
-#pragma unroll
-        for (int k = 0; k < kMaxTerms; ++k)
-            if (k < K) acc = fmaf(f->amps32[k], expf(-(f->coefs32[k] * st.q[k])), acc);
-        return f->scale32 * acc;
-    case K_EXP_ABS:
-#pragma unroll
-        for (int k = 0; k < kMaxTerms; ++k)
-            if (k < K) acc = fmaf(f->amps32[k], expf(-(f->coefs32[k] * sqrtf(st.q[k]))), acc);
-        return f->scale32 * acc;
-    case K_BALLS:
-#pragma unroll
-        for (int k = 0; k < kMaxTerms; ++k)
-            if (k < K && st.q[k] < f->rad2_32[k]) acc = acc + f->amps32[k];
-        return f->scale32 * acc;
-    case K_CORR_GAUSS: {
-        float q = 0.0f;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            float z = 0.0f;
-#pragma unroll
-            for (int e = d; e < D; ++e) z = fmaf(f->chol32[d * D + e], st.t[e], z);
-            q = fmaf(z, z, q);
-        }
-        return f->scale32 * expf(-0.5f * q);
-    }
-    case K_CONST:
-        return f->scale32;
-    case K_AFFINE:
-        return f->scale32 * st.lin;
-    default:
-        return __builtin_nanf("");
+        return (T)__builtin_nan("");
     }
 }
 
@@ -390,6 +378,14 @@ struct MapPair32 {
     }
 };
 
+// The per-request scalars the sample loop needs, read once before the loop.
+struct SampleHot {
+    uint32_t key0, key1, it;
+    int32_t n_g;
+    double R;
+    float R32;
+};
+
 // ---------------------------------------------------------------- one sample
 // Stratified y in hypercube k (Sec. 3): y^mu = (k_mu + u) / N_st, so
 // t = y N_g = (k_mu + u) R; vegas map (Sec. 2.2, Eqs. y and jac):
@@ -398,7 +394,7 @@ struct MapPair32 {
 // FP64: u from 53 bits -- the high word of axis mu is word mu of the
 // stream, its low word is word D + mu.
 template <int D, bool MAPLDS>
-__device__ __forceinline__ double sample_fp64(const SampleArgs& a, const MapPair64<MAPLDS>& map,
+__device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair64<MAPLDS>& map, const double* fc,
                                               uint32_t j, uint32_t h, const int32_t* k,
                                               int32_t* idx, int kind, int K)
 {
@@ -411,7 +407,7 @@ __device__ __forceinline__ double sample_fp64(const SampleArgs& a, const MapPair
     FState<D, double> st;
 #pragma unroll
     for (int kk = 0; kk < kMaxTerms; ++kk) st.q[kk] = 0.0;
-    st.lin = (kind == K_AFFINE) ? a.f->centers[0] : 0.0;
+    st.lin = fc[1];
     double jac = 1.0;
     uint32_t lo_blk[4];
     int lo_have = -1;  // index of the block held in lo_blk
@@ -443,15 +439,15 @@ __device__ __forceinline__ double sample_fp64(const SampleArgs& a, const MapPair
             const double x = fma(dx, delta, x0);
             jac = jac * ((double)n_g * dx);
             idx[mu] = i;
-            f_axis<D>(a.f, kind, K, mu, x, st);
+            f_axis<D, double>(fc, kind, K, mu, x, st);
         }
     }
-    return jac * f_finish<D>(a.f, kind, K, st);
+    return jac * f_finish<D, double>(fc, kind, K, st);
 }
 
 // FP32 split: u = (w >> 8) 2^-24 from the high word of each axis alone.
 template <int D, bool MAPLDS>
-__device__ __forceinline__ float sample_fp32(const SampleArgs& a, const MapPair32<MAPLDS>& map,
+__device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32<MAPLDS>& map, const float* fc,
                                              uint32_t j, uint32_t h, const int32_t* k, int32_t* idx,
                                              int kind, int K)
 {
@@ -460,7 +456,7 @@ __device__ __forceinline__ float sample_fp32(const SampleArgs& a, const MapPair3
     FState<D, float> st;
 #pragma unroll
     for (int kk = 0; kk < kMaxTerms; ++kk) st.q[kk] = 0.0f;
-    st.lin = (kind == K_AFFINE) ? a.f->centers32[0] : 0.0f;
+    st.lin = fc[1];
     float jac = 1.0f;
 #pragma unroll
     for (int g = 0; g < NG4; ++g) {
@@ -482,10 +478,10 @@ __device__ __forceinline__ float sample_fp32(const SampleArgs& a, const MapPair3
             const float x = fmaf(dx, delta, x0);
             jac = jac * ((float)n_g * dx);
             idx[mu] = i;
-            f_axis32<D>(a.f, kind, K, mu, x, st);
+            f_axis<D, float>(fc, kind, K, mu, x, st);
         }
     }
-    return jac * f_finish32<D>(a.f, kind, K, st);
+    return jac * f_finish<D, float>(fc, kind, K, st);
 }
 
 // ---------------------------------------------------------------- the kernel
@@ -494,12 +490,11 @@ __device__ __forceinline__ float sample_fp32(const SampleArgs& a, const MapPair3
 // Training data of one sample: atomics into the LDS bins of the privatised
 // axes, and for the other axes a record at the sample's position -- the
 // numerator value, n_h and those axes' increment indices (k_hist_records bins
-// them).
-template <int D>
-__device__ __forceinline__ void put_training(const SampleArgs& a, double* lds_hist, int lbins, int n_g, int64_t pos,
-                                             double hh, double hw, uint32_t n, const int32_t* idx)
+// them).  The three record arrays follow each other at rec (see SampleArgs).
+template <int D, bool REC>
+__device__ __forceinline__ void put_training(double* rec, int64_t stride, int ha, double* lds_hist, int lbins, int n_g,
+                                             int64_t pos, double hh, double hw, uint32_t n, const int32_t* idx)
 {
-    const int ha = a.hist_axes;
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) {
         if (mu < ha) {
@@ -508,27 +503,36 @@ __device__ __forceinline__ void put_training(const SampleArgs& a, double* lds_hi
             atomicAdd(&lds_hist[lbins + bin], hw);
         }
     }
-    if (ha < D) {
-        a.rec_h[pos] = hh;
-        a.rec_n[pos] = n;
+    if (REC && ha < D) {
+        uint32_t* rn = reinterpret_cast<uint32_t*>(rec + stride);
+        uint16_t* rb = reinterpret_cast<uint16_t*>(rn + stride);
+        rec[pos] = hh;
+        rn[pos] = n;
 #pragma unroll
         for (int mu = 0; mu < D; ++mu)
-            if (mu >= ha) a.rec_bin[(mu - ha) * a.rec_stride + pos] = (uint16_t)idx[mu];
+            if (mu >= ha) rb[(mu - ha) * stride + pos] = (uint16_t)idx[mu];
     }
 }
 
-template <int D, int PREC, bool MAPLDS, int KIND>
+// REC: some axes' training data go out as records (the bins of all D axes do
+// not fit in LDS); a separate instantiation, so that the common case carries
+// none of that code.
+template <int D, int PREC, bool MAPLDS, int KIND, bool REC>
 __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(LaunchSet L)
 {
     VP_REQ_PROLOGUE(L);
-    const SampleArgs a = q.s;
+    // The argument record stays in memory; the fields the loop needs are read
+    // into registers here, the others where they are used (a copy of the
+    // whole record would hold every field in scalar registers across the loop).
+    const SampleArgs& a = q.s;
     typedef typename AccOf<PREC>::type Acc;
     typedef typename std::conditional<PREC == P_FP64, double, float>::type MapT;
     extern __shared__ __align__(16) unsigned char lds_raw[];
 
     const int n_g = a.n_g;
     const int nbins = D * n_g;
-    const int lbins = a.hist_axes * n_g;  // bins per LDS plane
+    const int ha = REC ? a.hist_axes : D;  // axes privatised in LDS
+    const int lbins = ha * n_g;            // bins per LDS plane
     const size_t hist_bytes = (size_t)lbins * 16;
     double* lds_hist = reinterpret_cast<double*>(lds_raw);
     float* lds_histf = reinterpret_cast<float*>(lds_raw);
@@ -537,10 +541,25 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
     if constexpr (PREC == P_FP64) gmap = a.map;
     else gmap = a.map32;
 
+    const int kind = KIND ? KIND : a.f->kind;
+    const int K = a.f->n_terms;
+    MapT* lds_fc = reinterpret_cast<MapT*>(lds_raw + fc_lds_offset(hist_bytes, MAPLDS, PREC, D, n_g));
+
     for (int i = threadIdx.x; i < 2 * lbins; i += blockDim.x) lds_hist[i] = 0.0;
     if constexpr (MAPLDS)
         for (int i = threadIdx.x; i < D * (n_g + 1); i += blockDim.x) lds_map[i] = gmap[i];
+    for (int i = threadIdx.x; i < fc_count(kind, D); i += blockDim.x) lds_fc[i] = fc_value<MapT>(a.f, kind, D, i);
     __syncthreads();
+    // Gaussian-mixture constants (4 D + 16 values) are read into registers
+    // before the loop, where VALU instructions take them as scalar operands;
+    // the correlated Gaussian's D x D factor and the generic kernel read LDS.
+    constexpr bool FC_REG = (KIND == K_GAUSS_MIX);
+    MapT fcr[kFcHead + 4 * D];
+    if constexpr (FC_REG) {
+#pragma unroll
+        for (int i = 0; i < kFcHead + 4 * D; ++i) fcr[i] = fc_value<MapT>(a.f, kind, D, i);
+    }
+    const MapT* fcp = FC_REG ? fcr : lds_fc;
     typedef typename std::conditional<PREC == P_FP64, MapPair64<MAPLDS>, MapPair32<MAPLDS>>::type MapAcc;
     MapAcc map;
     map.lds = lds_map;
@@ -558,10 +577,20 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
     const int64_t s_a = n_tot * wave / n_waves;
     const int64_t s_b = n_tot * (wave + 1) / n_waves;
     const int C = a.chunk;
-    const int kind = KIND ? KIND : a.f->kind;
-    const int K = a.f->n_terms;
     const uint32_t n_st = (uint32_t)a.n_st;
     const bool literal = (a.hist_mode != 0);
+    double* __restrict__ S1 = a.S1;
+    double* __restrict__ S2 = a.S2;
+    EdgeRec* __restrict__ edges = a.edges;
+    double* rec = REC ? a.rec_h : nullptr;
+    const int64_t rec_stride = REC ? a.rec_stride : 0;
+    SampleHot hot;
+    hot.key0 = a.key0;
+    hot.key1 = a.key1;
+    hot.it = a.it;
+    hot.n_g = n_g;
+    hot.R = a.R;
+    hot.R32 = a.R32;
     uint32_t bad = 0;
 
     if (s_a < s_b) {
@@ -613,8 +642,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                             head_closed = true;
                             in_head = false;
                         } else {
-                            a.S1[hh32] = run.sa();
-                            a.S2[hh32] = run.sb();
+                            S1[hh32] = run.sa();
+                            S2[hh32] = run.sb();
                         }
                         run.zero();
                         ++hh32;
@@ -632,24 +661,24 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                     }
                     int32_t idx[D];
                     if constexpr (PREC == P_FP64) {
-                        const double v = sample_fp64<D, MAPLDS>(a, map, j, hh32, k, idx, kind, K);
+                        const double v = sample_fp64<D, MAPLDS>(hot, map, fcp, j, hh32, k, idx, kind, K);
                         run.add(v);
                         if (!isfinite(v)) ++bad;
                         const double v2 = v * v;
                         const double hh = literal ? v2 : v2 * inv_n;
                         const double hw = literal ? 1.0 : inv_n;
-                        put_training<D>(a, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
+                        put_training<D, REC>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
                     } else if constexpr (PREC == P_FP32_ACC64) {
-                        const float v32 = sample_fp32<D, MAPLDS>(a, map, j, hh32, k, idx, kind, K);
+                        const float v32 = sample_fp32<D, MAPLDS>(hot, map, fcp, j, hh32, k, idx, kind, K);
                         const double v = (double)v32;
                         run.add(v);
                         if (!isfinite(v32)) ++bad;
                         const double v2 = v * v;
                         const double hh = literal ? v2 : v2 * inv_n;
                         const double hw = literal ? 1.0 : inv_n;
-                        put_training<D>(a, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
+                        put_training<D, REC>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
                     } else {
-                        const float v32 = sample_fp32<D, MAPLDS>(a, map, j, hh32, k, idx, kind, K);
+                        const float v32 = sample_fp32<D, MAPLDS>(hot, map, fcp, j, hh32, k, idx, kind, K);
                         run.addf(v32);
                         if (!isfinite(v32)) ++bad;
                         const float v2 = v32 * v32;
@@ -670,8 +699,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         head_closed = true;
                         in_head = false;
                     } else {
-                        a.S1[hh32] = run.sa();
-                        a.S2[hh32] = run.sb();
+                        S1[hh32] = run.sa();
+                        S2[hh32] = run.sb();
                     }
                     run.zero();
                     h_end = (int64_t)hh32 + 1;
@@ -715,10 +744,10 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                     r.h = head_h;
                     r.s1 = tot.sa();
                     r.s2 = tot.sb();
-                    a.edges[2 * wave] = r;
+                    edges[2 * wave] = r;
                 } else {
-                    a.S1[head_h] = tot.sa();
-                    a.S2[head_h] = tot.sb();
+                    S1[head_h] = tot.sa();
+                    S2[head_h] = tot.sb();
                 }
             }
             // carry into the next tile: lane 63's inclusive map applied to the carry
@@ -746,14 +775,14 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                 r.s2 = carry.sb();
                 if (carry_ext) {
                     r.h = h_a;
-                    a.edges[2 * wave] = r;
-                    a.edges[2 * wave + 1] = empty;
+                    edges[2 * wave] = r;
+                    edges[2 * wave + 1] = empty;
                 } else {
                     r.h = h_open;
-                    a.edges[2 * wave + 1] = r;
+                    edges[2 * wave + 1] = r;
                 }
             } else {
-                a.edges[2 * wave + 1] = empty;
+                edges[2 * wave + 1] = empty;
             }
         }
     } else if (lane == 0) {
@@ -761,8 +790,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
         empty.h = -1;
         empty.s1 = 0.0;
         empty.s2 = 0.0;
-        a.edges[2 * wave] = empty;
-        a.edges[2 * wave + 1] = empty;
+        edges[2 * wave] = empty;
+        edges[2 * wave + 1] = empty;
     }
 
     // non-finite samples: one atomic per wave
@@ -786,32 +815,50 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
     }
 }
 
-template <int D, int PREC, bool MAPLDS, int KIND>
+template <int D, int PREC, bool MAPLDS, int KIND, bool REC>
 void launch_sample(const LaunchSet& L, int grid, int block, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sample<D, PREC, MAPLDS, KIND>), dim3(grid), dim3(block), lds, s, L);
+    hipLaunchKernelGGL((k_sample<D, PREC, MAPLDS, KIND, REC>), dim3(grid), dim3(block), lds, s, L);
 }
 
-template <int D, int PREC, bool MAPLDS, int KIND>
+template <int D, int PREC, bool MAPLDS, int KIND, bool REC>
 int sample_occupancy(int block, size_t lds)
 {
     int n = 0;
-    (void)hipFuncSetAttribute((const void*)k_sample<D, PREC, MAPLDS, KIND>,
+    (void)hipFuncSetAttribute((const void*)k_sample<D, PREC, MAPLDS, KIND, REC>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sample<D, PREC, MAPLDS, KIND>, block, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sample<D, PREC, MAPLDS, KIND, REC>, block, lds) !=
         hipSuccess)
         return 0;
     return n;
 }
 
-template <int D, int PREC, bool MAPLDS, int KIND>
+template <int D, int PREC, bool MAPLDS, int KIND, bool REC>
 SampleEntry make_entry()
 {
     SampleEntry e;
-    e.launch = launch_sample<D, PREC, MAPLDS, KIND>;
-    e.occupancy = sample_occupancy<D, PREC, MAPLDS, KIND>;
+    e.launch = launch_sample<D, PREC, MAPLDS, KIND, REC>;
+    e.occupancy = sample_occupancy<D, PREC, MAPLDS, KIND, REC>;
     e.block = sample_block(PREC, KIND, D, MAPLDS);
     return e;
+}
+
+// The instantiation for a layout: map in LDS (all training data in LDS), map
+// in global memory with all training data in LDS, or with records.
+template <int D, int PREC, int KIND>
+SampleEntry entry_for(bool map_lds, bool rec)
+{
+    if (map_lds) return rec ? SampleEntry{nullptr, nullptr, 0} : make_entry<D, PREC, true, KIND, false>();
+    return rec ? make_entry<D, PREC, false, KIND, true>() : make_entry<D, PREC, false, KIND, false>();
+}
+
+// The same without the map-in-LDS variant (kernels whose integrand leaves no
+// room for it).
+template <int D, int PREC, int KIND>
+SampleEntry entry_for_global(bool map_lds, bool rec)
+{
+    if (map_lds) return SampleEntry{nullptr, nullptr, 0};
+    return rec ? make_entry<D, PREC, false, KIND, true>() : make_entry<D, PREC, false, KIND, false>();
 }
 
 }  // namespace vp

@@ -1,49 +1,65 @@
 // vp_sample_fp32neu.hip -- instantiations of the fused sampling kernel: single-precision map and integrand, compensated single-precision sums, D = 1..16.
+// Written by gen_instances.py.
 #include "vp_sample.hpp"
 
 namespace vp {
 
-SampleEntry sample_entry_fp32neu(int kind, int dim, bool map_lds)
+// Compensated sums need every axis's bins in LDS: no record variants.
+template <int D, int PREC, int KIND>
+static SampleEntry entry_for_lds_only(bool map_lds, bool rec)
+{
+    if (rec) return SampleEntry{nullptr, nullptr, 0};
+    return map_lds ? make_entry<D, PREC, true, KIND, false>() : make_entry<D, PREC, false, KIND, false>();
+}
+
+template <int D, int PREC, int KIND>
+static SampleEntry entry_for_global_lds_only(bool map_lds, bool rec)
+{
+    if (rec || map_lds) return SampleEntry{nullptr, nullptr, 0};
+    return make_entry<D, PREC, false, KIND, false>();
+}
+
+SampleEntry sample_entry_fp32neu(int kind, int dim, bool map_lds, bool rec)
 {
     SampleEntry e = {nullptr, nullptr, 0};
     if (kind == K_GAUSS_MIX) {
         switch (dim) {
-        case 1: e = map_lds ? make_entry<1, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<1, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 2: e = map_lds ? make_entry<2, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<2, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 3: e = map_lds ? make_entry<3, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<3, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 4: e = map_lds ? make_entry<4, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<4, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 5: e = map_lds ? make_entry<5, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<5, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 6: e = map_lds ? make_entry<6, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<6, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 7: e = map_lds ? make_entry<7, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<7, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 8: e = map_lds ? make_entry<8, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<8, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 9: e = map_lds ? make_entry<9, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<9, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 10: e = map_lds ? make_entry<10, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<10, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 11: e = map_lds ? make_entry<11, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<11, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 12: e = map_lds ? make_entry<12, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<12, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 13: e = map_lds ? make_entry<13, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<13, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 14: e = map_lds ? make_entry<14, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<14, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 15: e = map_lds ? make_entry<15, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<15, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
-        case 16: e = map_lds ? make_entry<16, P_FP32_NEUMAIER, true, K_GAUSS_MIX>() : make_entry<16, P_FP32_NEUMAIER, false, K_GAUSS_MIX>(); break;
+        case 1: e = entry_for_lds_only<1, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 2: e = entry_for_lds_only<2, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 3: e = entry_for_lds_only<3, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 4: e = entry_for_lds_only<4, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 5: e = entry_for_lds_only<5, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 6: e = entry_for_lds_only<6, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 7: e = entry_for_lds_only<7, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 8: e = entry_for_lds_only<8, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 9: e = entry_for_lds_only<9, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 10: e = entry_for_lds_only<10, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 11: e = entry_for_lds_only<11, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 12: e = entry_for_lds_only<12, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 13: e = entry_for_lds_only<13, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 14: e = entry_for_lds_only<14, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 15: e = entry_for_lds_only<15, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
+        case 16: e = entry_for_lds_only<16, P_FP32_NEUMAIER, K_GAUSS_MIX>(map_lds, rec); break;
         default: break;
         }
     } else {
         switch (dim) {
-        case 1: if (!map_lds) e = make_entry<1, P_FP32_NEUMAIER, false, 0>(); break;
-        case 2: if (!map_lds) e = make_entry<2, P_FP32_NEUMAIER, false, 0>(); break;
-        case 3: if (!map_lds) e = make_entry<3, P_FP32_NEUMAIER, false, 0>(); break;
-        case 4: if (!map_lds) e = make_entry<4, P_FP32_NEUMAIER, false, 0>(); break;
-        case 5: if (!map_lds) e = make_entry<5, P_FP32_NEUMAIER, false, 0>(); break;
-        case 6: if (!map_lds) e = make_entry<6, P_FP32_NEUMAIER, false, 0>(); break;
-        case 7: if (!map_lds) e = make_entry<7, P_FP32_NEUMAIER, false, 0>(); break;
-        case 8: if (!map_lds) e = make_entry<8, P_FP32_NEUMAIER, false, 0>(); break;
-        case 9: if (!map_lds) e = make_entry<9, P_FP32_NEUMAIER, false, 0>(); break;
-        case 10: if (!map_lds) e = make_entry<10, P_FP32_NEUMAIER, false, 0>(); break;
-        case 11: if (!map_lds) e = make_entry<11, P_FP32_NEUMAIER, false, 0>(); break;
-        case 12: if (!map_lds) e = make_entry<12, P_FP32_NEUMAIER, false, 0>(); break;
-        case 13: if (!map_lds) e = make_entry<13, P_FP32_NEUMAIER, false, 0>(); break;
-        case 14: if (!map_lds) e = make_entry<14, P_FP32_NEUMAIER, false, 0>(); break;
-        case 15: if (!map_lds) e = make_entry<15, P_FP32_NEUMAIER, false, 0>(); break;
-        case 16: if (!map_lds) e = make_entry<16, P_FP32_NEUMAIER, false, 0>(); break;
+        case 1: e = entry_for_global_lds_only<1, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 2: e = entry_for_global_lds_only<2, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 3: e = entry_for_global_lds_only<3, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 4: e = entry_for_global_lds_only<4, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 5: e = entry_for_global_lds_only<5, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 6: e = entry_for_global_lds_only<6, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 7: e = entry_for_global_lds_only<7, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 8: e = entry_for_global_lds_only<8, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 9: e = entry_for_global_lds_only<9, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 10: e = entry_for_global_lds_only<10, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 11: e = entry_for_global_lds_only<11, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 12: e = entry_for_global_lds_only<12, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 13: e = entry_for_global_lds_only<13, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 14: e = entry_for_global_lds_only<14, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 15: e = entry_for_global_lds_only<15, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
+        case 16: e = entry_for_global_lds_only<16, P_FP32_NEUMAIER, 0>(map_lds, rec); break;
         default: break;
         }
     }

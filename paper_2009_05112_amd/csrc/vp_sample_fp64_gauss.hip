@@ -1,28 +1,29 @@
 // vp_sample_fp64_gauss.hip -- instantiations of the fused sampling kernel: double precision, Gaussian-mixture integrand, D = 1..16.
+// Written by gen_instances.py.
 #include "vp_sample.hpp"
 
 namespace vp {
 
-SampleEntry sample_entry_fp64_gauss(int dim, bool map_lds)
+SampleEntry sample_entry_fp64_gauss(int dim, bool map_lds, bool rec)
 {
     SampleEntry e = {nullptr, nullptr, 0};
     switch (dim) {
-    case 1: e = map_lds ? make_entry<1, P_FP64, true, K_GAUSS_MIX>() : make_entry<1, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 2: e = map_lds ? make_entry<2, P_FP64, true, K_GAUSS_MIX>() : make_entry<2, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 3: e = map_lds ? make_entry<3, P_FP64, true, K_GAUSS_MIX>() : make_entry<3, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 4: e = map_lds ? make_entry<4, P_FP64, true, K_GAUSS_MIX>() : make_entry<4, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 5: e = map_lds ? make_entry<5, P_FP64, true, K_GAUSS_MIX>() : make_entry<5, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 6: e = map_lds ? make_entry<6, P_FP64, true, K_GAUSS_MIX>() : make_entry<6, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 7: e = map_lds ? make_entry<7, P_FP64, true, K_GAUSS_MIX>() : make_entry<7, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 8: e = map_lds ? make_entry<8, P_FP64, true, K_GAUSS_MIX>() : make_entry<8, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 9: e = map_lds ? make_entry<9, P_FP64, true, K_GAUSS_MIX>() : make_entry<9, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 10: e = map_lds ? make_entry<10, P_FP64, true, K_GAUSS_MIX>() : make_entry<10, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 11: e = map_lds ? make_entry<11, P_FP64, true, K_GAUSS_MIX>() : make_entry<11, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 12: e = map_lds ? make_entry<12, P_FP64, true, K_GAUSS_MIX>() : make_entry<12, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 13: e = map_lds ? make_entry<13, P_FP64, true, K_GAUSS_MIX>() : make_entry<13, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 14: e = map_lds ? make_entry<14, P_FP64, true, K_GAUSS_MIX>() : make_entry<14, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 15: e = map_lds ? make_entry<15, P_FP64, true, K_GAUSS_MIX>() : make_entry<15, P_FP64, false, K_GAUSS_MIX>(); break;
-    case 16: e = map_lds ? make_entry<16, P_FP64, true, K_GAUSS_MIX>() : make_entry<16, P_FP64, false, K_GAUSS_MIX>(); break;
+    case 1: e = entry_for<1, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 2: e = entry_for<2, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 3: e = entry_for<3, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 4: e = entry_for<4, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 5: e = entry_for<5, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 6: e = entry_for<6, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 7: e = entry_for<7, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 8: e = entry_for<8, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 9: e = entry_for<9, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 10: e = entry_for<10, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 11: e = entry_for<11, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 12: e = entry_for<12, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 13: e = entry_for<13, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 14: e = entry_for<14, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 15: e = entry_for<15, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
+    case 16: e = entry_for<16, P_FP64, K_GAUSS_MIX>(map_lds, rec); break;
     default: break;
     }
     return e;
