@@ -13,8 +13,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvegasp.so")
-SOURCES = ["vp_runtime.hip", "vp_server.hip", "vp_aux.hip", "vp_sample_fp64_gauss.hip", "vp_sample_fp64_corr.hip",
-           "vp_sample_fp64_generic.hip", "vp_sample_fp32acc.hip", "vp_sample_fp32neu.hip"]
+def _instances():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("gen_instances", os.path.join(CSRC, "gen_instances.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.sources()
+
+
+# largest translation units first, so that they start compiling first
+SOURCES = _instances() + ["vp_runtime.hip", "vp_server.hip", "vp_aux.hip"]
 ARCH = os.environ.get("VEGASP_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

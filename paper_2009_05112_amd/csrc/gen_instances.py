@@ -10,33 +10,40 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# file, function, precision, [(kind condition, kind constant, dims, helper)], description
-TABLES = [
-    ("vp_sample_fp64_gauss.hip", "sample_entry_fp64_gauss(int dim, bool map_lds, bool rec)", "P_FP64",
-     [(None, "K_GAUSS_MIX", range(1, 17), "entry_for")],
-     "double precision, Gaussian-mixture integrand, D = 1..16"),
+# file, function, precision, [(kind condition, kind constant, dims, helper, terms)], description
+PRECS = [("fp64", "P_FP64", "double precision", "entry_for"),
+         ("fp32acc", "P_FP32_ACC64", "single-precision map and integrand, double sums", "entry_for"),
+         ("fp32neu", "P_FP32_NEUMAIER", "single-precision map and integrand, compensated single-precision sums",
+          "entry_for_lds_only")]
+TABLES = []
+for tag, prec, desc, helper in PRECS:
+    dmax = 16
+    for kt in range(1, 5):
+        TABLES.append((f"vp_sample_{tag}_gauss_k{kt}.hip",
+                       f"sample_entry_{tag}_gauss_k{kt}(int dim, bool map_lds, bool rec)", prec,
+                       [(None, "K_GAUSS_MIX", range(1, dmax + 1), helper, kt)],
+                       f"{desc}, Gaussian mixture of {kt} term{'s' if kt > 1 else ''}, D = 1..{dmax}"))
+TABLES += [
     ("vp_sample_fp64_corr.hip", "sample_entry_fp64_corr(int dim, bool map_lds, bool rec)", "P_FP64",
-     [(None, "K_CORR_GAUSS", range(1, 25), "entry_for_global")],
+     [(None, "K_CORR_GAUSS", range(1, 25), "entry_for_global", 0)],
      "double precision, correlated-Gaussian integrand, D = 1..24"),
     ("vp_sample_fp64_generic.hip", "sample_entry_fp64_generic(int dim, bool map_lds, bool rec)", "P_FP64",
-     [(None, "0", range(1, 25), "entry_for_global")],
+     [(None, "0", range(1, 25), "entry_for_global", 0)],
      "double precision, any integrand kind, D = 1..24"),
-    ("vp_sample_fp32acc.hip", "sample_entry_fp32acc(int kind, int dim, bool map_lds, bool rec)", "P_FP32_ACC64",
-     [("kind == K_GAUSS_MIX", "K_GAUSS_MIX", range(1, 17), "entry_for"),
-      ("true", "0", range(1, 17), "entry_for_global")],
-     "single-precision map and integrand, double sums, D = 1..16"),
-    ("vp_sample_fp32neu.hip", "sample_entry_fp32neu(int kind, int dim, bool map_lds, bool rec)", "P_FP32_NEUMAIER",
-     [("kind == K_GAUSS_MIX", "K_GAUSS_MIX", range(1, 17), "entry_for_lds_only"),
-      ("true", "0", range(1, 17), "entry_for_global_lds_only")],
-     "single-precision map and integrand, compensated single-precision sums, D = 1..16"),
+    ("vp_sample_fp32acc_generic.hip", "sample_entry_fp32acc_generic(int dim, bool map_lds, bool rec)",
+     "P_FP32_ACC64", [(None, "0", range(1, 17), "entry_for_global", 0)],
+     "single-precision map and integrand, double sums, any integrand kind, D = 1..16"),
+    ("vp_sample_fp32neu_generic.hip", "sample_entry_fp32neu_generic(int dim, bool map_lds, bool rec)",
+     "P_FP32_NEUMAIER", [(None, "0", range(1, 17), "entry_for_global_lds_only", 0)],
+     "single-precision map and integrand, compensated single-precision sums, any integrand kind, D = 1..16"),
 ]
 
 
-def switch(prec, kind, dims, helper, indent):
+def switch(prec, kind, dims, helper, kt, indent):
     pad = " " * indent
     out = [f"{pad}switch (dim) {{"]
     for d in dims:
-        out.append(f"{pad}case {d}: e = {helper}<{d}, {prec}, {kind}>(map_lds, rec); break;")
+        out.append(f"{pad}case {d}: e = {helper}<{d}, {prec}, {kind}, {kt}>(map_lds, rec); break;")
     out.append(f"{pad}default: break;")
     out.append(f"{pad}}}")
     return out
@@ -46,33 +53,17 @@ def render(fname, func, prec, parts, desc):
     lines = [f"// {fname} -- instantiations of the fused sampling kernel: {desc}.",
              "// Written by gen_instances.py.",
              '#include "vp_sample.hpp"', "", "namespace vp {", ""]
-    if prec == "P_FP32_NEUMAIER":
-        lines += ["// Compensated sums need every axis's bins in LDS: no record variants.",
-                  "template <int D, int PREC, int KIND>",
-                  "static SampleEntry entry_for_lds_only(bool map_lds, bool rec)",
-                  "{",
-                  "    if (rec) return SampleEntry{nullptr, nullptr, 0};",
-                  "    return map_lds ? make_entry<D, PREC, true, KIND, false>() : make_entry<D, PREC, false, KIND, false>();",
-                  "}", "",
-                  "template <int D, int PREC, int KIND>",
-                  "static SampleEntry entry_for_global_lds_only(bool map_lds, bool rec)",
-                  "{",
-                  "    if (rec || map_lds) return SampleEntry{nullptr, nullptr, 0};",
-                  "    return make_entry<D, PREC, false, KIND, false>();",
-                  "}", ""]
     lines += [f"SampleEntry {func}", "{", "    SampleEntry e = {nullptr, nullptr, 0};"]
-    if len(parts) == 1 and parts[0][0] is None:
-        _, kind, dims, helper = parts[0]
-        lines += switch(prec, kind, dims, helper, 4)
-    else:
-        for i, (cond, kind, dims, helper) in enumerate(parts):
-            head = f"    if ({cond}) {{" if i == 0 else ("    } else {" if cond == "true" else f"    }} else if ({cond}) {{")
-            lines.append(head)
-            lines += switch(prec, kind, dims, helper, 8)
-        lines.append("    }")
+    for cond, kind, dims, helper, kt in parts:
+        lines += switch(prec, kind, dims, helper, kt, 4)
     lines += ["    return e;", "}", "", "}  // namespace vp", ""]
     with open(os.path.join(HERE, fname), "w") as f:
         f.write("\n".join(lines))
+
+
+def sources():
+    """The generated translation units."""
+    return [t[0] for t in TABLES]
 
 
 def main():

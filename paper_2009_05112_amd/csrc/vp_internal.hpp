@@ -165,14 +165,23 @@ struct SampleEntry {
     int block;                  // workgroup size the kernel is built for
 };
 
-// Specialised kernel for (precision, integrand kind, dim, map in LDS,
-// training records), or an entry with launch == nullptr when none is built.
-SampleEntry sample_entry(int prec, int kind, int dim, bool map_lds, bool rec);
-SampleEntry sample_entry_fp64_gauss(int dim, bool map_lds, bool rec);
+// Specialised kernel for (precision, integrand kind and terms, dim, map in
+// LDS, training records), or an entry with launch == nullptr when none is
+// built.
+SampleEntry sample_entry(int prec, int kind, int n_terms, int dim, bool map_lds, bool rec);
+#define VP_DECL_GAUSS(tag)                                          \
+    SampleEntry sample_entry_##tag##_gauss_k1(int dim, bool map_lds, bool rec); \
+    SampleEntry sample_entry_##tag##_gauss_k2(int dim, bool map_lds, bool rec); \
+    SampleEntry sample_entry_##tag##_gauss_k3(int dim, bool map_lds, bool rec); \
+    SampleEntry sample_entry_##tag##_gauss_k4(int dim, bool map_lds, bool rec);
+VP_DECL_GAUSS(fp64)
+VP_DECL_GAUSS(fp32acc)
+VP_DECL_GAUSS(fp32neu)
+#undef VP_DECL_GAUSS
 SampleEntry sample_entry_fp64_corr(int dim, bool map_lds, bool rec);
 SampleEntry sample_entry_fp64_generic(int dim, bool map_lds, bool rec);
-SampleEntry sample_entry_fp32acc(int kind, int dim, bool map_lds, bool rec);
-SampleEntry sample_entry_fp32neu(int kind, int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp32acc_generic(int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp32neu_generic(int dim, bool map_lds, bool rec);
 
 // sampling kernels' LDS needs (bytes) for histogram and map
 inline size_t hist_lds_bytes(int dim, int n_g) { return (size_t)dim * n_g * 2 * sizeof(double); }

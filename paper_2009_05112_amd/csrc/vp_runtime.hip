@@ -54,18 +54,22 @@ constexpr uint32_t kStateMagic = 0x56504C53u;  // "SLPV"
 }  // namespace
 
 // ---------------------------------------------------------------- helpers
-SampleEntry vp::sample_entry(int prec, int kind, int dim, bool map_lds, bool rec)
+SampleEntry vp::sample_entry(int prec, int kind, int n_terms, int dim, bool map_lds, bool rec)
 {
+    typedef SampleEntry (*Table)(int, bool, bool);
+    static const Table gauss[3][4] = {
+        {sample_entry_fp64_gauss_k1, sample_entry_fp64_gauss_k2, sample_entry_fp64_gauss_k3, sample_entry_fp64_gauss_k4},
+        {sample_entry_fp32acc_gauss_k1, sample_entry_fp32acc_gauss_k2, sample_entry_fp32acc_gauss_k3,
+         sample_entry_fp32acc_gauss_k4},
+        {sample_entry_fp32neu_gauss_k1, sample_entry_fp32neu_gauss_k2, sample_entry_fp32neu_gauss_k3,
+         sample_entry_fp32neu_gauss_k4}};
+    static const Table generic[3] = {sample_entry_fp64_generic, sample_entry_fp32acc_generic,
+                                     sample_entry_fp32neu_generic};
     SampleEntry e = {nullptr, nullptr, 0};
-    if (prec == P_FP64) {
-        if (kind == K_GAUSS_MIX) e = sample_entry_fp64_gauss(dim, map_lds, rec);
-        else if (kind == K_CORR_GAUSS) e = sample_entry_fp64_corr(dim, map_lds, rec);
-        if (!e.launch) e = sample_entry_fp64_generic(dim, map_lds, rec);
-    } else if (prec == P_FP32_ACC64) {
-        e = sample_entry_fp32acc(kind, dim, map_lds, rec);
-    } else if (prec == P_FP32_NEUMAIER) {
-        e = sample_entry_fp32neu(kind, dim, map_lds, rec);
-    }
+    if (prec < 0 || prec > 2) return e;
+    if (kind == K_GAUSS_MIX && n_terms >= 1 && n_terms <= kMaxTerms) e = gauss[prec][n_terms - 1](dim, map_lds, rec);
+    else if (kind == K_CORR_GAUSS && prec == P_FP64) e = sample_entry_fp64_corr(dim, map_lds, rec);
+    if (!e.launch) e = generic[prec](dim, map_lds, rec);
     return e;
 }
 
@@ -426,10 +430,10 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     sh->map_lds = hb + mb + fcb <= ctx->lds_max ? 1 : 0;
     const bool rec = sh->hist_axes < D;
     if (rec) sh->map_lds = 0;
-    sh->entry = sample_entry(prec, f->kind, D, sh->map_lds != 0, rec);
+    sh->entry = sample_entry(prec, f->kind, f->n_terms, D, sh->map_lds != 0, rec);
     if (!sh->entry.launch && sh->map_lds) {
         sh->map_lds = 0;
-        sh->entry = sample_entry(prec, f->kind, D, false, rec);
+        sh->entry = sample_entry(prec, f->kind, f->n_terms, D, false, rec);
     }
     if (!sh->entry.launch) return fail(VP_ERR_INVALID_ARG, "no sampling kernel for dim %d", D);
     sh->block = sh->entry.block;

@@ -270,17 +270,19 @@ __device__ __forceinline__ float vsqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double vfma(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float vfma(float a, float b, float c) { return fmaf(a, b, c); }
 
-template <int D, typename T>
+// KT: number of terms fixed at compile time (0: the run-time K).
+template <int D, int KT, typename T>
 __device__ __forceinline__ void f_axis(const T* __restrict__ fc, int kind, int K, int mu, T x, FState<D, T>& st)
 {
+    constexpr int KN = KT ? KT : kMaxTerms;
     const T* c = fc + kFcHead + 4 * mu;
     if (kind == K_GAUSS_MIX || kind == K_EXP_ABS || kind == K_BALLS) {
-        T cv[kMaxTerms];
+        T cv[KN];
 #pragma unroll
-        for (int k = 0; k < kMaxTerms; ++k) cv[k] = c[k];
+        for (int k = 0; k < KN; ++k) cv[k] = c[k];
 #pragma unroll
-        for (int k = 0; k < kMaxTerms; ++k) {
-            if (k < K) {
+        for (int k = 0; k < KN; ++k) {
+            if (KT || k < K) {
                 const T tt = x - cv[k];
                 st.q[k] = vfma(tt, tt, st.q[k]);
             }
@@ -292,9 +294,10 @@ __device__ __forceinline__ void f_axis(const T* __restrict__ fc, int kind, int K
     }
 }
 
-template <int D, typename T>
+template <int D, int KT, typename T>
 __device__ __forceinline__ T f_finish(const T* __restrict__ fc, int kind, int K, FState<D, T>& st)
 {
+    constexpr int KN = KT ? KT : kMaxTerms;
     const T scale = fc[0];
     const T* coefs = fc + 4;
     const T* amps = fc + 8;
@@ -303,18 +306,18 @@ __device__ __forceinline__ T f_finish(const T* __restrict__ fc, int kind, int K,
     switch (kind) {
     case K_GAUSS_MIX:
 #pragma unroll
-        for (int k = 0; k < kMaxTerms; ++k)
-            if (k < K) acc = vfma(amps[k], vexp(-(coefs[k] * st.q[k])), acc);
+        for (int k = 0; k < KN; ++k)
+            if (KT || k < K) acc = vfma(amps[k], vexp(-(coefs[k] * st.q[k])), acc);
         return scale * acc;
     case K_EXP_ABS:
 #pragma unroll
-        for (int k = 0; k < kMaxTerms; ++k)
-            if (k < K) acc = vfma(amps[k], vexp(-(coefs[k] * vsqrt(st.q[k]))), acc);
+        for (int k = 0; k < KN; ++k)
+            if (KT || k < K) acc = vfma(amps[k], vexp(-(coefs[k] * vsqrt(st.q[k]))), acc);
         return scale * acc;
     case K_BALLS:
 #pragma unroll
-        for (int k = 0; k < kMaxTerms; ++k)
-            if (k < K && st.q[k] < rad2[k]) acc = acc + amps[k];
+        for (int k = 0; k < KN; ++k)
+            if ((KT || k < K) && st.q[k] < rad2[k]) acc = acc + amps[k];
         return scale * acc;
     case K_CORR_GAUSS: {
         const T* chol = fc + kFcHead + 4 * D;
@@ -393,7 +396,7 @@ struct SampleHot {
 // x = x_i + Delta x_i delta, J = prod_mu N_g Delta x_i.
 // FP64: u from 53 bits -- the high word of axis mu is word mu of the
 // stream, its low word is word D + mu.
-template <int D, bool MAPLDS>
+template <int D, bool MAPLDS, int KT>
 __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair64<MAPLDS>& map, const double* fc,
                                               uint32_t j, uint32_t h, const int32_t* k,
                                               int32_t* idx, int kind, int K)
@@ -439,14 +442,14 @@ __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair6
             const double x = fma(dx, delta, x0);
             jac = jac * ((double)n_g * dx);
             idx[mu] = i;
-            f_axis<D, double>(fc, kind, K, mu, x, st);
+            f_axis<D, KT, double>(fc, kind, K, mu, x, st);
         }
     }
-    return jac * f_finish<D, double>(fc, kind, K, st);
+    return jac * f_finish<D, KT, double>(fc, kind, K, st);
 }
 
 // FP32 split: u = (w >> 8) 2^-24 from the high word of each axis alone.
-template <int D, bool MAPLDS>
+template <int D, bool MAPLDS, int KT>
 __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32<MAPLDS>& map, const float* fc,
                                              uint32_t j, uint32_t h, const int32_t* k, int32_t* idx,
                                              int kind, int K)
@@ -478,10 +481,10 @@ __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32
             const float x = fmaf(dx, delta, x0);
             jac = jac * ((float)n_g * dx);
             idx[mu] = i;
-            f_axis<D, float>(fc, kind, K, mu, x, st);
+            f_axis<D, KT, float>(fc, kind, K, mu, x, st);
         }
     }
-    return jac * f_finish<D, float>(fc, kind, K, st);
+    return jac * f_finish<D, KT, float>(fc, kind, K, st);
 }
 
 // ---------------------------------------------------------------- the kernel
@@ -517,7 +520,8 @@ __device__ __forceinline__ void put_training(double* rec, int64_t stride, int ha
 // REC: some axes' training data go out as records (the bins of all D axes do
 // not fit in LDS); a separate instantiation, so that the common case carries
 // none of that code.
-template <int D, int PREC, bool MAPLDS, int KIND, bool REC>
+// KT: Gaussian-mixture terms fixed at compile time (0: read at run time).
+template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT>
 __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(LaunchSet L)
 {
     VP_REQ_PROLOGUE(L);
@@ -661,7 +665,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                     }
                     int32_t idx[D];
                     if constexpr (PREC == P_FP64) {
-                        const double v = sample_fp64<D, MAPLDS>(hot, map, fcp, j, hh32, k, idx, kind, K);
+                        const double v = sample_fp64<D, MAPLDS, KT>(hot, map, fcp, j, hh32, k, idx, kind, K);
                         run.add(v);
                         if (!isfinite(v)) ++bad;
                         const double v2 = v * v;
@@ -669,7 +673,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         const double hw = literal ? 1.0 : inv_n;
                         put_training<D, REC>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
                     } else if constexpr (PREC == P_FP32_ACC64) {
-                        const float v32 = sample_fp32<D, MAPLDS>(hot, map, fcp, j, hh32, k, idx, kind, K);
+                        const float v32 = sample_fp32<D, MAPLDS, KT>(hot, map, fcp, j, hh32, k, idx, kind, K);
                         const double v = (double)v32;
                         run.add(v);
                         if (!isfinite(v32)) ++bad;
@@ -678,7 +682,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         const double hw = literal ? 1.0 : inv_n;
                         put_training<D, REC>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
                     } else {
-                        const float v32 = sample_fp32<D, MAPLDS>(hot, map, fcp, j, hh32, k, idx, kind, K);
+                        const float v32 = sample_fp32<D, MAPLDS, KT>(hot, map, fcp, j, hh32, k, idx, kind, K);
                         run.addf(v32);
                         if (!isfinite(v32)) ++bad;
                         const float v2 = v32 * v32;
@@ -815,50 +819,65 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
     }
 }
 
-template <int D, int PREC, bool MAPLDS, int KIND, bool REC>
+template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT>
 void launch_sample(const LaunchSet& L, int grid, int block, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sample<D, PREC, MAPLDS, KIND, REC>), dim3(grid), dim3(block), lds, s, L);
+    hipLaunchKernelGGL((k_sample<D, PREC, MAPLDS, KIND, REC, KT>), dim3(grid), dim3(block), lds, s, L);
 }
 
-template <int D, int PREC, bool MAPLDS, int KIND, bool REC>
+template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT>
 int sample_occupancy(int block, size_t lds)
 {
     int n = 0;
-    (void)hipFuncSetAttribute((const void*)k_sample<D, PREC, MAPLDS, KIND, REC>,
+    (void)hipFuncSetAttribute((const void*)k_sample<D, PREC, MAPLDS, KIND, REC, KT>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sample<D, PREC, MAPLDS, KIND, REC>, block, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sample<D, PREC, MAPLDS, KIND, REC, KT>, block, lds) !=
         hipSuccess)
         return 0;
     return n;
 }
 
-template <int D, int PREC, bool MAPLDS, int KIND, bool REC>
+template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT>
 SampleEntry make_entry()
 {
     SampleEntry e;
-    e.launch = launch_sample<D, PREC, MAPLDS, KIND, REC>;
-    e.occupancy = sample_occupancy<D, PREC, MAPLDS, KIND, REC>;
+    e.launch = launch_sample<D, PREC, MAPLDS, KIND, REC, KT>;
+    e.occupancy = sample_occupancy<D, PREC, MAPLDS, KIND, REC, KT>;
     e.block = sample_block(PREC, KIND, D, MAPLDS);
     return e;
 }
 
 // The instantiation for a layout: map in LDS (all training data in LDS), map
 // in global memory with all training data in LDS, or with records.
-template <int D, int PREC, int KIND>
+template <int D, int PREC, int KIND, int KT = 0>
 SampleEntry entry_for(bool map_lds, bool rec)
 {
-    if (map_lds) return rec ? SampleEntry{nullptr, nullptr, 0} : make_entry<D, PREC, true, KIND, false>();
-    return rec ? make_entry<D, PREC, false, KIND, true>() : make_entry<D, PREC, false, KIND, false>();
+    if (map_lds) return rec ? SampleEntry{nullptr, nullptr, 0} : make_entry<D, PREC, true, KIND, false, KT>();
+    return rec ? make_entry<D, PREC, false, KIND, true, KT>() : make_entry<D, PREC, false, KIND, false, KT>();
 }
 
 // The same without the map-in-LDS variant (kernels whose integrand leaves no
 // room for it).
-template <int D, int PREC, int KIND>
+template <int D, int PREC, int KIND, int KT = 0>
 SampleEntry entry_for_global(bool map_lds, bool rec)
 {
     if (map_lds) return SampleEntry{nullptr, nullptr, 0};
-    return rec ? make_entry<D, PREC, false, KIND, true>() : make_entry<D, PREC, false, KIND, false>();
+    return rec ? make_entry<D, PREC, false, KIND, true, KT>() : make_entry<D, PREC, false, KIND, false, KT>();
+}
+
+// Compensated sums need every axis's bins in LDS: no record variants.
+template <int D, int PREC, int KIND, int KT = 0>
+SampleEntry entry_for_lds_only(bool map_lds, bool rec)
+{
+    if (rec) return SampleEntry{nullptr, nullptr, 0};
+    return map_lds ? make_entry<D, PREC, true, KIND, false, KT>() : make_entry<D, PREC, false, KIND, false, KT>();
+}
+
+template <int D, int PREC, int KIND, int KT = 0>
+SampleEntry entry_for_global_lds_only(bool map_lds, bool rec)
+{
+    if (rec || map_lds) return SampleEntry{nullptr, nullptr, 0};
+    return make_entry<D, PREC, false, KIND, false, KT>();
 }
 
 }  // namespace vp
