@@ -33,14 +33,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "integrand samples/sec/GPU (D=8, 1e8/iter) + p50/p99 solve latency vs plain"
-PEAK_VALU_SLOTS = 256 * 64 * 2.4e9  # lane-slots per second: 256 CUs x 64 lanes x 2.4 GHz
-# Algorithmic VALU lane-slots per sample of the fused sampling kernel at D=8
-# with three Gaussian terms (derivation in the design notes): Philox blocks
-# x 10 rounds x (2 wide multiplies at 4 slots + 2 three-way xors), the
-# uniform-to-increment arithmetic, the map, the integrand and the sums.
-# The compensated FP32 sums take 4 slots per addition instead of 1 for the two
+PEAK_VALU_SLOTS = 256 * 64 * 2.4e9  # full-rate VALU lane-operations per second: 256 CUs x 64 lanes x 2.4 GHz
+# Algorithmic VALU slots per sample of the fused sampling kernel at D=8 with
+# three Gaussian terms (derivation in the design notes; instruction costs
+# measured by paper_2009_05112_amd/isa_rates): Philox blocks x 10 rounds x
+# (2 full-rate 64-bit multiply-adds + 2 three-way xors), the uniform-to-
+# increment arithmetic, the map, the integrand and the sums.  FP32 operations
+# issue at twice the FP64/integer rate on gfx950 and count half a slot; the
+# compensated FP32 sums take 4 operations per addition for the two
 # per-hypercube sums and the 2D training-data values.
-SLOTS_PER_SAMPLE = {"fp64": 656.0, "fp32_acc64": 413.0, "fp32_neumaier": 413.0 + 3 * (2 + 2 * 8)}
+SLOTS_PER_SAMPLE = {"fp64": 416.0, "fp32_acc64": 204.0, "fp32_neumaier": 204.0 + 3 * (2 + 2 * 8)}
+COUNTERS = os.path.join(ROOT, "profiles", "k_sample_d8_fp64_counters.md")
+
+
+def measured_traffic(precision):
+    """HBM bytes per sampling launch from the committed counter summary, or
+    None when that summary is for other kernel sources (or another path)."""
+    import hashlib
+    if precision != "fp64" or not os.path.exists(COUNTERS):
+        return None
+    vals = {}
+    for line in open(COUNTERS):
+        line = line.strip()
+        for key in ("traffic_bytes_per_launch:", "sources_sha256:", "sources:"):
+            if line.startswith(key):
+                vals[key] = line[len(key):].strip()
+    if len(vals) != 3:
+        return None
+    h = hashlib.sha256()
+    for f in vals["sources:"].split():
+        path = os.path.join(ROOT, f)
+        if not os.path.exists(path):
+            return None
+        h.update(open(path, "rb").read())
+    if h.hexdigest() != vals["sources_sha256:"]:
+        return None
+    return float(vals["traffic_bytes_per_launch:"])
 
 
 def cpu_baseline(p, f, budget_s=12.0):
@@ -274,7 +302,8 @@ def main():
                                "normalised; N_ev=1e8 per iteration, N_g=1000, alpha=0.5, beta=0.75",
                    "dim": 8, "n_ev": args.n_ev, "n_g": 1000, "n_hc": gp.n_hc, "precision": args.precision},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
-                     "unit": "Tslot/s", "frac": achieved / PEAK_VALU_SLOTS, "traffic": None,
+                     "unit": "Tslot/s", "frac": achieved / PEAK_VALU_SLOTS,
+                     "traffic": measured_traffic(args.precision),
                      "kernel": "k_sample (fused sampling)", "kernel_ms": 1e3 * k_avg_s,
                      "slots_per_sample": SLOTS_PER_SAMPLE[args.precision]},
         "iteration_ms_device": it_ms / max(it_n, 1),

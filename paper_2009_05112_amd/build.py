@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvegasp.so")
+RATES = os.path.join(HERE, "isa_rates")  # instruction-rate diagnostic (not part of the library)
 def _instances():
     import importlib.util
     spec = importlib.util.spec_from_file_location("gen_instances", os.path.join(CSRC, "gen_instances.py"))
@@ -62,8 +63,12 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
+    r = subprocess.run([_hipcc()] + [f for f in FLAGS if f != "-fPIC"] +
+                       [os.path.join(CSRC, "isa_rates.hip"), "-o", RATES], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("isa_rates failed:\n" + r.stdout + r.stderr)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", RATES)
     return LIB
 
 
