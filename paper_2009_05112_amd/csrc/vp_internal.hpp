@@ -83,6 +83,7 @@ struct SampleArgs {
     EdgeRec* edges;         // [2 * n_waves]
     unsigned long long* nonfinite;
     const IntegrandDev* f;
+    const void* fc;         // integrand constants in the sampler's layout (double, or float on the split paths)
     int64_t n_hc;
     int32_t n_g, n_st;
     double R;               // n_g / n_st
@@ -192,8 +193,10 @@ inline size_t map_lds_bytes(int prec, int dim, int n_g)
     return (size_t)dim * (n_g + 1) * (prec == P_FP64 ? sizeof(double) : sizeof(float));
 }
 
-// Integrand constants the sampling kernel stages in LDS after the training
-// data and the map: elements (double on the FP64 path, float otherwise).
+// Integrand constants in the layout the sampling kernel reads (see
+// vp_sample.hpp): elements (double on the FP64 path, float otherwise).  They
+// are built on the host; kernels that stage them in LDS put them after the
+// training data and the map.
 constexpr int kFcHead = 16;
 __host__ __device__ constexpr int fc_count(int kind, int dim)
 {

@@ -246,6 +246,7 @@ static void fill_req(vp_problem* p)
     a.edges = p->edges;
     a.nonfinite = &p->st->nonfinite;
     a.f = p->f_d;
+    a.fc = p->fc;
     a.n_hc = p->n_hc;
     a.n_g = P.n_g;
     a.n_st = p->n_st;
@@ -395,6 +396,50 @@ struct Shape {
     int32_t rec_chunks, rec_slices, rec_axes;
 };
 
+// The integrand constants in the sampling kernel's layout (fc_count elements:
+// scale, affine constant, coefficients, amplitudes, radii^2, the K centres of
+// each axis side by side, the Cholesky factor), as double on the FP64 path and
+// as float on the split paths.
+static void write_constants(const IntegrandDev& f, int prec, int D, char* out)
+{
+    const int n = fc_count(f.kind, D);
+    const bool gauss_like = f.kind == VP_F_GAUSS_MIX || f.kind == VP_F_EXP_ABS || f.kind == VP_F_BALLS;
+    for (int i = 0; i < n; ++i) {
+        double v = 0.0;
+        float v32 = 0.0f;
+        if (i == 0) {
+            v = f.scale;
+            v32 = f.scale32;
+        } else if (i == 1) {
+            if (f.kind == VP_F_AFFINE) {
+                v = f.centers[0];
+                v32 = f.centers32[0];
+            }
+        } else if (i >= 4 && i < kFcHead) {
+            const int k = i & 3;
+            const double* src = i < 8 ? f.coefs : (i < 12 ? f.amps : f.rad2);
+            const float* src32 = i < 8 ? f.coefs32 : (i < 12 ? f.amps32 : f.rad2_32);
+            v = src[k];
+            v32 = src32[k];
+        } else if (i >= kFcHead && i < kFcHead + 4 * D) {
+            const int mu = (i - kFcHead) >> 2, k = (i - kFcHead) & 3;
+            int c = -1;
+            if (gauss_like && k < f.n_terms) c = k * D + mu;
+            else if (f.kind == VP_F_CORR_GAUSS && k == 0) c = mu;
+            else if (f.kind == VP_F_AFFINE && k == 0) c = mu + 1;
+            if (c >= 0) {
+                v = f.centers[c];
+                v32 = f.centers32[c];
+            }
+        } else if (i >= kFcHead + 4 * D) {
+            v = f.chol[i - kFcHead - 4 * D];
+            v32 = f.chol32[i - kFcHead - 4 * D];
+        }
+        if (prec == VP_FP64) memcpy(out + i * sizeof(double), &v, sizeof v);
+        else memcpy(out + i * sizeof(float), &v32, sizeof v32);
+    }
+}
+
 // Resident sampling workgroups per CU; the query (and the kernel attribute it
 // sets) is made once per device, kernel, block size and LDS size.
 static int cached_occupancy(int device, const SampleEntry& e, int block, size_t lds)
@@ -472,7 +517,7 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
 // records the host writes at creation (integrand, scalars, argument record,
 // map bounds) come first, so one copy initialises them.
 struct Layout {
-    size_t f_d, st, d_req, bounds, head_end, map, map32;
+    size_t f_d, st, d_req, bounds, fc, head_end, map, map32;
     size_t n_h, offs, bsum, S1, S2, dh, H, W, hist, edges, est_part, hist_I, hist_V, rec_h, rec_n, rec_bin, total;
 };
 
@@ -490,6 +535,7 @@ static Layout layout_of(const vp_params* P, const Shape& sh)
     L.st = take(sizeof(DevState));
     L.d_req = take(sizeof(ReqArgs));
     L.bounds = take((size_t)2 * D * sizeof(double));
+    L.fc = take(fc_lds_bytes(VP_FP64, VP_F_CORR_GAUSS, (int)D));
     L.head_end = at;
     L.map = take((size_t)D * (NG + 1) * sizeof(double));
     L.map32 = take((size_t)D * (NG + 1) * sizeof(float));
@@ -593,6 +639,7 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
     p->arena_bytes = lay.total;
     char* base = p->arena;
     p->f_d = (IntegrandDev*)(base + lay.f_d);
+    p->fc = base + lay.fc;
     p->st = (DevState*)(base + lay.st);
     p->d_req = (ReqArgs*)(base + lay.d_req);
     p->map = (double*)(base + lay.map);
@@ -628,6 +675,7 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
     memcpy(head.data() + lay.d_req, &p->req, sizeof(ReqArgs));
     memcpy(head.data() + lay.bounds, p->lower.data(), D * sizeof(double));
     memcpy(head.data() + lay.bounds + D * sizeof(double), p->upper.data(), D * sizeof(double));
+    write_constants(p->fh, P->precision, D, head.data() + lay.fc);
     hipStream_t sm = ctx->stream;
     int64_t n0 = P->n_ev / nhc;
     if (n0 < 2) n0 = 2;

@@ -229,39 +229,12 @@ struct FState {
     T t[D];
 };
 
-// Integrand constants staged in LDS once per workgroup (reading them from
-// LDS costs no VALU slot, while keeping the K*D centres and the Cholesky
-// factor in scalar registers spills).  Layout, in units of T (double on the
-// FP64 path, float on the split paths):
+// Integrand constants in the sampler's layout, built on the host in the
+// problem's device memory (SampleArgs::fc).  Layout, in units of T (double on
+// the FP64 path, float on the split paths):
 //   [0] scale, [1] affine constant, [4..7] coefs, [8..11] amps, [12..15] radii^2,
 //   [16 + 4 mu + k] centre k of axis mu (the four terms of an axis adjacent),
 //   [16 + 4 D + d D + e] Cholesky factor (correlated Gaussian only).
-
-template <typename T>
-__device__ __forceinline__ T fc_value(const IntegrandDev* __restrict__ f, int kind, int D, int i)
-{
-    constexpr bool F64 = sizeof(T) == 8;
-    if (i < kFcHead) {
-        if (i == 0) return F64 ? (T)f->scale : (T)f->scale32;
-        if (i == 1) return kind == K_AFFINE ? (F64 ? (T)f->centers[0] : (T)f->centers32[0]) : (T)0;
-        if (i < 4) return (T)0;
-        const int k = i & 3;
-        if (i < 8) return F64 ? (T)f->coefs[k] : (T)f->coefs32[k];
-        if (i < 12) return F64 ? (T)f->amps[k] : (T)f->amps32[k];
-        return F64 ? (T)f->rad2[k] : (T)f->rad2_32[k];
-    }
-    i -= kFcHead;
-    if (i < 4 * D) {
-        const int mu = i >> 2, k = i & 3;
-        if (kind == K_GAUSS_MIX || kind == K_EXP_ABS || kind == K_BALLS)
-            return k < f->n_terms ? (F64 ? (T)f->centers[k * D + mu] : (T)f->centers32[k * D + mu]) : (T)0;
-        if (kind == K_CORR_GAUSS) return k == 0 ? (F64 ? (T)f->centers[mu] : (T)f->centers32[mu]) : (T)0;
-        if (kind == K_AFFINE) return k == 0 ? (F64 ? (T)f->centers[mu + 1] : (T)f->centers32[mu + 1]) : (T)0;
-        return (T)0;
-    }
-    i -= 4 * D;
-    return F64 ? (T)f->chol[i] : (T)f->chol32[i];
-}
 
 __device__ __forceinline__ double vexp(double x) { return exp(x); }
 __device__ __forceinline__ float vexp(float x) { return expf(x); }
@@ -271,11 +244,13 @@ __device__ __forceinline__ double vfma(double a, double b, double c) { return fm
 __device__ __forceinline__ float vfma(float a, float b, float c) { return fmaf(a, b, c); }
 
 // KT: number of terms fixed at compile time (0: the run-time K).
-template <int D, int KT, typename T>
-__device__ __forceinline__ void f_axis(const T* __restrict__ fc, int kind, int K, int mu, T x, FState<D, T>& st)
+// FP: pointer to the constants -- LDS, or the constant address space (read
+// through the scalar cache into scalar registers).
+template <int D, int KT, typename T, typename FP>
+__device__ __forceinline__ void f_axis(FP fc, int kind, int K, int mu, T x, FState<D, T>& st)
 {
     constexpr int KN = KT ? KT : kMaxTerms;
-    const T* c = fc + kFcHead + 4 * mu;
+    const auto c = fc + kFcHead + 4 * mu;
     if (kind == K_GAUSS_MIX || kind == K_EXP_ABS || kind == K_BALLS) {
         T cv[KN];
 #pragma unroll
@@ -294,14 +269,14 @@ __device__ __forceinline__ void f_axis(const T* __restrict__ fc, int kind, int K
     }
 }
 
-template <int D, int KT, typename T>
-__device__ __forceinline__ T f_finish(const T* __restrict__ fc, int kind, int K, FState<D, T>& st)
+template <int D, int KT, typename T, typename FP>
+__device__ __forceinline__ T f_finish(FP fc, int kind, int K, FState<D, T>& st)
 {
     constexpr int KN = KT ? KT : kMaxTerms;
     const T scale = fc[0];
-    const T* coefs = fc + 4;
-    const T* amps = fc + 8;
-    const T* rad2 = fc + 12;
+    const auto coefs = fc + 4;
+    const auto amps = fc + 8;
+    const auto rad2 = fc + 12;
     T acc = (T)0;
     switch (kind) {
     case K_GAUSS_MIX:
@@ -320,7 +295,7 @@ __device__ __forceinline__ T f_finish(const T* __restrict__ fc, int kind, int K,
             if ((KT || k < K) && st.q[k] < rad2[k]) acc = acc + amps[k];
         return scale * acc;
     case K_CORR_GAUSS: {
-        const T* chol = fc + kFcHead + 4 * D;
+        const auto chol = fc + kFcHead + 4 * D;
         T q = (T)0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -396,8 +371,8 @@ struct SampleHot {
 // x = x_i + Delta x_i delta, J = prod_mu N_g Delta x_i.
 // FP64: u from 53 bits -- the high word of axis mu is word mu of the
 // stream, its low word is word D + mu.
-template <int D, bool MAPLDS, int KT>
-__device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair64<MAPLDS>& map, const double* fc,
+template <int D, bool MAPLDS, int KT, typename FP>
+__device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair64<MAPLDS>& map, FP fc,
                                               uint32_t j, uint32_t h, const int32_t* k,
                                               int32_t* idx, int kind, int K)
 {
@@ -442,15 +417,15 @@ __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair6
             const double x = fma(dx, delta, x0);
             jac = jac * ((double)n_g * dx);
             idx[mu] = i;
-            f_axis<D, KT, double>(fc, kind, K, mu, x, st);
+            f_axis<D, KT, double, FP>(fc, kind, K, mu, x, st);
         }
     }
-    return jac * f_finish<D, KT, double>(fc, kind, K, st);
+    return jac * f_finish<D, KT, double, FP>(fc, kind, K, st);
 }
 
 // FP32 split: u = (w >> 8) 2^-24 from the high word of each axis alone.
-template <int D, bool MAPLDS, int KT>
-__device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32<MAPLDS>& map, const float* fc,
+template <int D, bool MAPLDS, int KT, typename FP>
+__device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32<MAPLDS>& map, FP fc,
                                              uint32_t j, uint32_t h, const int32_t* k, int32_t* idx,
                                              int kind, int K)
 {
@@ -481,10 +456,10 @@ __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32
             const float x = fmaf(dx, delta, x0);
             jac = jac * ((float)n_g * dx);
             idx[mu] = i;
-            f_axis<D, KT, float>(fc, kind, K, mu, x, st);
+            f_axis<D, KT, float, FP>(fc, kind, K, mu, x, st);
         }
     }
-    return jac * f_finish<D, KT, float>(fc, kind, K, st);
+    return jac * f_finish<D, KT, float, FP>(fc, kind, K, st);
 }
 
 // ---------------------------------------------------------------- the kernel
@@ -552,18 +527,20 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
     for (int i = threadIdx.x; i < 2 * lbins; i += blockDim.x) lds_hist[i] = 0.0;
     if constexpr (MAPLDS)
         for (int i = threadIdx.x; i < D * (n_g + 1); i += blockDim.x) lds_map[i] = gmap[i];
-    for (int i = threadIdx.x; i < fc_count(kind, D); i += blockDim.x) lds_fc[i] = fc_value<MapT>(a.f, kind, D, i);
-    __syncthreads();
-    // Gaussian-mixture constants (4 D + 16 values) are read into registers
-    // before the loop, where VALU instructions take them as scalar operands;
-    // the correlated Gaussian's D x D factor and the generic kernel read LDS.
-    constexpr bool FC_REG = (KIND == K_GAUSS_MIX);
-    MapT fcr[kFcHead + 4 * D];
-    if constexpr (FC_REG) {
-#pragma unroll
-        for (int i = 0; i < kFcHead + 4 * D; ++i) fcr[i] = fc_value<MapT>(a.f, kind, D, i);
+    // Gaussian-mixture constants (4 D + 16 values) are read through the
+    // scalar cache at every sample, from the constant address space: the
+    // VALU takes them as scalar operands, and they occupy no register across
+    // the loop (held there for the whole loop, they spill).  The correlated
+    // Gaussian's D x D factor and the generic kernel's constants are staged
+    // in LDS.
+    constexpr bool FC_SMEM = (KIND == K_GAUSS_MIX);
+    typedef __attribute__((address_space(4))) const MapT ConstT;
+    ConstT* fcg = (ConstT*)a.fc;
+    if constexpr (!FC_SMEM) {
+        const MapT* src = reinterpret_cast<const MapT*>(a.fc);
+        for (int i = threadIdx.x; i < fc_count(kind, D); i += blockDim.x) lds_fc[i] = src[i];
     }
-    const MapT* fcp = FC_REG ? fcr : lds_fc;
+    __syncthreads();
     typedef typename std::conditional<PREC == P_FP64, MapPair64<MAPLDS>, MapPair32<MAPLDS>>::type MapAcc;
     MapAcc map;
     map.lds = lds_map;
@@ -664,8 +641,17 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         }
                     }
                     int32_t idx[D];
+                    // an offset the compiler cannot see through keeps the
+                    // scalar loads of the constants inside the loop
+                    ConstT* fcs = fcg;
+                    if constexpr (FC_SMEM) {
+                        int z;
+                        asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+                        fcs = fcg + z;
+                    }
                     if constexpr (PREC == P_FP64) {
-                        const double v = sample_fp64<D, MAPLDS, KT>(hot, map, fcp, j, hh32, k, idx, kind, K);
+                        const double v = (FC_SMEM ? sample_fp64<D, MAPLDS, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
+                                           : sample_fp64<D, MAPLDS, KT, const MapT*>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
                         run.add(v);
                         if (!isfinite(v)) ++bad;
                         const double v2 = v * v;
@@ -673,7 +659,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         const double hw = literal ? 1.0 : inv_n;
                         put_training<D, REC>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
                     } else if constexpr (PREC == P_FP32_ACC64) {
-                        const float v32 = sample_fp32<D, MAPLDS, KT>(hot, map, fcp, j, hh32, k, idx, kind, K);
+                        const float v32 = (FC_SMEM ? sample_fp32<D, MAPLDS, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
+                                           : sample_fp32<D, MAPLDS, KT, const MapT*>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
                         const double v = (double)v32;
                         run.add(v);
                         if (!isfinite(v32)) ++bad;
@@ -682,7 +669,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         const double hw = literal ? 1.0 : inv_n;
                         put_training<D, REC>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
                     } else {
-                        const float v32 = sample_fp32<D, MAPLDS, KT>(hot, map, fcp, j, hh32, k, idx, kind, K);
+                        const float v32 = (FC_SMEM ? sample_fp32<D, MAPLDS, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
+                                           : sample_fp32<D, MAPLDS, KT, const MapT*>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
                         run.addf(v32);
                         if (!isfinite(v32)) ++bad;
                         const float v2 = v32 * v32;

@@ -59,6 +59,7 @@ struct vp_problem {
     vp::DevicePool* pool = nullptr;  // owner of the allocation, or none (own hipMalloc)
     std::vector<char> staging;  // host image of the allocation's head (initial copy)
     IntegrandDev* f_d = nullptr;
+    const void* fc = nullptr;  // integrand constants in the sampler's layout
     double* map = nullptr;
     float* map32 = nullptr;
     int32_t* n_h = nullptr;
