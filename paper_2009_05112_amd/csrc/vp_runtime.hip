@@ -483,7 +483,7 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     if (!sh->entry.launch) return fail(VP_ERR_INVALID_ARG, "no sampling kernel for dim %d", D);
     sh->block = sh->entry.block;
     sh->lds = fc_lds_offset(hb, sh->map_lds != 0, prec, D, NG) + fc_lds_bytes(prec, f->kind, D);
-    sh->chunk = 8;
+    sh->chunk = 16;
     int occ = cached_occupancy(ctx->device, sh->entry, sh->block, sh->lds);
     if (occ < 1) occ = 1;
     const int64_t n_tot_max = P->n_ev + 2 * nhc;

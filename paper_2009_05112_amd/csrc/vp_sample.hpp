@@ -56,6 +56,17 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     out[3] = c3;
 }
 
+// 1/n for a sample count n >= 1: the hardware reciprocal refined by one
+// Newton step (within an ulp of the correctly rounded quotient; the weights
+// 1/n_h of the training data are compared at 1e-12).
+__device__ __forceinline__ double recip_count(uint32_t n)
+{
+    const double d = (double)n;
+    const double r = __builtin_amdgcn_rcp(d);
+    const double e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
 // ---------------------------------------------------------------- wave helpers
 __device__ __forceinline__ int64_t shfl64(int64_t v, int src)
 {
@@ -614,7 +625,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                     }
                 }
                 uint32_t n_cur = (uint32_t)(gofs(offs, ob, h + 1) - o_cur0);
-                double inv_n = 1.0 / (double)n_cur;
+                double inv_n = recip_count(n_cur);
                 float inv_n32 = 1.0f / (float)n_cur;
                 for (uint32_t s = (uint32_t)(s_l - s_a); s < s_end; ++s, ++j) {
                     if (s == next) {
@@ -632,12 +643,17 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         const uint32_t nn = (uint32_t)(gofs(offs, ob, (int64_t)hh32 + 1) - s_a);
                         n_cur = nn - next;
                         next = nn;
-                        inv_n = 1.0 / (double)n_cur;
+                        inv_n = recip_count(n_cur);
                         inv_n32 = 1.0f / (float)n_cur;
+                        // next hypercube: increment the last coordinate with
+                        // carry, without branches (the lanes of a wave switch
+                        // hypercubes at different samples)
+                        int32_t carry = 1;
 #pragma unroll
                         for (int m = D - 1; m >= 0; --m) {
-                            if (++k[m] < (int32_t)n_st) break;
-                            k[m] = 0;
+                            const int32_t v = k[m] + carry;
+                            carry = v == (int32_t)n_st ? 1 : 0;
+                            k[m] = carry ? 0 : v;
                         }
                     }
                     int32_t idx[D];
