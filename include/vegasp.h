@@ -67,6 +67,10 @@ vp_status vp_ctx_info(vp_ctx* ctx, int32_t* n_cu, int64_t* lds_bytes_per_block);
  *  VP_F_CONST:      scale
  *  VP_F_AFFINE:     scale * (a_0 + sum_d a_{d+1} x_d), a = centers[0..dim]
  *  VP_F_BALLS:      scale * sum_k amps[k] [ |x - c_k| < coefs[k] ], n_terms <= 4
+ *  VP_F_BATCH:      scale * (the user's function): a batched ("vectorised")
+ *                   integrand evaluated by `fn` on a whole iteration's
+ *                   samples at once (Sec. 1: vegas evaluates the integrand
+ *                   in batches).  Double precision only; not servable.
  * The host arrays are copied at create time. */
 enum {
     VP_F_GAUSS_MIX = 1,
@@ -74,8 +78,21 @@ enum {
     VP_F_EXP_ABS = 3,
     VP_F_CONST = 4,
     VP_F_AFFINE = 5,
-    VP_F_BALLS = 6
+    VP_F_BALLS = 6,
+    VP_F_BATCH = 100
 };
+
+/* A batched integrand.  Called from vp_iterate once per iteration, on the
+ * host thread that called it, after the library has written the iteration's
+ * n sample points to x_soa in device memory: x_soa[d * n + s] is coordinate d
+ * of sample s (structure of arrays, the samples of one hypercube adjacent).
+ * It must enqueue on hip_stream (a hipStream_t) work that writes f(x_s) to
+ * f_out[s], s < n (device memory), and may return before that work is done;
+ * the library's next kernels on the stream read f_out.  Both buffers belong
+ * to the library and are valid only during the call.  A non-zero return
+ * fails the iteration with VP_ERR_DEVICE. */
+typedef int (*vp_batch_fn)(void* user, void* hip_stream, int64_t n, int32_t dim, const double* x_soa,
+                           double* f_out);
 
 typedef struct {
     int32_t kind;
@@ -86,6 +103,8 @@ typedef struct {
     const double* amps;    /* host, n_terms */
     const double* chol;    /* host, dim*dim (VP_F_CORR_GAUSS only, else NULL) */
     double scale;
+    vp_batch_fn fn;        /* VP_F_BATCH only, else NULL */
+    void* user;            /* passed to fn unchanged */
 } vp_integrand;
 
 /* Arithmetic of the sampling path (the split is not in the paper):

@@ -30,11 +30,29 @@ class VegaspError(RuntimeError):
         self.status = status
 
 
+VP_F_BATCH = 100
+# int fn(void* user, void* hip_stream, int64 n, int32 dim, const double* x_soa, double* f_out)
+BATCH_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p)
+
+
 class vp_integrand(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("n_terms", C.c_int32),
                 ("centers", C.POINTER(C.c_double)), ("coefs", C.POINTER(C.c_double)),
                 ("amps", C.POINTER(C.c_double)), ("chol", C.POINTER(C.c_double)),
-                ("scale", C.c_double)]
+                ("scale", C.c_double), ("fn", C.c_void_p), ("user", C.c_void_p)]
+
+
+class BatchIntegrand:
+    """A batched integrand (VP_F_BATCH): ``fn`` is the address of a
+    vp_batch_fn (or a BATCH_FN callback object, kept alive here), ``user``
+    the pointer passed to it; the library multiplies its values by scale."""
+
+    def __init__(self, dim: int, fn, user=None, scale: float = 1.0):
+        self.dim = dim
+        self.scale = scale
+        self._fn_obj = fn if isinstance(fn, BATCH_FN) else None
+        self.fn = C.cast(fn, C.c_void_p).value if isinstance(fn, BATCH_FN) else int(fn)
+        self.user = user
 
 
 class vp_params(C.Structure):
@@ -165,7 +183,8 @@ class Context:
 
 
 def marshal(params, integrand):
-    """(vp_params, vp_integrand, keep-alive list) from workloads.Params / Integrand."""
+    """(vp_params, vp_integrand, keep-alive list) from workloads.Params and a
+    workloads.Integrand or a BatchIntegrand."""
     keep = []
     f = integrand
 
@@ -176,8 +195,12 @@ def marshal(params, integrand):
         keep.append(x)
         return _dp(x)
 
-    fi = vp_integrand(_KIND[f.kind], f.dim, f.n_terms, arr(f.centers), arr(f.coefs), arr(f.amps),
-                      arr(f.chol), float(f.scale))
+    if isinstance(f, BatchIntegrand):
+        keep.append(f)
+        fi = vp_integrand(VP_F_BATCH, f.dim, 0, None, None, None, None, float(f.scale), f.fn, f.user)
+    else:
+        fi = vp_integrand(_KIND[f.kind], f.dim, f.n_terms, arr(f.centers), arr(f.coefs), arr(f.amps),
+                          arr(f.chol), float(f.scale), None, None)
     p = params
     pp = vp_params(p.dim, int(p.n_ev), p.n_g, p.n_iter, float(p.alpha), float(p.beta), arr(p.lower),
                    arr(p.upper), int(p.seed) & ((1 << 64) - 1), _PREC[p.precision], _HIST[p.hist_mode],
@@ -376,9 +399,46 @@ class Server:
             pass
 
 
-def declared_symbols() -> list:
+EXAMPLES_PATH = os.path.join(HERE, "libvegasp_examples.so")
+_examples = None
+
+
+def examples():
+    """libvegasp_examples.so (include/vegasp_examples.h): example batched
+    integrands; raises if it has not been built."""
+    global _examples
+    if _examples is None:
+        if not os.path.exists(EXAMPLES_PATH):
+            raise RuntimeError(f"{EXAMPLES_PATH} is missing: build it first")
+        L = C.CDLL(EXAMPLES_PATH)
+        dp = C.POINTER(C.c_double)
+        L.vp_example_gauss_mix_user.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, C.POINTER(C.c_void_p)]
+        L.vp_example_gauss_mix_user.restype = C.c_int
+        L.vp_example_free_user.argtypes = [C.c_void_p]
+        L.vp_example_free_user.restype = C.c_int
+        _examples = L
+    return _examples
+
+
+def example_gauss_mix(integrand):
+    """A BatchIntegrand evaluating a workloads gauss_mix Integrand through the
+    example library (same operations as the built-in kind)."""
+    L = examples()
+    f = integrand
+    c = np.ascontiguousarray(f.centers, dtype=np.float64).ravel()
+    k = np.ascontiguousarray(f.coefs, dtype=np.float64)
+    a = np.ascontiguousarray(f.amps, dtype=np.float64)
+    user = C.c_void_p()
+    rc = L.vp_example_gauss_mix_user(f.dim, f.n_terms, _dp(c), _dp(k), _dp(a), C.byref(user))
+    if rc != 0:
+        raise VegaspError(VP_ERR_INVALID_ARG, f"vp_example_gauss_mix_user returned {rc}")
+    fn = C.cast(L.vp_example_gauss_mix, C.c_void_p).value
+    return BatchIntegrand(f.dim, fn, user.value, scale=f.scale)
+
+
+def declared_symbols(header: str = HEADER) -> list:
     """Function names declared in include/vegasp.h."""
     import re
-    src = open(HEADER).read()
+    src = open(header).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(vp_\w+)\s*\(", src, flags=re.M)))

@@ -30,6 +30,15 @@ TABLES += [
     ("vp_sample_fp64_generic.hip", "sample_entry_fp64_generic(int dim, bool map_lds, bool rec)", "P_FP64",
      [(None, "0", range(1, 25), "entry_for_global", 0)],
      "double precision, any integrand kind, D = 1..24"),
+    ("vp_sample_fp64_batch.hip", "sample_entry_fp64_batch_acc(int dim, bool map_lds, bool rec)", "P_FP64",
+     [(None, "K_BATCH_ACC", range(1, 25), "entry_for_global", 0)],
+     "double precision, batched integrand (accumulation of the user's values), D = 1..24",
+     ["SampleEntry sample_entry_fp64_batch_gen(int dim)",
+      "{",
+      "    SampleEntry e = {nullptr, nullptr, 0};",
+      "    switch (dim) {"] +
+     [f"    case {d}: e = make_entry<{d}, P_FP64, false, K_BATCH_GEN, false, 0>(); break;" for d in range(1, 25)] +
+     ["    default: break;", "    }", "    return e;", "}", ""]),
     ("vp_sample_fp32acc_generic.hip", "sample_entry_fp32acc_generic(int dim, bool map_lds, bool rec)",
      "P_FP32_ACC64", [(None, "0", range(1, 17), "entry_for_global", 0)],
      "single-precision map and integrand, double sums, any integrand kind, D = 1..16"),
@@ -49,10 +58,11 @@ def switch(prec, kind, dims, helper, kt, indent):
     return out
 
 
-def render(fname, func, prec, parts, desc):
+def render(fname, func, prec, parts, desc, extra=()):
     lines = [f"// {fname} -- instantiations of the fused sampling kernel: {desc}.",
              "// Written by gen_instances.py.",
              '#include "vp_sample.hpp"', "", "namespace vp {", ""]
+    lines += list(extra)
     lines += [f"SampleEntry {func}", "{", "    SampleEntry e = {nullptr, nullptr, 0};"]
     for cond, kind, dims, helper, kt in parts:
         lines += switch(prec, kind, dims, helper, kt, 4)

@@ -780,14 +780,24 @@ hipError_t aux_init(size_t lds_max)
     return e;
 }
 
-void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin, hipEvent_t sample_end)
+void enqueue_head(const IterPlan& P, hipStream_t s)
 {
     launch(k_scan_local, P.scan_local, P.n_scan_local, kScanBlock, 0, s);
     launch(k_scan_top, P.one, P.n_one, kScanBlock, 0, s);
+}
+
+void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin, hipEvent_t sample_end)
+{
+    enqueue_head(P, s);
     if (sample_begin) (void)hipEventRecord(sample_begin, s);
     for (int g = 0; g < P.n_groups; ++g)
         P.groups[g].entry.launch(P.groups[g].L, P.groups[g].blocks, P.groups[g].entry.block, P.groups[g].lds, s);
     if (sample_end) (void)hipEventRecord(sample_end, s);
+    enqueue_tail(P, s);
+}
+
+void enqueue_tail(const IterPlan& P, hipStream_t s)
+{
     launch(k_hist_records, P.rec, P.n_rec, kRecBlock, P.rec_lds, s);
     launch(k_edge_fixup, P.fixup, P.n_fixup, kFixBlock, 0, s);
     launch(k_hist_reduce, P.hist, P.n_hist, 256, 0, s);

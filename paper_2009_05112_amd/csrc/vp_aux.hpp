@@ -73,5 +73,9 @@ hipError_t aux_init(size_t lds_max);
 // Enqueues one iteration of every request of the plan; when given, the two
 // events bracket the sampling launches.
 void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin, hipEvent_t sample_end);
+// The parts of an iteration before the sampling launches (allocation scan)
+// and after them (training data, estimate, reallocation, refinement).
+void enqueue_head(const IterPlan& P, hipStream_t s);
+void enqueue_tail(const IterPlan& P, hipStream_t s);
 
 }  // namespace vp

@@ -13,7 +13,10 @@ constexpr int kMaxDimSplit = 16;  // FP32 sampling paths
 constexpr int kMaxNg = 4096;      // refinement keeps one axis in LDS
 
 enum Prec { P_FP64 = 0, P_FP32_ACC64 = 1, P_FP32_NEUMAIER = 2 };
-enum Kind { K_GAUSS_MIX = 1, K_CORR_GAUSS = 2, K_EXP_ABS = 3, K_CONST = 4, K_AFFINE = 5, K_BALLS = 6 };
+enum Kind { K_GAUSS_MIX = 1, K_CORR_GAUSS = 2, K_EXP_ABS = 3, K_CONST = 4, K_AFFINE = 5, K_BALLS = 6, K_BATCH = 100 };
+// Sampling-kernel modes of a batched integrand: generate the sample points,
+// then accumulate the values the user's function wrote.
+enum BatchMode { K_BATCH_GEN = 101, K_BATCH_ACC = 102 };
 
 // Sampling workgroup size (one workgroup per CU holds the LDS training data):
 // the largest of 1024 / 768 / 512 threads whose register budget (128 / 168 /
@@ -80,6 +83,13 @@ struct SampleArgs {
     uint32_t* rec_n;        // = rec_h + rec_stride (as bytes: 8 rec_stride further)
     uint16_t* rec_bin;      // = rec_n + rec_stride
     int64_t rec_stride;     // a multiple of 64
+    // batched integrand: x [dim][N_tot] (structure of arrays, packed to the
+    // iteration's N_tot), J and f [cap], increment indices [dim][cap]
+    double* bx;
+    double* bj;
+    const double* bf;
+    uint16_t* bidx;
+    int64_t bcap;
     EdgeRec* edges;         // [2 * n_waves]
     unsigned long long* nonfinite;
     const IntegrandDev* f;
@@ -182,6 +192,8 @@ VP_DECL_GAUSS(fp32neu)
 SampleEntry sample_entry_fp64_corr(int dim, bool map_lds, bool rec);
 SampleEntry sample_entry_fp64_generic(int dim, bool map_lds, bool rec);
 SampleEntry sample_entry_fp32acc_generic(int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp64_batch_gen(int dim);
+SampleEntry sample_entry_fp64_batch_acc(int dim, bool map_lds, bool rec);
 SampleEntry sample_entry_fp32neu_generic(int dim, bool map_lds, bool rec);
 
 // sampling kernels' LDS needs (bytes) for histogram and map

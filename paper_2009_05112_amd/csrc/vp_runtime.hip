@@ -67,6 +67,7 @@ SampleEntry vp::sample_entry(int prec, int kind, int n_terms, int dim, bool map_
                                      sample_entry_fp32neu_generic};
     SampleEntry e = {nullptr, nullptr, 0};
     if (prec < 0 || prec > 2) return e;
+    if (kind == K_BATCH) return prec == P_FP64 ? sample_entry_fp64_batch_acc(dim, map_lds, rec) : e;
     if (kind == K_GAUSS_MIX && n_terms >= 1 && n_terms <= kMaxTerms) e = gauss[prec][n_terms - 1](dim, map_lds, rec);
     else if (kind == K_CORR_GAUSS && prec == P_FP64) e = sample_entry_fp64_corr(dim, map_lds, rec);
     if (!e.launch) e = generic[prec](dim, map_lds, rec);
@@ -138,6 +139,10 @@ vp_status vp::validate(const vp_params* P, const vp_integrand* f)
         if (!f->centers) return fail(VP_ERR_INVALID_ARG, "centers (affine coefficients) required");
         break;
     case VP_F_CONST:
+        break;
+    case VP_F_BATCH:
+        if (!f->fn) return fail(VP_ERR_INVALID_ARG, "a batched integrand needs fn");
+        if (P->precision != VP_FP64) return fail(VP_ERR_INVALID_ARG, "batched integrands are double precision only");
         break;
     default:
         return fail(VP_ERR_INVALID_ARG, "unknown integrand kind %d", f->kind);
@@ -243,6 +248,11 @@ static void fill_req(vp_problem* p)
     a.rec_n = p->rec_n;
     a.rec_bin = p->rec_bin;
     a.rec_stride = p->rec_stride;
+    a.bx = p->bx;
+    a.bj = p->bj;
+    a.bf = p->bf;
+    a.bidx = p->bidx;
+    a.bcap = p->bcap;
     a.edges = p->edges;
     a.nonfinite = &p->st->nonfinite;
     a.f = p->f_d;
@@ -394,6 +404,11 @@ struct Shape {
     int32_t hist_cap;
     int64_t rec_stride;  // records path: sample positions held (0: LDS path)
     int32_t rec_chunks, rec_slices, rec_axes;
+    // batched integrand: the generate-mode kernel, its LDS, and the sample
+    // capacity of the point buffers (0: not batched)
+    SampleEntry gen_entry;
+    size_t gen_lds;
+    int64_t bcap;
 };
 
 // The integrand constants in the sampling kernel's layout (fc_count elements:
@@ -472,7 +487,8 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     if (prec == VP_FP32_NEUMAIER && sh->hist_axes < D)
         return fail(VP_ERR_INVALID_ARG, "compensated sums need dim * n_g * 16 <= %zu bytes of LDS", ctx->lds_max);
     const size_t hb = hist_lds_bytes(sh->hist_axes, NG), mb = map_lds_bytes(prec, D, NG);
-    sh->map_lds = hb + mb + fcb <= ctx->lds_max ? 1 : 0;
+    const bool batch = f->kind == VP_F_BATCH;
+    sh->map_lds = !batch && hb + mb + fcb <= ctx->lds_max ? 1 : 0;  // the accumulate mode reads no map
     const bool rec = sh->hist_axes < D;
     if (rec) sh->map_lds = 0;
     sh->entry = sample_entry(prec, f->kind, f->n_terms, D, sh->map_lds != 0, rec);
@@ -487,6 +503,16 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     int occ = cached_occupancy(ctx->device, sh->entry, sh->block, sh->lds);
     if (occ < 1) occ = 1;
     const int64_t n_tot_max = P->n_ev + 2 * nhc;
+    sh->bcap = 0;
+    sh->gen_lds = 0;
+    sh->gen_entry = SampleEntry{nullptr, nullptr, 0};
+    if (batch) {
+        sh->gen_entry = sample_entry_fp64_batch_gen(D);
+        if (!sh->gen_entry.launch) return fail(VP_ERR_INVALID_ARG, "no batched-integrand kernel for dim %d", D);
+        sh->gen_lds = fc_lds_offset(0, false, VP_FP64, D, NG) + fc_lds_bytes(VP_FP64, VP_F_BATCH, D);
+        (void)cached_occupancy(ctx->device, sh->gen_entry, sh->gen_entry.block, sh->gen_lds);
+        sh->bcap = (n_tot_max + 63) / 64 * 64;
+    }
     const int64_t waves_per_block = sh->block / kWave;
     const int64_t useful_waves = std::max<int64_t>(1, n_tot_max / ((int64_t)kWave * sh->chunk));
     int64_t grid = (int64_t)ctx->n_cu * occ;
@@ -518,7 +544,8 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
 // map bounds) come first, so one copy initialises them.
 struct Layout {
     size_t f_d, st, d_req, bounds, fc, head_end, map, map32;
-    size_t n_h, offs, bsum, S1, S2, dh, H, W, hist, edges, est_part, hist_I, hist_V, rec_h, rec_n, rec_bin, total;
+    size_t n_h, offs, bsum, S1, S2, dh, H, W, hist, edges, est_part, hist_I, hist_V, rec_h, rec_n, rec_bin;
+    size_t bx, bj, bf, bidx, total;
 };
 
 static Layout layout_of(const vp_params* P, const Shape& sh)
@@ -557,6 +584,11 @@ static Layout layout_of(const vp_params* P, const Shape& sh)
     L.rec_h = take((size_t)sh.rec_stride * sizeof(double));
     L.rec_n = take((size_t)sh.rec_stride * sizeof(uint32_t));
     L.rec_bin = take((size_t)sh.rec_stride * (D - sh.hist_axes) * sizeof(uint16_t));
+    // batched integrand: points, J, f and increment indices
+    L.bx = take((size_t)sh.bcap * D * sizeof(double));
+    L.bj = take((size_t)sh.bcap * sizeof(double));
+    L.bf = take((size_t)sh.bcap * sizeof(double));
+    L.bidx = take((size_t)sh.bcap * D * sizeof(uint16_t));
     L.total = at;
     return L;
 }
@@ -660,6 +692,15 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
     p->rec_h = sh.rec_stride ? (double*)(base + lay.rec_h) : nullptr;
     p->rec_n = sh.rec_stride ? (uint32_t*)(base + lay.rec_n) : nullptr;
     p->rec_bin = sh.rec_stride ? (uint16_t*)(base + lay.rec_bin) : nullptr;
+    p->bcap = sh.bcap;
+    p->bx = sh.bcap ? (double*)(base + lay.bx) : nullptr;
+    p->bj = sh.bcap ? (double*)(base + lay.bj) : nullptr;
+    p->bf = sh.bcap ? (double*)(base + lay.bf) : nullptr;
+    p->bidx = sh.bcap ? (uint16_t*)(base + lay.bidx) : nullptr;
+    p->gen_entry = sh.gen_entry;
+    p->gen_lds = sh.gen_lds;
+    p->batch_fn = f->kind == VP_F_BATCH ? f->fn : nullptr;
+    p->batch_user = f->kind == VP_F_BATCH ? f->user : nullptr;
     p->edges = (EdgeRec*)(base + lay.edges);
     p->est_part = (double*)(base + lay.est_part);
     p->hist_I = (double*)(base + lay.hist_I);
@@ -724,6 +765,48 @@ vp_status vp::result_from_state(const DevState& st, vp_result* out)
     return VP_OK;
 }
 
+// One iteration with a batched integrand (Sec. 1: the integrand is evaluated
+// on batches of points): the allocation scan, the generate-mode sampler
+// writing the iteration's points, the user's function on the library's
+// stream, the accumulate-mode sampler, then the same passes as the fused path.
+// The host reads N_tot (one synchronisation) to tell the function how many
+// points there are.
+static vp_status iterate_batch(vp_problem* p, int32_t n_iter)
+{
+    hipStream_t s = p->ctx->stream;
+    const SampleGroup& g = p->plan.groups[0];
+    const int64_t* total = p->bsum + scan_blocks(p->n_hc);
+    for (int32_t r = 0; r < n_iter; ++r) {
+        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+        if (p->prof) {
+            e0 = take_event(p), e1 = take_event(p), e2 = take_event(p), e3 = take_event(p);
+            VP_HIP(hipEventRecord(e2, s));
+        }
+        enqueue_head(p->plan, s);
+        if (e0) VP_HIP(hipEventRecord(e0, s));
+        p->gen_entry.launch(g.L, g.blocks, p->gen_entry.block, p->gen_lds, s);
+        int64_t n_tot = 0;
+        VP_HIP(hipMemcpyAsync(&n_tot, total, sizeof n_tot, hipMemcpyDeviceToHost, s));
+        VP_HIP(hipStreamSynchronize(s));
+        const int rc = p->batch_fn(p->batch_user, (void*)s, n_tot, p->P.dim, p->bx, p->bf);
+        if (rc != 0) return fail(VP_ERR_DEVICE, "the batched integrand returned %d", rc);
+        g.entry.launch(g.L, g.blocks, g.entry.block, g.lds, s);
+        if (e1) VP_HIP(hipEventRecord(e1, s));
+        enqueue_tail(p->plan, s);
+        if (e3) {
+            VP_HIP(hipEventRecord(e3, s));
+            p->ev_pending.push_back(e0);
+            p->ev_pending.push_back(e1);
+            p->ev_pending.push_back(e2);
+            p->ev_pending.push_back(e3);
+        }
+        VP_HIP(hipGetLastError());
+        p->it += 1;
+        p->slot += 1;
+    }
+    return VP_OK;
+}
+
 extern "C" {
 
 vp_status vp_problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, vp_problem** out)
@@ -759,6 +842,7 @@ vp_status vp_iterate(vp_problem* p, int32_t n_iter)
         VP_HIP(p->planner.build(pr, &p->plan));
         p->plan_built = true;
     }
+    if (p->batch_fn) return iterate_batch(p, n_iter);
     for (int32_t r = 0; r < n_iter; ++r) {
         if (p->prof) {
             hipEvent_t e0 = take_event(p), e1 = take_event(p), e2 = take_event(p), e3 = take_event(p);

@@ -382,10 +382,19 @@ struct SampleHot {
 // x = x_i + Delta x_i delta, J = prod_mu N_g Delta x_i.
 // FP64: u from 53 bits -- the high word of axis mu is word mu of the
 // stream, its low word is word D + mu.
-template <int D, bool MAPLDS, int KT, typename FP>
+// Where the generate mode of a batched integrand puts a sample: x at
+// x[mu * n + pos], J at jac[pos], the increment index at idx[mu * cap + pos].
+struct BatchOut {
+    double* x;
+    double* jac;
+    uint16_t* idx;
+    int64_t n, cap, pos;
+};
+
+template <int D, bool MAPLDS, int KT, typename FP, bool GEN = false>
 __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair64<MAPLDS>& map, FP fc,
                                               uint32_t j, uint32_t h, const int32_t* k,
-                                              int32_t* idx, int kind, int K)
+                                              int32_t* idx, int kind, int K, const BatchOut* out = nullptr)
 {
     // Axes are processed in groups of four: group g takes its high words from
     // block g and its low words from the block(s) holding words D+4g..D+4g+3,
@@ -428,10 +437,20 @@ __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair6
             const double x = fma(dx, delta, x0);
             jac = jac * ((double)n_g * dx);
             idx[mu] = i;
-            f_axis<D, KT, double, FP>(fc, kind, K, mu, x, st);
+            if constexpr (GEN) {
+                out->x[mu * out->n + out->pos] = x;
+                out->idx[mu * out->cap + out->pos] = (uint16_t)i;
+            } else {
+                f_axis<D, KT, double, FP>(fc, kind, K, mu, x, st);
+            }
         }
     }
-    return jac * f_finish<D, KT, double, FP>(fc, kind, K, st);
+    if constexpr (GEN) {
+        out->jac[out->pos] = jac;
+        return 0.0;
+    } else {
+        return jac * f_finish<D, KT, double, FP>(fc, kind, K, st);
+    }
 }
 
 // FP32 split: u = (w >> 8) 2^-24 from the high word of each axis alone.
@@ -519,9 +538,14 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
     typedef typename std::conditional<PREC == P_FP64, double, float>::type MapT;
     extern __shared__ __align__(16) unsigned char lds_raw[];
 
+    // modes of a batched integrand (FP64 only): GEN writes the sample points
+    // and touches no sums; ACC takes v = J f from memory
+    constexpr bool GEN = (KIND == K_BATCH_GEN);
+    constexpr bool ACC = (KIND == K_BATCH_ACC);
+    static_assert(!(GEN || ACC) || PREC == P_FP64, "batched integrands are double precision");
     const int n_g = a.n_g;
     const int nbins = D * n_g;
-    const int ha = REC ? a.hist_axes : D;  // axes privatised in LDS
+    const int ha = GEN ? 0 : (REC ? a.hist_axes : D);  // axes privatised in LDS
     const int lbins = ha * n_g;            // bins per LDS plane
     const size_t hist_bytes = (size_t)lbins * 16;
     double* lds_hist = reinterpret_cast<double*>(lds_raw);
@@ -576,6 +600,18 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
     EdgeRec* __restrict__ edges = a.edges;
     double* rec = REC ? a.rec_h : nullptr;
     const int64_t rec_stride = REC ? a.rec_stride : 0;
+    BatchOut bout;
+    const double* bf = nullptr;
+    double bscale = 0.0;
+    if constexpr (GEN || ACC) {
+        bout.x = a.bx;
+        bout.jac = a.bj;
+        bout.idx = a.bidx;
+        bout.n = n_tot;
+        bout.cap = a.bcap;
+        bf = a.bf;
+        bscale = lds_fc[0];
+    }
     SampleHot hot;
     hot.key0 = a.key0;
     hot.key1 = a.key1;
@@ -634,8 +670,10 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                             head_closed = true;
                             in_head = false;
                         } else {
-                            S1[hh32] = run.sa();
-                            S2[hh32] = run.sb();
+                            if constexpr (!GEN) {
+                                S1[hh32] = run.sa();
+                                S2[hh32] = run.sb();
+                            }
                         }
                         run.zero();
                         ++hh32;
@@ -665,9 +703,21 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         asm volatile("s_mov_b32 %0, 0" : "=s"(z));
                         fcs = fcg + z;
                     }
-                    if constexpr (PREC == P_FP64) {
-                        const double v = (FC_SMEM ? sample_fp64<D, MAPLDS, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
-                                           : sample_fp64<D, MAPLDS, KT, const MapT*>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
+                    if constexpr (GEN) {
+                        bout.pos = s_a + (int64_t)s;
+                        (void)sample_fp64<D, MAPLDS, 0, const MapT*, true>(hot, map, lds_fc, j, hh32, k, idx, kind, K,
+                                                                           &bout);
+                    } else if constexpr (PREC == P_FP64) {
+                        double v;
+                        if constexpr (ACC) {
+                            const int64_t pos = s_a + (int64_t)s;
+                            v = bout.jac[pos] * (bscale * bf[pos]);
+#pragma unroll
+                            for (int mu = 0; mu < D; ++mu) idx[mu] = bout.idx[mu * bout.cap + pos];
+                        } else {
+                            v = (FC_SMEM ? sample_fp64<D, MAPLDS, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
+                                         : sample_fp64<D, MAPLDS, KT, const MapT*>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
+                        }
                         run.add(v);
                         if (!isfinite(v)) ++bad;
                         const double v2 = v * v;
@@ -707,8 +757,10 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         head_closed = true;
                         in_head = false;
                     } else {
-                        S1[hh32] = run.sa();
-                        S2[hh32] = run.sb();
+                        if constexpr (!GEN) {
+                            S1[hh32] = run.sa();
+                            S2[hh32] = run.sb();
+                        }
                     }
                     run.zero();
                     h_end = (int64_t)hh32 + 1;
@@ -752,8 +804,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                     r.h = head_h;
                     r.s1 = tot.sa();
                     r.s2 = tot.sb();
-                    edges[2 * wave] = r;
-                } else {
+                    if constexpr (!GEN) edges[2 * wave] = r;
+                } else if constexpr (!GEN) {
                     S1[head_h] = tot.sa();
                     S2[head_h] = tot.sb();
                 }
@@ -772,7 +824,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
             h_open = shfl64(h_end, last_active);
             h_cur = shfl64(h_end, kWave - 1);
         }
-        if (lane == 0) {
+        if (lane == 0 && !GEN) {
             EdgeRec empty;
             empty.h = -1;
             empty.s1 = 0.0;
@@ -793,7 +845,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                 edges[2 * wave + 1] = empty;
             }
         }
-    } else if (lane == 0) {
+    } else if (lane == 0 && !GEN) {
         EdgeRec empty;
         empty.h = -1;
         empty.s1 = 0.0;

@@ -399,6 +399,8 @@ vp_status vp_server_submit(vp_server* s, const vp_params* P, const vp_integrand*
     if (!s || !ticket) return fail(VP_ERR_INVALID_ARG, "server and ticket are required");
     vp_status st = validate(P, f);
     if (st != VP_OK) return st;
+    if (f->kind == VP_F_BATCH)
+        return fail(VP_ERR_INVALID_ARG, "batched integrands call host code between kernels and are not servable");
     size_t bytes = 0;
     st = problem_bytes(s->ctx, P, f, kServeSamplesPerWG, &bytes);
     if (st != VP_OK) return st;

@@ -76,6 +76,16 @@ struct vp_problem {
     uint16_t* rec_bin = nullptr;
     int64_t rec_stride = 0;
     int32_t rec_chunks = 0, rec_slices = 0, rec_axes = 0;
+    // batched integrand (VP_F_BATCH)
+    double* bx = nullptr;
+    double* bj = nullptr;
+    double* bf = nullptr;
+    uint16_t* bidx = nullptr;
+    int64_t bcap = 0;
+    SampleEntry gen_entry = {nullptr, nullptr, 0};
+    size_t gen_lds = 0;
+    vp_batch_fn batch_fn = nullptr;
+    void* batch_user = nullptr;
     EdgeRec* edges = nullptr;
     double* est_part = nullptr;
     double* hist_I = nullptr;

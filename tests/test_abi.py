@@ -14,6 +14,23 @@ def test_library_exports_declared_symbols():
     assert not missing, missing
 
 
+def test_examples_library_exports_declared_symbols():
+    header = os.path.join(os.path.dirname(B.HEADER), "vegasp_examples.h")
+    names = B.declared_symbols(header)
+    assert "vp_example_gauss_mix" in names and len(names) >= 4
+    lib = ctypes.CDLL(B.EXAMPLES_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_batch_integrand_struct():
+    # the batched integrand's function pointer and user pointer follow scale
+    names = [f[0] for f in B.vp_integrand._fields_]
+    assert names[-3:] == ["scale", "fn", "user"]
+    src = open(B.HEADER).read()
+    assert "VP_F_BATCH = 100" in src
+
+
 def test_status_strings_and_header_enums():
     L = B.lib()
     for s in range(8):
