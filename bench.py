@@ -130,6 +130,33 @@ def run_split(B, W, ctx, n_ev, steps):
     return out
 
 
+def run_batch_path(B, W, ctx, n_ev, steps):
+    """The D=8 workload through the batched-integrand path: the library
+    writes the points as structure-of-arrays buffers, the example library's
+    Gaussian mixture (same arithmetic as the built-in kind) fills f."""
+    p, f = W.cfg_diag_d8(n_ev=n_ev)
+    bf = B.example_gauss_mix(f)
+    try:
+        gp = B.Problem(ctx, p.with_(n_iter=steps + 2), bf)
+        gp.iterate(2)
+        r0 = gp.result()
+        gp.profile(True)
+        gp.sync()
+        t0 = time.perf_counter()
+        gp.iterate(steps)
+        gp.sync()
+        dt = time.perf_counter() - t0
+        r1 = gp.result()
+        gp.close()
+    finally:
+        B.examples().vp_example_free_user(bf.user)
+    n = r1["n_evals"] - r0["n_evals"]
+    return {"workload": "D=8 three-Gaussian workload, N_ev=1e8, FP64, integrand evaluated by a user function "
+                        "over structure-of-arrays points (example library)",
+            "samples_per_s": n / dt, "ms_per_step": 1e3 * dt / steps, "mean": r1["mean"], "sdev": r1["sdev"],
+            "bytes_per_sample_moved": 8 * 8 + 8 + 8 + 2 * 8 + 8 * 8 + 8 + 8 + 2 * 8}
+
+
 def run_plain(B, ctx, reqs):
     """vp_integrate one request after another; per-request service times."""
     svc, res = [], []
@@ -238,8 +265,9 @@ def main():
     ap.add_argument("--n-ev", type=int, default=100_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the precision split and serving sections")
-    ap.add_argument("--sections", default="split,batch,stream",
-                    help="extra sections to run after the headline steps (comma list of split, batch, stream)")
+    ap.add_argument("--sections", default="split,batchfn,batch,stream",
+                    help="extra sections to run after the headline steps (comma list of split, batchfn "
+                         "(batched-integrand path), batch (served batch), stream)")
     ap.add_argument("--batch", type=int, default=4096, help="requests in the served batch")
     ap.add_argument("--stream", type=int, default=300, help="requests in the Poisson stream")
     ap.add_argument("--load", type=float, default=0.8, help="plain-path utilisation that sets the stream rate")
@@ -315,6 +343,9 @@ def main():
     if "split" in sections:
         print("precision split ...", file=sys.stderr, flush=True)
         line["precision_split"] = run_split(B, W, ctx, args.n_ev, 10)
+    if "batchfn" in sections:
+        print("batched-integrand path ...", file=sys.stderr, flush=True)
+        line["batched_integrand"] = run_batch_path(B, W, ctx, args.n_ev, 5)
     serving, latency = {}, {}
     if "batch" in sections:
         print("served batch ...", file=sys.stderr, flush=True)

@@ -85,7 +85,8 @@ enum {
 /* A batched integrand.  Called from vp_iterate once per iteration, on the
  * host thread that called it, after the library has written the iteration's
  * n sample points to x_soa in device memory: x_soa[d * n + s] is coordinate d
- * of sample s (structure of arrays, the samples of one hypercube adjacent).
+ * of sample s (structure of arrays; the order of the samples is the
+ * library's, chosen so that its kernels read and write them coalesced).
  * It must enqueue on hip_stream (a hipStream_t) work that writes f(x_s) to
  * f_out[s], s < n (device memory), and may return before that work is done;
  * the library's next kernels on the stream read f_out.  Both buffers belong

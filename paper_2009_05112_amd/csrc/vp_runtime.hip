@@ -408,6 +408,7 @@ struct Shape {
     // capacity of the point buffers (0: not batched)
     SampleEntry gen_entry;
     size_t gen_lds;
+    int gen_grid;  // its own grid: it holds no training data, so many workgroups fit per CU
     int64_t bcap;
 };
 
@@ -505,12 +506,17 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     const int64_t n_tot_max = P->n_ev + 2 * nhc;
     sh->bcap = 0;
     sh->gen_lds = 0;
+    sh->gen_grid = 0;
     sh->gen_entry = SampleEntry{nullptr, nullptr, 0};
     if (batch) {
         sh->gen_entry = sample_entry_fp64_batch_gen(D);
         if (!sh->gen_entry.launch) return fail(VP_ERR_INVALID_ARG, "no batched-integrand kernel for dim %d", D);
         sh->gen_lds = fc_lds_offset(0, false, VP_FP64, D, NG) + fc_lds_bytes(VP_FP64, VP_F_BATCH, D);
-        (void)cached_occupancy(ctx->device, sh->gen_entry, sh->gen_entry.block, sh->gen_lds);
+        const int gocc = std::max(1, cached_occupancy(ctx->device, sh->gen_entry, sh->gen_entry.block, sh->gen_lds));
+        const int64_t gwpb = sh->gen_entry.block / kWave;
+        const int64_t guseful = std::max<int64_t>(1, n_tot_max / ((int64_t)kWave * 16));
+        sh->gen_grid = (int)std::max<int64_t>(
+            1, std::min<int64_t>((int64_t)ctx->n_cu * gocc, (guseful + gwpb - 1) / gwpb));
         sh->bcap = (n_tot_max + 63) / 64 * 64;
     }
     const int64_t waves_per_block = sh->block / kWave;
@@ -699,6 +705,7 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
     p->bidx = sh.bcap ? (uint16_t*)(base + lay.bidx) : nullptr;
     p->gen_entry = sh.gen_entry;
     p->gen_lds = sh.gen_lds;
+    p->gen_grid = sh.gen_grid;
     p->batch_fn = f->kind == VP_F_BATCH ? f->fn : nullptr;
     p->batch_user = f->kind == VP_F_BATCH ? f->user : nullptr;
     p->edges = (EdgeRec*)(base + lay.edges);
@@ -775,6 +782,17 @@ static vp_status iterate_batch(vp_problem* p, int32_t n_iter)
 {
     hipStream_t s = p->ctx->stream;
     const SampleGroup& g = p->plan.groups[0];
+    if (!p->gen_plan_built) {
+        // the generate mode's own launch table: the same argument record, its
+        // own grid (the kernel partitions the samples by its launch's blocks
+        // and writes no per-workgroup state)
+        ReqArgs gq = p->req;
+        gq.grid = p->gen_grid;
+        std::vector<PlanReq> pr = {{&gq, p->d_req, p->gen_entry, p->gen_lds}};
+        VP_HIP(p->gen_planner.build(pr, &p->gen_plan));
+        p->gen_plan_built = true;
+    }
+    const SampleGroup& gg = p->gen_plan.groups[0];
     const int64_t* total = p->bsum + scan_blocks(p->n_hc);
     for (int32_t r = 0; r < n_iter; ++r) {
         hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
@@ -784,7 +802,7 @@ static vp_status iterate_batch(vp_problem* p, int32_t n_iter)
         }
         enqueue_head(p->plan, s);
         if (e0) VP_HIP(hipEventRecord(e0, s));
-        p->gen_entry.launch(g.L, g.blocks, p->gen_entry.block, p->gen_lds, s);
+        p->gen_entry.launch(gg.L, gg.blocks, p->gen_entry.block, p->gen_lds, s);
         int64_t n_tot = 0;
         VP_HIP(hipMemcpyAsync(&n_tot, total, sizeof n_tot, hipMemcpyDeviceToHost, s));
         VP_HIP(hipStreamSynchronize(s));

@@ -382,6 +382,21 @@ struct SampleHot {
 // x = x_i + Delta x_i delta, J = prod_mu N_g Delta x_i.
 // FP64: u from 53 bits -- the high word of axis mu is word mu of the
 // stream, its low word is word D + mu.
+// Position of sample pos in the point buffers of a batched integrand.  The
+// samples are taken in aligned groups of 64 x 16; within a whole group the
+// sample at offset r goes to (r mod 16) * 64 + r / 16, so that when the lanes
+// of a wave each walk 16 consecutive samples, they touch consecutive
+// addresses.  Defined on absolute positions, so every kernel and launch shape
+// agrees; the last, partial group keeps its order.
+constexpr int kBatchGroup = kWave * 16;
+__device__ __forceinline__ int64_t batch_pos(int64_t pos, int64_t n_tot)
+{
+    const int64_t base = pos & ~(int64_t)(kBatchGroup - 1);
+    if (base + kBatchGroup > n_tot) return pos;
+    const int r = (int)(pos - base);
+    return base + (int64_t)(r & 15) * kWave + (r >> 4);
+}
+
 // Where the generate mode of a batched integrand puts a sample: x at
 // x[mu * n + pos], J at jac[pos], the increment index at idx[mu * cap + pos].
 struct BatchOut {
@@ -590,8 +605,16 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
     const int64_t* __restrict__ ob = a.obase;
     const int64_t n_hc = a.n_hc;
     const int64_t n_tot = gofs(offs, ob, n_hc);
-    const int64_t s_a = n_tot * wave / n_waves;
-    const int64_t s_b = n_tot * (wave + 1) / n_waves;
+    // the batched-integrand modes start every wave at a group boundary of the
+    // point buffers (batch_pos), so that its tiles coincide with the groups
+    // and each buffer row is written whole
+    auto wave_start = [&](int64_t w) -> int64_t {
+        const int64_t x = n_tot * w / n_waves;
+        if constexpr (GEN || ACC) return w == n_waves ? n_tot : (x & ~(int64_t)(kBatchGroup - 1));
+        return x;
+    };
+    const int64_t s_a = wave_start(wave);
+    const int64_t s_b = wave_start(wave + 1);
     const int C = a.chunk;
     const uint32_t n_st = (uint32_t)a.n_st;
     const bool literal = (a.hist_mode != 0);
@@ -703,14 +726,15 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         asm volatile("s_mov_b32 %0, 0" : "=s"(z));
                         fcs = fcg + z;
                     }
+                    const int64_t bpos = batch_pos(s_a + (int64_t)s, n_tot);
                     if constexpr (GEN) {
-                        bout.pos = s_a + (int64_t)s;
+                        bout.pos = bpos;
                         (void)sample_fp64<D, MAPLDS, 0, const MapT*, true>(hot, map, lds_fc, j, hh32, k, idx, kind, K,
                                                                            &bout);
                     } else if constexpr (PREC == P_FP64) {
                         double v;
                         if constexpr (ACC) {
-                            const int64_t pos = s_a + (int64_t)s;
+                            const int64_t pos = bpos;
                             v = bout.jac[pos] * (bscale * bf[pos]);
 #pragma unroll
                             for (int mu = 0; mu < D; ++mu) idx[mu] = bout.idx[mu * bout.cap + pos];

@@ -84,6 +84,10 @@ struct vp_problem {
     int64_t bcap = 0;
     SampleEntry gen_entry = {nullptr, nullptr, 0};
     size_t gen_lds = 0;
+    int gen_grid = 0;
+    PlanBuilder gen_planner;  // launch table of the generate mode
+    IterPlan gen_plan;
+    bool gen_plan_built = false;
     vp_batch_fn batch_fn = nullptr;
     void* batch_user = nullptr;
     EdgeRec* edges = nullptr;

@@ -33,11 +33,13 @@ def _mix(dim, k, seed):
     return W.Integrand("gauss_mix", dim, centers, coefs, amps, scale=1.7)
 
 
-@pytest.mark.parametrize("dim,k,n_ev,n_g", [(4, 3, 100_000, 200), (8, 2, 400_000, 1000), (12, 1, 300_000, 1000)])
+@pytest.mark.parametrize("dim,k,n_ev,n_g", [(4, 3, 100_000, 200), (8, 2, 400_000, 1000), (12, 1, 300_000, 1000),
+                                           (8, 3, 4_000_000, 1000)])
 def test_batched_equals_builtin(ctx, dim, k, n_ev, n_g):
     """Each step starts both problems from the same state (map, allocation,
     iteration): same points and values, sums in another order (the two
-    kernels split the samples over waves differently)."""
+    kernels split the samples over waves differently).  At 4e6 samples the
+    generate and accumulate kernels run on different grids."""
     f = _mix(dim, k, dim)
     p = W.Params(dim=dim, n_ev=n_ev, n_g=n_g, n_iter=4, seed=11)
     bf = B.example_gauss_mix(f)
