@@ -134,7 +134,14 @@ enum { VP_HIST_WEIGHTED = 0, VP_HIST_LITERAL = 1 };
  *        (largest n with 4 n^dim <= n_ev); a user value must keep
  *        2 n_st^dim <= n_ev.
  *  n_discard: iterations left out of the combined estimate (Sec. 2.5).
- *  realloc_plus2: use n_h = floor(q) + 2 instead of max(2, floor(q)). */
+ *  realloc_plus2: use n_h = floor(q) + 2 instead of max(2, floor(q)).
+ *  n_adapt: 0, or the number of adapting iterations: an iteration whose
+ *        index (the one its Philox counters carry) is n_adapt or more
+ *        neither reallocates nor refines, so the map and the allocation stay
+ *        as the last adapting iteration left them (the frozen phase of
+ *        Sec. 2.5, alpha = 0; with n_discard = n_adapt the combined estimate
+ *        uses frozen iterations only).  >= 0.
+ *  average: VP_AVG_WEIGHTED or VP_AVG_UNWEIGHTED (vp_result). */
 typedef struct {
     int32_t dim;
     int64_t n_ev;
@@ -150,10 +157,21 @@ typedef struct {
     int32_t realloc_plus2;
     int32_t n_discard;
     int32_t n_st;
+    int32_t n_adapt;
+    int32_t average;
 } vp_params;
 
-/* Combined estimate over the iterations done so far (Sec. 2.5):
- * inverse-variance weighted mean, its error, chi^2 with dof = used - 1.
+enum { VP_AVG_WEIGHTED = 0, VP_AVG_UNWEIGHTED = 1 };
+
+/* Combined estimate over iterations n_discard .. n_iter_done - 1 (Sec. 2.5):
+ *  VP_AVG_WEIGHTED:   inverse-variance weighted mean I, error
+ *                     (sum 1/sigma_j^2)^(-1/2); when some sigma_j is zero,
+ *                     the plain mean with error 0;
+ *  VP_AVG_UNWEIGHTED: the plain mean of the I_j, error (mean of the
+ *                     sigma_j) / sqrt(count) (unbiased once the map and
+ *                     allocation no longer adapt: see n_adapt);
+ * chi^2 = sum (I_j - I)^2 / sigma_j^2 (NaN when some sigma_j is zero) with
+ * dof = count - 1.
  * n_evals counts actual integrand evaluations (sum of n_h over iterations).
  * n_near_ties counts allocations where N_ev d_h / sum d lay within 1e-9
  * (relative) of an integer that decides n_h. */

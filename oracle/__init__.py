@@ -25,7 +25,8 @@ _HIST = {"weighted": 0, "literal": 1}
 class _Params(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_ev", C.c_int64), ("n_g", C.c_int32), ("n_st", C.c_int32),
                 ("alpha", C.c_double), ("beta", C.c_double), ("seed", C.c_uint64),
-                ("precision", C.c_int32), ("hist_mode", C.c_int32), ("realloc_plus2", C.c_int32)]
+                ("precision", C.c_int32), ("hist_mode", C.c_int32), ("realloc_plus2", C.c_int32),
+                ("n_adapt", C.c_int32)]
 
 
 class _Integrand(C.Structure):
@@ -79,7 +80,7 @@ def lib():
         L.or_refine_stages.restype = C.c_int
         L.or_refine.argtypes = [C.POINTER(_Params), dp, dp, dp]
         L.or_refine.restype = C.c_int
-        L.or_combine.argtypes = [dp, dp, C.c_int32, C.c_int32, dp, dp, dp, ip]
+        L.or_combine.argtypes = [dp, dp, C.c_int32, C.c_int32, C.c_int32, dp, dp, dp, ip]
         L.or_iteration.argtypes = [C.POINTER(_Params), C.POINTER(_Integrand), dp, ip, C.c_int32,
                                    dp, dp, dp, dp, dp, dp]
         L.or_iteration.restype = C.c_int64
@@ -126,7 +127,7 @@ class Problem:
         self.p = _Params(params.dim, int(params.n_ev), params.n_g, ns, float(params.alpha),
                          float(params.beta), int(params.seed) & ((1 << 64) - 1),
                          _PREC[params.precision], _HIST[params.hist_mode],
-                         1 if params.realloc_plus2 else 0)
+                         1 if params.realloc_plus2 else 0, int(getattr(params, "n_adapt", 0) or 0))
         f = integrand
         self._centers = np.ascontiguousarray(f.centers, dtype=np.float64).ravel()
         self._coefs = np.ascontiguousarray(f.coefs, dtype=np.float64)
@@ -248,19 +249,19 @@ class Problem:
         if rc != 0:
             raise RuntimeError("or_integrate failed")
         sig = np.sqrt(V)
-        mean, sdev, chi2, dof = combine(I, sig, self.params.n_discard)
+        mean, sdev, chi2, dof = combine(I, sig, self.params.n_discard, getattr(self.params, "average", "weighted"))
         return {"I": I, "V": V, "sig": sig, "mean": mean, "sdev": sdev, "chi2": chi2, "dof": dof,
                 "map": m, "n_h": n, "ties": int(ties.value)}
 
 
-def combine(I, sig, n_discard: int = 0):
+def combine(I, sig, n_discard: int = 0, average: str = "weighted"):
     I = np.ascontiguousarray(I, dtype=np.float64)
     sig = np.ascontiguousarray(sig, dtype=np.float64)
     mean = C.c_double()
     sdev = C.c_double()
     chi2 = C.c_double()
     dof = C.c_int32()
-    lib().or_combine(_dp(I), _dp(sig), I.size, n_discard, C.byref(mean), C.byref(sdev), C.byref(chi2),
+    lib().or_combine(_dp(I), _dp(sig), I.size, n_discard, 1 if average == "unweighted" else 0, C.byref(mean), C.byref(sdev), C.byref(chi2),
                      C.byref(dof))
     return mean.value, sdev.value, chi2.value, int(dof.value)
 

@@ -277,6 +277,7 @@ typedef struct {
     int32_t precision;      /* OR_FP64 / OR_FP32_ACC64 / OR_FP32_NEUMAIER */
     int32_t hist_mode;      /* OR_HIST_WEIGHTED / OR_HIST_LITERAL */
     int32_t realloc_plus2;  /* 1: n_h = floor(q) + 2 (Sec. 3, alternative rule) */
+    int32_t n_adapt;        /* > 0: iterations it >= n_adapt keep map and n_h (Sec. 2.5) */
 } or_params;
 
 int64_t or_n_hypercubes(const or_params* p)
@@ -785,8 +786,11 @@ int or_refine(const or_params* p, const double* H, const double* W, double* map)
 /* standard error and chi^2 over iterations n_discard..n-1.  When any sigma_j */
 /* is zero the weights are undefined: the plain mean is returned with zero    */
 /* error and chi^2 = NaN.                                                     */
+/* With unweighted != 0 (for iterations that no longer adapt, Sec. 2.5): the  */
+/* plain mean of the I_j, and the plain mean of the sigma_j divided by the    */
+/* square root of their count as its error; chi^2 about that mean.            */
 /* ------------------------------------------------------------------------ */
-void or_combine(const double* I, const double* sig, int32_t n, int32_t n_discard,
+void or_combine(const double* I, const double* sig, int32_t n, int32_t n_discard, int32_t unweighted,
                 double* mean, double* sdev, double* chi2, int32_t* dof)
 {
     int32_t first = n_discard < 0 ? 0 : n_discard;
@@ -799,6 +803,23 @@ void or_combine(const double* I, const double* sig, int32_t n, int32_t n_discard
     for (int32_t j = first; j < n; ++j)
         if (!(sig[j] > 0.0)) zero = 1;
     *dof = cnt - 1;
+    if (unweighted) {
+        double s = 0.0, ss = 0.0;
+        for (int32_t j = first; j < n; ++j) {
+            s = s + I[j];
+            ss = ss + sig[j];
+        }
+        double m = s / (double)cnt;
+        double c2 = 0.0;
+        for (int32_t j = first; j < n; ++j) {
+            double r = I[j] - m;
+            c2 = c2 + r * r / (sig[j] * sig[j]);
+        }
+        *mean = m;
+        *sdev = (ss / (double)cnt) / sqrt((double)cnt);
+        *chi2 = zero ? NAN : c2;
+        return;
+    }
     if (zero) {
         double s = 0.0;
         for (int32_t j = first; j < n; ++j) s = s + I[j];
@@ -839,6 +860,9 @@ int64_t or_iteration(const or_params* p, const or_integrand* f, double* map, int
     memset(W, 0, sizeof(double) * (size_t)p->dim * p->n_g);
     if (or_sample_range(p, f, map, n_h, it, 0, nhc, S1, S2, H, W, NULL, 0, NULL) != 0) return -1;
     or_reduce(p, n_h, S1, S2, I_out, V_out);
+    /* Sec. 2.5: once adaptation has ended (alpha = 0), the map and the
+     * allocation are those of the last adapting iteration. */
+    if (p->n_adapt > 0 && it >= p->n_adapt) return 0;
     int32_t* n_new = (int32_t*)malloc(sizeof(int32_t) * (size_t)nhc);
     if (!n_new) return -1;
     int64_t ties = or_realloc(p, S1, S2, n_h, n_new);

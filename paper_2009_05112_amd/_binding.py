@@ -19,6 +19,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "vegasp.h")
 _KIND = {"gauss_mix": 1, "corr_gauss": 2, "exp_abs": 3, "const": 4, "affine": 5, "balls": 6}
 _PREC = {"fp64": 0, "fp32_acc64": 1, "fp32_neumaier": 2}
 _HIST = {"weighted": 0, "literal": 1}
+_AVG = {"weighted": 0, "unweighted": 1}
 
 VP_OK, VP_ERR_INVALID_ARG, VP_ERR_OOM, VP_ERR_DEVICE, VP_ERR_NUMERIC, VP_ERR_NOT_READY, \
     VP_ERR_CANCELLED, VP_ERR_STATE = range(8)
@@ -60,7 +61,7 @@ class vp_params(C.Structure):
                 ("alpha", C.c_double), ("beta", C.c_double), ("lower", C.POINTER(C.c_double)),
                 ("upper", C.POINTER(C.c_double)), ("seed", C.c_uint64), ("precision", C.c_int32),
                 ("hist_mode", C.c_int32), ("realloc_plus2", C.c_int32), ("n_discard", C.c_int32),
-                ("n_st", C.c_int32)]
+                ("n_st", C.c_int32), ("n_adapt", C.c_int32), ("average", C.c_int32)]
 
 
 class vp_result(C.Structure):
@@ -204,7 +205,8 @@ def marshal(params, integrand):
     p = params
     pp = vp_params(p.dim, int(p.n_ev), p.n_g, p.n_iter, float(p.alpha), float(p.beta), arr(p.lower),
                    arr(p.upper), int(p.seed) & ((1 << 64) - 1), _PREC[p.precision], _HIST[p.hist_mode],
-                   1 if p.realloc_plus2 else 0, int(p.n_discard), int(getattr(p, "n_st", 0) or 0))
+                   1 if p.realloc_plus2 else 0, int(p.n_discard), int(getattr(p, "n_st", 0) or 0),
+                   int(getattr(p, "n_adapt", 0) or 0), _AVG[getattr(p, "average", "weighted")])
     return pp, fi, keep
 
 

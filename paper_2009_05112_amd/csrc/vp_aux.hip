@@ -475,8 +475,18 @@ __global__ __launch_bounds__(kRedBlock) void k_est_partial(LaunchSet L)
     }
 }
 
+// Adaptation ends after the first n_adapt iterations (Sec. 2.5: the map and
+// the allocation are frozen so that later estimates are independent of one
+// another's fluctuations).
+__device__ __forceinline__ bool frozen(const ReqArgs& q)
+{
+    return q.n_adapt > 0 && q.s.it >= (uint32_t)q.n_adapt;
+}
+
 // Totals over the partials (one block, fixed tree order), the iteration's
-// record, and the combination over iterations n_discard..it (Sec. 2.5).
+// record, and the combination over iterations n_discard..it (Sec. 2.5):
+// inverse-variance weighted, or the unweighted mean with the mean sigma_j
+// over sqrt(count) as its error.
 __global__ __launch_bounds__(kRedBlock) void k_est_final(LaunchSet L)
 {
     VP_REQ_PROLOGUE(L);
@@ -535,6 +545,24 @@ __global__ __launch_bounds__(kRedBlock) void k_est_final(LaunchSet L)
     bool zero = false;
     for (int j = first; j < n; ++j)
         if (!(hist_V[j] > 0.0)) zero = true;
+    if (q.average == 1) {
+        double s = 0.0, ss = 0.0;
+        for (int j = first; j < n; ++j) {
+            s = s + hist_I[j];
+            ss = ss + sqrt(hist_V[j]);
+        }
+        const double m = s / (double)cnt;
+        double c2 = 0.0;
+        for (int j = first; j < n; ++j) {
+            const double sig = sqrt(hist_V[j]);
+            const double r = hist_I[j] - m;
+            c2 = c2 + r * r / (sig * sig);
+        }
+        st->mean = m;
+        st->sdev = (ss / (double)cnt) / sqrt((double)cnt);
+        st->chi2 = zero ? __builtin_nan("") : c2;
+        return;
+    }
     if (zero) {
         double s = 0.0;
         for (int j = first; j < n; ++j) s = s + hist_I[j];
@@ -576,7 +604,7 @@ __global__ __launch_bounds__(kRedBlock) void k_realloc(LaunchSet L)
     const DevState* __restrict__ st = q.st;
     unsigned long long* __restrict__ ties = &q.st->ties;
     const double sumd = st->sumd;
-    if (!(sumd > 0.0)) return;
+    if (!(sumd > 0.0) || frozen(q)) return;
     unsigned long long nt = 0;
     const double first_visible = plus2 ? 1.0 : 3.0;
     for (int64_t h = (int64_t)bid * blockDim.x + threadIdx.x; h < n_hc; h += (int64_t)nblk * blockDim.x) {
@@ -672,7 +700,7 @@ __global__ __launch_bounds__(kRefineBlock) void k_refine(LaunchSet L)
     float* xm32 = map32 + (int64_t)mu * (n_g + 1);
     const double* Hm = H + (int64_t)mu * n_g;
     const double* Wm = W + (int64_t)mu * n_g;
-    if (alpha == 0.0 || n_g < 2) return;
+    if (alpha == 0.0 || n_g < 2 || frozen(q)) return;
 
     for (int i = tid; i <= n_g; i += kRefineBlock) x[i] = xm[i];
     DD part = dd_from(0.0);

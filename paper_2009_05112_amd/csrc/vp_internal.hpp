@@ -132,6 +132,8 @@ struct ReqArgs {
     int32_t dim, n_g;
     double omega, omega2, alpha, beta, n_ev;
     int32_t plus2, n_discard;
+    int32_t n_adapt;        // > 0: iterations with s.it >= n_adapt neither reallocate nor refine
+    int32_t average;        // 0 inverse-variance weighted, 1 unweighted combination
     int32_t slot;           // history slot of the current iteration (advanced on the device)
     int32_t grid;           // sampling workgroups
     int32_t est_blocks;     // workgroups of the estimate and reallocation passes

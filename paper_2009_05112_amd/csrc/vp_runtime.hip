@@ -116,6 +116,9 @@ vp_status vp::validate(const vp_params* P, const vp_integrand* f)
     if (P->hist_mode != VP_HIST_WEIGHTED && P->hist_mode != VP_HIST_LITERAL)
         return fail(VP_ERR_INVALID_ARG, "unknown hist_mode %d", P->hist_mode);
     if (P->n_st < 0) return fail(VP_ERR_INVALID_ARG, "n_st must be >= 0");
+    if (P->n_adapt < 0) return fail(VP_ERR_INVALID_ARG, "n_adapt must be >= 0");
+    if (P->average != VP_AVG_WEIGHTED && P->average != VP_AVG_UNWEIGHTED)
+        return fail(VP_ERR_INVALID_ARG, "unknown average %d", P->average);
     if (P->n_st > 0 && !pow_le(P->n_st, P->dim, 2, P->n_ev))
         return fail(VP_ERR_INVALID_ARG, "n_st %d leaves fewer than 2 samples per hypercube", P->n_st);
     if (P->lower && P->upper)
@@ -296,6 +299,8 @@ static void fill_req(vp_problem* p)
     q.n_ev = (double)P.n_ev;
     q.plus2 = P.realloc_plus2;
     q.n_discard = P.n_discard;
+    q.n_adapt = P.n_adapt;
+    q.average = P.average;
     q.slot = p->slot;
     q.grid = p->grid;
     q.est_blocks = est_grid(p->n_hc);

@@ -81,6 +81,8 @@ class Params:
     hist_mode: str = "weighted"
     realloc_plus2: bool = False
     n_discard: int = 0
+    n_adapt: int = 0            # > 0: iterations from this index on neither reallocate nor refine
+    average: str = "weighted"   # combination of the kept iterations: "weighted" or "unweighted"
     lower: Optional[np.ndarray] = None
     upper: Optional[np.ndarray] = None
 

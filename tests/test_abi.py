@@ -1,6 +1,7 @@
 """The C-ABI library loads and exports every symbol include/vegasp.h declares
 (no compute calls: this runs without a GPU)."""
 import ctypes
+import subprocess
 import os
 
 from paper_2009_05112_amd import _binding as B
@@ -45,6 +46,32 @@ def test_binding_struct_layout_matches_header_sizes():
     # field order of the ctypes mirrors follows the header declaration
     assert [f[0] for f in B.vp_params._fields_][:4] == ["dim", "n_ev", "n_g", "n_iter"]
     assert ctypes.sizeof(B.vp_result) == 8 * 3 + 4 * 2 + 8 * 3
+
+
+def test_binding_struct_offsets_match_the_c_compiler(tmp_path):
+    # every field offset and struct size of the ctypes mirrors, as the host C
+    # compiler lays out the header's structs
+    structs = {"vp_params": B.vp_params, "vp_result": B.vp_result, "vp_integrand": B.vp_integrand,
+               "vp_server_stats": B.vp_server_stats}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", f'#include "{B.HEADER}"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in filter(None, out):
+        name, field, val = line.split()
+        cls = structs[name]
+        want = ctypes.sizeof(cls) if field == "sizeof" else getattr(cls, field).offset
+        assert int(val) == want, (name, field, int(val), want)
+        seen += 1
+    assert seen == sum(len(c._fields_) + 1 for c in structs.values())
 
 
 def test_no_gpu_fails_loudly():

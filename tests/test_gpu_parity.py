@@ -174,6 +174,37 @@ def test_alpha_zero_beta_zero(ctx):
     np.testing.assert_array_equal(gp.alloc(), n0)
 
 
+@pytest.mark.parametrize("average", ["weighted", "unweighted"])
+def test_frozen_phase(ctx, average):
+    """Sec. 2.5: three adapting iterations, then four in which neither the map
+    nor the allocation changes; the combination over the frozen iterations,
+    weighted or plain."""
+    p, f = W.cfg_small_d4()
+    p = p.with_(n_iter=7, n_adapt=3, n_discard=3, average=average, seed=21)
+    gp, op = _pair(ctx, p, f)
+    ro = op.integrate()
+    for _ in range(3):
+        step_and_compare(gp, op)
+    m3, n3 = gp.map(), gp.alloc()
+    for _ in range(4):
+        step_and_compare(gp, op, check_map=False, check_alloc=False)
+        np.testing.assert_array_equal(gp.map(), m3)
+        np.testing.assert_array_equal(gp.alloc(), n3)
+    rg = gp.result()
+    np.testing.assert_array_equal(n3, ro["n_h"])
+    assert_close(m3, ro["map"], RTOL64, scale=np.ones_like(m3), what="frozen map")
+    assert_close(rg["I"], ro["I"], RTOL64, what="I_j")
+    assert_close(rg["V"], ro["V"], RTOL64, what="V_j")
+    assert_close(rg["mean"], ro["mean"], RTOL64, what="mean")
+    assert_close(rg["sdev"], ro["sdev"], RTOL64, what="sdev")
+    assert_close(rg["chi2"], ro["chi2"], 1e-9, what="chi2")
+    assert rg["dof"] == ro["dof"] == 3
+    if average == "unweighted":
+        sig = np.sqrt(rg["V"][3:])
+        assert rg["mean"] == pytest.approx(rg["I"][3:].mean(), rel=1e-14)
+        assert rg["sdev"] == pytest.approx(sig.mean() / 2.0, rel=1e-14)
+
+
 def test_constant_integrand(ctx):
     lo, hi = np.array([0.0, 0.0, 1.0]), np.array([2.0, 0.5, 4.0])
     p = W.Params(dim=3, n_ev=3000, n_g=40, n_iter=3, lower=lo, upper=hi, seed=4)

@@ -38,6 +38,8 @@ def small_mix():
     reqs.append((p.with_(n_iter=3, seed=77), f))
     p, f = W.cfg_diag_d8(n_ev=40_000, precision="fp32_neumaier")
     reqs.append((p.with_(n_iter=3, seed=78, hist_mode="literal"), f))
+    p, f = W.cfg_small_d4()
+    reqs.append((p.with_(n_ev=20_000, n_iter=6, n_adapt=3, n_discard=3, average="unweighted", seed=79), f))
     return reqs
 
 

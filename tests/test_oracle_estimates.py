@@ -206,6 +206,50 @@ def test_combination_fixtures(orc):
     mean, sdev, chi2, dof = orc.combine(d["I"], d["sig"], d["n_discard"])
     assert (mean, dof) == (pytest.approx(d["mean"]), d["dof"])
     assert sdev == pytest.approx(d["sdev"]) and chi2 == pytest.approx(d["chi2"])
+    for c in g["unweighted"]:
+        mean, sdev, chi2, dof = orc.combine(c["I"], c["sig"], c["n_discard"], "unweighted")
+        assert mean == pytest.approx(c["mean"], rel=1e-14)
+        assert sdev == pytest.approx(c["sdev"], rel=1e-14)
+        assert (math.isnan(chi2) if c["chi2"] is None else chi2 == pytest.approx(c["chi2"], rel=1e-14))
+        assert dof == c["dof"]
+
+
+# ---------------------------------------------------------------- frozen phase
+def test_frozen_phase_keeps_map_and_allocation(orc):
+    # Sec. 2.5: after the adapting iterations the map and the allocation stop
+    # changing (alpha = 0, and no reallocation), so every later iteration
+    # samples the same distribution.
+    f = W.gauss_single(3)
+    p = W.Params(dim=3, n_ev=20_000, n_g=64, n_iter=3, seed=11)
+    head = orc.Problem(p, f).integrate()
+    frozen = orc.Problem(p.with_(n_iter=7, n_adapt=3), f).integrate()
+    free = orc.Problem(p.with_(n_iter=7), f).integrate()
+    assert np.array_equal(frozen["I"][:3], head["I"])
+    assert np.array_equal(frozen["map"], head["map"])
+    assert np.array_equal(frozen["n_h"], head["n_h"])
+    assert not np.array_equal(free["map"], head["map"])
+    assert not np.array_equal(free["n_h"], head["n_h"])
+    # each frozen iteration: a fresh set of samples (new Philox iteration index)
+    assert len(set(frozen["I"][3:].tolist())) == 4
+
+
+def test_frozen_phase_unweighted_average_is_unbiased(orc):
+    # Sec. 2.5: with the map frozen the iterations are independent, identically
+    # distributed estimates; their plain average carries no weighting bias and
+    # its error is the mean sigma_j over sqrt(count).  Closed form: a single
+    # narrow Gaussian in D = 2, exact integral from erf.
+    f = W.gauss_single(2)
+    n_adapt, n_iter = 6, 46
+    p = W.Params(dim=2, n_ev=4_000, n_g=50, n_iter=n_iter, seed=5, n_adapt=n_adapt, n_discard=n_adapt,
+                 average="unweighted")
+    r = orc.Problem(p, f).integrate()
+    kept = r["I"][n_adapt:]
+    assert r["mean"] == pytest.approx(kept.mean(), rel=1e-13)
+    assert r["sdev"] == pytest.approx(r["sig"][n_adapt:].mean() / math.sqrt(kept.size), rel=1e-13)
+    assert r["dof"] == kept.size - 1
+    assert abs(r["mean"] - f.exact) < 4 * r["sdev"]
+    # the spread of the frozen iterations agrees with their own sigma_j
+    assert 0.5 < r["chi2"] / r["dof"] < 2.0
 
 
 # ---------------------------------------------------------------- the paper's own numbers
