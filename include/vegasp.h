@@ -141,7 +141,18 @@ enum { VP_HIST_WEIGHTED = 0, VP_HIST_LITERAL = 1 };
  *        as the last adapting iteration left them (the frozen phase of
  *        Sec. 2.5, alpha = 0; with n_discard = n_adapt the combined estimate
  *        uses frozen iterations only).  >= 0.
- *  average: VP_AVG_WEIGHTED or VP_AVG_UNWEIGHTED (vp_result). */
+ *  average: VP_AVG_WEIGHTED or VP_AVG_UNWEIGHTED (vp_result).
+ *  strat: stratifications per axis N_st^mu (Sec. 4, mixed stratification):
+ *        VP_STRAT_UNIFORM: n_st (or its rule) on every axis;
+ *        VP_STRAT_MIXED:   N_st + 1 on the first d axes and N_st on the
+ *                          others, N_st from the rule above and d the
+ *                          largest with 4 (N_st + 1)^d N_st^(dim - d) <= n_ev
+ *                          (n_st must be 0).
+ *  n_st_axes: NULL, or a host array of dim counts >= 1 that overrides both
+ *        (e.g. 46, 46, 1, ..., 1); their product must keep 2 samples per
+ *        hypercube and stay below 2^31.
+ * Hypercube h has digits k_mu in the mixed radix of the counts, axis 0 most
+ * significant; y^mu = (k_mu + u) / N_st^mu. */
 typedef struct {
     int32_t dim;
     int64_t n_ev;
@@ -159,9 +170,12 @@ typedef struct {
     int32_t n_st;
     int32_t n_adapt;
     int32_t average;
+    int32_t strat;
+    const int32_t* n_st_axes;
 } vp_params;
 
 enum { VP_AVG_WEIGHTED = 0, VP_AVG_UNWEIGHTED = 1 };
+enum { VP_STRAT_UNIFORM = 0, VP_STRAT_MIXED = 1 };
 
 /* Combined estimate over iterations n_discard .. n_iter_done - 1 (Sec. 2.5):
  *  VP_AVG_WEIGHTED:   inverse-variance weighted mean I, error
@@ -193,8 +207,10 @@ typedef struct {
 vp_status vp_problem_create(vp_ctx* ctx, const vp_params* params, const vp_integrand* f,
                             vp_problem** out);
 vp_status vp_problem_destroy(vp_problem* p);
-/* Derived sizes: stratifications per axis and number of hypercubes. */
+/* Derived sizes: stratifications of axis 0 and number of hypercubes. */
 vp_status vp_problem_info(vp_problem* p, int32_t* n_st, int64_t* n_hc);
+/* Stratifications of every axis: n_st_axes host array of dim entries. */
+vp_status vp_problem_strat(vp_problem* p, int32_t* n_st_axes);
 
 /* Enqueues n_iter iterations (asynchronous).  Each iteration (Sec. 2.3 and 3):
  * scan of n_h into sample offsets; sampling, map, integrand, per-hypercube

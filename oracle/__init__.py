@@ -26,7 +26,7 @@ class _Params(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_ev", C.c_int64), ("n_g", C.c_int32), ("n_st", C.c_int32),
                 ("alpha", C.c_double), ("beta", C.c_double), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("hist_mode", C.c_int32), ("realloc_plus2", C.c_int32),
-                ("n_adapt", C.c_int32)]
+                ("n_adapt", C.c_int32), ("n_st_axes", C.c_int32 * 64)]
 
 
 class _Integrand(C.Structure):
@@ -56,6 +56,8 @@ def lib():
         L.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
         L.or_nst.argtypes = [C.c_int32, C.c_int64]
         L.or_nst.restype = C.c_int32
+        L.or_nst_mixed.argtypes = [C.c_int32, C.c_int64, C.POINTER(C.c_int32)]
+        L.or_nst_mixed.restype = C.c_int32
         L.or_nst_classic.argtypes = [C.c_int32, C.c_int64]
         L.or_nst_classic.restype = C.c_int32
         L.or_integrand_eval.argtypes = [C.POINTER(_Integrand), dp]
@@ -104,6 +106,13 @@ def nst(dim: int, n_ev: int) -> int:
     return int(lib().or_nst(dim, n_ev))
 
 
+def nst_mixed(dim: int, n_ev: int):
+    """Per-axis stratifications of the mixed rule and its d (Sec. 4)."""
+    out = np.zeros(dim, dtype=np.int32)
+    d = lib().or_nst_mixed(dim, n_ev, _ip(out))
+    return out, int(d)
+
+
 def nst_classic(dim: int, n_ev: int) -> int:
     return int(lib().or_nst_classic(dim, n_ev))
 
@@ -123,11 +132,21 @@ class Problem:
         self.params = params
         self.f = integrand
         ns = n_st if n_st is not None else nst(params.dim, params.n_ev)
+        axes = getattr(params, "n_st_axes", None)
+        if axes is not None:
+            axes = np.asarray(axes, dtype=np.int32).ravel()
+        elif getattr(params, "strat", "uniform") == "mixed":
+            axes, _ = nst_mixed(params.dim, params.n_ev)
+        else:
+            axes = np.full(params.dim, ns, dtype=np.int32)
+        self.n_st_axes = axes
+        ns = int(axes[0])
         self.n_st = ns
         self.p = _Params(params.dim, int(params.n_ev), params.n_g, ns, float(params.alpha),
                          float(params.beta), int(params.seed) & ((1 << 64) - 1),
                          _PREC[params.precision], _HIST[params.hist_mode],
-                         1 if params.realloc_plus2 else 0, int(getattr(params, "n_adapt", 0) or 0))
+                         1 if params.realloc_plus2 else 0, int(getattr(params, "n_adapt", 0) or 0),
+                         (C.c_int32 * 64)(*[int(v) for v in axes]))
         f = integrand
         self._centers = np.ascontiguousarray(f.centers, dtype=np.float64).ravel()
         self._coefs = np.ascontiguousarray(f.coefs, dtype=np.float64)

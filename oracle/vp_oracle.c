@@ -101,6 +101,30 @@ int32_t or_nst_classic(int32_t dim, int64_t n_ev)
     return (int32_t)n;
 }
 
+/* Mixed stratification, Sec. 4: N_st + 1 stratifications on the first d     */
+/* axes and N_st on the others, with N_st from Eq. (Nst_vegasp) and d the     */
+/* largest number of axes that still leaves an average of 4 samples per       */
+/* hypercube, i.e. 4 (N_st + 1)^d N_st^(D - d) <= N_ev.  out[0..dim-1].       */
+/* ------------------------------------------------------------------------ */
+int32_t or_nst_mixed(int32_t dim, int64_t n_ev, int32_t* out)
+{
+    int32_t n = or_nst(dim, n_ev);
+    if (n < 1) return 0;
+    int32_t best = 0;
+    for (int32_t d = 0; d <= dim; ++d) {
+        /* 4 (n + 1)^d n^(dim - d), stopping once it passes n_ev */
+        double prod = 4.0;
+        int ok = 1;
+        for (int32_t mu = 0; mu < dim; ++mu) {
+            prod *= (mu < d) ? (double)(n + 1) : (double)n;
+            if (prod > (double)n_ev) { ok = 0; break; }
+        }
+        if (ok) best = d;
+    }
+    for (int32_t mu = 0; mu < dim; ++mu) out[mu] = mu < best ? n + 1 : n;
+    return best;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Integrands.  f(x) as the user defines it; the sampler multiplies by J.     */
 /* ------------------------------------------------------------------------ */
@@ -278,12 +302,20 @@ typedef struct {
     int32_t hist_mode;      /* OR_HIST_WEIGHTED / OR_HIST_LITERAL */
     int32_t realloc_plus2;  /* 1: n_h = floor(q) + 2 (Sec. 3, alternative rule) */
     int32_t n_adapt;        /* > 0: iterations it >= n_adapt keep map and n_h (Sec. 2.5) */
+    int32_t n_st_axes[64];  /* stratifications of axis mu (Sec. 4); 0: n_st */
 } or_params;
 
+/* N_st^mu, the stratifications of axis mu */
+static int32_t or_nst_axis(const or_params* p, int32_t mu)
+{
+    return p->n_st_axes[mu] > 0 ? p->n_st_axes[mu] : p->n_st;
+}
+
+/* Number of hypercubes, prod_mu N_st^mu (Sec. 3: N_st^D when uniform). */
 int64_t or_n_hypercubes(const or_params* p)
 {
     int64_t n = 1;
-    for (int32_t d = 0; d < p->dim; ++d) n *= p->n_st;
+    for (int32_t d = 0; d < p->dim; ++d) n *= or_nst_axis(p, d);
     return n;
 }
 
@@ -377,10 +409,18 @@ int or_sample_range(const or_params* p, const or_integrand* f, const double* map
                     double* S1, double* S2, double* H, double* W,
                     or_sample_rec* rec, int64_t rec_cap, int64_t* rec_count)
 {
-    const int32_t D = p->dim, NG = p->n_g, NST = p->n_st;
-    if (D < 1 || D > 64 || NG < 1 || NST < 1) return -1;
-    const double R = (double)NG / (double)NST;
-    const float R32 = (float)NG / (float)NST;
+    const int32_t D = p->dim, NG = p->n_g;
+    if (D < 1 || D > 64 || NG < 1) return -1;
+    /* y^mu = (k_mu + u) / N_st^mu, so t = y^mu N_g = (k_mu + u) R_mu */
+    int32_t NST[64];
+    double R[64];
+    float R32[64];
+    for (int32_t mu = 0; mu < D; ++mu) {
+        NST[mu] = or_nst_axis(p, mu);
+        if (NST[mu] < 1) return -1;
+        R[mu] = (double)NG / (double)NST[mu];
+        R32[mu] = (float)NG / (float)NST[mu];
+    }
     const uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32)};
     const int fp32 = (p->precision != OR_FP64);
     const int nwords = fp32 ? D : 2 * D;
@@ -419,11 +459,11 @@ int or_sample_range(const or_params* p, const or_integrand* f, const double* map
     int64_t nrec = 0;
 
     for (int64_t h = h_begin; h < h_end; ++h) {
-        /* digits of h in base N_st, axis 0 most significant */
+        /* digits of h in the mixed radix (N_st^0, ..., N_st^(D-1)), axis 0 most significant */
         int64_t rem = h;
         for (int32_t mu = D - 1; mu >= 0; --mu) {
-            k[mu] = (int32_t)(rem % NST);
-            rem /= NST;
+            k[mu] = (int32_t)(rem % NST[mu]);
+            rem /= NST[mu];
         }
         const int32_t n = n_h[h];
         const double inv_n = 1.0 / (double)n;
@@ -444,7 +484,7 @@ int or_sample_range(const or_params* p, const or_integrand* f, const double* map
                     uint64_t a = (uint64_t)(w[mu] >> 5);
                     uint64_t bb = (uint64_t)(w[D + mu] >> 6);
                     double u = (double)((a << 26) | bb) * 0x1p-53;
-                    double t = ((double)k[mu] + u) * R;
+                    double t = ((double)k[mu] + u) * R[mu];
                     int32_t i = (int32_t)floor(t);
                     if (i > NG - 1) i = NG - 1;
                     double delta = t - (double)i;
@@ -463,7 +503,7 @@ int or_sample_range(const or_params* p, const or_integrand* f, const double* map
                 float jac = 1.0f;
                 for (int32_t mu = 0; mu < D; ++mu) {
                     float u = (float)(w[mu] >> 8) * 0x1p-24f;
-                    float t = ((float)k[mu] + u) * R32;
+                    float t = ((float)k[mu] + u) * R32[mu];
                     int32_t i = (int32_t)floorf(t);
                     if (i > NG - 1) i = NG - 1;
                     float delta = t - (float)i;
@@ -559,9 +599,16 @@ int or_sample_range(const or_params* p, const or_integrand* f, const double* map
 int or_sample_indices(const or_params* p, const int32_t* n_h, int32_t it, int64_t h_begin,
                       int64_t h_end, int32_t* idx_out, double* t_out, int64_t cap)
 {
-    const int32_t D = p->dim, NG = p->n_g, NST = p->n_st;
-    const double R = (double)NG / (double)NST;
-    const float R32 = (float)NG / (float)NST;
+    const int32_t D = p->dim, NG = p->n_g;
+    if (D < 1 || D > 64) return -1;
+    int32_t NST[64];
+    double R[64];
+    float R32[64];
+    for (int32_t mu = 0; mu < D; ++mu) {
+        NST[mu] = or_nst_axis(p, mu);
+        R[mu] = (double)NG / (double)NST[mu];
+        R32[mu] = (float)NG / (float)NST[mu];
+    }
     const uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32)};
     const int fp32 = (p->precision != OR_FP64);
     const int nblk = ((fp32 ? D : 2 * D) + 3) / 4;
@@ -571,8 +618,8 @@ int or_sample_indices(const or_params* p, const int32_t* n_h, int32_t it, int64_
         int32_t k[64];
         int64_t rem = h;
         for (int32_t mu = D - 1; mu >= 0; --mu) {
-            k[mu] = (int32_t)(rem % NST);
-            rem /= NST;
+            k[mu] = (int32_t)(rem % NST[mu]);
+            rem /= NST[mu];
         }
         for (int32_t j = 0; j < n_h[h]; ++j, ++s) {
             if (s >= cap) return -1;
@@ -587,11 +634,11 @@ int or_sample_indices(const or_params* p, const int32_t* n_h, int32_t it, int64_
                     uint64_t a = (uint64_t)(w[mu] >> 5);
                     uint64_t bb = (uint64_t)(w[D + mu] >> 6);
                     double u = (double)((a << 26) | bb) * 0x1p-53;
-                    tt = ((double)k[mu] + u) * R;
+                    tt = ((double)k[mu] + u) * R[mu];
                     i = (int32_t)floor(tt);
                 } else {
                     float u = (float)(w[mu] >> 8) * 0x1p-24f;
-                    float t32 = ((float)k[mu] + u) * R32;
+                    float t32 = ((float)k[mu] + u) * R32[mu];
                     tt = (double)t32;
                     i = (int32_t)floorf(t32);
                 }

@@ -20,6 +20,7 @@ _KIND = {"gauss_mix": 1, "corr_gauss": 2, "exp_abs": 3, "const": 4, "affine": 5,
 _PREC = {"fp64": 0, "fp32_acc64": 1, "fp32_neumaier": 2}
 _HIST = {"weighted": 0, "literal": 1}
 _AVG = {"weighted": 0, "unweighted": 1}
+_STRAT = {"uniform": 0, "mixed": 1}
 
 VP_OK, VP_ERR_INVALID_ARG, VP_ERR_OOM, VP_ERR_DEVICE, VP_ERR_NUMERIC, VP_ERR_NOT_READY, \
     VP_ERR_CANCELLED, VP_ERR_STATE = range(8)
@@ -61,7 +62,8 @@ class vp_params(C.Structure):
                 ("alpha", C.c_double), ("beta", C.c_double), ("lower", C.POINTER(C.c_double)),
                 ("upper", C.POINTER(C.c_double)), ("seed", C.c_uint64), ("precision", C.c_int32),
                 ("hist_mode", C.c_int32), ("realloc_plus2", C.c_int32), ("n_discard", C.c_int32),
-                ("n_st", C.c_int32), ("n_adapt", C.c_int32), ("average", C.c_int32)]
+                ("n_st", C.c_int32), ("n_adapt", C.c_int32), ("average", C.c_int32),
+                ("strat", C.c_int32), ("n_st_axes", C.POINTER(C.c_int32))]
 
 
 class vp_result(C.Structure):
@@ -104,6 +106,7 @@ def lib():
             "vp_problem_create": ([vp, C.POINTER(vp_params), C.POINTER(vp_integrand), C.POINTER(vp)], C.c_int),
             "vp_problem_destroy": ([vp], C.c_int),
             "vp_problem_info": ([vp, ip, C.POINTER(C.c_int64)], C.c_int),
+            "vp_problem_strat": ([vp, ip], C.c_int),
             "vp_iterate": ([vp, C.c_int32], C.c_int),
             "vp_sync": ([vp], C.c_int),
             "vp_result_get": ([vp, C.POINTER(vp_result), dp, dp, C.c_int32], C.c_int),
@@ -203,10 +206,15 @@ def marshal(params, integrand):
         fi = vp_integrand(_KIND[f.kind], f.dim, f.n_terms, arr(f.centers), arr(f.coefs), arr(f.amps),
                           arr(f.chol), float(f.scale), None, None)
     p = params
+    axes = getattr(p, "n_st_axes", None)
+    if axes is not None:
+        axes = np.ascontiguousarray(axes, dtype=np.int32).ravel()
+        keep.append(axes)
     pp = vp_params(p.dim, int(p.n_ev), p.n_g, p.n_iter, float(p.alpha), float(p.beta), arr(p.lower),
                    arr(p.upper), int(p.seed) & ((1 << 64) - 1), _PREC[p.precision], _HIST[p.hist_mode],
                    1 if p.realloc_plus2 else 0, int(p.n_discard), int(getattr(p, "n_st", 0) or 0),
-                   int(getattr(p, "n_adapt", 0) or 0), _AVG[getattr(p, "average", "weighted")])
+                   int(getattr(p, "n_adapt", 0) or 0), _AVG[getattr(p, "average", "weighted")],
+                   _STRAT[getattr(p, "strat", "uniform")], None if axes is None else _ip(axes))
     return pp, fi, keep
 
 
@@ -225,6 +233,9 @@ class Problem:
         nh = C.c_int64()
         check(lib().vp_problem_info(self.h, C.byref(ns), C.byref(nh)))
         self.n_st, self.n_hc = ns.value, nh.value
+        ax = np.empty(params.dim, dtype=np.int32)
+        check(lib().vp_problem_strat(self.h, _ip(ax)))
+        self.n_st_axes = ax
 
     def iterate(self, n: int = 1):
         check(lib().vp_iterate(self.h, n), "vp_iterate")

@@ -45,6 +45,27 @@ TABLES += [
     ("vp_sample_fp32neu_generic.hip", "sample_entry_fp32neu_generic(int dim, bool map_lds, bool rec)",
      "P_FP32_NEUMAIER", [(None, "0", range(1, 17), "entry_for_global_lds_only", 0)],
      "single-precision map and integrand, compensated single-precision sums, any integrand kind, D = 1..16"),
+    # mixed stratification (per-axis counts)
+    ("vp_sample_fp64_generic_mix.hip", "sample_entry_fp64_generic_mix(int dim, bool map_lds, bool rec)", "P_FP64",
+     [(None, "0", range(1, 25), "entry_for_global", "0, true")],
+     "double precision, any integrand kind, mixed stratification, D = 1..24"),
+    ("vp_sample_fp32acc_generic_mix.hip", "sample_entry_fp32acc_generic_mix(int dim, bool map_lds, bool rec)",
+     "P_FP32_ACC64", [(None, "0", range(1, 17), "entry_for_global", "0, true")],
+     "single-precision map and integrand, double sums, any integrand kind, mixed stratification, D = 1..16"),
+    ("vp_sample_fp32neu_generic_mix.hip", "sample_entry_fp32neu_generic_mix(int dim, bool map_lds, bool rec)",
+     "P_FP32_NEUMAIER", [(None, "0", range(1, 17), "entry_for_global_lds_only", "0, true")],
+     "single-precision map and integrand, compensated single-precision sums, any integrand kind, "
+     "mixed stratification, D = 1..16"),
+    ("vp_sample_fp64_batch_mix.hip", "sample_entry_fp64_batch_acc_mix(int dim, bool map_lds, bool rec)", "P_FP64",
+     [(None, "K_BATCH_ACC", range(1, 25), "entry_for_global", "0, true")],
+     "double precision, batched integrand (accumulation of the user's values), mixed stratification, D = 1..24",
+     ["SampleEntry sample_entry_fp64_batch_gen_mix(int dim)",
+      "{",
+      "    SampleEntry e = {nullptr, nullptr, 0};",
+      "    switch (dim) {"] +
+     [f"    case {d}: e = make_entry<{d}, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;"
+      for d in range(1, 25)] +
+     ["    default: break;", "    }", "    return e;", "}", ""]),
 ]
 
 

@@ -181,7 +181,7 @@ struct SampleEntry {
 // Specialised kernel for (precision, integrand kind and terms, dim, map in
 // LDS, training records), or an entry with launch == nullptr when none is
 // built.
-SampleEntry sample_entry(int prec, int kind, int n_terms, int dim, bool map_lds, bool rec);
+SampleEntry sample_entry(int prec, int kind, int n_terms, int dim, bool map_lds, bool rec, bool mix = false);
 #define VP_DECL_GAUSS(tag)                                          \
     SampleEntry sample_entry_##tag##_gauss_k1(int dim, bool map_lds, bool rec); \
     SampleEntry sample_entry_##tag##_gauss_k2(int dim, bool map_lds, bool rec); \
@@ -197,6 +197,12 @@ SampleEntry sample_entry_fp32acc_generic(int dim, bool map_lds, bool rec);
 SampleEntry sample_entry_fp64_batch_gen(int dim);
 SampleEntry sample_entry_fp64_batch_acc(int dim, bool map_lds, bool rec);
 SampleEntry sample_entry_fp32neu_generic(int dim, bool map_lds, bool rec);
+// mixed stratification (per-axis counts): generic kinds and batched integrands
+SampleEntry sample_entry_fp64_generic_mix(int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp32acc_generic_mix(int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp32neu_generic_mix(int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp64_batch_gen_mix(int dim);
+SampleEntry sample_entry_fp64_batch_acc_mix(int dim, bool map_lds, bool rec);
 
 // sampling kernels' LDS needs (bytes) for histogram and map
 inline size_t hist_lds_bytes(int dim, int n_g) { return (size_t)dim * n_g * 2 * sizeof(double); }
@@ -210,11 +216,17 @@ inline size_t map_lds_bytes(int prec, int dim, int n_g)
 // Integrand constants in the layout the sampling kernel reads (see
 // vp_sample.hpp): elements (double on the FP64 path, float otherwise).  They
 // are built on the host; kernels that stage them in LDS put them after the
-// training data and the map.
+// training data and the map.  The stratification of every axis follows the
+// integrand's constants: R_mu = N_g / N_st^mu, then N_st^mu (exact as values
+// of either type), read by the kernels of mixed stratification.
 constexpr int kFcHead = 16;
-__host__ __device__ constexpr int fc_count(int kind, int dim)
+__host__ __device__ constexpr int fc_strat_offset(int kind, int dim)
 {
     return kFcHead + 4 * dim + (kind == K_CORR_GAUSS ? dim * dim : 0);
+}
+__host__ __device__ constexpr int fc_count(int kind, int dim)
+{
+    return fc_strat_offset(kind, dim) + 2 * dim;
 }
 __host__ __device__ constexpr size_t fc_lds_bytes(int prec, int kind, int dim)
 {

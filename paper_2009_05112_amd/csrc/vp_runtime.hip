@@ -54,8 +54,18 @@ constexpr uint32_t kStateMagic = 0x56504C53u;  // "SLPV"
 }  // namespace
 
 // ---------------------------------------------------------------- helpers
-SampleEntry vp::sample_entry(int prec, int kind, int n_terms, int dim, bool map_lds, bool rec)
+SampleEntry vp::sample_entry(int prec, int kind, int n_terms, int dim, bool map_lds, bool rec, bool mix)
 {
+    if (mix) {
+        // per-axis stratification: the generic kernels (constants in LDS)
+        typedef SampleEntry (*Table)(int, bool, bool);
+        static const Table generic_mix[3] = {sample_entry_fp64_generic_mix, sample_entry_fp32acc_generic_mix,
+                                             sample_entry_fp32neu_generic_mix};
+        if (prec < 0 || prec > 2) return SampleEntry{nullptr, nullptr, 0};
+        if (kind == K_BATCH)
+            return prec == P_FP64 ? sample_entry_fp64_batch_acc_mix(dim, map_lds, rec) : SampleEntry{nullptr, nullptr, 0};
+        return generic_mix[prec](dim, map_lds, rec);
+    }
     typedef SampleEntry (*Table)(int, bool, bool);
     static const Table gauss[3][4] = {
         {sample_entry_fp64_gauss_k1, sample_entry_fp64_gauss_k2, sample_entry_fp64_gauss_k3, sample_entry_fp64_gauss_k4},
@@ -101,6 +111,40 @@ static bool pow_le(int64_t n, int dim, int64_t mult, int64_t limit)
     return acc <= limit;
 }
 
+// mult * prod(counts) <= limit, without overflow
+static bool prod_le(const int32_t* counts, int dim, int64_t mult, int64_t limit)
+{
+    int64_t acc = mult;
+    if (acc > limit) return false;
+    for (int d = 0; d < dim; ++d) {
+        if (acc > limit / counts[d]) return false;
+        acc *= counts[d];
+    }
+    return acc <= limit;
+}
+
+// Stratifications of every axis (Sec. 3 and Sec. 4): the user's per-axis
+// counts; or N_st + 1 on the first d axes and N_st on the rest, d the largest
+// that leaves 4 samples per hypercube on average; or N_st on every axis.
+static void strat_counts(const vp_params* P, int32_t* out)
+{
+    const int D = P->dim;
+    if (P->n_st_axes) {
+        for (int d = 0; d < D; ++d) out[d] = P->n_st_axes[d];
+        return;
+    }
+    const int32_t n = P->n_st > 0 ? P->n_st : nst_rule(D, P->n_ev);
+    for (int d = 0; d < D; ++d) out[d] = n;
+    if (P->strat != VP_STRAT_MIXED) return;
+    for (int d = 0; d < D; ++d) {
+        out[d] = n + 1;
+        if (!prod_le(out, D, 4, P->n_ev)) {
+            out[d] = n;
+            break;
+        }
+    }
+}
+
 vp_status vp::validate(const vp_params* P, const vp_integrand* f)
 {
     if (!P || !f) return fail(VP_ERR_INVALID_ARG, "params and integrand are required");
@@ -117,6 +161,18 @@ vp_status vp::validate(const vp_params* P, const vp_integrand* f)
         return fail(VP_ERR_INVALID_ARG, "unknown hist_mode %d", P->hist_mode);
     if (P->n_st < 0) return fail(VP_ERR_INVALID_ARG, "n_st must be >= 0");
     if (P->n_adapt < 0) return fail(VP_ERR_INVALID_ARG, "n_adapt must be >= 0");
+    if (P->strat != VP_STRAT_UNIFORM && P->strat != VP_STRAT_MIXED)
+        return fail(VP_ERR_INVALID_ARG, "unknown strat %d", P->strat);
+    if (P->strat == VP_STRAT_MIXED && P->n_st > 0 && !P->n_st_axes)
+        return fail(VP_ERR_INVALID_ARG, "the mixed rule takes N_st from n_ev: n_st must be 0");
+    if (P->n_st_axes) {
+        for (int d = 0; d < P->dim; ++d)
+            if (P->n_st_axes[d] < 1) return fail(VP_ERR_INVALID_ARG, "n_st_axes[%d] = %d < 1", d, P->n_st_axes[d]);
+        if (!prod_le(P->n_st_axes, P->dim, 2, P->n_ev))
+            return fail(VP_ERR_INVALID_ARG, "n_st_axes leave fewer than 2 samples per hypercube");
+        if (!prod_le(P->n_st_axes, P->dim, 1, 2147483647LL))
+            return fail(VP_ERR_INVALID_ARG, "n_st_axes give 2^31 or more hypercubes");
+    }
     if (P->average != VP_AVG_WEIGHTED && P->average != VP_AVG_UNWEIGHTED)
         return fail(VP_ERR_INVALID_ARG, "unknown average %d", P->average);
     if (P->n_st > 0 && !pow_le(P->n_st, P->dim, 2, P->n_ev))
@@ -399,7 +455,9 @@ vp_status vp_ctx_info(vp_ctx* c, int32_t* n_cu, int64_t* lds)
 
 // Derived sizes and the sampling launch shape of a problem.
 struct Shape {
-    int32_t n_st;
+    int32_t n_st;           // axis 0
+    int32_t nst_ax[kMaxDim];
+    bool mix;               // counts differ between axes
     int64_t n_hc;
     int hist_axes, map_lds;
     SampleEntry entry;
@@ -421,9 +479,10 @@ struct Shape {
 // scale, affine constant, coefficients, amplitudes, radii^2, the K centres of
 // each axis side by side, the Cholesky factor), as double on the FP64 path and
 // as float on the split paths.
-static void write_constants(const IntegrandDev& f, int prec, int D, char* out)
+static void write_constants(const IntegrandDev& f, int prec, int D, int n_g, const int32_t* nst_ax, char* out)
 {
     const int n = fc_count(f.kind, D);
+    const int so = fc_strat_offset(f.kind, D);
     const bool gauss_like = f.kind == VP_F_GAUSS_MIX || f.kind == VP_F_EXP_ABS || f.kind == VP_F_BALLS;
     for (int i = 0; i < n; ++i) {
         double v = 0.0;
@@ -452,6 +511,13 @@ static void write_constants(const IntegrandDev& f, int prec, int D, char* out)
                 v = f.centers[c];
                 v32 = f.centers32[c];
             }
+        } else if (i >= so + D) {
+            v = (double)nst_ax[i - so - D];
+            v32 = (float)nst_ax[i - so - D];
+        } else if (i >= so) {
+            // R_mu as the uniform path computes R (double) and R32 (float)
+            v = (double)n_g / (double)nst_ax[i - so];
+            v32 = (float)n_g / (float)nst_ax[i - so];
         } else if (i >= kFcHead + 4 * D) {
             v = f.chol[i - kFcHead - 4 * D];
             v32 = f.chol32[i - kFcHead - 4 * D];
@@ -480,9 +546,14 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
                                Shape* sh)
 {
     const int D = P->dim, NG = P->n_g;
-    sh->n_st = P->n_st > 0 ? P->n_st : nst_rule(D, P->n_ev);
+    strat_counts(P, sh->nst_ax);
+    sh->n_st = sh->nst_ax[0];
+    sh->mix = false;
     int64_t nhc = 1;
-    for (int d = 0; d < D; ++d) nhc *= sh->n_st;
+    for (int d = 0; d < D; ++d) {
+        nhc *= sh->nst_ax[d];
+        if (sh->nst_ax[d] != sh->n_st) sh->mix = true;
+    }
     sh->n_hc = nhc;
     const int prec = P->precision;
     // training data: as many axes as fit privatised in LDS beside the
@@ -497,10 +568,10 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     sh->map_lds = !batch && hb + mb + fcb <= ctx->lds_max ? 1 : 0;  // the accumulate mode reads no map
     const bool rec = sh->hist_axes < D;
     if (rec) sh->map_lds = 0;
-    sh->entry = sample_entry(prec, f->kind, f->n_terms, D, sh->map_lds != 0, rec);
+    sh->entry = sample_entry(prec, f->kind, f->n_terms, D, sh->map_lds != 0, rec, sh->mix);
     if (!sh->entry.launch && sh->map_lds) {
         sh->map_lds = 0;
-        sh->entry = sample_entry(prec, f->kind, f->n_terms, D, false, rec);
+        sh->entry = sample_entry(prec, f->kind, f->n_terms, D, false, rec, sh->mix);
     }
     if (!sh->entry.launch) return fail(VP_ERR_INVALID_ARG, "no sampling kernel for dim %d", D);
     sh->block = sh->entry.block;
@@ -514,7 +585,7 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     sh->gen_grid = 0;
     sh->gen_entry = SampleEntry{nullptr, nullptr, 0};
     if (batch) {
-        sh->gen_entry = sample_entry_fp64_batch_gen(D);
+        sh->gen_entry = sh->mix ? sample_entry_fp64_batch_gen_mix(D) : sample_entry_fp64_batch_gen(D);
         if (!sh->gen_entry.launch) return fail(VP_ERR_INVALID_ARG, "no batched-integrand kernel for dim %d", D);
         sh->gen_lds = fc_lds_offset(0, false, VP_FP64, D, NG) + fc_lds_bytes(VP_FP64, VP_F_BATCH, D);
         const int gocc = std::max(1, cached_occupancy(ctx->device, sh->gen_entry, sh->gen_entry.block, sh->gen_lds));
@@ -645,6 +716,8 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
     p->P.upper = p->upper.data();
     fill_integrand(p->fh, f);
     p->n_st = sh.n_st;
+    p->nst_ax.assign(sh.nst_ax, sh.nst_ax + D);
+    p->P.n_st_axes = p->nst_ax.data();
     const int64_t nhc = sh.n_hc;
     p->n_hc = nhc;
     p->omega = 1.0 / (double)nhc;
@@ -728,7 +801,7 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
     memcpy(head.data() + lay.d_req, &p->req, sizeof(ReqArgs));
     memcpy(head.data() + lay.bounds, p->lower.data(), D * sizeof(double));
     memcpy(head.data() + lay.bounds + D * sizeof(double), p->upper.data(), D * sizeof(double));
-    write_constants(p->fh, P->precision, D, head.data() + lay.fc);
+    write_constants(p->fh, P->precision, D, NG, sh.nst_ax, head.data() + lay.fc);
     hipStream_t sm = ctx->stream;
     int64_t n0 = P->n_ev / nhc;
     if (n0 < 2) n0 = 2;
@@ -851,6 +924,13 @@ vp_status vp_problem_info(vp_problem* p, int32_t* n_st, int64_t* n_hc)
     if (!p) return fail(VP_ERR_INVALID_ARG, "problem is NULL");
     if (n_st) *n_st = p->n_st;
     if (n_hc) *n_hc = p->n_hc;
+    return VP_OK;
+}
+
+vp_status vp_problem_strat(vp_problem* p, int32_t* n_st_axes)
+{
+    if (!p || !n_st_axes) return fail(VP_ERR_INVALID_ARG, "problem and n_st_axes are required");
+    for (size_t d = 0; d < p->nst_ax.size(); ++d) n_st_axes[d] = p->nst_ax[d];
     return VP_OK;
 }
 

@@ -373,11 +373,13 @@ struct SampleHot {
     int32_t n_g;
     double R;
     float R32;
+    const double* Rv;    // mixed stratification: R_mu per axis (LDS)
+    const float* Rv32;
 };
 
 // ---------------------------------------------------------------- one sample
 // Stratified y in hypercube k (Sec. 3): y^mu = (k_mu + u) / N_st, so
-// t = y N_g = (k_mu + u) R; vegas map (Sec. 2.2, Eqs. y and jac):
+// t = y N_g = (k_mu + u) R (MIX: N_st^mu and R_mu per axis, Sec. 4); vegas map (Sec. 2.2, Eqs. y and jac):
 // i = floor(t) (clamped to N_g - 1), delta = t - i (clamped to 1),
 // x = x_i + Delta x_i delta, J = prod_mu N_g Delta x_i.
 // FP64: u from 53 bits -- the high word of axis mu is word mu of the
@@ -406,7 +408,7 @@ struct BatchOut {
     int64_t n, cap, pos;
 };
 
-template <int D, bool MAPLDS, int KT, typename FP, bool GEN = false>
+template <int D, bool MAPLDS, int KT, typename FP, bool GEN = false, bool MIX = false>
 __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair64<MAPLDS>& map, FP fc,
                                               uint32_t j, uint32_t h, const int32_t* k,
                                               int32_t* idx, int kind, int K, const BatchOut* out = nullptr)
@@ -441,7 +443,7 @@ __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair6
             const double hi = (double)(hi_blk[r] >> 5);
             const double lo = (double)(lo_blk[lw % 4] >> 6);
             const double u = fma(hi, 0x1p-27, lo * 0x1p-53);  // exact: a 53-bit integer times 2^-53
-            const double t = ((double)k[mu] + u) * a.R;
+            const double t = ((double)k[mu] + u) * (MIX ? a.Rv[mu] : a.R);
             int i = (int)t;
             i = i < n_g - 1 ? i : n_g - 1;
             double delta = t - (double)i;
@@ -469,7 +471,7 @@ __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair6
 }
 
 // FP32 split: u = (w >> 8) 2^-24 from the high word of each axis alone.
-template <int D, bool MAPLDS, int KT, typename FP>
+template <int D, bool MAPLDS, int KT, typename FP, bool MIX = false>
 __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32<MAPLDS>& map, FP fc,
                                              uint32_t j, uint32_t h, const int32_t* k, int32_t* idx,
                                              int kind, int K)
@@ -490,7 +492,7 @@ __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32
             const int mu = 4 * g + r;
             if (mu >= D) break;
             const float u = (float)(w[r] >> 8) * 0x1p-24f;
-            const float t = ((float)k[mu] + u) * a.R32;
+            const float t = ((float)k[mu] + u) * (MIX ? a.Rv32[mu] : a.R32);
             int i = (int)t;
             i = i < n_g - 1 ? i : n_g - 1;
             float delta = t - (float)i;
@@ -541,7 +543,9 @@ __device__ __forceinline__ void put_training(double* rec, int64_t stride, int ha
 // not fit in LDS); a separate instantiation, so that the common case carries
 // none of that code.
 // KT: Gaussian-mixture terms fixed at compile time (0: read at run time).
-template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT>
+// MIX: per-axis stratification counts (Sec. 4), read with R_mu from the
+// constants staged in LDS; only kernels that stage them there have it.
+template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT, bool MIX>
 __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(LaunchSet L)
 {
     VP_REQ_PROLOGUE(L);
@@ -584,6 +588,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
     // Gaussian's D x D factor and the generic kernel's constants are staged
     // in LDS.
     constexpr bool FC_SMEM = (KIND == K_GAUSS_MIX);
+    static_assert(!(MIX && FC_SMEM), "mixed stratification reads its constants from LDS");
     typedef __attribute__((address_space(4))) const MapT ConstT;
     ConstT* fcg = (ConstT*)a.fc;
     if constexpr (!FC_SMEM) {
@@ -642,6 +647,16 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
     hot.n_g = n_g;
     hot.R = a.R;
     hot.R32 = a.R32;
+    // mixed stratification: R_mu, then N_st^mu, after the integrand constants
+    const MapT* mix_r = lds_fc + fc_strat_offset(kind, D);
+    const MapT* mix_n = mix_r + D;
+    if constexpr (PREC == P_FP64) {
+        hot.Rv = reinterpret_cast<const double*>(mix_r);
+        hot.Rv32 = nullptr;
+    } else {
+        hot.Rv = nullptr;
+        hot.Rv32 = reinterpret_cast<const float*>(mix_r);
+    }
     uint32_t bad = 0;
 
     if (s_a < s_b) {
@@ -679,8 +694,9 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                     uint32_t r = hh32;
 #pragma unroll
                     for (int m = D - 1; m >= 0; --m) {
-                        k[m] = (int32_t)(r % n_st);
-                        r /= n_st;
+                        const uint32_t nm = MIX ? (uint32_t)mix_n[m] : n_st;
+                        k[m] = (int32_t)(r % nm);
+                        r /= nm;
                     }
                 }
                 uint32_t n_cur = (uint32_t)(gofs(offs, ob, h + 1) - o_cur0);
@@ -713,7 +729,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
 #pragma unroll
                         for (int m = D - 1; m >= 0; --m) {
                             const int32_t v = k[m] + carry;
-                            carry = v == (int32_t)n_st ? 1 : 0;
+                            carry = v == (MIX ? (int32_t)mix_n[m] : (int32_t)n_st) ? 1 : 0;
                             k[m] = carry ? 0 : v;
                         }
                     }
@@ -729,7 +745,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                     const int64_t bpos = batch_pos(s_a + (int64_t)s, n_tot);
                     if constexpr (GEN) {
                         bout.pos = bpos;
-                        (void)sample_fp64<D, MAPLDS, 0, const MapT*, true>(hot, map, lds_fc, j, hh32, k, idx, kind, K,
+                        (void)sample_fp64<D, MAPLDS, 0, const MapT*, true, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K,
                                                                            &bout);
                     } else if constexpr (PREC == P_FP64) {
                         double v;
@@ -740,7 +756,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                             for (int mu = 0; mu < D; ++mu) idx[mu] = bout.idx[mu * bout.cap + pos];
                         } else {
                             v = (FC_SMEM ? sample_fp64<D, MAPLDS, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
-                                         : sample_fp64<D, MAPLDS, KT, const MapT*>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
+                                         : sample_fp64<D, MAPLDS, KT, const MapT*, false, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
                         }
                         run.add(v);
                         if (!isfinite(v)) ++bad;
@@ -750,7 +766,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         put_training<D, REC>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
                     } else if constexpr (PREC == P_FP32_ACC64) {
                         const float v32 = (FC_SMEM ? sample_fp32<D, MAPLDS, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
-                                           : sample_fp32<D, MAPLDS, KT, const MapT*>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
+                                           : sample_fp32<D, MAPLDS, KT, const MapT*, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
                         const double v = (double)v32;
                         run.add(v);
                         if (!isfinite(v32)) ++bad;
@@ -760,7 +776,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         put_training<D, REC>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
                     } else {
                         const float v32 = (FC_SMEM ? sample_fp32<D, MAPLDS, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
-                                           : sample_fp32<D, MAPLDS, KT, const MapT*>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
+                                           : sample_fp32<D, MAPLDS, KT, const MapT*, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
                         run.addf(v32);
                         if (!isfinite(v32)) ++bad;
                         const float v2 = v32 * v32;
@@ -899,65 +915,65 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
     }
 }
 
-template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT>
+template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT, bool MIX>
 void launch_sample(const LaunchSet& L, int grid, int block, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sample<D, PREC, MAPLDS, KIND, REC, KT>), dim3(grid), dim3(block), lds, s, L);
+    hipLaunchKernelGGL((k_sample<D, PREC, MAPLDS, KIND, REC, KT, MIX>), dim3(grid), dim3(block), lds, s, L);
 }
 
-template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT>
+template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT, bool MIX>
 int sample_occupancy(int block, size_t lds)
 {
     int n = 0;
-    (void)hipFuncSetAttribute((const void*)k_sample<D, PREC, MAPLDS, KIND, REC, KT>,
+    (void)hipFuncSetAttribute((const void*)k_sample<D, PREC, MAPLDS, KIND, REC, KT, MIX>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sample<D, PREC, MAPLDS, KIND, REC, KT>, block, lds) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sample<D, PREC, MAPLDS, KIND, REC, KT, MIX>, block,
+                                                     lds) != hipSuccess)
         return 0;
     return n;
 }
 
-template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT>
+template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT, bool MIX = false>
 SampleEntry make_entry()
 {
     SampleEntry e;
-    e.launch = launch_sample<D, PREC, MAPLDS, KIND, REC, KT>;
-    e.occupancy = sample_occupancy<D, PREC, MAPLDS, KIND, REC, KT>;
+    e.launch = launch_sample<D, PREC, MAPLDS, KIND, REC, KT, MIX>;
+    e.occupancy = sample_occupancy<D, PREC, MAPLDS, KIND, REC, KT, MIX>;
     e.block = sample_block(PREC, KIND, D, MAPLDS);
     return e;
 }
 
 // The instantiation for a layout: map in LDS (all training data in LDS), map
 // in global memory with all training data in LDS, or with records.
-template <int D, int PREC, int KIND, int KT = 0>
+template <int D, int PREC, int KIND, int KT = 0, bool MIX = false>
 SampleEntry entry_for(bool map_lds, bool rec)
 {
-    if (map_lds) return rec ? SampleEntry{nullptr, nullptr, 0} : make_entry<D, PREC, true, KIND, false, KT>();
-    return rec ? make_entry<D, PREC, false, KIND, true, KT>() : make_entry<D, PREC, false, KIND, false, KT>();
+    if (map_lds) return rec ? SampleEntry{nullptr, nullptr, 0} : make_entry<D, PREC, true, KIND, false, KT, MIX>();
+    return rec ? make_entry<D, PREC, false, KIND, true, KT, MIX>() : make_entry<D, PREC, false, KIND, false, KT, MIX>();
 }
 
 // The same without the map-in-LDS variant (kernels whose integrand leaves no
 // room for it).
-template <int D, int PREC, int KIND, int KT = 0>
+template <int D, int PREC, int KIND, int KT = 0, bool MIX = false>
 SampleEntry entry_for_global(bool map_lds, bool rec)
 {
     if (map_lds) return SampleEntry{nullptr, nullptr, 0};
-    return rec ? make_entry<D, PREC, false, KIND, true, KT>() : make_entry<D, PREC, false, KIND, false, KT>();
+    return rec ? make_entry<D, PREC, false, KIND, true, KT, MIX>() : make_entry<D, PREC, false, KIND, false, KT, MIX>();
 }
 
 // Compensated sums need every axis's bins in LDS: no record variants.
-template <int D, int PREC, int KIND, int KT = 0>
+template <int D, int PREC, int KIND, int KT = 0, bool MIX = false>
 SampleEntry entry_for_lds_only(bool map_lds, bool rec)
 {
     if (rec) return SampleEntry{nullptr, nullptr, 0};
-    return map_lds ? make_entry<D, PREC, true, KIND, false, KT>() : make_entry<D, PREC, false, KIND, false, KT>();
+    return map_lds ? make_entry<D, PREC, true, KIND, false, KT, MIX>() : make_entry<D, PREC, false, KIND, false, KT, MIX>();
 }
 
-template <int D, int PREC, int KIND, int KT = 0>
+template <int D, int PREC, int KIND, int KT = 0, bool MIX = false>
 SampleEntry entry_for_global_lds_only(bool map_lds, bool rec)
 {
     if (rec || map_lds) return SampleEntry{nullptr, nullptr, 0};
-    return make_entry<D, PREC, false, KIND, false, KT>();
+    return make_entry<D, PREC, false, KIND, false, KT, MIX>();
 }
 
 }  // namespace vp

@@ -44,6 +44,7 @@ struct ServedReq {
     uint64_t ticket = 0;
     vp_params P;
     std::vector<double> lower, upper;
+    std::vector<int32_t> nst_ax;
     vp_integrand f;
     std::vector<double> centers, coefs, amps, chol;
     size_t bytes = 0;
@@ -111,6 +112,10 @@ static void copy_request(ServedReq* r, const vp_params* P, const vp_integrand* f
         r->upper.assign(P->upper, P->upper + P->dim);
         r->P.lower = r->lower.data();
         r->P.upper = r->upper.data();
+    }
+    if (P->n_st_axes) {
+        r->nst_ax.assign(P->n_st_axes, P->n_st_axes + P->dim);
+        r->P.n_st_axes = r->nst_ax.data();
     }
     r->f = *f;
     const int D = f->dim, K = f->n_terms;

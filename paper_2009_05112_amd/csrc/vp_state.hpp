@@ -47,6 +47,7 @@ struct vp_problem {
     vp_ctx* ctx;
     vp_params P;
     std::vector<double> lower, upper;
+    std::vector<int32_t> nst_ax;  // stratifications of every axis
     IntegrandDev fh;
     int32_t n_st;
     int64_t n_hc;

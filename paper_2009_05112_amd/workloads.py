@@ -83,6 +83,8 @@ class Params:
     n_discard: int = 0
     n_adapt: int = 0            # > 0: iterations from this index on neither reallocate nor refine
     average: str = "weighted"   # combination of the kept iterations: "weighted" or "unweighted"
+    strat: str = "uniform"      # stratifications per axis: "uniform" or "mixed" (N_st + 1 on the first axes)
+    n_st_axes: Optional[np.ndarray] = None  # explicit per-axis stratifications (override strat)
     lower: Optional[np.ndarray] = None
     upper: Optional[np.ndarray] = None
 

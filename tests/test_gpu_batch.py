@@ -84,6 +84,23 @@ def test_batched_stepwise_against_oracle(ctx, dim, n_ev, n_g):
         B.examples().vp_example_free_user(bf.user)
 
 
+def test_batched_mixed_stratification(ctx):
+    """Per-axis stratification (the mixed rule: 5, 5, 4, 4, 4, 4) in the
+    generate and accumulate modes, against the oracle."""
+    f = _mix(6, 2, 66)
+    p = W.Params(dim=6, n_ev=30_000, n_g=100, n_iter=3, seed=6, strat="mixed")
+    bf = B.example_gauss_mix(f)
+    try:
+        gp = B.Problem(ctx, p, bf)
+        op = oracle.Problem(p, f)
+        assert list(gp.n_st_axes) == list(op.n_st_axes) == [5, 5, 4, 4, 4, 4]
+        for _ in range(3):
+            step_and_compare(gp, op)
+        gp.close()
+    finally:
+        B.examples().vp_example_free_user(bf.user)
+
+
 def test_python_callback(ctx):
     """A batched integrand given as a Python function: it counts the calls and
     hands the device buffers to the example library's kernel."""

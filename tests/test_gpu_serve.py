@@ -40,6 +40,8 @@ def small_mix():
     reqs.append((p.with_(n_iter=3, seed=78, hist_mode="literal"), f))
     p, f = W.cfg_small_d4()
     reqs.append((p.with_(n_ev=20_000, n_iter=6, n_adapt=3, n_discard=3, average="unweighted", seed=79), f))
+    reqs.append((p.with_(n_ev=30_000, n_iter=4, strat="mixed", seed=80), f))
+    reqs.append((p.with_(n_ev=20_000, n_iter=3, n_st_axes=np.array([7, 1, 5, 2]), seed=81), f))
     return reqs
 
 
