@@ -241,6 +241,22 @@ vp_status vp_iteration_set(vp_problem* p, int32_t it);
  * increment).  Any pointer may be NULL. */
 vp_status vp_accum_get(vp_problem* p, double* S1, double* S2, double* H, double* W);
 
+/* Synchronising.  Preconditioned map (Sec. 5.2): trains the map on given
+ * samples {x, f(x)} (from MCMC, a peak finder, ...) before integrating.  Each
+ * of n_iter passes finds every point's increment on every axis by inverting
+ * the current map, takes its Jacobian J (the product over the axes of
+ * N_g Delta x_i), sets
+ *   d_i^mu = (1 / n_i^mu) sum over the points in increment i of (J f)^2
+ * (H and W of vp_accum_get then hold these sums and counts), and refines the
+ * map from them with damping alpha as after an iteration.  The same points
+ * serve every pass.  The allocation and the estimates are not touched; run
+ * the integration afterwards (alpha = 0 in the problem's parameters keeps the
+ * trained map).
+ *  x: host [n][dim], every point inside the integration box; f: host [n],
+ *  finite.  The arrays are copied; VP_ERR_INVALID_ARG on points outside the
+ *  box or non-finite values. */
+vp_status vp_map_train(vp_problem* p, int64_t n, const double* x, const double* f, int32_t n_iter, double alpha);
+
 /* Checkpoint: map, n_h, iteration index and estimate history, as an opaque
  * byte blob.  With buf == NULL, *size receives the required size. */
 vp_status vp_state_export(vp_problem* p, void* buf, size_t* size);

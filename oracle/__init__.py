@@ -56,6 +56,10 @@ def lib():
         L.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
         L.or_nst.argtypes = [C.c_int32, C.c_int64]
         L.or_nst.restype = C.c_int32
+        L.or_train_hist.argtypes = [C.POINTER(_Params), dp, dp, C.c_int64, dp, dp, dp]
+        L.or_train_hist.restype = C.c_int
+        L.or_map_train.argtypes = [C.POINTER(_Params), dp, dp, C.c_int64, dp, C.c_int32, C.c_double]
+        L.or_map_train.restype = C.c_int
         L.or_nst_mixed.argtypes = [C.c_int32, C.c_int64, C.POINTER(C.c_int32)]
         L.or_nst_mixed.restype = C.c_int32
         L.or_nst_classic.argtypes = [C.c_int32, C.c_int64]
@@ -216,6 +220,28 @@ class Problem:
         if rc != 0:
             raise RuntimeError("or_sample_indices failed")
         return (idx, t) if with_t else idx
+
+    def train_hist(self, x, fx, fmap):
+        """Training data of the preconditioned map (Sec. 5.2) for points x
+        [n][dim] with values fx under the map fmap: H, W [dim][n_g]."""
+        P = self.params
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        fx = np.ascontiguousarray(fx, dtype=np.float64)
+        m = np.ascontiguousarray(fmap, dtype=np.float64)
+        H = np.empty((P.dim, P.n_g))
+        W = np.empty((P.dim, P.n_g))
+        if lib().or_train_hist(C.byref(self.p), _dp(x), _dp(fx), len(fx), _dp(m), _dp(H), _dp(W)) != 0:
+            raise RuntimeError("or_train_hist failed")
+        return H, W
+
+    def map_train(self, x, fx, fmap, n_iter, alpha):
+        """n_iter training passes from fmap; returns the trained map."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        fx = np.ascontiguousarray(fx, dtype=np.float64)
+        m = np.array(fmap, dtype=np.float64, copy=True)
+        if lib().or_map_train(C.byref(self.p), _dp(x), _dp(fx), len(fx), _dp(m), n_iter, float(alpha)) != 0:
+            raise RuntimeError("or_map_train failed")
+        return m
 
     def reduce(self, n_h, S1, S2):
         I = C.c_double()

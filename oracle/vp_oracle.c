@@ -829,6 +829,75 @@ int or_refine(const or_params* p, const double* H, const double* W, double* map)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Preconditioned map, Sec. 5.2: training on given samples {x, f(x)} before   */
+/* integrating.  Each point's y = y(x) is found by inverting the map axis by  */
+/* axis: x lies in increment i of axis mu when x_i <= x^mu (the last such i,  */
+/* at most N_g - 1).  Its Jacobian J(y(x)) is the product over the axes of    */
+/* N_g Delta x_i (Eq. jac).  The training data are                            */
+/*   d_i^mu = (1 / n_i^mu) sum over the points in increment i of (J f)^2,     */
+/* i.e. H_i = sum (J f)^2 and W_i = n_i, and the map is refined from them as  */
+/* after an iteration (Sec. 2.3), with the training damping alpha.  The same  */
+/* points are used again in every training pass.                              */
+/* x: [n][dim] inside the map's box; fx: [n].                                 */
+/* ------------------------------------------------------------------------ */
+int32_t or_map_locate(const double* xm, int32_t NG, double x)
+{
+    for (int32_t i = NG - 1; i > 0; --i)
+        if (xm[i] <= x) return i;
+    return 0;
+}
+
+int or_train_hist(const or_params* p, const double* x, const double* fx, int64_t n, const double* map,
+                  double* H, double* W)
+{
+    const int32_t D = p->dim, NG = p->n_g;
+    or_ksum* kH = (or_ksum*)calloc((size_t)D * NG, sizeof(or_ksum));
+    if (!kH) return -1;
+    for (int64_t q = 0; q < (int64_t)D * NG; ++q) W[q] = 0.0;
+    for (int64_t s = 0; s < n; ++s) {
+        const double* xs = x + s * D;
+        double jac = 1.0;
+        for (int32_t mu = 0; mu < D; ++mu) {
+            const double* xm = map + (int64_t)mu * (NG + 1);
+            const int32_t i = or_map_locate(xm, NG, xs[mu]);
+            jac = jac * ((double)NG * (xm[i + 1] - xm[i]));
+        }
+        const double v = jac * fx[s];
+        const double v2 = v * v;
+        for (int32_t mu = 0; mu < D; ++mu) {
+            const double* xm = map + (int64_t)mu * (NG + 1);
+            const int32_t i = or_map_locate(xm, NG, xs[mu]);
+            or_kadd(&kH[(int64_t)mu * NG + i], v2);
+            W[(int64_t)mu * NG + i] += 1.0;
+        }
+    }
+    for (int64_t q = 0; q < (int64_t)D * NG; ++q) H[q] = or_kval(&kH[q]);
+    free(kH);
+    return 0;
+}
+
+int or_map_train(const or_params* p, const double* x, const double* fx, int64_t n, double* map,
+                 int32_t n_iter, double alpha)
+{
+    const int32_t D = p->dim, NG = p->n_g;
+    or_params q = *p;
+    q.alpha = alpha;
+    double* H = (double*)malloc(sizeof(double) * (size_t)D * NG);
+    double* W = (double*)malloc(sizeof(double) * (size_t)D * NG);
+    if (!H || !W) {
+        free(H); free(W);
+        return -1;
+    }
+    int rc = 0;
+    for (int32_t it = 0; it < n_iter && rc == 0; ++it) {
+        rc = or_train_hist(&q, x, fx, n, map, H, W);
+        if (rc == 0) rc = or_refine(&q, H, W, map);
+    }
+    free(H); free(W);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Combining iterations, Sec. 2.5: inverse-variance weighted mean, its        */
 /* standard error and chi^2 over iterations n_discard..n-1.  When any sigma_j */
 /* is zero the weights are undefined: the plain mean is returned with zero    */

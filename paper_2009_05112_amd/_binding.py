@@ -107,6 +107,7 @@ def lib():
             "vp_problem_destroy": ([vp], C.c_int),
             "vp_problem_info": ([vp, ip, C.POINTER(C.c_int64)], C.c_int),
             "vp_problem_strat": ([vp, ip], C.c_int),
+            "vp_map_train": ([vp, C.c_int64, dp, dp, C.c_int32, C.c_double], C.c_int),
             "vp_iterate": ([vp, C.c_int32], C.c_int),
             "vp_sync": ([vp], C.c_int),
             "vp_result_get": ([vp, C.POINTER(vp_result), dp, dp, C.c_int32], C.c_int),
@@ -255,6 +256,13 @@ class Problem:
         return {"mean": r.mean, "sdev": r.sdev, "chi2": r.chi2, "dof": r.dof, "n_iter_done": n,
                 "n_evals": r.n_evals, "ties": r.n_near_ties, "nonfinite": r.n_nonfinite,
                 "I": I[:n].copy(), "V": V[:n].copy(), "sig": np.sqrt(V[:n])}
+
+    def train_map(self, x, fx, n_iter: int, alpha: float):
+        """Preconditioned map: n_iter training passes on points x [n][dim]
+        with values fx (vp_map_train)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        fx = np.ascontiguousarray(fx, dtype=np.float64)
+        check(lib().vp_map_train(self.h, len(fx), _dp(x), _dp(fx), int(n_iter), float(alpha)), "vp_map_train")
 
     def map(self):
         P = self.params

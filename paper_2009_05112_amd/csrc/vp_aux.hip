@@ -780,6 +780,46 @@ __global__ __launch_bounds__(kRefineBlock) void k_refine(LaunchSet L)
     }
 }
 
+// ---------------------------------------------------------------- map training
+// Preconditioned map (Sec. 5.2): training data from given points {x, f(x)}.
+// A point's increment on axis mu is the last i <= N_g - 1 with x_i <= x^mu
+// (inverting the map), its Jacobian the product over the axes of
+// N_g Delta x_i; it adds (J f)^2 to H and 1 to W of its increment on every
+// axis, so that H_i / W_i is the mean of (J f)^2 over the points there.  One
+// thread per point; x is [dim][n].
+__device__ __forceinline__ int map_locate(const double* __restrict__ xm, int n_g, double x)
+{
+    int lo = 0, hi = n_g - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (xm[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_train_hist(TrainArgs a)
+{
+    const int n_g = a.n_g, D = a.dim;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.n; s += stride) {
+        double jac = 1.0;
+        for (int mu = 0; mu < D; ++mu) {
+            const double* xm = a.map + (int64_t)mu * (n_g + 1);
+            const int i = map_locate(xm, n_g, a.x[(int64_t)mu * a.n + s]);
+            jac = jac * ((double)n_g * (xm[i + 1] - xm[i]));
+        }
+        const double v = jac * a.f[s];
+        const double v2 = v * v;
+        for (int mu = 0; mu < D; ++mu) {
+            const double* xm = a.map + (int64_t)mu * (n_g + 1);
+            const int i = map_locate(xm, n_g, a.x[(int64_t)mu * a.n + s]);
+            atomicAdd(&a.H[(int64_t)mu * n_g + i], v2);
+            atomicAdd(&a.W[(int64_t)mu * n_g + i], 1.0);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- advance
 // End of an iteration: the next iteration's Philox counter and history slot.
 __global__ void k_advance(LaunchSet L)
@@ -850,6 +890,19 @@ void launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s)
     if (g > 4096) g = 4096;
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)g), dim3(256), 0, s, x, n, v);
+}
+
+void launch_train_hist(const TrainArgs& a, hipStream_t s)
+{
+    int64_t g = (a.n + 255) / 256;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_train_hist, dim3((unsigned)g), dim3(256), 0, s, a);
+}
+
+void launch_refine(const LaunchSet& L, int blocks, int max_ng, hipStream_t s)
+{
+    launch(k_refine, L, blocks, kRefineBlock, (size_t)(4 * max_ng + 3) * sizeof(double), s);
 }
 
 int est_grid(int64_t n_hc)

@@ -42,6 +42,21 @@ void launch_init(const InitArgs& a, hipStream_t s);
 // Copies the estimate scalars of n problems into host-visible memory.
 void launch_gather_states(DevState* const* states, int n, DevState* out, hipStream_t s);
 void launch_fill_f64(double* x, int64_t n, double v, hipStream_t s);
+
+// Training data of a preconditioned map from given points (x: [dim][n],
+// f: [n]) under the current map, added into H and W (zeroed by the caller).
+struct TrainArgs {
+    const double* x;
+    const double* f;
+    const double* map;
+    double* H;
+    double* W;
+    int64_t n;
+    int32_t dim, n_g;
+};
+void launch_train_hist(const TrainArgs& a, hipStream_t s);
+// The refinement of every axis (one workgroup per axis) of the requests of L.
+void launch_refine(const LaunchSet& L, int blocks, int max_ng, hipStream_t s);
 void launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s);
 int est_grid(int64_t n_hc);
 

@@ -1067,6 +1067,71 @@ vp_status vp_accum_get(vp_problem* p, double* S1, double* S2, double* H, double*
     return VP_OK;
 }
 
+vp_status vp_map_train(vp_problem* p, int64_t n, const double* x, const double* f, int32_t n_iter, double alpha)
+{
+    if (!p || n < 1 || !x || !f || n_iter < 0)
+        return fail(VP_ERR_INVALID_ARG, "problem, n >= 1 points, x, f and n_iter >= 0 are required");
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(VP_ERR_INVALID_ARG, "alpha must be >= 0");
+    const int D = p->P.dim, NG = p->P.n_g;
+    for (int64_t s = 0; s < n; ++s) {
+        if (!std::isfinite(f[s])) return fail(VP_ERR_INVALID_ARG, "f[%lld] is not finite", (long long)s);
+        for (int mu = 0; mu < D; ++mu) {
+            const double v = x[s * D + mu];
+            if (!(v >= p->lower[mu] && v <= p->upper[mu]))
+                return fail(VP_ERR_INVALID_ARG, "point %lld lies outside the box on axis %d", (long long)s, mu);
+        }
+    }
+    if (n_iter == 0) return VP_OK;
+    VP_HIP(hipSetDevice(p->ctx->device));
+    hipStream_t sm = p->ctx->stream;
+    // one device buffer: points as [dim][n], values, and a one-request launch
+    // set whose record carries the training damping (and no frozen phase)
+    const size_t xb = sizeof(double) * (size_t)n * D, fb = sizeof(double) * (size_t)n;
+    const size_t qo = (xb + fb + 255) / 256 * 256, to = qo + (sizeof(ReqArgs) + 255) / 256 * 256;
+    const size_t total = to + 64;
+    std::vector<char> h(total, 0);
+    double* hx = reinterpret_cast<double*>(h.data());
+    for (int64_t s = 0; s < n; ++s)
+        for (int mu = 0; mu < D; ++mu) hx[(size_t)mu * n + s] = x[s * D + mu];
+    memcpy(h.data() + xb, f, fb);
+    ReqArgs q = p->req;
+    q.alpha = alpha;
+    q.n_adapt = 0;
+    memcpy(h.data() + qo, &q, sizeof q);
+    char* d = nullptr;
+    VP_HIP(hipMalloc((void**)&d, total));
+    ReqArgs* dq = reinterpret_cast<ReqArgs*>(d + qo);
+    memcpy(h.data() + to, &dq, sizeof dq);
+    const int32_t bb[2] = {0, D};
+    memcpy(h.data() + to + 16, bb, sizeof bb);
+    hipError_t e = hipMemcpyAsync(d, h.data(), total, hipMemcpyHostToDevice, sm);
+    TrainArgs ta;
+    ta.x = reinterpret_cast<const double*>(d);
+    ta.f = reinterpret_cast<const double*>(d + xb);
+    ta.map = p->map;
+    ta.H = p->H;
+    ta.W = p->W;
+    ta.n = n;
+    ta.dim = D;
+    ta.n_g = NG;
+    LaunchSet L;
+    L.reqs = reinterpret_cast<ReqArgs* const*>(d + to);
+    L.bbase = reinterpret_cast<const int32_t*>(d + to + 16);
+    L.n = 1;
+    for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
+        launch_fill_f64(p->H, (int64_t)D * NG, 0.0, sm);
+        launch_fill_f64(p->W, (int64_t)D * NG, 0.0, sm);
+        launch_train_hist(ta, sm);
+        launch_refine(L, D, NG, sm);
+        e = hipGetLastError();
+    }
+    const hipError_t e2 = hipStreamSynchronize(sm);
+    (void)hipFree(d);
+    if (e != hipSuccess || e2 != hipSuccess)
+        return fail(VP_ERR_DEVICE, "map training: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    return VP_OK;
+}
+
 struct StateHeader {
     uint32_t magic, version;
     int32_t dim, n_g;

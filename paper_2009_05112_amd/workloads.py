@@ -199,6 +199,25 @@ def served_batch(n_req: int = 4096, seed: int = 0, d_range=(2, 16), nev_log=(4.0
     return out
 
 
+def precondition_points(n: int, centers, coef: float, width: float = 1.0, seed: int = 0) -> np.ndarray:
+    """Points drawn from Gaussians exp(-coef |x - c|^2) around the given
+    centres (one chosen uniformly per point), widened by `width`, kept inside
+    the unit box by redrawing: the kind of sample an MCMC run or a peak finder
+    supplies for training a map before integrating.  [n][dim]."""
+    rng = np.random.default_rng(seed)
+    centers = np.asarray(centers, dtype=np.float64)
+    sd = width / math.sqrt(2.0 * coef)
+    out = np.empty((n, centers.shape[1]))
+    have = 0
+    while have < n:
+        k = rng.integers(0, len(centers), size=n - have)
+        x = centers[k] + sd * rng.standard_normal((n - have, centers.shape[1]))
+        x = x[np.all((x >= 0.0) & (x <= 1.0), axis=1)]
+        out[have:have + len(x)] = x
+        have += len(x)
+    return out
+
+
 def haar_rotation(rng: np.random.Generator, dim: int) -> np.ndarray:
     """Haar-random orthogonal matrix: QR of a Gaussian matrix with the signs of
     R's diagonal folded into Q (Mezzadri 2007)."""
