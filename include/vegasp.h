@@ -89,6 +89,8 @@ enum {
  * library's, chosen so that its kernels read and write them coalesced).
  * It must enqueue on hip_stream (a hipStream_t) work that writes f(x_s) to
  * f_out[s], s < n (device memory), and may return before that work is done;
+ * a vector-valued integrand (n_out > 1 components) writes component a of
+ * sample s to f_out[a * n + s];
  * the library's next kernels on the stream read f_out.  Both buffers belong
  * to the library and are valid only during the call.  A non-zero return
  * fails the iteration with VP_ERR_DEVICE. */
@@ -106,7 +108,19 @@ typedef struct {
     double scale;
     vp_batch_fn fn;        /* VP_F_BATCH only, else NULL */
     void* user;            /* passed to fn unchanged */
+    int32_t n_out;         /* components: 0 or 1 scalar; 2..16 VP_F_BATCH only */
 } vp_integrand;
+
+/* Vector-valued integrands (Sec. 6: several integrals of one density, such
+ * as its normalisation, means and covariances, estimated from the same
+ * samples).  Component 0 drives the adaptation (sigma_h of the allocation,
+ * the map's training data) and is the scalar result of vp_result_get.  Every
+ * component a gets per hypercube the sums S1_a = sum J f_a and, for every
+ * pair, S2_ab = sum (J f_a)(J f_b); the iteration's estimates and their
+ * covariance are
+ *   I_a = sum_h Omega S1_a / n_h,
+ *   C_ab = sum_h (Omega^2 S2_ab / n_h - (Omega S1_a / n_h)(Omega S1_b / n_h)) / (n_h - 1)
+ * (diagonal terms at least 0), the multivariable form of Eq. sigest. */
 
 /* Arithmetic of the sampling path (the split is not in the paper):
  *  VP_FP64:          everything in double precision;
@@ -226,6 +240,19 @@ vp_status vp_sync(vp_problem* p);
  * I_j and variances V_j = sigma_j^2 (host arrays of at least cap entries;
  * the first min(cap, n_iter_done) are written). */
 vp_status vp_result_get(vp_problem* p, vp_result* out, double* I_j, double* V_j, int32_t cap);
+
+/* Synchronising.  Vector results (n_out components, 1 for a scalar problem)
+ * over iterations n_discard .. n_iter_done - 1:
+ *  VP_AVG_WEIGHTED:   mean = (sum_j C_j^-1)^-1 sum_j C_j^-1 I_j with
+ *                     covariance (sum_j C_j^-1)^-1; when some C_j is not
+ *                     positive definite, the unweighted result and chi^2 NaN;
+ *  VP_AVG_UNWEIGHTED: mean of the I_j, covariance (sum_j C_j) / count^2;
+ * chi^2 = sum_j (I_j - mean)^T C_j^-1 (I_j - mean), dof = (count - 1) n_out.
+ * mean: host [n_out]; cov: host [n_out][n_out]; I_j: host [cap][n_out] and
+ * C_j: host [cap][n_out][n_out], the first min(cap, n_iter_done) iterations.
+ * Any pointer may be NULL.  Vector histories hold 4096 iterations. */
+vp_status vp_result_vec_get(vp_problem* p, double* mean, double* cov, double* chi2, int32_t* dof, double* I_j,
+                            double* C_j, int32_t cap);
 
 /* Synchronising state access for inspection, checkpoints and parity tests.
  * map: host [dim][n_g + 1]; n_h: host [n_hc]. */

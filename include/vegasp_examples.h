@@ -30,6 +30,16 @@ int vp_example_gauss_mix_user(int32_t dim, int32_t n_terms, const double* center
 int vp_example_gauss_mix(void* user, void* hip_stream, int64_t n, int32_t dim, const double* x_soa,
                          double* f_out);
 
+/* Vector-valued (n_out components, 1 <= n_out <= 16): component a is
+ * g(x) m_a(x) with g the mixture above and the monomial
+ * m_a = (e1[a] < 0 ? 1 : x_e1[a]) * (e2[a] < 0 ? 1 : x_e2[a]), e.g. the
+ * normalisation, the means and the second moments of the density g. */
+int vp_example_gauss_moments_user(int32_t dim, int32_t n_terms, const double* centers, const double* coefs,
+                                  const double* amps, int32_t n_out, const int32_t* e1, const int32_t* e2,
+                                  void** user);
+int vp_example_gauss_moments(void* user, void* hip_stream, int64_t n, int32_t dim, const double* x_soa,
+                             double* f_out);
+
 /* Always fails (returns 7) and writes nothing: for testing error paths. */
 int vp_example_failing(void* user, void* hip_stream, int64_t n, int32_t dim, const double* x_soa, double* f_out);
 

@@ -56,6 +56,9 @@ def lib():
         L.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
         L.or_nst.argtypes = [C.c_int32, C.c_int64]
         L.or_nst.restype = C.c_int32
+        L.or_vec_iteration.argtypes = [C.POINTER(_Params), C.POINTER(_Integrand), dp, ip, C.c_int32, C.c_int32,
+                                       ip, ip, dp, dp, dp]
+        L.or_vec_iteration.restype = C.c_int
         L.or_train_hist.argtypes = [C.POINTER(_Params), dp, dp, C.c_int64, dp, dp, dp]
         L.or_train_hist.restype = C.c_int
         L.or_map_train.argtypes = [C.POINTER(_Params), dp, dp, C.c_int64, dp, C.c_int32, C.c_double]
@@ -221,6 +224,23 @@ class Problem:
             raise RuntimeError("or_sample_indices failed")
         return (idx, t) if with_t else idx
 
+    def vec_iteration(self, fmap, n_h, it, e1, e2):
+        """Vector estimates of one iteration (Sec. 6) for the components
+        f * (x_e1 or 1) * (x_e2 or 1): I [M], C [M][M] and the scale [M] of
+        the variance terms before cancellation."""
+        e1 = np.ascontiguousarray(e1, dtype=np.int32)
+        e2 = np.ascontiguousarray(e2, dtype=np.int32)
+        M = len(e1)
+        I = np.empty(M)
+        Cm = np.empty((M, M))
+        sc = np.empty(M)
+        rc = lib().or_vec_iteration(C.byref(self.p), C.byref(self.fi), _dp(np.ascontiguousarray(fmap)),
+                                    _ip(np.ascontiguousarray(n_h, dtype=np.int32)), it, M, _ip(e1), _ip(e2),
+                                    _dp(I), _dp(Cm), _dp(sc))
+        if rc != 0:
+            raise RuntimeError("or_vec_iteration failed")
+        return I, Cm, sc
+
     def train_hist(self, x, fx, fmap):
         """Training data of the preconditioned map (Sec. 5.2) for points x
         [n][dim] with values fx under the map fmap: H, W [dim][n_g]."""
@@ -309,6 +329,53 @@ def combine(I, sig, n_discard: int = 0, average: str = "weighted"):
     lib().or_combine(_dp(I), _dp(sig), I.size, n_discard, 1 if average == "unweighted" else 0, C.byref(mean), C.byref(sdev), C.byref(chi2),
                      C.byref(dof))
     return mean.value, sdev.value, chi2.value, int(dof.value)
+
+
+def _positive_definite(A):
+    """Cholesky pivots all above 1e-14 of their diagonal entries (the rule
+    that decides between the weighted and the unweighted combination)."""
+    m = A.shape[0]
+    L = np.zeros_like(A)
+    for i in range(m):
+        for j in range(i + 1):
+            s = A[i, j] - sum(L[i, k] * L[j, k] for k in range(j))
+            if i == j:
+                if not s > 1e-14 * A[i, i]:
+                    return False
+                L[i, i] = np.sqrt(s)
+            else:
+                L[i, j] = s / L[j, j]
+    return True
+
+
+def combine_vec(I, Cs, n_discard: int = 0, average: str = "weighted"):
+    """Combination of vector estimates over iterations n_discard.. (Sec. 2.5
+    for several correlated integrals, Sec. 6): with C_j^-1 weights, the mean
+    (sum C_j^-1)^-1 sum C_j^-1 I_j and its covariance (sum C_j^-1)^-1; else
+    (or when some C_j is not positive definite) the plain mean with covariance
+    sum C_j / count^2.  chi^2 = sum (I_j - mean)^T C_j^-1 (I_j - mean), NaN
+    when some C_j is not positive definite; dof = (count - 1) M."""
+    I = np.asarray(I, dtype=np.float64)
+    Cs = np.asarray(Cs, dtype=np.float64)
+    first = max(0, n_discard)
+    I, Cs = I[first:], Cs[first:]
+    cnt, M = I.shape
+    if cnt <= 0:
+        return np.full(M, np.nan), np.full((M, M), np.nan), float("nan"), 0
+    pd = all(_positive_definite(c) for c in Cs)
+    if average == "weighted" and pd:
+        Ws = [np.linalg.inv(c) for c in Cs]
+        SW = sum(Ws)
+        cov = np.linalg.inv(SW)
+        mean = cov @ sum(w @ i for w, i in zip(Ws, I))
+    else:
+        mean = I.mean(axis=0)
+        cov = Cs.sum(axis=0) / cnt ** 2
+    if pd:
+        chi2 = float(sum((i - mean) @ np.linalg.solve(c, i - mean) for i, c in zip(I, Cs)))
+    else:
+        chi2 = float("nan")
+    return mean, cov, chi2, (cnt - 1) * M
 
 
 def refine_axis(params, H, W, x):

@@ -404,6 +404,32 @@ typedef struct {
 /* Outputs S1[h - h_begin], S2[h - h_begin] are written for every h in the   */
 /* range; H and W (dim x n_g) are accumulated into (callers zero them).       */
 /* ------------------------------------------------------------------------ */
+/* One FP64 sample point from its Philox words w (Sec. 3 and Sec. 2.2): u from 53
+ * bits (the high word of axis mu is word mu, its low word word D + mu),
+ * t = (k_mu + u) R_mu, i = floor(t) (at most N_g - 1), delta = t - i (at most 1),
+ * x = x_i + Delta x_i delta, J = prod_mu N_g Delta x_i.  Returns J. */
+static double or_point64(int32_t D, int32_t NG, const double* R, const int32_t* k, const uint32_t* w,
+                         const double* map, double* xs, int32_t* idx)
+{
+    double jac = 1.0;
+    for (int32_t mu = 0; mu < D; ++mu) {
+        uint64_t a = (uint64_t)(w[mu] >> 5);
+        uint64_t bb = (uint64_t)(w[D + mu] >> 6);
+        double u = (double)((a << 26) | bb) * 0x1p-53;
+        double t = ((double)k[mu] + u) * R[mu];
+        int32_t i = (int32_t)floor(t);
+        if (i > NG - 1) i = NG - 1;
+        double delta = t - (double)i;
+        if (delta > 1.0) delta = 1.0;
+        const double* xm = map + (int64_t)mu * (NG + 1);
+        double dx = xm[i + 1] - xm[i];
+        xs[mu] = fma(dx, delta, xm[i]);
+        jac = jac * ((double)NG * dx);
+        idx[mu] = i;
+    }
+    return jac;
+}
+
 int or_sample_range(const or_params* p, const or_integrand* f, const double* map,
                     const int32_t* n_h, int32_t it, int64_t h_begin, int64_t h_end,
                     double* S1, double* S2, double* H, double* W,
@@ -479,22 +505,7 @@ int or_sample_range(const or_params* p, const or_integrand* f, const double* map
             }
             double v, jac_out, f_out;
             if (!fp32) {
-                double jac = 1.0;
-                for (int32_t mu = 0; mu < D; ++mu) {
-                    uint64_t a = (uint64_t)(w[mu] >> 5);
-                    uint64_t bb = (uint64_t)(w[D + mu] >> 6);
-                    double u = (double)((a << 26) | bb) * 0x1p-53;
-                    double t = ((double)k[mu] + u) * R[mu];
-                    int32_t i = (int32_t)floor(t);
-                    if (i > NG - 1) i = NG - 1;
-                    double delta = t - (double)i;
-                    if (delta > 1.0) delta = 1.0;
-                    const double* xm = map + (int64_t)mu * (NG + 1);
-                    double dx = xm[i + 1] - xm[i];
-                    xs[mu] = fma(dx, delta, xm[i]);
-                    jac = jac * ((double)NG * dx);
-                    idx[mu] = i;
-                }
+                double jac = or_point64(D, NG, R, k, w, map, xs, idx);
                 double fx = or_integrand_eval(f, xs);
                 v = jac * fx;
                 jac_out = jac;
@@ -825,6 +836,93 @@ int or_refine(const or_params* p, const double* H, const double* W, double* map)
         or_refine_axis(p, H + (int64_t)mu * NG, W + (int64_t)mu * NG, map + (int64_t)mu * (NG + 1),
                        work);
     free(work);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Vector-valued integrands, Sec. 6: several integrals from the same samples. */
+/* Component a of the integrand is g(x) m_a(x), g the (unscaled) integrand f  */
+/* and m_a = (e1[a] < 0 ? 1 : x_e1[a]) (e2[a] < 0 ? 1 : x_e2[a]); the value   */
+/* of a sample is v_a = J (scale (g m_a)).  Per hypercube the sums            */
+/* S1_a = sum v_a and S2_ab = sum v_a v_b give                                */
+/*   I_a  = sum_h Omega S1_a / n_h,                                           */
+/*   C_ab = sum_h (Omega^2 S2_ab / n_h - (Omega S1_a / n_h)(Omega S1_b / n_h)) */
+/*          / (n_h - 1),  diagonal terms at least 0                            */
+/* (the covariance form of Eq. sigest).  FP64 only.  I_out [M], C_out [M][M]; */
+/* scale_out [M] (or NULL): sum_h Omega^2 S2_aa / n_h / (n_h - 1), the size   */
+/* of the terms before their cancellation.                                    */
+/* ------------------------------------------------------------------------ */
+int or_vec_iteration(const or_params* p, const or_integrand* f, const double* map, const int32_t* n_h,
+                     int32_t it, int32_t M, const int32_t* e1, const int32_t* e2, double* I_out, double* C_out,
+                     double* scale_out)
+{
+    const int32_t D = p->dim, NG = p->n_g;
+    if (D < 1 || D > 64 || M < 1 || M > 16) return -1;
+    int32_t NST[64];
+    double R[64];
+    for (int32_t mu = 0; mu < D; ++mu) {
+        NST[mu] = or_nst_axis(p, mu);
+        R[mu] = (double)NG / (double)NST[mu];
+    }
+    or_integrand g = *f;
+    g.scale = 1.0;
+    const uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32)};
+    const int nblk = (2 * D + 3) / 4;
+    const int64_t nhc = or_n_hypercubes(p);
+    const double om = 1.0 / (double)nhc;
+    or_ksum kI[16], kC[16 * 16], kS[16];
+    memset(kI, 0, sizeof kI);
+    memset(kS, 0, sizeof kS);
+    memset(kC, 0, sizeof kC);
+    uint32_t w[4 * 33];
+    int32_t k[64], idx[64];
+    double xs[64], v[16];
+    for (int64_t h = 0; h < nhc; ++h) {
+        int64_t rem = h;
+        for (int32_t mu = D - 1; mu >= 0; --mu) {
+            k[mu] = (int32_t)(rem % NST[mu]);
+            rem /= NST[mu];
+        }
+        const int32_t n = n_h[h];
+        or_ksum s1[16], s2[16 * 16];
+        memset(s1, 0, sizeof s1);
+        memset(s2, 0, sizeof s2);
+        for (int32_t j = 0; j < n; ++j) {
+            for (int b = 0; b < nblk; ++b) {
+                uint32_t ctr[4] = {(uint32_t)j, (uint32_t)h, (uint32_t)it, (uint32_t)b};
+                or_philox4x32_10(ctr, key, &w[4 * b]);
+            }
+            const double jac = or_point64(D, NG, R, k, w, map, xs, idx);
+            const double gx = or_integrand_eval(&g, xs);
+            for (int32_t a = 0; a < M; ++a) {
+                double m = 1.0;
+                if (e1[a] >= 0) m = xs[e1[a]];
+                if (e2[a] >= 0) m = m * xs[e2[a]];
+                v[a] = jac * (f->scale * (gx * m));
+            }
+            for (int32_t a = 0; a < M; ++a) {
+                or_kadd(&s1[a], v[a]);
+                for (int32_t b = 0; b < M; ++b) or_kadd(&s2[a * M + b], v[a] * v[b]);
+            }
+        }
+        const double nd = (double)n;
+        for (int32_t a = 0; a < M; ++a) {
+            const double ma = om * or_kval(&s1[a]) / nd;
+            or_kadd(&kI[a], ma);
+            or_kadd(&kS[a], om * om * or_kval(&s2[a * M + a]) / nd / (nd - 1.0));
+            for (int32_t b = 0; b < M; ++b) {
+                const double mb = om * or_kval(&s1[b]) / nd;
+                double c = (om * om * or_kval(&s2[a * M + b]) / nd - ma * mb) / (nd - 1.0);
+                if (a == b && !(c > 0.0)) c = 0.0;
+                or_kadd(&kC[a * M + b], c);
+            }
+        }
+    }
+    for (int32_t a = 0; a < M; ++a) {
+        I_out[a] = or_kval(&kI[a]);
+        if (scale_out) scale_out[a] = or_kval(&kS[a]);
+        for (int32_t b = 0; b < M; ++b) C_out[a * M + b] = or_kval(&kC[a * M + b]);
+    }
     return 0;
 }
 

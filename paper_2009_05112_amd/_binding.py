@@ -41,7 +41,7 @@ class vp_integrand(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("n_terms", C.c_int32),
                 ("centers", C.POINTER(C.c_double)), ("coefs", C.POINTER(C.c_double)),
                 ("amps", C.POINTER(C.c_double)), ("chol", C.POINTER(C.c_double)),
-                ("scale", C.c_double), ("fn", C.c_void_p), ("user", C.c_void_p)]
+                ("scale", C.c_double), ("fn", C.c_void_p), ("user", C.c_void_p), ("n_out", C.c_int32)]
 
 
 class BatchIntegrand:
@@ -49,9 +49,10 @@ class BatchIntegrand:
     vp_batch_fn (or a BATCH_FN callback object, kept alive here), ``user``
     the pointer passed to it; the library multiplies its values by scale."""
 
-    def __init__(self, dim: int, fn, user=None, scale: float = 1.0):
+    def __init__(self, dim: int, fn, user=None, scale: float = 1.0, n_out: int = 1):
         self.dim = dim
         self.scale = scale
+        self.n_out = n_out
         self._fn_obj = fn if isinstance(fn, BATCH_FN) else None
         self.fn = C.cast(fn, C.c_void_p).value if isinstance(fn, BATCH_FN) else int(fn)
         self.user = user
@@ -108,6 +109,7 @@ def lib():
             "vp_problem_info": ([vp, ip, C.POINTER(C.c_int64)], C.c_int),
             "vp_problem_strat": ([vp, ip], C.c_int),
             "vp_map_train": ([vp, C.c_int64, dp, dp, C.c_int32, C.c_double], C.c_int),
+            "vp_result_vec_get": ([vp, dp, dp, dp, ip, dp, dp, C.c_int32], C.c_int),
             "vp_iterate": ([vp, C.c_int32], C.c_int),
             "vp_sync": ([vp], C.c_int),
             "vp_result_get": ([vp, C.POINTER(vp_result), dp, dp, C.c_int32], C.c_int),
@@ -202,10 +204,11 @@ def marshal(params, integrand):
 
     if isinstance(f, BatchIntegrand):
         keep.append(f)
-        fi = vp_integrand(VP_F_BATCH, f.dim, 0, None, None, None, None, float(f.scale), f.fn, f.user)
+        fi = vp_integrand(VP_F_BATCH, f.dim, 0, None, None, None, None, float(f.scale), f.fn, f.user,
+                          int(getattr(f, "n_out", 1)))
     else:
         fi = vp_integrand(_KIND[f.kind], f.dim, f.n_terms, arr(f.centers), arr(f.coefs), arr(f.amps),
-                          arr(f.chol), float(f.scale), None, None)
+                          arr(f.chol), float(f.scale), None, None, 1)
     p = params
     axes = getattr(p, "n_st_axes", None)
     if axes is not None:
@@ -256,6 +259,26 @@ class Problem:
         return {"mean": r.mean, "sdev": r.sdev, "chi2": r.chi2, "dof": r.dof, "n_iter_done": n,
                 "n_evals": r.n_evals, "ties": r.n_near_ties, "nonfinite": r.n_nonfinite,
                 "I": I[:n].copy(), "V": V[:n].copy(), "sig": np.sqrt(V[:n])}
+
+    def result_vec(self, m: int, cap: int = 4096):
+        """Vector results (vp_result_vec_get) of an integrand with m components."""
+        mean = np.empty(m)
+        cov = np.empty((m, m))
+        chi2 = C.c_double()
+        dof = C.c_int32()
+        I = np.empty((cap, m))
+        Cj = np.empty((cap, m, m))
+        check(lib().vp_result_vec_get(self.h, _dp(mean), _dp(cov), C.byref(chi2), C.byref(dof), _dp(I), _dp(Cj),
+                                      cap), "vp_result_vec_get")
+        n = min(cap, self.it_done())
+        return {"mean": mean, "cov": cov, "chi2": chi2.value, "dof": dof.value, "I": I[:n].copy(), "C": Cj[:n].copy()}
+
+    def it_done(self):
+        r = vp_result()
+        st = lib().vp_result_get(self.h, C.byref(r), None, None, 0)
+        if st not in (0, VP_ERR_NUMERIC):
+            check(st, "vp_result_get")
+        return r.n_iter_done
 
     def train_map(self, x, fx, n_iter: int, alpha: float):
         """Preconditioned map: n_iter training passes on points x [n][dim]
@@ -435,6 +458,10 @@ def examples():
         dp = C.POINTER(C.c_double)
         L.vp_example_gauss_mix_user.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, C.POINTER(C.c_void_p)]
         L.vp_example_gauss_mix_user.restype = C.c_int
+        ip = C.POINTER(C.c_int32)
+        L.vp_example_gauss_moments_user.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, C.c_int32, ip, ip,
+                                                    C.POINTER(C.c_void_p)]
+        L.vp_example_gauss_moments_user.restype = C.c_int
         L.vp_example_free_user.argtypes = [C.c_void_p]
         L.vp_example_free_user.restype = C.c_int
         _examples = L
@@ -455,6 +482,25 @@ def example_gauss_mix(integrand):
         raise VegaspError(VP_ERR_INVALID_ARG, f"vp_example_gauss_mix_user returned {rc}")
     fn = C.cast(L.vp_example_gauss_mix, C.c_void_p).value
     return BatchIntegrand(f.dim, fn, user.value, scale=f.scale)
+
+
+def example_gauss_moments(integrand, e1, e2):
+    """A vector-valued BatchIntegrand: component a is the workloads gauss_mix
+    density times the monomial (x_e1[a] or 1)(x_e2[a] or 1)."""
+    L = examples()
+    f = integrand
+    c = np.ascontiguousarray(f.centers, dtype=np.float64).ravel()
+    k = np.ascontiguousarray(f.coefs, dtype=np.float64)
+    a = np.ascontiguousarray(f.amps, dtype=np.float64)
+    i1 = np.ascontiguousarray(e1, dtype=np.int32)
+    i2 = np.ascontiguousarray(e2, dtype=np.int32)
+    user = C.c_void_p()
+    rc = L.vp_example_gauss_moments_user(f.dim, f.n_terms, _dp(c), _dp(k), _dp(a), len(i1), _ip(i1), _ip(i2),
+                                         C.byref(user))
+    if rc != 0:
+        raise VegaspError(VP_ERR_INVALID_ARG, f"vp_example_gauss_moments_user returned {rc}")
+    fn = C.cast(L.vp_example_gauss_moments, C.c_void_p).value
+    return BatchIntegrand(f.dim, fn, user.value, scale=f.scale, n_out=len(i1))
 
 
 def declared_symbols(header: str = HEADER) -> list:

@@ -820,6 +820,212 @@ __global__ __launch_bounds__(256) void k_train_hist(TrainArgs a)
     }
 }
 
+// ---------------------------------------------------------------- vector integrands
+// Component pair (a, b), a <= b, of pair index p: (0,0), (0,1), .., (0,M-1),
+// (1,1), ..
+__device__ __forceinline__ void vec_pair(int p, int m, int& a, int& b)
+{
+    a = 0;
+    while (p >= m - a) {
+        p -= m - a;
+        ++a;
+    }
+    b = a + p;
+}
+
+// One thread per hypercube and one grid row per pair of components: the
+// hypercube's sums S1_a, S1_b, S2_ab over its samples, its covariance term
+// (Omega^2 S2_ab / n - (Omega S1_a / n)(Omega S1_b / n)) / (n - 1), at least 0
+// on the diagonal (the multivariable form of Eq. sigest), and on the diagonal
+// its estimate term Omega S1_a / n; block sums in a fixed tree order.
+__global__ __launch_bounds__(kVecBlock) void k_vec_partial(VecArgs a)
+{
+    const int p = blockIdx.y;
+    int ia, ib;
+    vec_pair(p, a.n_out, ia, ib);
+    const int64_t n_tot = gofs(a.offs, a.obase, a.n_hc);
+    // the user's function wrote component c of sample s at c * n_tot + s
+    const double* __restrict__ fa = a.f + (int64_t)ia * n_tot;
+    const double* __restrict__ fb = a.f + (int64_t)ib * n_tot;
+    double c = 0.0, t = 0.0;
+    for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < a.n_hc;
+         h += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o0 = gofs(a.offs, a.obase, h), o1 = gofs(a.offs, a.obase, h + 1);
+        double s1a = 0.0, s1b = 0.0, s2 = 0.0;
+        for (int64_t s = o0; s < o1; ++s) {
+            const int64_t pos = batch_pos(s, n_tot);
+            const double J = a.jac[pos];
+            const double va = J * (a.scale * fa[pos]);
+            const double vb = J * (a.scale * fb[pos]);
+            s1a = s1a + va;
+            s1b = s1b + vb;
+            s2 = s2 + va * vb;
+        }
+        const double n = (double)(o1 - o0);
+        const double ma = a.omega * s1a / n, mb = a.omega * s1b / n;
+        double cab = (a.omega2 * s2 / n - ma * mb) / (n - 1.0);
+        if (ia == ib && !(cab > 0.0)) cab = 0.0;
+        c = c + cab;
+        t = t + ma;
+    }
+    __shared__ double red[2][kVecBlock];
+    red[0][threadIdx.x] = c;
+    red[1][threadIdx.x] = t;
+    __syncthreads();
+    for (int d = kVecBlock / 2; d >= 1; d >>= 1) {
+        if ((int)threadIdx.x < d) {
+            red[0][threadIdx.x] = red[0][threadIdx.x] + red[0][threadIdx.x + d];
+            red[1][threadIdx.x] = red[1][threadIdx.x] + red[1][threadIdx.x + d];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.part[(int64_t)p * a.grid + blockIdx.x] = red[0][0];
+        if (ia == ib) a.part[(int64_t)(vec_pairs(a.n_out) + ia) * a.grid + blockIdx.x] = red[1][0];
+    }
+}
+
+// Cholesky factor of the m x m matrix A (row-major) into L; false when a
+// pivot is not above 1e-14 of its diagonal entry (not positive definite to
+// working precision).
+__device__ bool vec_chol(const double* A, double* L, int m)
+{
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = A[i * m + j];
+            for (int k = 0; k < j; ++k) s = s - L[i * m + k] * L[j * m + k];
+            if (i == j) {
+                if (!(s > 1e-14 * A[i * m + i])) return false;
+                L[i * m + i] = sqrt(s);
+            } else {
+                L[i * m + j] = s / L[j * m + j];
+            }
+        }
+    return true;
+}
+
+// A^-1 from its Cholesky factor L (columns by forward and back substitution).
+__device__ void vec_inv(const double* L, double* X, double* y, int m)
+{
+    for (int c = 0; c < m; ++c) {
+        for (int i = 0; i < m; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) s = s - L[i * m + k] * y[k];
+            y[i] = s / L[i * m + i];
+        }
+        for (int i = m - 1; i >= 0; --i) {
+            double s = y[i];
+            for (int k = i + 1; k < m; ++k) s = s - L[k * m + i] * X[k * m + c];
+            X[i * m + c] = s / L[i * m + i];
+        }
+    }
+}
+
+// d^T W d for the m x m matrix W.
+__device__ double vec_quad(const double* W, const double* d, int m)
+{
+    double q = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double r = 0.0;
+        for (int j = 0; j < m; ++j) r = r + W[i * m + j] * d[j];
+        q = q + d[i] * r;
+    }
+    return q;
+}
+
+// Totals of the partials (one block, fixed order), the iteration's record,
+// and the combination over iterations n_discard..slot: inverse-covariance
+// weighted (Sec. 2.5 for several correlated estimates) or unweighted.
+__global__ __launch_bounds__(kVecBlock) void k_vec_final(VecArgs a)
+{
+    const int m = a.n_out, np = vec_pairs(m), nt = np + m;
+    __shared__ double tot[kMaxOut * (kMaxOut + 1) / 2 + kMaxOut];
+    for (int e = threadIdx.x; e < nt; e += blockDim.x) {
+        double s = 0.0;
+        for (int b = 0; b < a.grid; ++b) s = s + a.part[(int64_t)e * a.grid + b];
+        tot[e] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double* hI = a.hist_I + (int64_t)a.slot * m;
+    double* hC = a.hist_C + (int64_t)a.slot * m * m;
+    for (int p = 0; p < np; ++p) {
+        int i, j;
+        vec_pair(p, m, i, j);
+        hC[i * m + j] = tot[p];
+        hC[j * m + i] = tot[p];
+    }
+    for (int i = 0; i < m; ++i) hI[i] = tot[np + i];
+
+    __shared__ double L[kMaxOut * kMaxOut], W[kMaxOut * kMaxOut], SW[kMaxOut * kMaxOut];
+    __shared__ double SWI[kMaxOut], y[kMaxOut], d[kMaxOut];
+    double* mean = a.out;
+    double* cov = a.out + m;
+    double* chi2 = a.out + m + m * m;
+    double* dof = chi2 + 1;
+    const int first = a.n_discard < 0 ? 0 : a.n_discard;
+    const int cnt = a.slot + 1 - first;
+    if (cnt <= 0) {
+        for (int i = 0; i < m + m * m + 1; ++i) a.out[i] = __builtin_nan("");
+        *dof = 0.0;
+        return;
+    }
+    *dof = (double)((cnt - 1) * m);
+    bool pd = true;
+    for (int j = first; j <= a.slot && pd; ++j) pd = vec_chol(a.hist_C + (int64_t)j * m * m, L, m);
+    if (a.average == 0 && pd) {
+        for (int i = 0; i < m * m; ++i) SW[i] = 0.0;
+        for (int i = 0; i < m; ++i) SWI[i] = 0.0;
+        for (int j = first; j <= a.slot; ++j) {
+            (void)vec_chol(a.hist_C + (int64_t)j * m * m, L, m);
+            vec_inv(L, W, y, m);
+            const double* Ij = a.hist_I + (int64_t)j * m;
+            for (int r = 0; r < m; ++r) {
+                double s = 0.0;
+                for (int c = 0; c < m; ++c) {
+                    SW[r * m + c] = SW[r * m + c] + W[r * m + c];
+                    s = s + W[r * m + c] * Ij[c];
+                }
+                SWI[r] = SWI[r] + s;
+            }
+        }
+        if (vec_chol(SW, L, m)) {
+            vec_inv(L, cov, y, m);
+            for (int r = 0; r < m; ++r) {
+                double s = 0.0;
+                for (int c = 0; c < m; ++c) s = s + cov[r * m + c] * SWI[c];
+                mean[r] = s;
+            }
+        } else {
+            pd = false;
+        }
+    }
+    if (a.average != 0 || !pd) {
+        for (int r = 0; r < m; ++r) {
+            double s = 0.0;
+            for (int j = first; j <= a.slot; ++j) s = s + a.hist_I[(int64_t)j * m + r];
+            mean[r] = s / (double)cnt;
+        }
+        for (int e = 0; e < m * m; ++e) {
+            double s = 0.0;
+            for (int j = first; j <= a.slot; ++j) s = s + a.hist_C[(int64_t)j * m * m + e];
+            cov[e] = s / ((double)cnt * (double)cnt);
+        }
+    }
+    if (!pd) {
+        *chi2 = __builtin_nan("");
+        return;
+    }
+    double c2 = 0.0;
+    for (int j = first; j <= a.slot; ++j) {
+        (void)vec_chol(a.hist_C + (int64_t)j * m * m, L, m);
+        vec_inv(L, W, y, m);
+        for (int r = 0; r < m; ++r) d[r] = a.hist_I[(int64_t)j * m + r] - mean[r];
+        c2 = c2 + vec_quad(W, d, m);
+    }
+    *chi2 = c2;
+}
+
 // ---------------------------------------------------------------- advance
 // End of an iteration: the next iteration's Philox counter and history slot.
 __global__ void k_advance(LaunchSet L)
@@ -903,6 +1109,20 @@ void launch_train_hist(const TrainArgs& a, hipStream_t s)
 void launch_refine(const LaunchSet& L, int blocks, int max_ng, hipStream_t s)
 {
     launch(k_refine, L, blocks, kRefineBlock, (size_t)(4 * max_ng + 3) * sizeof(double), s);
+}
+
+int vec_grid(int64_t n_hc)
+{
+    int64_t g = (n_hc + kVecBlock - 1) / kVecBlock;
+    if (g > kVecMaxGrid) g = kVecMaxGrid;
+    return (int)(g < 1 ? 1 : g);
+}
+
+void launch_vec(const VecArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_vec_partial, dim3((unsigned)a.grid, (unsigned)vec_pairs(a.n_out)), dim3(kVecBlock), 0, s,
+                       a);
+    hipLaunchKernelGGL(k_vec_final, dim3(1), dim3(kVecBlock), 0, s, a);
 }
 
 int est_grid(int64_t n_hc)

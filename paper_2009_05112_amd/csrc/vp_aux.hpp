@@ -55,6 +55,30 @@ struct TrainArgs {
     int32_t dim, n_g;
 };
 void launch_train_hist(const TrainArgs& a, hipStream_t s);
+// Vector-valued batched integrands: per-iteration estimates I_a and
+// covariance C_ab of every component from the point buffers, and their
+// combination over iterations.
+constexpr int kMaxOut = 16;
+constexpr int kVecBlock = 256;
+constexpr int kVecMaxGrid = 1024;
+constexpr int kVecHistory = 4096;
+struct VecArgs {
+    const double* jac;     // [cap] J of every sample (batch positions)
+    const double* f;       // [n_out][n_tot] the user's values
+    const int64_t* offs;   // hypercube offsets (see gofs)
+    const int64_t* obase;
+    double* part;          // [n_pairs + n_out][grid] partial sums
+    double* hist_I;        // [kVecHistory][n_out]
+    double* hist_C;        // [kVecHistory][n_out][n_out]
+    double* out;           // mean [n_out], cov [n_out][n_out], chi2, dof
+    int64_t n_hc, cap;
+    double scale, omega, omega2;
+    int32_t n_out, grid, slot, n_discard, average;
+};
+__host__ __device__ inline int vec_pairs(int n_out) { return n_out * (n_out + 1) / 2; }
+int vec_grid(int64_t n_hc);
+void launch_vec(const VecArgs& a, hipStream_t s);
+
 // The refinement of every axis (one workgroup per axis) of the requests of L.
 void launch_refine(const LaunchSet& L, int blocks, int max_ng, hipStream_t s);
 void launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s);

@@ -38,6 +38,41 @@ __global__ void k_gauss_mix(const GaussMix* __restrict__ g, int64_t n, const dou
     f[s] = acc;
 }
 
+constexpr int kOut = 16;
+
+struct GaussMoments {
+    GaussMix g;
+    int32_t n_out;
+    int32_t e1[kOut], e2[kOut];  // component a: g(x) * x_e1 * x_e2 (-1: factor 1)
+};
+
+// One thread per point: the mixture g as in k_gauss_mix, then every
+// component g * m_a with the monomial m_a = (x_e1 or 1) * (x_e2 or 1).
+__global__ void k_gauss_moments(const GaussMoments* __restrict__ gm, int64_t n, const double* __restrict__ x,
+                                double* __restrict__ f)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const GaussMix* g = &gm->g;
+    const int D = g->dim, K = g->n_terms;
+    double q[kTerms] = {0.0, 0.0, 0.0, 0.0};
+    for (int d = 0; d < D; ++d) {
+        const double xd = x[(int64_t)d * n + s];
+        for (int k = 0; k < K; ++k) {
+            const double t = xd - g->centers[k * D + d];
+            q[k] = fma(t, t, q[k]);
+        }
+    }
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k) acc = fma(g->amps[k], exp(-(g->coefs[k] * q[k])), acc);
+    for (int a = 0; a < gm->n_out; ++a) {
+        double m = 1.0;
+        if (gm->e1[a] >= 0) m = x[(int64_t)gm->e1[a] * n + s];
+        if (gm->e2[a] >= 0) m = m * x[(int64_t)gm->e2[a] * n + s];
+        f[(int64_t)a * n + s] = acc * m;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -74,6 +109,49 @@ int vp_example_gauss_mix(void* user, void* hip_stream, int64_t n, int32_t dim, c
     const int64_t grid = (n + block - 1) / block;
     hipLaunchKernelGGL(k_gauss_mix, dim3((unsigned)grid), dim3(block), 0, (hipStream_t)hip_stream,
                        (const GaussMix*)user, n, x_soa, f_out);
+    return hipGetLastError() == hipSuccess ? 0 : 4;
+}
+
+int vp_example_gauss_moments_user(int32_t dim, int32_t n_terms, const double* centers, const double* coefs,
+                                  const double* amps, int32_t n_out, const int32_t* e1, const int32_t* e2, void** user)
+{
+    if (!user || dim < 1 || dim > kDim || n_terms < 1 || n_terms > kTerms || !centers || !coefs || !amps ||
+        n_out < 1 || n_out > kOut || !e1 || !e2)
+        return 1;
+    GaussMoments h;
+    memset(&h, 0, sizeof h);
+    h.g.dim = dim;
+    h.g.n_terms = n_terms;
+    for (int i = 0; i < dim * n_terms; ++i) h.g.centers[i] = centers[i];
+    for (int k = 0; k < n_terms; ++k) {
+        h.g.coefs[k] = coefs[k];
+        h.g.amps[k] = amps[k];
+    }
+    h.n_out = n_out;
+    for (int a = 0; a < n_out; ++a) {
+        if (e1[a] < -1 || e1[a] >= dim || e2[a] < -1 || e2[a] >= dim) return 1;
+        h.e1[a] = e1[a];
+        h.e2[a] = e2[a];
+    }
+    GaussMoments* d = nullptr;
+    if (hipMalloc((void**)&d, sizeof h) != hipSuccess) return 2;
+    if (hipMemcpy(d, &h, sizeof h, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return 3;
+    }
+    *user = d;
+    return 0;
+}
+
+int vp_example_gauss_moments(void* user, void* hip_stream, int64_t n, int32_t dim, const double* x_soa, double* f_out)
+{
+    (void)dim;
+    if (!user || n < 0) return 1;
+    if (n == 0) return 0;
+    const int block = 256;
+    const int64_t grid = (n + block - 1) / block;
+    hipLaunchKernelGGL(k_gauss_moments, dim3((unsigned)grid), dim3(block), 0, (hipStream_t)hip_stream,
+                       (const GaussMoments*)user, n, x_soa, f_out);
     return hipGetLastError() == hipSuccess ? 0 : 4;
 }
 

@@ -68,6 +68,22 @@ __device__ __forceinline__ int64_t gofs(const int64_t* __restrict__ loc, const i
     return loc[h] + base[h / kOffsTile];
 }
 
+// Position of sample pos in the point buffers of a batched integrand.  The
+// samples are taken in aligned groups of 64 x 16; within a whole group the
+// sample at offset r goes to (r mod 16) * 64 + r / 16, so that when the lanes
+// of a wave each walk 16 consecutive samples, they touch consecutive
+// addresses.  Defined on absolute positions, so every kernel and launch shape
+// agrees; the last, partial group keeps its order.
+constexpr int kBatchGroup = kWave * 16;
+__device__ __forceinline__ int64_t batch_pos(int64_t pos, int64_t n_tot)
+{
+    const int64_t base = pos & ~(int64_t)(kBatchGroup - 1);
+    if (base + kBatchGroup > n_tot) return pos;
+    const int r = (int)(pos - base);
+    return base + (int64_t)(r & 15) * kWave + (r >> 4);
+}
+
+
 struct SampleArgs {
     const double* map;      // [dim][n_g + 1]
     const float* map32;     // FP32 copy (split paths)

@@ -201,11 +201,15 @@ vp_status vp::validate(const vp_params* P, const vp_integrand* f)
         break;
     case VP_F_BATCH:
         if (!f->fn) return fail(VP_ERR_INVALID_ARG, "a batched integrand needs fn");
+        if (f->n_out < 0 || f->n_out > kMaxOut)
+            return fail(VP_ERR_INVALID_ARG, "n_out %d outside 0..%d", f->n_out, kMaxOut);
         if (P->precision != VP_FP64) return fail(VP_ERR_INVALID_ARG, "batched integrands are double precision only");
         break;
     default:
         return fail(VP_ERR_INVALID_ARG, "unknown integrand kind %d", f->kind);
     }
+    if (f->kind != VP_F_BATCH && f->n_out > 1)
+        return fail(VP_ERR_INVALID_ARG, "vector-valued integrands (n_out > 1) are batched integrands");
     return VP_OK;
 }
 
@@ -473,6 +477,8 @@ struct Shape {
     size_t gen_lds;
     int gen_grid;  // its own grid: it holds no training data, so many workgroups fit per CU
     int64_t bcap;
+    int n_out;     // components of the integrand (1: scalar)
+    int vec_grid;  // vector estimates: workgroups per pair of components
 };
 
 // The integrand constants in the sampling kernel's layout (fc_count elements:
@@ -581,6 +587,8 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     if (occ < 1) occ = 1;
     const int64_t n_tot_max = P->n_ev + 2 * nhc;
     sh->bcap = 0;
+    sh->n_out = f->n_out > 1 ? f->n_out : 1;
+    sh->vec_grid = sh->n_out > 1 ? vec_grid(nhc) : 0;
     sh->gen_lds = 0;
     sh->gen_grid = 0;
     sh->gen_entry = SampleEntry{nullptr, nullptr, 0};
@@ -627,7 +635,8 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
 struct Layout {
     size_t f_d, st, d_req, bounds, fc, head_end, map, map32;
     size_t n_h, offs, bsum, S1, S2, dh, H, W, hist, edges, est_part, hist_I, hist_V, rec_h, rec_n, rec_bin;
-    size_t bx, bj, bf, bidx, total;
+    size_t bx, bj, bf, bidx;
+    size_t vI, vC, vpart, vout, total;
 };
 
 static Layout layout_of(const vp_params* P, const Shape& sh)
@@ -669,8 +678,15 @@ static Layout layout_of(const vp_params* P, const Shape& sh)
     // batched integrand: points, J, f and increment indices
     L.bx = take((size_t)sh.bcap * D * sizeof(double));
     L.bj = take((size_t)sh.bcap * sizeof(double));
-    L.bf = take((size_t)sh.bcap * sizeof(double));
+    L.bf = take((size_t)sh.bcap * sh.n_out * sizeof(double));
     L.bidx = take((size_t)sh.bcap * D * sizeof(uint16_t));
+    // vector-valued integrand: per-iteration estimates and covariances,
+    // partial sums, combined result
+    const size_t M = sh.n_out > 1 ? (size_t)sh.n_out : 0;
+    L.vI = take((size_t)kVecHistory * M * sizeof(double));
+    L.vC = take((size_t)kVecHistory * M * M * sizeof(double));
+    L.vpart = take((size_t)(M * (M + 1) / 2 + M) * sh.vec_grid * sizeof(double));
+    L.vout = take((M ? M + M * M + 2 : 0) * sizeof(double));
     L.total = at;
     return L;
 }
@@ -784,6 +800,12 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
     p->gen_entry = sh.gen_entry;
     p->gen_lds = sh.gen_lds;
     p->gen_grid = sh.gen_grid;
+    p->n_out = sh.n_out;
+    p->vec_grid = sh.vec_grid;
+    p->vI = sh.n_out > 1 ? (double*)(base + lay.vI) : nullptr;
+    p->vC = sh.n_out > 1 ? (double*)(base + lay.vC) : nullptr;
+    p->vpart = sh.n_out > 1 ? (double*)(base + lay.vpart) : nullptr;
+    p->vout = sh.n_out > 1 ? (double*)(base + lay.vout) : nullptr;
     p->batch_fn = f->kind == VP_F_BATCH ? f->fn : nullptr;
     p->batch_user = f->kind == VP_F_BATCH ? f->user : nullptr;
     p->edges = (EdgeRec*)(base + lay.edges);
@@ -888,6 +910,28 @@ static vp_status iterate_batch(vp_problem* p, int32_t n_iter)
         if (rc != 0) return fail(VP_ERR_DEVICE, "the batched integrand returned %d", rc);
         g.entry.launch(g.L, g.blocks, g.entry.block, g.lds, s);
         if (e1) VP_HIP(hipEventRecord(e1, s));
+        if (p->n_out > 1) {
+            VecArgs va;
+            va.jac = p->bj;
+            va.f = p->bf;
+            va.offs = p->offs;
+            va.obase = p->bsum;
+            va.part = p->vpart;
+            va.hist_I = p->vI;
+            va.hist_C = p->vC;
+            va.out = p->vout;
+            va.n_hc = p->n_hc;
+            va.cap = p->bcap;
+            va.scale = p->fh.scale;
+            va.omega = p->omega;
+            va.omega2 = p->omega2;
+            va.n_out = p->n_out;
+            va.grid = p->vec_grid;
+            va.slot = p->slot;
+            va.n_discard = p->P.n_discard;
+            va.average = p->P.average;
+            launch_vec(va, s);
+        }
         enqueue_tail(p->plan, s);
         if (e3) {
             VP_HIP(hipEventRecord(e3, s));
@@ -938,6 +982,8 @@ vp_status vp_iterate(vp_problem* p, int32_t n_iter)
 {
     if (!p || n_iter < 0) return fail(VP_ERR_INVALID_ARG, "problem is NULL or n_iter < 0");
     if (p->slot + n_iter > p->hist_cap) return fail(VP_ERR_STATE, "more than %d iterations", p->hist_cap);
+    if (p->n_out > 1 && p->slot + n_iter > kVecHistory)
+        return fail(VP_ERR_STATE, "more than %d iterations of a vector-valued integrand", kVecHistory);
     VP_HIP(hipSetDevice(p->ctx->device));
     hipStream_t s = p->ctx->stream;
     if (!p->plan_built) {
@@ -1064,6 +1110,42 @@ vp_status vp_accum_get(vp_problem* p, double* S1, double* S2, double* H, double*
     if (S2) VP_HIP(hipMemcpy(S2, p->S2, sizeof(double) * p->n_hc, hipMemcpyDeviceToHost));
     if (H) VP_HIP(hipMemcpy(H, p->H, sizeof(double) * nb, hipMemcpyDeviceToHost));
     if (W) VP_HIP(hipMemcpy(W, p->W, sizeof(double) * nb, hipMemcpyDeviceToHost));
+    return VP_OK;
+}
+
+vp_status vp_result_vec_get(vp_problem* p, double* mean, double* cov, double* chi2, int32_t* dof, double* I_j,
+                            double* C_j, int32_t cap)
+{
+    if (!p || cap < 0) return fail(VP_ERR_INVALID_ARG, "problem is NULL or cap < 0");
+    const int m = p->n_out;
+    if (m <= 1) {
+        // a scalar problem: its result as a vector of one component
+        vp_result r;
+        vp_status st = vp_result_get(p, &r, I_j, C_j, cap);
+        if (st != VP_OK && st != VP_ERR_NUMERIC) return st;
+        if (mean) mean[0] = r.mean;
+        if (cov) cov[0] = r.sdev * r.sdev;
+        if (chi2) *chi2 = r.chi2;
+        if (dof) *dof = r.dof;
+        return st;
+    }
+    VP_HIP(hipSetDevice(p->ctx->device));
+    VP_HIP(hipStreamSynchronize(p->ctx->stream));
+    std::vector<double> out((size_t)m + m * m + 2);
+    const int done = p->slot;
+    if (done > 0) {
+        VP_HIP(hipMemcpy(out.data(), p->vout, out.size() * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+        for (auto& v : out) v = std::nan("");
+        out[(size_t)m + m * m + 1] = 0.0;
+    }
+    if (mean) memcpy(mean, out.data(), sizeof(double) * m);
+    if (cov) memcpy(cov, out.data() + m, sizeof(double) * m * m);
+    if (chi2) *chi2 = out[(size_t)m + m * m];
+    if (dof) *dof = (int32_t)out[(size_t)m + m * m + 1];
+    const int n = std::min(cap, done);
+    if (I_j && n > 0) VP_HIP(hipMemcpy(I_j, p->vI, sizeof(double) * n * m, hipMemcpyDeviceToHost));
+    if (C_j && n > 0) VP_HIP(hipMemcpy(C_j, p->vC, sizeof(double) * n * m * m, hipMemcpyDeviceToHost));
     return VP_OK;
 }
 

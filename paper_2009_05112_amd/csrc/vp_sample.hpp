@@ -384,21 +384,6 @@ struct SampleHot {
 // x = x_i + Delta x_i delta, J = prod_mu N_g Delta x_i.
 // FP64: u from 53 bits -- the high word of axis mu is word mu of the
 // stream, its low word is word D + mu.
-// Position of sample pos in the point buffers of a batched integrand.  The
-// samples are taken in aligned groups of 64 x 16; within a whole group the
-// sample at offset r goes to (r mod 16) * 64 + r / 16, so that when the lanes
-// of a wave each walk 16 consecutive samples, they touch consecutive
-// addresses.  Defined on absolute positions, so every kernel and launch shape
-// agrees; the last, partial group keeps its order.
-constexpr int kBatchGroup = kWave * 16;
-__device__ __forceinline__ int64_t batch_pos(int64_t pos, int64_t n_tot)
-{
-    const int64_t base = pos & ~(int64_t)(kBatchGroup - 1);
-    if (base + kBatchGroup > n_tot) return pos;
-    const int r = (int)(pos - base);
-    return base + (int64_t)(r & 15) * kWave + (r >> 4);
-}
-
 // Where the generate mode of a batched integrand puts a sample: x at
 // x[mu * n + pos], J at jac[pos], the increment index at idx[mu * cap + pos].
 struct BatchOut {

@@ -48,6 +48,12 @@ struct vp_problem {
     vp_params P;
     std::vector<double> lower, upper;
     std::vector<int32_t> nst_ax;  // stratifications of every axis
+    int n_out = 1;               // components of a vector-valued batched integrand
+    int vec_grid = 0;
+    double* vI = nullptr;        // [kVecHistory][n_out] per-iteration estimates
+    double* vC = nullptr;        // [kVecHistory][n_out][n_out] their covariances
+    double* vpart = nullptr;     // partial sums of the vector estimate
+    double* vout = nullptr;      // combined mean, covariance, chi^2, dof
     IntegrandDev fh;
     int32_t n_st;
     int64_t n_hc;

@@ -27,7 +27,7 @@ def test_examples_library_exports_declared_symbols():
 def test_batch_integrand_struct():
     # the batched integrand's function pointer and user pointer follow scale
     names = [f[0] for f in B.vp_integrand._fields_]
-    assert names[-3:] == ["scale", "fn", "user"]
+    assert names[-4:] == ["scale", "fn", "user", "n_out"]
     src = open(B.HEADER).read()
     assert "VP_F_BATCH = 100" in src
 
