@@ -225,6 +225,15 @@ vp_status vp_problem_destroy(vp_problem* p);
 vp_status vp_problem_info(vp_problem* p, int32_t* n_st, int64_t* n_hc);
 /* Stratifications of every axis: n_st_axes host array of dim entries. */
 vp_status vp_problem_strat(vp_problem* p, int32_t* n_st_axes);
+/* Where the sampling kernel keeps its per-workgroup data (diagnostics; either
+ * pointer may be NULL).  map_place: VP_MAP_GLOBAL, the map read from device
+ * memory; VP_MAP_LDS, all of it staged in LDS; VP_MAP_INNER, its two innermost
+ * axes staged in LDS and the others read from device memory.  hist_axes: the
+ * number of leading axes whose increment training data are accumulated in
+ * LDS (the others are written out as per-sample records and binned by a
+ * second pass). */
+enum { VP_MAP_GLOBAL = 0, VP_MAP_LDS = 1, VP_MAP_INNER = 2 };
+vp_status vp_problem_layout(vp_problem* p, int32_t* map_place, int32_t* hist_axes);
 
 /* Enqueues n_iter iterations (asynchronous).  Each iteration (Sec. 2.3 and 3):
  * scan of n_h into sample offsets; sampling, map, integrand, per-hypercube

@@ -108,6 +108,7 @@ def lib():
             "vp_problem_destroy": ([vp], C.c_int),
             "vp_problem_info": ([vp, ip, C.POINTER(C.c_int64)], C.c_int),
             "vp_problem_strat": ([vp, ip], C.c_int),
+            "vp_problem_layout": ([vp, ip, ip], C.c_int),
             "vp_map_train": ([vp, C.c_int64, dp, dp, C.c_int32, C.c_double], C.c_int),
             "vp_result_vec_get": ([vp, dp, dp, dp, ip, dp, dp, C.c_int32], C.c_int),
             "vp_iterate": ([vp, C.c_int32], C.c_int),
@@ -240,6 +241,10 @@ class Problem:
         ax = np.empty(params.dim, dtype=np.int32)
         check(lib().vp_problem_strat(self.h, _ip(ax)))
         self.n_st_axes = ax
+        mp = C.c_int32()
+        ha = C.c_int32()
+        check(lib().vp_problem_layout(self.h, C.byref(mp), C.byref(ha)))
+        self.map_place, self.hist_axes = ("global", "lds", "inner")[mp.value], ha.value
 
     def iterate(self, n: int = 1):
         check(lib().vp_iterate(self.h, n), "vp_iterate")

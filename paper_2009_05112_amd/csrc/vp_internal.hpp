@@ -13,6 +13,13 @@ constexpr int kMaxDimSplit = 16;  // FP32 sampling paths
 constexpr int kMaxNg = 4096;      // refinement keeps one axis in LDS
 
 enum Prec { P_FP64 = 0, P_FP32_ACC64 = 1, P_FP32_NEUMAIER = 2 };
+// Where the sampling kernel reads the vegas map: all of it from global memory
+// (buffer loads), all of it staged in LDS, or the kMapInnerAxes innermost axes
+// staged in LDS and the others from global memory.  The innermost axes are
+// the ones whose increments the lanes of a wave scatter over the whole axis
+// (consecutive hypercubes differ in their last digits).
+enum MapPlace { MAP_GLOBAL = 0, MAP_LDS = 1, MAP_INNER = 2 };
+constexpr int kMapInnerAxes = 2;
 enum Kind { K_GAUSS_MIX = 1, K_CORR_GAUSS = 2, K_EXP_ABS = 3, K_CONST = 4, K_AFFINE = 5, K_BALLS = 6, K_BATCH = 100 };
 // Sampling-kernel modes of a batched integrand: generate the sample points,
 // then accumulate the values the user's function wrote.
@@ -117,7 +124,7 @@ struct SampleArgs {
     uint32_t key0, key1, it;
     int32_t hist_mode;      // 0 weighted, 1 literal
     int32_t hist_axes;      // training data of axes [0, hist_axes) privatised in LDS
-    int32_t map_lds;        // 1: map staged in LDS
+    int32_t map_lds;        // map placement (MapPlace)
     int32_t chunk;          // samples per lane per tile
 };
 
@@ -194,39 +201,43 @@ struct SampleEntry {
     int block;                  // workgroup size the kernel is built for
 };
 
-// Specialised kernel for (precision, integrand kind and terms, dim, map in
-// LDS, training records), or an entry with launch == nullptr when none is
-// built.
-SampleEntry sample_entry(int prec, int kind, int n_terms, int dim, bool map_lds, bool rec, bool mix = false);
+// Specialised kernel for (precision, integrand kind and terms, dim, map
+// placement, training records), or an entry with launch == nullptr when none
+// is built.
+SampleEntry sample_entry(int prec, int kind, int n_terms, int dim, int map, bool rec, bool mix = false);
 #define VP_DECL_GAUSS(tag)                                          \
-    SampleEntry sample_entry_##tag##_gauss_k1(int dim, bool map_lds, bool rec); \
-    SampleEntry sample_entry_##tag##_gauss_k2(int dim, bool map_lds, bool rec); \
-    SampleEntry sample_entry_##tag##_gauss_k3(int dim, bool map_lds, bool rec); \
-    SampleEntry sample_entry_##tag##_gauss_k4(int dim, bool map_lds, bool rec);
+    SampleEntry sample_entry_##tag##_gauss_k1(int dim, int map, bool rec); \
+    SampleEntry sample_entry_##tag##_gauss_k2(int dim, int map, bool rec); \
+    SampleEntry sample_entry_##tag##_gauss_k3(int dim, int map, bool rec); \
+    SampleEntry sample_entry_##tag##_gauss_k4(int dim, int map, bool rec);
 VP_DECL_GAUSS(fp64)
 VP_DECL_GAUSS(fp32acc)
 VP_DECL_GAUSS(fp32neu)
 #undef VP_DECL_GAUSS
-SampleEntry sample_entry_fp64_corr(int dim, bool map_lds, bool rec);
-SampleEntry sample_entry_fp64_generic(int dim, bool map_lds, bool rec);
-SampleEntry sample_entry_fp32acc_generic(int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp64_corr(int dim, int map, bool rec);
+SampleEntry sample_entry_fp64_generic(int dim, int map, bool rec);
+SampleEntry sample_entry_fp32acc_generic(int dim, int map, bool rec);
 SampleEntry sample_entry_fp64_batch_gen(int dim);
-SampleEntry sample_entry_fp64_batch_acc(int dim, bool map_lds, bool rec);
-SampleEntry sample_entry_fp32neu_generic(int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp64_batch_acc(int dim, int map, bool rec);
+SampleEntry sample_entry_fp32neu_generic(int dim, int map, bool rec);
 // mixed stratification (per-axis counts): generic kinds and batched integrands
-SampleEntry sample_entry_fp64_generic_mix(int dim, bool map_lds, bool rec);
-SampleEntry sample_entry_fp32acc_generic_mix(int dim, bool map_lds, bool rec);
-SampleEntry sample_entry_fp32neu_generic_mix(int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp64_generic_mix(int dim, int map, bool rec);
+SampleEntry sample_entry_fp32acc_generic_mix(int dim, int map, bool rec);
+SampleEntry sample_entry_fp32neu_generic_mix(int dim, int map, bool rec);
 SampleEntry sample_entry_fp64_batch_gen_mix(int dim);
-SampleEntry sample_entry_fp64_batch_acc_mix(int dim, bool map_lds, bool rec);
+SampleEntry sample_entry_fp64_batch_acc_mix(int dim, int map, bool rec);
 
 // sampling kernels' LDS needs (bytes) for histogram and map
 inline size_t hist_lds_bytes(int dim, int n_g) { return (size_t)dim * n_g * 2 * sizeof(double); }
 // Workgroup size of the records-to-histogram pass.
 constexpr int kRecBlock = 1024;
-inline size_t map_lds_bytes(int prec, int dim, int n_g)
+__host__ __device__ constexpr int map_staged_axes(int map, int dim)
 {
-    return (size_t)dim * (n_g + 1) * (prec == P_FP64 ? sizeof(double) : sizeof(float));
+    return map == MAP_LDS ? dim : (map == MAP_INNER ? kMapInnerAxes : 0);
+}
+inline size_t map_lds_bytes(int prec, int dim, int n_g, int map)
+{
+    return (size_t)map_staged_axes(map, dim) * (n_g + 1) * (prec == P_FP64 ? sizeof(double) : sizeof(float));
 }
 
 // Integrand constants in the layout the sampling kernel reads (see
@@ -248,11 +259,11 @@ __host__ __device__ constexpr size_t fc_lds_bytes(int prec, int kind, int dim)
 {
     return (size_t)fc_count(kind, dim) * (prec == P_FP64 ? sizeof(double) : sizeof(float));
 }
-// Byte offset of the constants: after the training data and (when staged)
-// the map, rounded up to 16 bytes.
-__host__ __device__ constexpr size_t fc_lds_offset(size_t hist_bytes, bool map_lds, int prec, int dim, int n_g)
+// Byte offset of the constants: after the training data and the staged
+// axes of the map (map: a MapPlace), rounded up to 16 bytes.
+__host__ __device__ constexpr size_t fc_lds_offset(size_t hist_bytes, int map, int prec, int dim, int n_g)
 {
-    return (hist_bytes + (map_lds ? (size_t)dim * (n_g + 1) * (prec == P_FP64 ? 8 : 4) : 0) + 15) / 16 * 16;
+    return (hist_bytes + (size_t)map_staged_axes(map, dim) * (n_g + 1) * (prec == P_FP64 ? 8 : 4) + 15) / 16 * 16;
 }
 
 }  // namespace vp

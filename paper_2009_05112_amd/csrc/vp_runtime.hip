@@ -54,19 +54,19 @@ constexpr uint32_t kStateMagic = 0x56504C53u;  // "SLPV"
 }  // namespace
 
 // ---------------------------------------------------------------- helpers
-SampleEntry vp::sample_entry(int prec, int kind, int n_terms, int dim, bool map_lds, bool rec, bool mix)
+SampleEntry vp::sample_entry(int prec, int kind, int n_terms, int dim, int map, bool rec, bool mix)
 {
     if (mix) {
         // per-axis stratification: the generic kernels (constants in LDS)
-        typedef SampleEntry (*Table)(int, bool, bool);
+        typedef SampleEntry (*Table)(int, int, bool);
         static const Table generic_mix[3] = {sample_entry_fp64_generic_mix, sample_entry_fp32acc_generic_mix,
                                              sample_entry_fp32neu_generic_mix};
         if (prec < 0 || prec > 2) return SampleEntry{nullptr, nullptr, 0};
         if (kind == K_BATCH)
-            return prec == P_FP64 ? sample_entry_fp64_batch_acc_mix(dim, map_lds, rec) : SampleEntry{nullptr, nullptr, 0};
-        return generic_mix[prec](dim, map_lds, rec);
+            return prec == P_FP64 ? sample_entry_fp64_batch_acc_mix(dim, map, rec) : SampleEntry{nullptr, nullptr, 0};
+        return generic_mix[prec](dim, map, rec);
     }
-    typedef SampleEntry (*Table)(int, bool, bool);
+    typedef SampleEntry (*Table)(int, int, bool);
     static const Table gauss[3][4] = {
         {sample_entry_fp64_gauss_k1, sample_entry_fp64_gauss_k2, sample_entry_fp64_gauss_k3, sample_entry_fp64_gauss_k4},
         {sample_entry_fp32acc_gauss_k1, sample_entry_fp32acc_gauss_k2, sample_entry_fp32acc_gauss_k3,
@@ -77,10 +77,10 @@ SampleEntry vp::sample_entry(int prec, int kind, int n_terms, int dim, bool map_
                                      sample_entry_fp32neu_generic};
     SampleEntry e = {nullptr, nullptr, 0};
     if (prec < 0 || prec > 2) return e;
-    if (kind == K_BATCH) return prec == P_FP64 ? sample_entry_fp64_batch_acc(dim, map_lds, rec) : e;
-    if (kind == K_GAUSS_MIX && n_terms >= 1 && n_terms <= kMaxTerms) e = gauss[prec][n_terms - 1](dim, map_lds, rec);
-    else if (kind == K_CORR_GAUSS && prec == P_FP64) e = sample_entry_fp64_corr(dim, map_lds, rec);
-    if (!e.launch) e = generic[prec](dim, map_lds, rec);
+    if (kind == K_BATCH) return prec == P_FP64 ? sample_entry_fp64_batch_acc(dim, map, rec) : e;
+    if (kind == K_GAUSS_MIX && n_terms >= 1 && n_terms <= kMaxTerms) e = gauss[prec][n_terms - 1](dim, map, rec);
+    else if (kind == K_CORR_GAUSS && prec == P_FP64) e = sample_entry_fp64_corr(dim, map, rec);
+    if (!e.launch) e = generic[prec](dim, map, rec);
     return e;
 }
 
@@ -569,19 +569,28 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     sh->hist_axes = std::min(D, fit);
     if (prec == VP_FP32_NEUMAIER && sh->hist_axes < D)
         return fail(VP_ERR_INVALID_ARG, "compensated sums need dim * n_g * 16 <= %zu bytes of LDS", ctx->lds_max);
-    const size_t hb = hist_lds_bytes(sh->hist_axes, NG), mb = map_lds_bytes(prec, D, NG);
+    const size_t hb = hist_lds_bytes(sh->hist_axes, NG);
     const bool batch = f->kind == VP_F_BATCH;
-    sh->map_lds = !batch && hb + mb + fcb <= ctx->lds_max ? 1 : 0;  // the accumulate mode reads no map
     const bool rec = sh->hist_axes < D;
-    if (rec) sh->map_lds = 0;
-    sh->entry = sample_entry(prec, f->kind, f->n_terms, D, sh->map_lds != 0, rec, sh->mix);
-    if (!sh->entry.launch && sh->map_lds) {
-        sh->map_lds = 0;
-        sh->entry = sample_entry(prec, f->kind, f->n_terms, D, false, rec, sh->mix);
+    // Map placement.  Double precision: the whole map in LDS when it fits
+    // beside the training data, else its innermost axes when they fit, else
+    // global memory.  The split precisions read it from global memory (their
+    // kernels are bound by the LDS atomics of the training data).  The
+    // accumulate mode of a batched integrand reads no map.
+    sh->map_lds = MAP_GLOBAL;
+    if (!batch && !rec && prec == VP_FP64) {
+        if (hb + map_lds_bytes(prec, D, NG, MAP_LDS) + fcb <= ctx->lds_max) sh->map_lds = MAP_LDS;
+        else if (D > kMapInnerAxes && hb + map_lds_bytes(prec, D, NG, MAP_INNER) + fcb <= ctx->lds_max)
+            sh->map_lds = MAP_INNER;
+    }
+    sh->entry = sample_entry(prec, f->kind, f->n_terms, D, sh->map_lds, rec, sh->mix);
+    if (!sh->entry.launch && sh->map_lds != MAP_GLOBAL) {
+        sh->map_lds = MAP_GLOBAL;
+        sh->entry = sample_entry(prec, f->kind, f->n_terms, D, MAP_GLOBAL, rec, sh->mix);
     }
     if (!sh->entry.launch) return fail(VP_ERR_INVALID_ARG, "no sampling kernel for dim %d", D);
     sh->block = sh->entry.block;
-    sh->lds = fc_lds_offset(hb, sh->map_lds != 0, prec, D, NG) + fc_lds_bytes(prec, f->kind, D);
+    sh->lds = fc_lds_offset(hb, sh->map_lds, prec, D, NG) + fc_lds_bytes(prec, f->kind, D);
     sh->chunk = 16;
     int occ = cached_occupancy(ctx->device, sh->entry, sh->block, sh->lds);
     if (occ < 1) occ = 1;
@@ -968,6 +977,16 @@ vp_status vp_problem_info(vp_problem* p, int32_t* n_st, int64_t* n_hc)
     if (!p) return fail(VP_ERR_INVALID_ARG, "problem is NULL");
     if (n_st) *n_st = p->n_st;
     if (n_hc) *n_hc = p->n_hc;
+    return VP_OK;
+}
+
+vp_status vp_problem_layout(vp_problem* p, int32_t* map_place, int32_t* hist_axes)
+{
+    if (!p) return fail(VP_ERR_INVALID_ARG, "problem is NULL");
+    static_assert(VP_MAP_GLOBAL == MAP_GLOBAL && VP_MAP_LDS == MAP_LDS && VP_MAP_INNER == MAP_INNER,
+                  "map placements of the header and the kernels agree");
+    if (map_place) *map_place = p->map_lds;
+    if (hist_axes) *hist_axes = p->hist_axes;
     return VP_OK;
 }
 

@@ -331,17 +331,23 @@ __device__ __forceinline__ T f_finish(FP fc, int kind, int K, FState<D, T>& st)
 // From LDS: two adjacent reads.  From global memory: one 16-byte (FP64) or
 // 8-byte (FP32) buffer load with a 32-bit offset from a wave-uniform buffer
 // resource (bounds-checked by the hardware: reads past the map return zero).
+// MAPL (MapPlace) says where: all axes in global memory, all in LDS, or the
+// kMapInnerAxes innermost axes in LDS (their pairs start at element
+// `inner0` = (D - kMapInnerAxes) (N_g + 1) of the map) and the rest in global
+// memory.  `staged` is a compile-time property of the axis.
 constexpr int kBufferWord3 = 0x00020000;  // raw buffer, gfx9 family
 
-template <bool LDS>
+template <int MAPL>
 struct MapPair64 {
     const double* lds;
+    uint32_t inner0;
     __amdgpu_buffer_rsrc_t rsrc;
-    __device__ __forceinline__ void get(uint32_t pos, double& x0, double& x1) const
+    __device__ __forceinline__ void get(uint32_t pos, double& x0, double& x1, bool staged) const
     {
-        if constexpr (LDS) {
-            x0 = lds[pos];
-            x1 = lds[pos + 1];
+        if (MAPL == MAP_LDS || (MAPL == MAP_INNER && staged)) {
+            const uint32_t p = MAPL == MAP_INNER ? pos - inner0 : pos;
+            x0 = lds[p];
+            x1 = lds[p + 1];
         } else {
             const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, pos * 8u, 0, 0);
             x0 = __builtin_bit_cast(double, ((uint64_t)(uint32_t)v[1] << 32) | (uint32_t)v[0]);
@@ -350,15 +356,17 @@ struct MapPair64 {
     }
 };
 
-template <bool LDS>
+template <int MAPL>
 struct MapPair32 {
     const float* lds;
+    uint32_t inner0;
     __amdgpu_buffer_rsrc_t rsrc;
-    __device__ __forceinline__ void get(uint32_t pos, float& x0, float& x1) const
+    __device__ __forceinline__ void get(uint32_t pos, float& x0, float& x1, bool staged) const
     {
-        if constexpr (LDS) {
-            x0 = lds[pos];
-            x1 = lds[pos + 1];
+        if (MAPL == MAP_LDS || (MAPL == MAP_INNER && staged)) {
+            const uint32_t p = MAPL == MAP_INNER ? pos - inner0 : pos;
+            x0 = lds[p];
+            x1 = lds[p + 1];
         } else {
             const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, pos * 4u, 0, 0);
             x0 = __builtin_bit_cast(float, (uint32_t)v[0]);
@@ -393,8 +401,8 @@ struct BatchOut {
     int64_t n, cap, pos;
 };
 
-template <int D, bool MAPLDS, int KT, typename FP, bool GEN = false, bool MIX = false>
-__device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair64<MAPLDS>& map, FP fc,
+template <int D, int MAPL, int KT, typename FP, bool GEN = false, bool MIX = false>
+__device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair64<MAPL>& map, FP fc,
                                               uint32_t j, uint32_t h, const int32_t* k,
                                               int32_t* idx, int kind, int K, const BatchOut* out = nullptr)
 {
@@ -434,7 +442,7 @@ __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair6
             double delta = t - (double)i;
             delta = delta < 1.0 ? delta : 1.0;
             double x0, x1;
-            map.get((uint32_t)(mu * (n_g + 1) + i), x0, x1);
+            map.get((uint32_t)(mu * (n_g + 1) + i), x0, x1, mu >= D - kMapInnerAxes);
             const double dx = x1 - x0;
             const double x = fma(dx, delta, x0);
             jac = jac * ((double)n_g * dx);
@@ -456,8 +464,8 @@ __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair6
 }
 
 // FP32 split: u = (w >> 8) 2^-24 from the high word of each axis alone.
-template <int D, bool MAPLDS, int KT, typename FP, bool MIX = false>
-__device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32<MAPLDS>& map, FP fc,
+template <int D, int MAPL, int KT, typename FP, bool MIX = false>
+__device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32<MAPL>& map, FP fc,
                                              uint32_t j, uint32_t h, const int32_t* k, int32_t* idx,
                                              int kind, int K)
 {
@@ -483,7 +491,7 @@ __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32
             float delta = t - (float)i;
             delta = delta < 1.0f ? delta : 1.0f;
             float x0, x1;
-            map.get((uint32_t)(mu * (n_g + 1) + i), x0, x1);
+            map.get((uint32_t)(mu * (n_g + 1) + i), x0, x1, mu >= D - kMapInnerAxes);
             const float dx = x1 - x0;
             const float x = fmaf(dx, delta, x0);
             jac = jac * ((float)n_g * dx);
@@ -530,9 +538,10 @@ __device__ __forceinline__ void put_training(double* rec, int64_t stride, int ha
 // KT: Gaussian-mixture terms fixed at compile time (0: read at run time).
 // MIX: per-axis stratification counts (Sec. 4), read with R_mu from the
 // constants staged in LDS; only kernels that stage them there have it.
-template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT, bool MIX>
-__global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(LaunchSet L)
+template <int D, int PREC, int MAPL, int KIND, bool REC, int KT, bool MIX>
+__global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void k_sample(LaunchSet L)
 {
+    static_assert(MAPL != MAP_INNER || D > kMapInnerAxes, "staging the innermost axes needs more axes");
     VP_REQ_PROLOGUE(L);
     // The argument record stays in memory; the fields the loop needs are read
     // into registers here, the others where they are used (a copy of the
@@ -561,11 +570,14 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
 
     const int kind = KIND ? KIND : a.f->kind;
     const int K = a.f->n_terms;
-    MapT* lds_fc = reinterpret_cast<MapT*>(lds_raw + fc_lds_offset(hist_bytes, MAPLDS, PREC, D, n_g));
+    MapT* lds_fc = reinterpret_cast<MapT*>(lds_raw + fc_lds_offset(hist_bytes, MAPL, PREC, D, n_g));
 
     for (int i = threadIdx.x; i < 2 * lbins; i += blockDim.x) lds_hist[i] = 0.0;
-    if constexpr (MAPLDS)
+    if constexpr (MAPL == MAP_LDS)
         for (int i = threadIdx.x; i < D * (n_g + 1); i += blockDim.x) lds_map[i] = gmap[i];
+    const uint32_t inner0 = (uint32_t)((D - kMapInnerAxes) * (n_g + 1));
+    if constexpr (MAPL == MAP_INNER)
+        for (int i = threadIdx.x; i < kMapInnerAxes * (n_g + 1); i += blockDim.x) lds_map[i] = gmap[inner0 + i];
     // Gaussian-mixture constants (4 D + 16 values) are read through the
     // scalar cache at every sample, from the constant address space: the
     // VALU takes them as scalar operands, and they occupy no register across
@@ -581,9 +593,10 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
         for (int i = threadIdx.x; i < fc_count(kind, D); i += blockDim.x) lds_fc[i] = src[i];
     }
     __syncthreads();
-    typedef typename std::conditional<PREC == P_FP64, MapPair64<MAPLDS>, MapPair32<MAPLDS>>::type MapAcc;
+    typedef typename std::conditional<PREC == P_FP64, MapPair64<MAPL>, MapPair32<MAPL>>::type MapAcc;
     MapAcc map;
     map.lds = lds_map;
+    map.inner0 = inner0;
     map.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)gmap, (short)0,
                                                  (int)((size_t)D * (n_g + 1) * sizeof(MapT)), kBufferWord3);
 
@@ -730,7 +743,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                     const int64_t bpos = batch_pos(s_a + (int64_t)s, n_tot);
                     if constexpr (GEN) {
                         bout.pos = bpos;
-                        (void)sample_fp64<D, MAPLDS, 0, const MapT*, true, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K,
+                        (void)sample_fp64<D, MAPL, 0, const MapT*, true, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K,
                                                                            &bout);
                     } else if constexpr (PREC == P_FP64) {
                         double v;
@@ -740,8 +753,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
 #pragma unroll
                             for (int mu = 0; mu < D; ++mu) idx[mu] = bout.idx[mu * bout.cap + pos];
                         } else {
-                            v = (FC_SMEM ? sample_fp64<D, MAPLDS, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
-                                         : sample_fp64<D, MAPLDS, KT, const MapT*, false, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
+                            v = (FC_SMEM ? sample_fp64<D, MAPL, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
+                                         : sample_fp64<D, MAPL, KT, const MapT*, false, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
                         }
                         run.add(v);
                         if (!isfinite(v)) ++bad;
@@ -750,8 +763,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         const double hw = literal ? 1.0 : inv_n;
                         put_training<D, REC>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
                     } else if constexpr (PREC == P_FP32_ACC64) {
-                        const float v32 = (FC_SMEM ? sample_fp32<D, MAPLDS, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
-                                           : sample_fp32<D, MAPLDS, KT, const MapT*, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
+                        const float v32 = (FC_SMEM ? sample_fp32<D, MAPL, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
+                                           : sample_fp32<D, MAPL, KT, const MapT*, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
                         const double v = (double)v32;
                         run.add(v);
                         if (!isfinite(v32)) ++bad;
@@ -760,8 +773,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
                         const double hw = literal ? 1.0 : inv_n;
                         put_training<D, REC>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
                     } else {
-                        const float v32 = (FC_SMEM ? sample_fp32<D, MAPLDS, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
-                                           : sample_fp32<D, MAPLDS, KT, const MapT*, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
+                        const float v32 = (FC_SMEM ? sample_fp32<D, MAPL, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
+                                           : sample_fp32<D, MAPL, KT, const MapT*, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
                         run.addf(v32);
                         if (!isfinite(v32)) ++bad;
                         const float v2 = v32 * v32;
@@ -900,65 +913,70 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPLDS)) void k_sample(
     }
 }
 
-template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT, bool MIX>
+template <int D, int PREC, int MAPL, int KIND, bool REC, int KT, bool MIX>
 void launch_sample(const LaunchSet& L, int grid, int block, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sample<D, PREC, MAPLDS, KIND, REC, KT, MIX>), dim3(grid), dim3(block), lds, s, L);
+    hipLaunchKernelGGL((k_sample<D, PREC, MAPL, KIND, REC, KT, MIX>), dim3(grid), dim3(block), lds, s, L);
 }
 
-template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT, bool MIX>
+template <int D, int PREC, int MAPL, int KIND, bool REC, int KT, bool MIX>
 int sample_occupancy(int block, size_t lds)
 {
     int n = 0;
-    (void)hipFuncSetAttribute((const void*)k_sample<D, PREC, MAPLDS, KIND, REC, KT, MIX>,
+    (void)hipFuncSetAttribute((const void*)k_sample<D, PREC, MAPL, KIND, REC, KT, MIX>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sample<D, PREC, MAPLDS, KIND, REC, KT, MIX>, block,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sample<D, PREC, MAPL, KIND, REC, KT, MIX>, block,
                                                      lds) != hipSuccess)
         return 0;
     return n;
 }
 
-template <int D, int PREC, bool MAPLDS, int KIND, bool REC, int KT, bool MIX = false>
+template <int D, int PREC, int MAPL, int KIND, bool REC, int KT, bool MIX = false>
 SampleEntry make_entry()
 {
     SampleEntry e;
-    e.launch = launch_sample<D, PREC, MAPLDS, KIND, REC, KT, MIX>;
-    e.occupancy = sample_occupancy<D, PREC, MAPLDS, KIND, REC, KT, MIX>;
-    e.block = sample_block(PREC, KIND, D, MAPLDS);
+    e.launch = launch_sample<D, PREC, MAPL, KIND, REC, KT, MIX>;
+    e.occupancy = sample_occupancy<D, PREC, MAPL, KIND, REC, KT, MIX>;
+    e.block = sample_block(PREC, KIND, D, MAPL == MAP_LDS);
     return e;
 }
 
-// The instantiation for a layout: map in LDS (all training data in LDS), map
-// in global memory with all training data in LDS, or with records.
+// The instantiation for a layout (map: a MapPlace).  All training data in
+// LDS, with the whole map in LDS, its innermost axes in LDS, or the map in
+// global memory; or training records with the map in global memory.  The
+// split precisions read the map from global memory only: their kernels are
+// bound by the LDS atomics of the training data, and map reads from LDS
+// would queue behind them.
+constexpr SampleEntry kNoEntry = {nullptr, nullptr, 0};
+
 template <int D, int PREC, int KIND, int KT = 0, bool MIX = false>
-SampleEntry entry_for(bool map_lds, bool rec)
+SampleEntry entry_for(int map, bool rec)
 {
-    if (map_lds) return rec ? SampleEntry{nullptr, nullptr, 0} : make_entry<D, PREC, true, KIND, false, KT, MIX>();
-    return rec ? make_entry<D, PREC, false, KIND, true, KT, MIX>() : make_entry<D, PREC, false, KIND, false, KT, MIX>();
+    if (rec) return map == MAP_GLOBAL ? make_entry<D, PREC, MAP_GLOBAL, KIND, true, KT, MIX>() : kNoEntry;
+    if (map == MAP_GLOBAL) return make_entry<D, PREC, MAP_GLOBAL, KIND, false, KT, MIX>();
+    if constexpr (PREC == P_FP64) {
+        if (map == MAP_LDS) return make_entry<D, PREC, MAP_LDS, KIND, false, KT, MIX>();
+        if constexpr (D > kMapInnerAxes)
+            if (map == MAP_INNER) return make_entry<D, PREC, MAP_INNER, KIND, false, KT, MIX>();
+    }
+    return kNoEntry;
 }
 
-// The same without the map-in-LDS variant (kernels whose integrand leaves no
-// room for it).
+// The map in global memory only (kernels whose integrand constants take the
+// LDS the map would use).
 template <int D, int PREC, int KIND, int KT = 0, bool MIX = false>
-SampleEntry entry_for_global(bool map_lds, bool rec)
+SampleEntry entry_for_global(int map, bool rec)
 {
-    if (map_lds) return SampleEntry{nullptr, nullptr, 0};
-    return rec ? make_entry<D, PREC, false, KIND, true, KT, MIX>() : make_entry<D, PREC, false, KIND, false, KT, MIX>();
+    if (map != MAP_GLOBAL) return kNoEntry;
+    return rec ? make_entry<D, PREC, MAP_GLOBAL, KIND, true, KT, MIX>() : make_entry<D, PREC, MAP_GLOBAL, KIND, false, KT, MIX>();
 }
 
 // Compensated sums need every axis's bins in LDS: no record variants.
 template <int D, int PREC, int KIND, int KT = 0, bool MIX = false>
-SampleEntry entry_for_lds_only(bool map_lds, bool rec)
+SampleEntry entry_for_global_lds_only(int map, bool rec)
 {
-    if (rec) return SampleEntry{nullptr, nullptr, 0};
-    return map_lds ? make_entry<D, PREC, true, KIND, false, KT, MIX>() : make_entry<D, PREC, false, KIND, false, KT, MIX>();
-}
-
-template <int D, int PREC, int KIND, int KT = 0, bool MIX = false>
-SampleEntry entry_for_global_lds_only(bool map_lds, bool rec)
-{
-    if (rec || map_lds) return SampleEntry{nullptr, nullptr, 0};
-    return make_entry<D, PREC, false, KIND, false, KT, MIX>();
+    if (rec || map != MAP_GLOBAL) return kNoEntry;
+    return make_entry<D, PREC, MAP_GLOBAL, KIND, false, KT, MIX>();
 }
 
 }  // namespace vp

@@ -8,63 +8,63 @@ SampleEntry sample_entry_fp64_batch_gen_mix(int dim)
 {
     SampleEntry e = {nullptr, nullptr, 0};
     switch (dim) {
-    case 1: e = make_entry<1, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 2: e = make_entry<2, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 3: e = make_entry<3, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 4: e = make_entry<4, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 5: e = make_entry<5, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 6: e = make_entry<6, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 7: e = make_entry<7, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 8: e = make_entry<8, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 9: e = make_entry<9, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 10: e = make_entry<10, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 11: e = make_entry<11, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 12: e = make_entry<12, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 13: e = make_entry<13, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 14: e = make_entry<14, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 15: e = make_entry<15, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 16: e = make_entry<16, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 17: e = make_entry<17, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 18: e = make_entry<18, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 19: e = make_entry<19, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 20: e = make_entry<20, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 21: e = make_entry<21, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 22: e = make_entry<22, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 23: e = make_entry<23, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
-    case 24: e = make_entry<24, P_FP64, false, K_BATCH_GEN, false, 0, true>(); break;
+    case 1: e = make_entry<1, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 2: e = make_entry<2, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 3: e = make_entry<3, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 4: e = make_entry<4, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 5: e = make_entry<5, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 6: e = make_entry<6, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 7: e = make_entry<7, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 8: e = make_entry<8, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 9: e = make_entry<9, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 10: e = make_entry<10, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 11: e = make_entry<11, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 12: e = make_entry<12, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 13: e = make_entry<13, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 14: e = make_entry<14, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 15: e = make_entry<15, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 16: e = make_entry<16, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 17: e = make_entry<17, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 18: e = make_entry<18, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 19: e = make_entry<19, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 20: e = make_entry<20, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 21: e = make_entry<21, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 22: e = make_entry<22, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 23: e = make_entry<23, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 24: e = make_entry<24, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
     default: break;
     }
     return e;
 }
 
-SampleEntry sample_entry_fp64_batch_acc_mix(int dim, bool map_lds, bool rec)
+SampleEntry sample_entry_fp64_batch_acc_mix(int dim, int map, bool rec)
 {
     SampleEntry e = {nullptr, nullptr, 0};
     switch (dim) {
-    case 1: e = entry_for_global<1, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 2: e = entry_for_global<2, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 3: e = entry_for_global<3, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 4: e = entry_for_global<4, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 5: e = entry_for_global<5, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 6: e = entry_for_global<6, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 7: e = entry_for_global<7, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 8: e = entry_for_global<8, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 9: e = entry_for_global<9, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 10: e = entry_for_global<10, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 11: e = entry_for_global<11, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 12: e = entry_for_global<12, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 13: e = entry_for_global<13, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 14: e = entry_for_global<14, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 15: e = entry_for_global<15, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 16: e = entry_for_global<16, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 17: e = entry_for_global<17, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 18: e = entry_for_global<18, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 19: e = entry_for_global<19, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 20: e = entry_for_global<20, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 21: e = entry_for_global<21, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 22: e = entry_for_global<22, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 23: e = entry_for_global<23, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
-    case 24: e = entry_for_global<24, P_FP64, K_BATCH_ACC, 0, true>(map_lds, rec); break;
+    case 1: e = entry_for_global<1, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 2: e = entry_for_global<2, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 3: e = entry_for_global<3, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 4: e = entry_for_global<4, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 5: e = entry_for_global<5, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 6: e = entry_for_global<6, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 7: e = entry_for_global<7, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 8: e = entry_for_global<8, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 9: e = entry_for_global<9, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 10: e = entry_for_global<10, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 11: e = entry_for_global<11, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 12: e = entry_for_global<12, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 13: e = entry_for_global<13, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 14: e = entry_for_global<14, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 15: e = entry_for_global<15, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 16: e = entry_for_global<16, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 17: e = entry_for_global<17, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 18: e = entry_for_global<18, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 19: e = entry_for_global<19, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 20: e = entry_for_global<20, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 21: e = entry_for_global<21, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 22: e = entry_for_global<22, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 23: e = entry_for_global<23, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
+    case 24: e = entry_for_global<24, P_FP64, K_BATCH_ACC, 0, true>(map, rec); break;
     default: break;
     }
     return e;

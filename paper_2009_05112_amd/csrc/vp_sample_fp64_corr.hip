@@ -4,34 +4,34 @@
 
 namespace vp {
 
-SampleEntry sample_entry_fp64_corr(int dim, bool map_lds, bool rec)
+SampleEntry sample_entry_fp64_corr(int dim, int map, bool rec)
 {
     SampleEntry e = {nullptr, nullptr, 0};
     switch (dim) {
-    case 1: e = entry_for_global<1, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 2: e = entry_for_global<2, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 3: e = entry_for_global<3, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 4: e = entry_for_global<4, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 5: e = entry_for_global<5, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 6: e = entry_for_global<6, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 7: e = entry_for_global<7, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 8: e = entry_for_global<8, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 9: e = entry_for_global<9, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 10: e = entry_for_global<10, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 11: e = entry_for_global<11, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 12: e = entry_for_global<12, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 13: e = entry_for_global<13, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 14: e = entry_for_global<14, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 15: e = entry_for_global<15, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 16: e = entry_for_global<16, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 17: e = entry_for_global<17, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 18: e = entry_for_global<18, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 19: e = entry_for_global<19, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 20: e = entry_for_global<20, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 21: e = entry_for_global<21, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 22: e = entry_for_global<22, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 23: e = entry_for_global<23, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
-    case 24: e = entry_for_global<24, P_FP64, K_CORR_GAUSS, 0>(map_lds, rec); break;
+    case 1: e = entry_for_global<1, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 2: e = entry_for_global<2, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 3: e = entry_for_global<3, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 4: e = entry_for_global<4, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 5: e = entry_for_global<5, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 6: e = entry_for_global<6, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 7: e = entry_for_global<7, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 8: e = entry_for_global<8, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 9: e = entry_for_global<9, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 10: e = entry_for_global<10, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 11: e = entry_for_global<11, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 12: e = entry_for_global<12, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 13: e = entry_for_global<13, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 14: e = entry_for_global<14, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 15: e = entry_for_global<15, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 16: e = entry_for_global<16, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 17: e = entry_for_global<17, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 18: e = entry_for_global<18, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 19: e = entry_for_global<19, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 20: e = entry_for_global<20, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 21: e = entry_for_global<21, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 22: e = entry_for_global<22, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 23: e = entry_for_global<23, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
+    case 24: e = entry_for_global<24, P_FP64, K_CORR_GAUSS, 0>(map, rec); break;
     default: break;
     }
     return e;

@@ -76,10 +76,25 @@ def test_stepwise_diag_d8_mid(ctx):
     non-uniform allocations with large hypercubes spanning many waves."""
     p, f = W.cfg_diag_d8(n_ev=1_000_000)
     gp, op = _pair(ctx, p, f)
+    assert gp.map_place == "inner"  # the benchmark's layout: two innermost map axes in LDS
     for _ in range(6):
         out = step_and_compare(gp, op)
     n = out["n_new"]
     assert n.max() > 50 * n.min()  # the allocation really adapted
+
+
+@pytest.mark.parametrize("dim,n_ev,place", [(4, 100_000, "lds"), (9, 300_000, "inner"), (10, 200_000, "global")])
+def test_map_placements(ctx, dim, n_ev, place):
+    """The three places the FP64 sampler reads the map from (N_g = 1000):
+    all of it staged in LDS beside the training data (D=4), only the two
+    innermost axes (D=9: 144 KB of training data leave room for two axes),
+    or none (D=10), each step-wise against the oracle."""
+    p = W.Params(dim=dim, n_ev=n_ev, n_g=1000, n_iter=3, seed=dim + 3)
+    f = W.gauss_diag(dim, coef=50.0, cs=(0.3, 0.6))
+    gp, op = _pair(ctx, p, f)
+    assert gp.map_place == place and gp.hist_axes == dim
+    for _ in range(3):
+        step_and_compare(gp, op)
 
 
 def test_stepwise_literal_d8_counts_exact(ctx):

@@ -46,10 +46,12 @@ def test_split_stepwise_d8(ctx, prec, hist_mode):
 
 
 @pytest.mark.parametrize("prec", ["fp32_acc64", "fp32_neumaier"])
-def test_split_stepwise_d4_map_in_lds(ctx, prec):
+def test_split_stepwise_d4(ctx, prec):
     p, f = W.cfg_small_d4()
     p = p.with_(precision=prec)
     gp = B.Problem(ctx, p, f)
+    # the split kernels read the map by buffer loads, even where it would fit in LDS
+    assert gp.map_place == "global" and gp.hist_axes == 4
     op = oracle.Problem(p, f, n_st=gp.n_st)
     for _ in range(4):
         step_and_compare(gp, op, rtol=RTOL32, rtol_hist=RTOL32, floor=FLOOR32)
@@ -73,9 +75,9 @@ def test_split_error_vs_fp64_oracle(ctx, prec):
     assert abs(rs["sdev"] / ro["sdev"] - 1.0) < 0.01
 
 
-def test_split_map_in_global_memory(ctx):
-    """N_g = 1200 at D=8: the single-precision map no longer fits in LDS next
-    to the training data and is read through buffer loads."""
+def test_split_larger_map(ctx):
+    """N_g = 1200 at D=8: 9600 increments' training data in LDS, the map read
+    through buffer loads."""
     p, f = W.cfg_diag_d8(n_ev=500_000, precision="fp32_acc64")
     p = p.with_(n_g=1200)
     gp = B.Problem(ctx, p, f)
