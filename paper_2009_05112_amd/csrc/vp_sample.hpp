@@ -219,15 +219,50 @@ struct AccOf<P_FP32_NEUMAIER> {
     typedef AccN type;
 };
 
-// Exact rounding error of an LDS atomic add: the atomic returns the old value,
-// the stored sum is fl(old + x), and TwoSum recovers old + x - fl(old + x).
-__device__ __forceinline__ void lds_add_compensated(float* sum, float* comp, float x)
+// Compensated single-precision training data in LDS.  Each bin is one 8-byte
+// word holding the pair (sum, compensation); an update reads the pair, takes
+// Neumaier's step with the new value, and stores the result with a 64-bit
+// compare-and-swap, retried while another lane or wave changed the word in
+// between.  (Single-precision LDS atomic adds are several times slower than
+// the 64-bit compare-and-swap on this hardware.)  The 2 D updates of a sample
+// go out together: all reads, then all swaps, then the retries of the lanes
+// whose swap lost.
+__device__ __forceinline__ uint64_t pack_pair(float s, float c)
 {
-    const float old = atomicAdd(sum, x);
-    const float s = old + x;
-    const float bp = s - old;
-    const float err = (old - (s - bp)) + (x - bp);
-    if (err != 0.0f) atomicAdd(comp, err);
+    return ((uint64_t)__float_as_uint(c) << 32) | (uint64_t)__float_as_uint(s);
+}
+
+template <int D>
+__device__ __forceinline__ void lds_neumaier_sample(uint64_t* pairs, int lbins, int n_g, const int32_t* idx,
+                                                    float hh, float hw)
+{
+    uint64_t* addr[2 * D];
+    uint64_t cur[2 * D];
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        const int bin = mu * n_g + idx[mu];
+        addr[mu] = pairs + bin;
+        addr[D + mu] = pairs + lbins + bin;
+    }
+#pragma unroll
+    for (int m = 0; m < 2 * D; ++m)
+        cur[m] = __hip_atomic_load(addr[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    static_assert(2 * D <= 32, "one pending bit per update");
+    uint32_t pending = (uint32_t)(((uint64_t)1 << (2 * D)) - 1u);
+    do {
+#pragma unroll
+        for (int m = 0; m < 2 * D; ++m) {
+            if (pending & (1u << m)) {
+                float s = __uint_as_float((uint32_t)cur[m]);
+                float c = __uint_as_float((uint32_t)(cur[m] >> 32));
+                neumaier_add(s, c, m < D ? hh : hw);
+                const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(addr[m]),
+                                               (unsigned long long)cur[m], (unsigned long long)pack_pair(s, c));
+                if (old == cur[m]) pending &= ~(1u << m);
+                cur[m] = old;
+            }
+        }
+    } while (pending);
 }
 
 // ---------------------------------------------------------------- integrands
@@ -562,7 +597,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
     const int lbins = ha * n_g;            // bins per LDS plane
     const size_t hist_bytes = (size_t)lbins * 16;
     double* lds_hist = reinterpret_cast<double*>(lds_raw);
-    float* lds_histf = reinterpret_cast<float*>(lds_raw);
+    uint64_t* lds_pairs = reinterpret_cast<uint64_t*>(lds_raw);  // compensated single precision: (sum, comp) per bin
     MapT* lds_map = reinterpret_cast<MapT*>(lds_raw + hist_bytes);
     const MapT* gmap;
     if constexpr (PREC == P_FP64) gmap = a.map;
@@ -780,12 +815,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                         const float v2 = v32 * v32;
                         const float hh = literal ? v2 : v2 * inv_n32;
                         const float hw = literal ? 1.0f : inv_n32;
-#pragma unroll
-                        for (int mu = 0; mu < D; ++mu) {
-                            const int bin = mu * n_g + idx[mu];
-                            lds_add_compensated(&lds_histf[bin], &lds_histf[lbins + bin], hh);
-                            lds_add_compensated(&lds_histf[2 * lbins + bin], &lds_histf[3 * lbins + bin], hw);
-                        }
+                        lds_neumaier_sample<D>(lds_pairs, lbins, n_g, idx, hh, hw);
                     }
                 }
                 if (s_end == next) {
@@ -901,8 +931,9 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
         double* out = a.hist_part + (size_t)bid * 2 * nbins;
         if constexpr (PREC == P_FP32_NEUMAIER) {
             for (int i = threadIdx.x; i < lbins; i += blockDim.x) {
-                out[i] = (double)lds_histf[i] + (double)lds_histf[lbins + i];
-                out[nbins + i] = (double)lds_histf[2 * lbins + i] + (double)lds_histf[3 * lbins + i];
+                const uint64_t ph = lds_pairs[i], pw = lds_pairs[lbins + i];
+                out[i] = (double)__uint_as_float((uint32_t)ph) + (double)__uint_as_float((uint32_t)(ph >> 32));
+                out[nbins + i] = (double)__uint_as_float((uint32_t)pw) + (double)__uint_as_float((uint32_t)(pw >> 32));
             }
         } else {
             for (int i = threadIdx.x; i < lbins; i += blockDim.x) {
