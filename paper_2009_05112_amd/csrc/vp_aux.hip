@@ -49,22 +49,43 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_local(LaunchSet L)
     const int64_t n_hc = q.n_hc;
     int64_t* __restrict__ offs = q.offs;
     int64_t* __restrict__ bsum = q.bsum;
+    // each thread scans kScanPer consecutive counts; whole runs move as
+    // 16-byte loads and stores (the arrays are 256-byte aligned)
     const int64_t base = (int64_t)bid * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    const bool whole = base + kScanPer <= n_hc;
     int64_t v[kScanPer];
     int64_t t = 0;
+    if (whole) {
 #pragma unroll
-    for (int i = 0; i < kScanPer; ++i) {
-        const int64_t h = base + i;
-        v[i] = h < n_hc ? (int64_t)n_h[h] : 0;
-        t += v[i];
+        for (int i = 0; i < kScanPer; i += 4) {
+            const int4 c = *reinterpret_cast<const int4*>(n_h + base + i);
+            v[i] = c.x;
+            v[i + 1] = c.y;
+            v[i + 2] = c.z;
+            v[i + 3] = c.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i) v[i] = base + i < n_hc ? (int64_t)n_h[base + i] : 0;
     }
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) t += v[i];
     int64_t total;
     int64_t run = block_excl_scan(t, &total);
+    int64_t o[kScanPer];
 #pragma unroll
     for (int i = 0; i < kScanPer; ++i) {
-        const int64_t h = base + i;
-        if (h < n_hc) offs[h] = run;
+        o[i] = run;
         run += v[i];
+    }
+    if (whole) {
+#pragma unroll
+        for (int i = 0; i < kScanPer; i += 2)
+            *reinterpret_cast<longlong2*>(offs + base + i) = make_longlong2(o[i], o[i + 1]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i)
+            if (base + i < n_hc) offs[base + i] = o[i];
     }
     if (threadIdx.x == 0) bsum[bid] = total;
 }
@@ -255,9 +276,13 @@ __global__ __launch_bounds__(kFixBlock) void k_edge_fixup(LaunchSet L)
 }
 
 // ---------------------------------------------------------------- training data
-// Sum of the per-workgroup partials in workgroup order; each partial holds the
-// numerator plane H[nbins] followed by the weight plane W[nbins].
-__global__ void k_hist_reduce(LaunchSet L)
+// Sum of the per-workgroup partials; each partial holds the numerator plane
+// H[nbins] followed by the weight plane W[nbins].  A workgroup takes
+// kHistTile consecutive values; its kHistGroups thread groups each sum every
+// kHistGroups-th partial (two interleaved chains), and the group sums are
+// added in group order -- a fixed order, independent of timing, with
+// kHistGroups times more loads in flight than one thread per value.
+__global__ __launch_bounds__(kHistTile * kHistGroups) void k_hist_reduce(LaunchSet L)
 {
     VP_REQ_PROLOGUE(L);
     const double* __restrict__ part = q.hist_part;
@@ -265,22 +290,31 @@ __global__ void k_hist_reduce(LaunchSet L)
     const int64_t lbins = (int64_t)q.hist_axes * q.n_g;
     double* __restrict__ H = q.H;
     double* __restrict__ W = q.W;
-    for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < 2 * nbins; i += (int64_t)nblk * blockDim.x) {
-        // four interleaved chains keep four loads in flight; fixed order
+    __shared__ double red[kHistGroups][kHistTile];
+    const int b = threadIdx.x % kHistTile, g = threadIdx.x / kHistTile;
+    const int64_t i = (int64_t)bid * kHistTile + b;
+    double s = 0.0;
+    if (i < 2 * nbins) {
         const int64_t j = i < nbins ? i : i - nbins;
         const int n_part = j < lbins ? q.grid : q.rec_chunks;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int p = 0;
-        for (; p + 3 < n_part; p += 4) {
-            a0 = a0 + part[(int64_t)(p + 0) * 2 * nbins + i];
-            a1 = a1 + part[(int64_t)(p + 1) * 2 * nbins + i];
-            a2 = a2 + part[(int64_t)(p + 2) * 2 * nbins + i];
-            a3 = a3 + part[(int64_t)(p + 3) * 2 * nbins + i];
+        double a0 = 0.0, a1 = 0.0;
+        int p = g;
+#pragma unroll 4
+        for (; p + kHistGroups < n_part; p += 2 * kHistGroups) {
+            a0 = a0 + part[(int64_t)p * 2 * nbins + i];
+            a1 = a1 + part[(int64_t)(p + kHistGroups) * 2 * nbins + i];
         }
-        for (; p < n_part; ++p) a0 = a0 + part[(int64_t)p * 2 * nbins + i];
-        const double s = (a0 + a1) + (a2 + a3);
-        if (i >= nbins) W[i - nbins] = s;
-        else H[i] = s;
+        if (p < n_part) a0 = a0 + part[(int64_t)p * 2 * nbins + i];
+        s = a0 + a1;
+    }
+    red[g][b] = s;
+    __syncthreads();
+    if (g == 0 && i < 2 * nbins) {
+        double tot = red[0][b];
+#pragma unroll
+        for (int k = 1; k < kHistGroups; ++k) tot = tot + red[k][b];
+        if (i >= nbins) W[i - nbins] = tot;
+        else H[i] = tot;
     }
 }
 
@@ -442,6 +476,7 @@ __global__ __launch_bounds__(kRedBlock) void k_est_partial(LaunchSet L)
     double* __restrict__ dh = q.dh;
     const int quarter = beta_quarter(beta);
     double I = 0.0, V = 0.0, Sd = 0.0;
+#pragma unroll 4
     for (int64_t h = (int64_t)bid * blockDim.x + threadIdx.x; h < n_hc; h += (int64_t)nblk * blockDim.x) {
         double m, var, d;
         const int32_t n = n_h[h];
@@ -500,10 +535,10 @@ __global__ __launch_bounds__(kRedBlock) void k_est_final(LaunchSet L)
     const int64_t n_hc = q.n_hc;
     const int32_t it_slot = q.slot;
     const int32_t n_discard = q.n_discard;
+    // thread t sums partials t, t + blockDim, ... (coalesced reads, fixed order)
     double a = 0.0, b = 0.0, c = 0.0;
-    const int per = (n_part + kRedBlock - 1) / kRedBlock;
-    const int p0 = threadIdx.x * per;
-    for (int p = p0; p < p0 + per && p < n_part; ++p) {
+#pragma unroll 8
+    for (int p = threadIdx.x; p < n_part; p += kRedBlock) {
         a = a + part[3 * p + 0];
         b = b + part[3 * p + 1];
         c = c + part[3 * p + 2];
@@ -607,6 +642,7 @@ __global__ __launch_bounds__(kRedBlock) void k_realloc(LaunchSet L)
     if (!(sumd > 0.0) || frozen(q)) return;
     unsigned long long nt = 0;
     const double first_visible = plus2 ? 1.0 : 3.0;
+#pragma unroll 4
     for (int64_t h = (int64_t)bid * blockDim.x + threadIdx.x; h < n_hc; h += (int64_t)nblk * blockDim.x) {
         const double qv = n_ev * (dh[h] / sumd);
         const double fl = floor(qv);
@@ -1074,7 +1110,7 @@ void enqueue_tail(const IterPlan& P, hipStream_t s)
 {
     launch(k_hist_records, P.rec, P.n_rec, kRecBlock, P.rec_lds, s);
     launch(k_edge_fixup, P.fixup, P.n_fixup, kFixBlock, 0, s);
-    launch(k_hist_reduce, P.hist, P.n_hist, 256, 0, s);
+    launch(k_hist_reduce, P.hist, P.n_hist, kHistTile * kHistGroups, 0, s);
     launch(k_est_partial, P.est, P.n_est, kRedBlock, 0, s);
     launch(k_est_final, P.one, P.n_one, kRedBlock, 0, s);
     launch(k_realloc, P.est, P.n_est, kRedBlock, 0, s);

@@ -5,12 +5,15 @@
 
 namespace vp {
 
-constexpr int kScanBlock = 1024;
-constexpr int kScanPer = 4;
+constexpr int kScanBlock = 256;
+constexpr int kScanPer = 16;
 constexpr int kScanTile = kScanBlock * kScanPer;
 static_assert(kScanTile == kOffsTile, "scan tile and offset blocks must agree");
 constexpr int kRedBlock = 256;
-constexpr int kRedMaxGrid = 16384;
+// training-data reduction: values per workgroup, and thread groups splitting the partials
+constexpr int kHistTile = 16;
+constexpr int kHistGroups = 16;
+constexpr int kRedMaxGrid = 4096;
 constexpr int kRefineBlock = 256;
 constexpr int kFixBlock = 1024;  // edge fix-up: one workgroup per request
 
