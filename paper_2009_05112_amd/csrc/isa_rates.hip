@@ -99,7 +99,9 @@ constexpr int kBins = 8192;
 
 __device__ __forceinline__ uint32_t lcg(uint32_t a) { return a * 1664525u + 1013904223u; }
 
-// kind 0: ds_add_f64, 1: ds_add_f32, 2: ds_add_u32, 3: read + 64-bit compare-and-swap of a double
+// kind 0: ds_add_f64, 1: ds_add_f32, 2: ds_add_u32, 3: read + 64-bit compare-and-swap of a double,
+// 4: ds_add_f64 with the 64 lanes of a wave inside one window of 128 bins (a new window per
+// update), the pattern of the outer axes, whose increments a wave's samples share
 template <int KIND>
 __global__ __launch_bounds__(1024) void k_lds_atomic(double* out, uint32_t seed)
 {
@@ -109,8 +111,12 @@ __global__ __launch_bounds__(1024) void k_lds_atomic(double* out, uint32_t seed)
     uint32_t a = lcg(threadIdx.x * 2654435761u + blockIdx.x * 97u + seed);
     for (int r = 0; r < kAtomRep; ++r) {
         a = lcg(a);
-        const uint32_t b = a >> 19;  // < kBins
-        if constexpr (KIND == 0) {
+        uint32_t b = a >> 19;  // < kBins
+        if constexpr (KIND == 4) {
+            const uint32_t w = __builtin_amdgcn_readfirstlane(lcg(a ^ (uint32_t)r));
+            b = ((w >> 19) & ~127u) | (a >> 25);  // window of 128 bins, < kBins
+        }
+        if constexpr (KIND == 0 || KIND == 4) {
             atomicAdd(reinterpret_cast<double*>(bins) + b, 1.0);
         } else if constexpr (KIND == 1) {
             atomicAdd(reinterpret_cast<float*>(bins) + b, 1.0f);
@@ -241,6 +247,7 @@ int main()
     run_atomic<1>("ds_add_f32", (double*)buf, e0, e1);
     run_atomic<2>("ds_add_u32", (double*)buf, e0, e1);
     run_atomic<3>("ds_cmpst_rtn_b64", (double*)buf, e0, e1);
+    run_atomic<4>("ds_add_f64 window", (double*)buf, e0, e1);
     void* table = nullptr;
     if (hipMalloc(&table, kBins * 8) != hipSuccess) return 1;
     (void)hipMemset(table, 0, kBins * 8);
