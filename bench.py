@@ -113,15 +113,20 @@ def run_split(B, W, ctx, n_ev, steps):
         gp = B.Problem(ctx, p.with_(n_iter=steps + 2), f)
         gp.iterate(2)
         r0 = gp.result()
+        gp.profile(True)
         gp.sync()
         t0 = time.perf_counter()
         gp.iterate(steps)
         gp.sync()
         dt = time.perf_counter() - t0
         r1 = gp.result()
+        k_ms, k_n = gp.kernel_time(0)
         gp.close()
-        out[prec] = {"samples_per_s": (r1["n_evals"] - r0["n_evals"]) / dt, "mean": r1["mean"],
-                     "sdev": r1["sdev"], "pull_vs_exact": (r1["mean"] - 1.0) / r1["sdev"]}
+        samples = r1["n_evals"] - r0["n_evals"]
+        k_s = k_ms / max(k_n, 1) / 1e3
+        frac = SLOTS_PER_SAMPLE[prec] * (samples / max(k_n, 1)) / k_s / PEAK_VALU_SLOTS
+        out[prec] = {"samples_per_s": samples / dt, "kernel_ms": 1e3 * k_s, "roofline_frac": frac,
+                     "mean": r1["mean"], "sdev": r1["sdev"], "pull_vs_exact": (r1["mean"] - 1.0) / r1["sdev"]}
     ref = out["fp64"]
     for prec in ("fp32_acc64", "fp32_neumaier"):
         o = out[prec]
