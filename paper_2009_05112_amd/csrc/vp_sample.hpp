@@ -637,7 +637,13 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
 
     const int lane = threadIdx.x & (kWave - 1);
     const int waves_per_block = blockDim.x / kWave;
-    const int64_t wave = (int64_t)bid * waves_per_block + (threadIdx.x / kWave);
+    // Share of the sample range: the waves of one workgroup take shares nblk
+    // apart, so that the workgroup's waves work on distant hypercubes.  (The
+    // waves of a workgroup share its LDS bins; waves on neighbouring
+    // hypercubes update the same bins of the outer axes at the same time,
+    // which the compare-and-swap of the compensated form pays for in retries.)
+    // Edge records are indexed by share, so they stay in sample order.
+    const int64_t wave = (int64_t)(threadIdx.x / kWave) * nblk + bid;
     const int64_t n_waves = (int64_t)nblk * waves_per_block;
     const int64_t* __restrict__ offs = a.offs;
     const int64_t* __restrict__ ob = a.obase;
