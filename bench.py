@@ -210,45 +210,54 @@ def run_batch(B, W, ctx, n_req):
     }
 
 
-def run_stream(B, W, ctx, n_req, load):
+def run_stream(B, W, ctx, n_req, loads):
+    """Poisson arrivals of the stream workload, served live, at the rates at
+    which the plain path (service times measured one by one, replayed as a
+    first-come-first-served queue) is loads[0], loads[1], ... busy; the first
+    load is the headline, the others are summarised under by_load."""
     import numpy as np
     reqs = W.served_stream(n_req=n_req, rate=1.0)
     unit = np.array([r.arrival for r in reqs])  # arrivals at rate 1
     svc, plain = run_plain(B, ctx, reqs)
-    rate = load / float(np.mean(svc))  # requests/s at which the plain path is `load` busy
-    arr = unit / rate
-    # plain: first come, first served, one at a time
-    fin, t = [], 0.0
-    for a, s_ in zip(arr, svc):
-        t = max(t, a) + s_
-        fin.append(t)
-    plain_lat = [f - a for f, a in zip(fin, arr)]
-    srv = B.Server(ctx, max_slots=n_req)
-    tickets = [None] * n_req
 
-    def producer():
-        t0 = time.perf_counter()
-        for i, r in enumerate(reqs):
-            d = arr[i] - (time.perf_counter() - t0)
-            if d > 0:
-                time.sleep(d)
-            tickets[i] = srv.submit(r.params, r.integrand)
+    def at_load(load):
+        rate = load / float(np.mean(svc))  # requests/s at which the plain path is `load` busy
+        arr = unit / rate
+        # plain: first come, first served, one at a time
+        fin, t = [], 0.0
+        for a, s_ in zip(arr, svc):
+            t = max(t, a) + s_
+            fin.append(t)
+        plain_lat = [f - a for f, a in zip(fin, arr)]
+        srv = B.Server(ctx, max_slots=n_req)
+        tickets = [None] * n_req
 
-    import threading
-    th = threading.Thread(target=producer)
-    th.start()
-    th.join()
-    served = [srv.wait(t) for t in tickets]
-    times = [srv.times(t) for t in tickets]
-    st = srv.stats()
-    srv.close()
-    lat = [t[2] - t[0] for t in times]
+        def producer():
+            t0 = time.perf_counter()
+            for i, r in enumerate(reqs):
+                d = arr[i] - (time.perf_counter() - t0)
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(r.params, r.integrand)
+
+        import threading
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        served = [srv.wait(t) for t in tickets]
+        times = [srv.times(t) for t in tickets]
+        st = srv.stats()
+        srv.close()
+        lat = [t[2] - t[0] for t in times]
+        return rate, served, times, st, lat, plain_lat
+
+    rate, served, times, st, lat, plain_lat = at_load(loads[0])
     samples = sum(r["n_evals"] for r in served)
     span = max(t[2] for t in times) - min(t[0] for t in times)
-    return {
+    out = {
         "workload": f"{n_req} correlated-Gaussian requests (cond 100, scale 0.05), D 3..21, N_ev 1e5..1e7 "
                     f"log-uniform, 5-20 iterations, N_g=1000, fp64; Poisson arrivals at {rate:.1f}/s "
-                    f"(plain path {100 * load:.0f}% busy)",
+                    f"(plain path {100 * loads[0]:.0f}% busy)",
         "rate_per_s": rate,
         "samples": samples,
         "served": {"span_s": span, "samples_per_s": samples / span, **lat_summary(lat),
@@ -259,6 +268,14 @@ def run_stream(B, W, ctx, n_req, load):
         "plain": {"busy_s": float(sum(svc)), "samples_per_s": samples / float(sum(svc)), **lat_summary(plain_lat)},
         "max_diff_in_sdev": agreement(served, plain),
     }
+    by = {}
+    for load in loads[1:]:
+        r_, sv_, _, st_, lat_, pl_ = at_load(load)
+        by[f"{load:g}"] = {"rate_per_s": r_, "served": {**lat_summary(lat_), "peak_active": st_["peak_active"]},
+                           "plain": lat_summary(pl_), "max_diff_in_sdev": agreement(sv_, plain)}
+    if by:
+        out["by_load"] = by
+    return out
 
 
 def main():
@@ -275,7 +292,8 @@ def main():
                          "(batched-integrand path), batch (served batch), stream)")
     ap.add_argument("--batch", type=int, default=4096, help="requests in the served batch")
     ap.add_argument("--stream", type=int, default=300, help="requests in the Poisson stream")
-    ap.add_argument("--load", type=float, default=0.8, help="plain-path utilisation that sets the stream rate")
+    ap.add_argument("--loads", default="0.8,0.5,0.95",
+                    help="plain-path utilisations that set the stream rates (comma list; the first is the headline)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a buffer of this many MiB on the GPU (a plain copy kernel of known "
                          "size, the reference for the HBM byte counters) and exit")
@@ -359,7 +377,7 @@ def main():
                         "batch_plain_p50_s": b["plain"]["p50_s"], "batch_plain_p99_s": b["plain"]["p99_s"]})
     if "stream" in sections:
         print("served stream ...", file=sys.stderr, flush=True)
-        serving["stream"] = t = run_stream(B, W, ctx, args.stream, args.load)
+        serving["stream"] = t = run_stream(B, W, ctx, args.stream, [float(x) for x in args.loads.split(",") if x])
         latency.update({"stream_p50_s": t["served"]["p50_s"], "stream_p99_s": t["served"]["p99_s"],
                         "stream_plain_p50_s": t["plain"]["p50_s"], "stream_plain_p99_s": t["plain"]["p99_s"]})
     if serving:
