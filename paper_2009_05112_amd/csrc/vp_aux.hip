@@ -278,11 +278,11 @@ __global__ __launch_bounds__(kFixBlock) void k_edge_fixup(LaunchSet L)
 // ---------------------------------------------------------------- training data
 // Sum of the per-workgroup partials; each partial holds the numerator plane
 // H[nbins] followed by the weight plane W[nbins].  A workgroup takes
-// kHistTile consecutive values; its kHistGroups thread groups each sum every
-// kHistGroups-th partial (two interleaved chains), and the group sums are
-// added in group order -- a fixed order, independent of timing, with
-// kHistGroups times more loads in flight than one thread per value.
-__global__ __launch_bounds__(kHistTile * kHistGroups) void k_hist_reduce(LaunchSet L)
+// kHistBlock / G consecutive values; each of its G thread groups sums every
+// G-th partial (two interleaved chains), and the group sums are added in
+// group order -- a fixed order, independent of timing, with G times more
+// loads in flight than one thread per value.
+__global__ __launch_bounds__(kHistBlock) void k_hist_reduce(LaunchSet L)
 {
     VP_REQ_PROLOGUE(L);
     const double* __restrict__ part = q.hist_part;
@@ -290,9 +290,11 @@ __global__ __launch_bounds__(kHistTile * kHistGroups) void k_hist_reduce(LaunchS
     const int64_t lbins = (int64_t)q.hist_axes * q.n_g;
     double* __restrict__ H = q.H;
     double* __restrict__ W = q.W;
-    __shared__ double red[kHistGroups][kHistTile];
-    const int b = threadIdx.x % kHistTile, g = threadIdx.x / kHistTile;
-    const int64_t i = (int64_t)bid * kHistTile + b;
+    __shared__ double red[kHistBlock];
+    const int G = hist_groups(max(q.grid, q.rec_chunks));
+    const int tile = kHistBlock / G;
+    const int b = threadIdx.x % tile, g = threadIdx.x / tile;
+    const int64_t i = (int64_t)bid * tile + b;
     double s = 0.0;
     if (i < 2 * nbins) {
         const int64_t j = i < nbins ? i : i - nbins;
@@ -300,19 +302,18 @@ __global__ __launch_bounds__(kHistTile * kHistGroups) void k_hist_reduce(LaunchS
         double a0 = 0.0, a1 = 0.0;
         int p = g;
 #pragma unroll 4
-        for (; p + kHistGroups < n_part; p += 2 * kHistGroups) {
+        for (; p + G < n_part; p += 2 * G) {
             a0 = a0 + part[(int64_t)p * 2 * nbins + i];
-            a1 = a1 + part[(int64_t)(p + kHistGroups) * 2 * nbins + i];
+            a1 = a1 + part[(int64_t)(p + G) * 2 * nbins + i];
         }
         if (p < n_part) a0 = a0 + part[(int64_t)p * 2 * nbins + i];
         s = a0 + a1;
     }
-    red[g][b] = s;
+    red[threadIdx.x] = s;
     __syncthreads();
     if (g == 0 && i < 2 * nbins) {
-        double tot = red[0][b];
-#pragma unroll
-        for (int k = 1; k < kHistGroups; ++k) tot = tot + red[k][b];
+        double tot = red[b];
+        for (int k = 1; k < G; ++k) tot = tot + red[k * tile + b];
         if (i >= nbins) W[i - nbins] = tot;
         else H[i] = tot;
     }
@@ -1110,7 +1111,7 @@ void enqueue_tail(const IterPlan& P, hipStream_t s)
 {
     launch(k_hist_records, P.rec, P.n_rec, kRecBlock, P.rec_lds, s);
     launch(k_edge_fixup, P.fixup, P.n_fixup, kFixBlock, 0, s);
-    launch(k_hist_reduce, P.hist, P.n_hist, kHistTile * kHistGroups, 0, s);
+    launch(k_hist_reduce, P.hist, P.n_hist, kHistBlock, 0, s);
     launch(k_est_partial, P.est, P.n_est, kRedBlock, 0, s);
     launch(k_est_final, P.one, P.n_one, kRedBlock, 0, s);
     launch(k_realloc, P.est, P.n_est, kRedBlock, 0, s);

@@ -10,9 +10,17 @@ constexpr int kScanPer = 16;
 constexpr int kScanTile = kScanBlock * kScanPer;
 static_assert(kScanTile == kOffsTile, "scan tile and offset blocks must agree");
 constexpr int kRedBlock = 256;
-// training-data reduction: values per workgroup, and thread groups splitting the partials
-constexpr int kHistTile = 16;
-constexpr int kHistGroups = 16;
+// Training-data reduction: kHistBlock threads per workgroup, split into G
+// thread groups that each sum every G-th partial of kHistBlock / G values; G
+// grows with the number of partials (up to 16, for about 16 partials per
+// group), so that few partials do not leave most threads idle.
+constexpr int kHistBlock = 256;
+__host__ __device__ inline int hist_groups(int n_part)
+{
+    int g = 1;
+    while (g < 16 && g * 16 < n_part) g <<= 1;
+    return g;
+}
 constexpr int kRedMaxGrid = 4096;
 constexpr int kRefineBlock = 256;
 constexpr int kFixBlock = 1024;  // edge fix-up: one workgroup per request

@@ -66,7 +66,12 @@ public:
         int n_scan = 0, n_one = 0, n_hist = 0, n_rec = 0, n_fix = 0, n_est = 0, n_ref = 0;
         Pending ps = add_set([](const ReqArgs& q) { return (int)scan_blocks(q.n_hc); }, &n_scan);
         Pending po = add_set([](const ReqArgs&) { return 1; }, &n_one);
-        Pending ph = add_set([](const ReqArgs& q) { return (int)((2LL * q.dim * q.n_g + kHistTile - 1) / kHistTile); }, &n_hist);
+        Pending ph = add_set(
+            [](const ReqArgs& q) {
+                const int tile = kHistBlock / hist_groups(std::max(q.grid, q.rec_chunks));
+                return (int)((2LL * q.dim * q.n_g + tile - 1) / tile);
+            },
+            &n_hist);
         Pending prc = add_set(
             [](const ReqArgs& q) { return q.hist_axes < q.dim ? q.rec_chunks * q.rec_slices : 0; }, &n_rec);
         Pending pf = add_set([](const ReqArgs&) { return 1; }, &n_fix);
