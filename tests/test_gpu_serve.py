@@ -29,13 +29,16 @@ RTOL = {"mean": 1e-12, "sdev": 1e-12, "chi2": 1e-9}
 
 def small_mix():
     """Gaussian mixtures of the served-batch shape at small N_ev, correlated
-    Gaussians of the stream shape, and the two split precisions."""
+    Gaussians of the stream shape, the two split precisions, and the D=8
+    workload in FP64 (map partly staged in LDS)."""
     reqs = [(r.params, r.integrand) for r in
             W.served_batch(n_req=10, seed=3, nev_log=(3.5, 4.7), n_iter=4, n_g=500)]
     for r in W.served_stream(n_req=4, rate=0.0, seed=5, nev_log=(4.0, 4.5), it_range=(2, 4), n_g=300):
         reqs.append((r.params, r.integrand))
     p, f = W.cfg_diag_d8(n_ev=60_000, precision="fp32_acc64")
     reqs.append((p.with_(n_iter=3, seed=77), f))
+    p, f = W.cfg_diag_d8(n_ev=50_000)  # FP64 at N_g = 1000: two innermost map axes in LDS
+    reqs.append((p.with_(n_iter=3, seed=82), f))
     p, f = W.cfg_diag_d8(n_ev=40_000, precision="fp32_neumaier")
     reqs.append((p.with_(n_iter=3, seed=78, hist_mode="literal"), f))
     p, f = W.cfg_small_d4()
