@@ -33,11 +33,12 @@ TABLES += [
     ("vp_sample_fp64_batch.hip", "sample_entry_fp64_batch_acc(int dim, int map, bool rec)", "P_FP64",
      [(None, "K_BATCH_ACC", range(1, 25), "entry_for_global", 0)],
      "double precision, batched integrand (accumulation of the user's values), D = 1..24",
-     ["SampleEntry sample_entry_fp64_batch_gen(int dim)",
+     ["SampleEntry sample_entry_fp64_batch_gen(int dim, int map)",
       "{",
       "    SampleEntry e = {nullptr, nullptr, 0};",
       "    switch (dim) {"] +
-     [f"    case {d}: e = make_entry<{d}, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0>(); break;" for d in range(1, 25)] +
+     [f"    case {d}: e = map == MAP_LDS ? make_entry<{d}, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0>() "
+      f": make_entry<{d}, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0>(); break;" for d in range(1, 25)] +
      ["    default: break;", "    }", "    return e;", "}", ""]),
     ("vp_sample_fp32acc_generic.hip", "sample_entry_fp32acc_generic(int dim, int map, bool rec)",
      "P_FP32_ACC64", [(None, "0", range(1, 17), "entry_for_global", 0)],
@@ -59,11 +60,12 @@ TABLES += [
     ("vp_sample_fp64_batch_mix.hip", "sample_entry_fp64_batch_acc_mix(int dim, int map, bool rec)", "P_FP64",
      [(None, "K_BATCH_ACC", range(1, 25), "entry_for_global", "0, true")],
      "double precision, batched integrand (accumulation of the user's values), mixed stratification, D = 1..24",
-     ["SampleEntry sample_entry_fp64_batch_gen_mix(int dim)",
+     ["SampleEntry sample_entry_fp64_batch_gen_mix(int dim, int map)",
       "{",
       "    SampleEntry e = {nullptr, nullptr, 0};",
       "    switch (dim) {"] +
-     [f"    case {d}: e = make_entry<{d}, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;"
+     [f"    case {d}: e = map == MAP_LDS ? make_entry<{d}, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() "
+      f": make_entry<{d}, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;"
       for d in range(1, 25)] +
      ["    default: break;", "    }", "    return e;", "}", ""]),
 ]

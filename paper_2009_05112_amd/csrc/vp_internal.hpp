@@ -217,14 +217,14 @@ VP_DECL_GAUSS(fp32neu)
 SampleEntry sample_entry_fp64_corr(int dim, int map, bool rec);
 SampleEntry sample_entry_fp64_generic(int dim, int map, bool rec);
 SampleEntry sample_entry_fp32acc_generic(int dim, int map, bool rec);
-SampleEntry sample_entry_fp64_batch_gen(int dim);
+SampleEntry sample_entry_fp64_batch_gen(int dim, int map);
 SampleEntry sample_entry_fp64_batch_acc(int dim, int map, bool rec);
 SampleEntry sample_entry_fp32neu_generic(int dim, int map, bool rec);
 // mixed stratification (per-axis counts): generic kinds and batched integrands
 SampleEntry sample_entry_fp64_generic_mix(int dim, int map, bool rec);
 SampleEntry sample_entry_fp32acc_generic_mix(int dim, int map, bool rec);
 SampleEntry sample_entry_fp32neu_generic_mix(int dim, int map, bool rec);
-SampleEntry sample_entry_fp64_batch_gen_mix(int dim);
+SampleEntry sample_entry_fp64_batch_gen_mix(int dim, int map);
 SampleEntry sample_entry_fp64_batch_acc_mix(int dim, int map, bool rec);
 
 // sampling kernels' LDS needs (bytes) for histogram and map

@@ -602,9 +602,11 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     sh->gen_grid = 0;
     sh->gen_entry = SampleEntry{nullptr, nullptr, 0};
     if (batch) {
-        sh->gen_entry = sh->mix ? sample_entry_fp64_batch_gen_mix(D) : sample_entry_fp64_batch_gen(D);
+        // the generate mode holds no training data: its map goes to LDS whenever it fits
+        const int gmap = map_lds_bytes(VP_FP64, D, NG, MAP_LDS) + fcb <= ctx->lds_max ? MAP_LDS : MAP_GLOBAL;
+        sh->gen_entry = sh->mix ? sample_entry_fp64_batch_gen_mix(D, gmap) : sample_entry_fp64_batch_gen(D, gmap);
         if (!sh->gen_entry.launch) return fail(VP_ERR_INVALID_ARG, "no batched-integrand kernel for dim %d", D);
-        sh->gen_lds = fc_lds_offset(0, false, VP_FP64, D, NG) + fc_lds_bytes(VP_FP64, VP_F_BATCH, D);
+        sh->gen_lds = fc_lds_offset(0, gmap, VP_FP64, D, NG) + fc_lds_bytes(VP_FP64, VP_F_BATCH, D);
         const int gocc = std::max(1, cached_occupancy(ctx->device, sh->gen_entry, sh->gen_entry.block, sh->gen_lds));
         const int64_t gwpb = sh->gen_entry.block / kWave;
         const int64_t guseful = std::max<int64_t>(1, n_tot_max / ((int64_t)kWave * 16));

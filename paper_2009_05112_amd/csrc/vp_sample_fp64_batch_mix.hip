@@ -4,34 +4,34 @@
 
 namespace vp {
 
-SampleEntry sample_entry_fp64_batch_gen_mix(int dim)
+SampleEntry sample_entry_fp64_batch_gen_mix(int dim, int map)
 {
     SampleEntry e = {nullptr, nullptr, 0};
     switch (dim) {
-    case 1: e = make_entry<1, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 2: e = make_entry<2, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 3: e = make_entry<3, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 4: e = make_entry<4, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 5: e = make_entry<5, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 6: e = make_entry<6, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 7: e = make_entry<7, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 8: e = make_entry<8, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 9: e = make_entry<9, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 10: e = make_entry<10, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 11: e = make_entry<11, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 12: e = make_entry<12, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 13: e = make_entry<13, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 14: e = make_entry<14, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 15: e = make_entry<15, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 16: e = make_entry<16, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 17: e = make_entry<17, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 18: e = make_entry<18, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 19: e = make_entry<19, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 20: e = make_entry<20, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 21: e = make_entry<21, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 22: e = make_entry<22, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 23: e = make_entry<23, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
-    case 24: e = make_entry<24, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 1: e = map == MAP_LDS ? make_entry<1, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<1, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 2: e = map == MAP_LDS ? make_entry<2, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<2, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 3: e = map == MAP_LDS ? make_entry<3, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<3, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 4: e = map == MAP_LDS ? make_entry<4, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<4, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 5: e = map == MAP_LDS ? make_entry<5, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<5, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 6: e = map == MAP_LDS ? make_entry<6, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<6, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 7: e = map == MAP_LDS ? make_entry<7, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<7, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 8: e = map == MAP_LDS ? make_entry<8, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<8, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 9: e = map == MAP_LDS ? make_entry<9, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<9, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 10: e = map == MAP_LDS ? make_entry<10, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<10, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 11: e = map == MAP_LDS ? make_entry<11, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<11, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 12: e = map == MAP_LDS ? make_entry<12, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<12, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 13: e = map == MAP_LDS ? make_entry<13, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<13, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 14: e = map == MAP_LDS ? make_entry<14, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<14, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 15: e = map == MAP_LDS ? make_entry<15, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<15, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 16: e = map == MAP_LDS ? make_entry<16, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<16, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 17: e = map == MAP_LDS ? make_entry<17, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<17, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 18: e = map == MAP_LDS ? make_entry<18, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<18, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 19: e = map == MAP_LDS ? make_entry<19, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<19, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 20: e = map == MAP_LDS ? make_entry<20, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<20, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 21: e = map == MAP_LDS ? make_entry<21, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<21, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 22: e = map == MAP_LDS ? make_entry<22, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<22, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 23: e = map == MAP_LDS ? make_entry<23, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<23, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
+    case 24: e = map == MAP_LDS ? make_entry<24, P_FP64, MAP_LDS, K_BATCH_GEN, false, 0, true>() : make_entry<24, P_FP64, MAP_GLOBAL, K_BATCH_GEN, false, 0, true>(); break;
     default: break;
     }
     return e;
