@@ -371,6 +371,13 @@ __global__ void k_init(InitArgs a)
 {
     const int64_t nm = (int64_t)a.dim * (a.n_g + 1);
     const int64_t n = max(nm, max(a.n_hc, a.nbins));
+    if (a.head_src) {
+        const uint64_t* __restrict__ src = reinterpret_cast<const uint64_t*>(a.head_src);
+        uint64_t* __restrict__ dst = reinterpret_cast<uint64_t*>(a.head_dst);
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.head_bytes / 8;
+             i += (int64_t)gridDim.x * blockDim.x)
+            dst[i] = src[i];
+    }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         if (i < nm) {
             const int d = (int)(i / (a.n_g + 1)), k = (int)(i - (int64_t)d * (a.n_g + 1));

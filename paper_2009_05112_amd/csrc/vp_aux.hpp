@@ -42,6 +42,12 @@ inline int64_t scan_blocks(int64_t n_hc) { return (n_hc + kScanTile - 1) / kScan
 // (FP64 and its FP32 copy), the uniform allocation n0, zero sums.
 struct InitArgs {
     const double* bounds;  // [2][dim]: lower, upper
+    // when head_src is set, the kernel also copies head_bytes (a multiple of
+    // 8) from head_src (host memory the device can read) to head_dst, and
+    // bounds points into head_src
+    const char* head_src;
+    char* head_dst;
+    int64_t head_bytes;
     double* map;
     float* map32;
     int32_t* n_h;

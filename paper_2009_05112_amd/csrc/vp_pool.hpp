@@ -90,6 +90,47 @@ public:
     {
         for (Slab& s : slabs_) (void)hipFree(s.base);
         slabs_.clear();
+        for (Chunk& c : chunks_) (void)hipHostFree(c.base);
+        chunks_.clear();
+        chunk_ = 0;
+        chunk_off_ = 0;
+    }
+
+    // Pinned host memory holding the initial image of admitted requests'
+    // state, which the initialisation kernel reads directly (*dev: the same
+    // memory's device address).  Valid until reset_stage(), which the caller
+    // invokes only with those kernels complete; nullptr when no pinned memory
+    // can be had.
+    char* stage(size_t bytes, const char** dev)
+    {
+        bytes = round_up(bytes ? bytes : 1);
+        while (chunk_ < chunks_.size() && chunk_off_ + bytes > chunks_[chunk_].size) {
+            ++chunk_;
+            chunk_off_ = 0;
+        }
+        if (chunk_ == chunks_.size()) {
+            Chunk c;
+            c.size = bytes > kStageChunk ? bytes : kStageChunk;
+            if (hipHostMalloc((void**)&c.base, c.size, hipHostMallocDefault) != hipSuccess) return nullptr;
+            void* d = nullptr;
+            if (hipHostGetDevicePointer(&d, c.base, 0) != hipSuccess) {
+                (void)hipHostFree(c.base);
+                return nullptr;
+            }
+            c.dev = (const char*)d;
+            chunks_.push_back(c);
+            chunk_off_ = 0;
+        }
+        char* p = chunks_[chunk_].base + chunk_off_;
+        *dev = chunks_[chunk_].dev + chunk_off_;
+        chunk_off_ += bytes;
+        return p;
+    }
+    bool stage_used() const { return chunk_ > 0 || chunk_off_ > 0; }
+    void reset_stage()
+    {
+        chunk_ = 0;
+        chunk_off_ = 0;
     }
 
     size_t reserved() const
@@ -124,6 +165,15 @@ private:
 
     std::vector<Slab> slabs_;
     size_t slab_ = size_t(1) << 30;
+
+    struct Chunk {
+        char* base = nullptr;
+        const char* dev = nullptr;
+        size_t size = 0;
+    };
+    static constexpr size_t kStageChunk = size_t(16) << 20;
+    std::vector<Chunk> chunks_;
+    size_t chunk_ = 0, chunk_off_ = 0;
 };
 
 }  // namespace vp

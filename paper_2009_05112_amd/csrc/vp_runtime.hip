@@ -827,21 +827,34 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
     // bounds) is staged on the host and copied at once; the initial map
     // (Sec. 2.3: a uniform grid), the uniform allocation and the zero sums are
     // written by one kernel
-    std::vector<char>& head = p->staging;
-    head.assign(lay.head_end, 0);
-    memcpy(head.data() + lay.f_d, &p->fh, sizeof(IntegrandDev));
+    // (a served request's image goes to the pool's pinned staging memory,
+    // else to a host vector kept with the problem)
+    const char* head_dev = nullptr;
+    char* head = pool ? pool->stage(lay.head_end, &head_dev) : nullptr;
+    if (head) {
+        memset(head, 0, lay.head_end);
+    } else {
+        p->staging.assign(lay.head_end, 0);
+        head = p->staging.data();
+    }
+    memcpy(head + lay.f_d, &p->fh, sizeof(IntegrandDev));
     fill_req(p);
-    memcpy(head.data() + lay.d_req, &p->req, sizeof(ReqArgs));
-    memcpy(head.data() + lay.bounds, p->lower.data(), D * sizeof(double));
-    memcpy(head.data() + lay.bounds + D * sizeof(double), p->upper.data(), D * sizeof(double));
-    write_constants(p->fh, P->precision, D, NG, sh.nst_ax, head.data() + lay.fc);
+    memcpy(head + lay.d_req, &p->req, sizeof(ReqArgs));
+    memcpy(head + lay.bounds, p->lower.data(), D * sizeof(double));
+    memcpy(head + lay.bounds + D * sizeof(double), p->upper.data(), D * sizeof(double));
+    write_constants(p->fh, P->precision, D, NG, sh.nst_ax, head + lay.fc);
     hipStream_t sm = ctx->stream;
     int64_t n0 = P->n_ev / nhc;
     if (n0 < 2) n0 = 2;
-    e = hipMemcpyAsync(p->arena, head.data(), head.size(), hipMemcpyHostToDevice, sm);
+    // a pinned image is read by the initialisation kernel itself (one launch
+    // per request instead of a copy and a launch)
+    if (!head_dev) e = hipMemcpyAsync(p->arena, head, lay.head_end, hipMemcpyHostToDevice, sm);
     if (e == hipSuccess) {
         InitArgs ia;
-        ia.bounds = (const double*)(base + lay.bounds);
+        ia.head_src = head_dev;
+        ia.head_dst = head_dev ? p->arena : nullptr;
+        ia.head_bytes = head_dev ? (int64_t)lay.head_end : 0;
+        ia.bounds = (const double*)(head_dev ? head_dev + lay.bounds : base + lay.bounds);
         ia.map = p->map;
         ia.map32 = p->map32;
         ia.n_h = p->n_h;

@@ -248,6 +248,12 @@ static void scheduler(vp_server* s)
         }
         bool changed = false;
         const auto t_adm = std::chrono::steady_clock::now();
+        if (!admit.empty() && s->pool.stage_used()) {
+            // the previous admissions' initial copies read the pinned staging
+            // memory; it is reused once they are complete
+            (void)hipStreamSynchronize(s->ctx->stream);
+            s->pool.reset_stage();
+        }
         for (ServedReq* r : admit) {
             vp_status st = problem_create(s->ctx, &r->P, &r->f, kServeSamplesPerWG, &s->pool, &r->prob);
             if (st != VP_OK) {
