@@ -3,6 +3,8 @@
 // and combination, reallocation, and map refinement.
 #include "vp_aux.hpp"
 
+#include <algorithm>
+
 namespace vp {
 
 // ---------------------------------------------------------------- helpers
@@ -1104,12 +1106,36 @@ void enqueue_head(const IterPlan& P, hipStream_t s)
     launch(k_scan_top, P.one, P.n_one, kScanBlock, 0, s);
 }
 
-void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin, hipEvent_t sample_end)
+void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin, hipEvent_t sample_end,
+                       const SideStreams* side)
 {
     enqueue_head(P, s);
     if (sample_begin) (void)hipEventRecord(sample_begin, s);
-    for (int g = 0; g < P.n_groups; ++g)
-        P.groups[g].entry.launch(P.groups[g].L, P.groups[g].blocks, P.groups[g].entry.block, P.groups[g].lds, s);
+    const int ns = side ? std::min(side->n, P.n_groups - 1) : 0;
+    if (ns > 0) {
+        // groups go to the stream with the fewest workgroups so far, largest first
+        (void)hipEventRecord(side->fork, s);
+        for (int i = 0; i < ns; ++i) (void)hipStreamWaitEvent(side->st[i], side->fork, 0);
+        int order[kMaxGroups];
+        for (int g = 0; g < P.n_groups; ++g) order[g] = g;
+        std::sort(order, order + P.n_groups, [&](int a, int b) { return P.groups[a].blocks > P.groups[b].blocks; });
+        int64_t load[kMaxSide + 1] = {};
+        for (int o = 0; o < P.n_groups; ++o) {
+            const SampleGroup& G = P.groups[order[o]];
+            int best = 0;
+            for (int i = 1; i <= ns; ++i)
+                if (load[i] < load[best]) best = i;
+            load[best] += G.blocks;
+            G.entry.launch(G.L, G.blocks, G.entry.block, G.lds, best == 0 ? s : side->st[best - 1]);
+        }
+        for (int i = 0; i < ns; ++i) {
+            (void)hipEventRecord(side->join[i], side->st[i]);
+            (void)hipStreamWaitEvent(s, side->join[i], 0);
+        }
+    } else {
+        for (int g = 0; g < P.n_groups; ++g)
+            P.groups[g].entry.launch(P.groups[g].L, P.groups[g].blocks, P.groups[g].entry.block, P.groups[g].lds, s);
+    }
     if (sample_end) (void)hipEventRecord(sample_end, s);
     enqueue_tail(P, s);
 }

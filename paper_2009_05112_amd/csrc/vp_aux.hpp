@@ -126,9 +126,21 @@ struct IterPlan {
 // lds_max: the device's LDS per workgroup); done when a context is created,
 // so enqueue_iteration makes no such call and can be captured into a graph.
 hipError_t aux_init(size_t lds_max);
+// Streams beside the main one on which the sampling launches of different
+// kernel groups run side by side: they fork from the main stream and join it
+// again through events, so the iteration can also be captured into a graph
+// (as parallel branches).
+constexpr int kMaxSide = 3;
+struct SideStreams {
+    int n = 0;
+    hipStream_t st[kMaxSide] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kMaxSide] = {};
+};
 // Enqueues one iteration of every request of the plan; when given, the two
-// events bracket the sampling launches.
-void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin, hipEvent_t sample_end);
+// events bracket the sampling launches, and side streams take some of them.
+void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin, hipEvent_t sample_end,
+                       const SideStreams* side = nullptr);
 // The parts of an iteration before the sampling launches (allocation scan)
 // and after them (training data, estimate, reallocation, refinement).
 void enqueue_head(const IterPlan& P, hipStream_t s);

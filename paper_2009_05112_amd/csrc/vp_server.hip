@@ -85,6 +85,7 @@ struct vp_server {
     bool plan_valid = false;
     int64_t plan_steps = 0;  // steps run with the current plan
     hipGraphExec_t gexec = nullptr;
+    SideStreams side;  // sampling launches of different kernel groups side by side
     std::chrono::steady_clock::time_point t0;
     // gather of finished requests' estimates: pointers and results, host
     // (pinned) and device copies, max_slots entries each
@@ -147,6 +148,38 @@ static void free_gather(vp_server* s)
     s->d_out = nullptr;
 }
 
+// Side streams for the sampling launches (default priority, like the main
+// stream); without them the launches run one after another.
+static void make_side(vp_server* s)
+{
+    SideStreams& d = s->side;
+    d.n = 0;
+    if (hipEventCreateWithFlags(&d.fork, hipEventDisableTiming) != hipSuccess) {
+        d.fork = nullptr;
+        return;
+    }
+    for (int i = 0; i < kMaxSide; ++i) {
+        if (hipStreamCreateWithFlags(&d.st[i], hipStreamNonBlocking) != hipSuccess) break;
+        if (hipEventCreateWithFlags(&d.join[i], hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamDestroy(d.st[i]);
+            break;
+        }
+        d.n = i + 1;
+    }
+}
+
+static void free_side(vp_server* s)
+{
+    SideStreams& d = s->side;
+    for (int i = 0; i < d.n; ++i) {
+        (void)hipStreamSynchronize(d.st[i]);
+        (void)hipStreamDestroy(d.st[i]);
+        (void)hipEventDestroy(d.join[i]);
+    }
+    if (d.fork) (void)hipEventDestroy(d.fork);
+    d = SideStreams();
+}
+
 static void drop_graph(vp_server* s)
 {
     if (s->gexec) {
@@ -166,7 +199,7 @@ static bool run_step(vp_server* s)
             const auto t0 = std::chrono::steady_clock::now();
             hipGraph_t g = nullptr;
             if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
-            enqueue_iteration(s->plan, st, nullptr, nullptr);
+            enqueue_iteration(s->plan, st, nullptr, nullptr, &s->side);
             if (hipStreamEndCapture(st, &g) != hipSuccess) return false;
             hipError_t e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
@@ -186,7 +219,7 @@ static bool run_step(vp_server* s)
         return ok;
     }
     const auto t0 = std::chrono::steady_clock::now();
-    enqueue_iteration(s->plan, st, nullptr, nullptr);
+    enqueue_iteration(s->plan, st, nullptr, nullptr, &s->side);
     if (hipGetLastError() != hipSuccess) return false;
     const bool ok = hipStreamSynchronize(st) == hipSuccess;
     s->ss.t_step += s->tsec(t0);
@@ -393,6 +426,8 @@ vp_status vp_server_create(vp_ctx* ctx, size_t mem_budget_bytes, int32_t max_slo
         delete s;
         return fail(VP_ERR_OOM, "allocating the server's result buffers");
     }
+    (void)hipSetDevice(own->device);
+    make_side(s);
     s->budget = mem_budget_bytes;
     // slabs of at most 1 GiB and a quarter of the budget
     s->pool.set_slab_bytes(std::min<size_t>(size_t(1) << 30, mem_budget_bytes / 4));
@@ -545,6 +580,7 @@ vp_status vp_server_destroy(vp_server* s)
         delete kv.second;
     }
     (void)hipStreamSynchronize(s->ctx->stream);
+    free_side(s);
     s->pool.release_all();
     free_gather(s);
     vp_ctx_destroy(s->ctx);
