@@ -1137,18 +1137,35 @@ void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin
             P.groups[g].entry.launch(P.groups[g].L, P.groups[g].blocks, P.groups[g].entry.block, P.groups[g].lds, s);
     }
     if (sample_end) (void)hipEventRecord(sample_end, s);
-    enqueue_tail(P, s);
+    enqueue_tail(P, s, side);
 }
 
-void enqueue_tail(const IterPlan& P, hipStream_t s)
+void enqueue_tail(const IterPlan& P, hipStream_t s, const SideStreams* side)
 {
+    const size_t refine_lds = (size_t)(4 * P.max_ng + 3) * sizeof(double);
+    if (side && side->n > 0) {
+        hipStream_t m = side->st[0];
+        (void)hipEventRecord(side->fork, s);
+        (void)hipStreamWaitEvent(m, side->fork, 0);
+        launch(k_hist_records, P.rec, P.n_rec, kRecBlock, P.rec_lds, m);
+        launch(k_hist_reduce, P.hist, P.n_hist, kHistBlock, 0, m);
+        launch(k_refine, P.refine, P.n_refine, kRefineBlock, refine_lds, m);
+        (void)hipEventRecord(side->join[0], m);
+        launch(k_edge_fixup, P.fixup, P.n_fixup, kFixBlock, 0, s);
+        launch(k_est_partial, P.est, P.n_est, kRedBlock, 0, s);
+        launch(k_est_final, P.one, P.n_one, kRedBlock, 0, s);
+        launch(k_realloc, P.est, P.n_est, kRedBlock, 0, s);
+        (void)hipStreamWaitEvent(s, side->join[0], 0);
+        launch(k_advance, P.one, P.n_one, 64, 0, s);
+        return;
+    }
     launch(k_hist_records, P.rec, P.n_rec, kRecBlock, P.rec_lds, s);
     launch(k_edge_fixup, P.fixup, P.n_fixup, kFixBlock, 0, s);
     launch(k_hist_reduce, P.hist, P.n_hist, kHistBlock, 0, s);
     launch(k_est_partial, P.est, P.n_est, kRedBlock, 0, s);
     launch(k_est_final, P.one, P.n_one, kRedBlock, 0, s);
     launch(k_realloc, P.est, P.n_est, kRedBlock, 0, s);
-    launch(k_refine, P.refine, P.n_refine, kRefineBlock, (size_t)(4 * P.max_ng + 3) * sizeof(double), s);
+    launch(k_refine, P.refine, P.n_refine, kRefineBlock, refine_lds, s);
     launch(k_advance, P.one, P.n_one, 64, 0, s);
 }
 

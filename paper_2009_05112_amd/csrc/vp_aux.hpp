@@ -142,8 +142,11 @@ struct SideStreams {
 void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin, hipEvent_t sample_end,
                        const SideStreams* side = nullptr);
 // The parts of an iteration before the sampling launches (allocation scan)
-// and after them (training data, estimate, reallocation, refinement).
+// and after them (training data, estimate, reallocation, refinement).  With a
+// side stream, the tail's two independent chains run side by side: training
+// data and map refinement on the first side stream, edge fix-up, estimate and
+// reallocation on s; both join before the iteration counters advance.
 void enqueue_head(const IterPlan& P, hipStream_t s);
-void enqueue_tail(const IterPlan& P, hipStream_t s);
+void enqueue_tail(const IterPlan& P, hipStream_t s, const SideStreams* side = nullptr);
 
 }  // namespace vp

@@ -436,6 +436,16 @@ vp_status vp_ctx_create(int device, void* hip_stream, vp_ctx** out)
             return fail(VP_ERR_DEVICE, "configuring kernels: %s", hipGetErrorString(e));
         }
     }
+    // the side stream of the iteration tail (optional: without it the tail
+    // runs in one stream)
+    if (hipEventCreateWithFlags(&c->side.fork, hipEventDisableTiming) == hipSuccess) {
+        if (hipStreamCreateWithFlags(&c->side.st[0], hipStreamNonBlocking) == hipSuccess) {
+            if (hipEventCreateWithFlags(&c->side.join[0], hipEventDisableTiming) == hipSuccess) c->side.n = 1;
+            else (void)hipStreamDestroy(c->side.st[0]);
+        }
+    } else {
+        c->side.fork = nullptr;
+    }
     *out = c;
     return VP_OK;
 }
@@ -1030,14 +1040,14 @@ vp_status vp_iterate(vp_problem* p, int32_t n_iter)
         if (p->prof) {
             hipEvent_t e0 = take_event(p), e1 = take_event(p), e2 = take_event(p), e3 = take_event(p);
             VP_HIP(hipEventRecord(e2, s));
-            enqueue_iteration(p->plan, s, e0, e1);
+            enqueue_iteration(p->plan, s, e0, e1, &p->ctx->side);
             VP_HIP(hipEventRecord(e3, s));
             p->ev_pending.push_back(e0);
             p->ev_pending.push_back(e1);
             p->ev_pending.push_back(e2);
             p->ev_pending.push_back(e3);
         } else {
-            enqueue_iteration(p->plan, s, nullptr, nullptr);
+            enqueue_iteration(p->plan, s, nullptr, nullptr, &p->ctx->side);
         }
         VP_HIP(hipGetLastError());
         p->it += 1;

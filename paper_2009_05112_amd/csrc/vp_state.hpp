@@ -30,6 +30,10 @@ struct vp_ctx {
     int n_cu;
     size_t lds_max;
     int refs;
+    // one side stream (forked from and joined to `stream` with events) on
+    // which an iteration's map refinement chain runs beside its estimate and
+    // reallocation chain; n = 0 when it could not be created
+    vp::SideStreams side;
 };
 
 inline void ctx_release(vp_ctx* c)
@@ -40,6 +44,12 @@ inline void ctx_release(vp_ctx* c)
         (void)hipStreamSynchronize(c->stream);
         (void)hipStreamDestroy(c->stream);
     }
+    for (int i = 0; i < c->side.n; ++i) {
+        (void)hipStreamSynchronize(c->side.st[i]);
+        (void)hipStreamDestroy(c->side.st[i]);
+        (void)hipEventDestroy(c->side.join[i]);
+    }
+    if (c->side.fork) (void)hipEventDestroy(c->side.fork);
     delete c;
 }
 
