@@ -14,6 +14,14 @@
  * Every floating-point operation is a single IEEE round-to-nearest operation
  * (the file is compiled with -ffp-contract=off); fused multiply-adds appear
  * only where fma() is written.
+ *
+ * Pins: every function is checked by the tests against what the paper and
+ * the mathematics fix, with one exception.  The default, weighted increment
+ * training data (the sum of (J f)^2 / n_h over the sum of 1 / n_h, the reading
+ * of Sec. 2.3 under a non-uniform allocation) are pinned only where they
+ * coincide with the printed formula, at a uniform allocation; with adapted
+ * allocations they are parity unpinned.  The printed formula itself is the
+ * literal mode.
  */
 #include <math.h>
 #include <stdint.h>
