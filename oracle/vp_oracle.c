@@ -16,12 +16,14 @@
  * only where fma() is written.
  *
  * Pins: every function is checked by the tests against what the paper and
- * the mathematics fix, with one exception.  The default, weighted increment
- * training data (the sum of (J f)^2 / n_h over the sum of 1 / n_h, the reading
- * of Sec. 2.3 under a non-uniform allocation) are pinned only where they
- * coincide with the printed formula, at a uniform allocation; with adapted
- * allocations they are parity unpinned.  The printed formula itself is the
- * literal mode.
+ * the mathematics fix.  The default, weighted increment training data (the
+ * sum of (J f)^2 / n_h over the sum of 1 / n_h, the reading of Sec. 2.3 under
+ * a non-uniform allocation) are pinned exactly to the printed formula where
+ * the two coincide (uniform allocation), and statistically elsewhere: under
+ * an arbitrary allocation their ratio is an unbiased estimate of N_g times
+ * the increment's integral of (J f)^2, which the allocation-independence of
+ * the optimal map (Sec. 3) asks for, checked against a closed form.  The
+ * printed formula itself is the literal mode.
  */
 #include <math.h>
 #include <stdint.h>

@@ -324,3 +324,48 @@ def test_weighted_training_data_equal_printed_formula_at_uniform_allocation(orc)
     dw = np.where(a["W"] > 0, a["H"] / np.where(a["W"] > 0, a["W"], 1), 0)
     dl = np.where(b["W"] > 0, b["H"] / np.where(b["W"] > 0, b["W"], 1), 0)
     np.testing.assert_allclose(dw, dl, rtol=1e-12, atol=0)
+
+
+def test_weighted_training_data_unbiased_under_adapted_allocation(orc):
+    # Sec. 3: the optimal map does not depend on the allocation.  Under any
+    # allocation n_h, E[sum over increment i of (J f)^2 / n_h] equals N_hc times
+    # the integral of (J f)^2 over the increment's slab of y, and
+    # E[sum of 1 / n_h] equals N_hc / N_g, so d_i = H_i / W_i estimates N_g times
+    # the slab integral of (J f)^2 -- what the map is refined on -- whatever the
+    # allocation.  Closed form for a separable Gaussian on the identity map
+    # (J = 1), averaged over independent iterations, with an allocation that
+    # puts more samples near the peak; the count-normalised printed formula is
+    # biased there.
+    D, NG, a, c = 2, 16, 8.0, 0.3
+    p = W.Params(dim=D, n_ev=4000, n_g=NG, seed=11)
+    f = W.gauss_single(D, coef=a, c=c)
+    pw = orc.Problem(p, f)
+    pl = orc.Problem(p.with_(hist_mode="literal"), f)
+    fmap = pw.map_init()
+    nst = pw.n_st
+    centres = (np.arange(nst) + 0.5) / nst
+    g = np.exp(-a * (centres - c) ** 2)
+    rng = np.random.default_rng(5)
+    n_h = (2 + np.floor(58 * np.outer(g, g)).astype(np.int64) + rng.integers(0, 3, (nst, nst))).ravel()
+    assert n_h.min() >= 2 and n_h.max() > 20 * n_h.min()
+    n_h = n_h.astype(np.int32)
+
+    def g2_int(lo, hi):  # integral of exp(-2 a (y - c)^2) over [lo, hi]
+        s = math.sqrt(2 * a)
+        return math.sqrt(math.pi / (8 * a)) * (math.erf(s * (hi - c)) - math.erf(s * (lo - c)))
+
+    scale2 = f.scale ** 2
+    exact = np.array([NG * g2_int(i / NG, (i + 1) / NG) * g2_int(0.0, 1.0) * scale2 for i in range(NG)])
+    R = 40
+    dw = np.empty((R, NG))
+    dl = np.empty((R, NG))
+    for it in range(R):
+        A = pw.sample_range(fmap, n_h, it)
+        B = pl.sample_range(fmap, n_h, it)
+        dw[it] = A["H"][0] / A["W"][0]
+        dl[it] = B["H"][0] / B["W"][0]
+    zw = (dw.mean(0) - exact) / (dw.std(0, ddof=1) / math.sqrt(R))
+    zl = (dl.mean(0) - exact) / (dl.std(0, ddof=1) / math.sqrt(R))
+    print(f"weighted: max |z| {np.abs(zw).max():.2f}; printed formula: max |z| {np.abs(zl).max():.1f}")
+    assert np.abs(zw).max() < 5.0
+    assert np.abs(zl).max() > 10.0
