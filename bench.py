@@ -181,7 +181,7 @@ def agreement(served, plain):
     return worst
 
 
-def run_batch(B, W, ctx, n_req):
+def run_batch(B, W, ctx, n_req, plain_too=True):
     reqs = W.served_batch(n_req=n_req)
     srv = B.Server(ctx, max_slots=n_req)
     t0 = srv.now()
@@ -193,6 +193,13 @@ def run_batch(B, W, ctx, n_req):
     makespan = max(t[2] for t in times) - t0
     lat = [t[2] - t[0] for t in times]
     samples = sum(r["n_evals"] for r in served)
+    served_out = {"makespan_s": makespan, "samples_per_s": samples / makespan, **lat_summary(lat),
+                  "steps": st["steps"], "graph_launches": st["graph_launches"],
+                  "graph_captures": st["graph_captures"], "peak_active": st["peak_active"],
+                  "mem_peak_bytes": st["mem_peak"],
+                  "scheduler_s": {k: st[k] for k in ("t_admit", "t_plan", "t_step", "t_retire")}}
+    if not plain_too:
+        return {"samples": samples, "served": served_out}
     svc, plain = run_plain(B, ctx, reqs)
     import numpy as np
     plain_lat = list(np.cumsum(svc))  # all submitted at time 0, served in order
@@ -200,11 +207,7 @@ def run_batch(B, W, ctx, n_req):
         "workload": f"{n_req} Gaussian-mixture requests, D 2..16, N_ev 1e4..1e6 log-uniform, 1-4 terms, "
                     "10 iterations, N_g=500, fp64, all submitted at t=0",
         "samples": samples,
-        "served": {"makespan_s": makespan, "samples_per_s": samples / makespan, **lat_summary(lat),
-                   "steps": st["steps"], "graph_launches": st["graph_launches"],
-                   "graph_captures": st["graph_captures"], "peak_active": st["peak_active"],
-                   "mem_peak_bytes": st["mem_peak"],
-                   "scheduler_s": {k: st[k] for k in ("t_admit", "t_plan", "t_step", "t_retire")}},
+        "served": served_out,
         "plain": {"makespan_s": float(sum(svc)), "samples_per_s": samples / sum(svc), **lat_summary(plain_lat)},
         "max_diff_in_sdev": agreement(served, plain),
     }
@@ -292,6 +295,8 @@ def main():
                          "(batched-integrand path), batch (served batch), stream)")
     ap.add_argument("--batch", type=int, default=4096, help="requests in the served batch")
     ap.add_argument("--stream", type=int, default=300, help="requests in the Poisson stream")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="served batch only, without the plain path's one-after-another comparison (for profiling)")
     ap.add_argument("--loads", default="0.8,0.5,0.95",
                     help="plain-path utilisations that set the stream rates (comma list; the first is the headline)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -372,9 +377,10 @@ def main():
     serving, latency = {}, {}
     if "batch" in sections:
         print("served batch ...", file=sys.stderr, flush=True)
-        serving["batch"] = b = run_batch(B, W, ctx, args.batch)
-        latency.update({"batch_p50_s": b["served"]["p50_s"], "batch_p99_s": b["served"]["p99_s"],
-                        "batch_plain_p50_s": b["plain"]["p50_s"], "batch_plain_p99_s": b["plain"]["p99_s"]})
+        serving["batch"] = b = run_batch(B, W, ctx, args.batch, plain_too=not args.no_plain)
+        latency.update({"batch_p50_s": b["served"]["p50_s"], "batch_p99_s": b["served"]["p99_s"]})
+        if "plain" in b:
+            latency.update({"batch_plain_p50_s": b["plain"]["p50_s"], "batch_plain_p99_s": b["plain"]["p99_s"]})
     if "stream" in sections:
         print("served stream ...", file=sys.stderr, flush=True)
         serving["stream"] = t = run_stream(B, W, ctx, args.stream, [float(x) for x in args.loads.split(",") if x])
