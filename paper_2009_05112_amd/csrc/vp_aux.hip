@@ -279,11 +279,12 @@ __global__ __launch_bounds__(kFixBlock) void k_edge_fixup(LaunchSet L)
 
 // ---------------------------------------------------------------- training data
 // Sum of the per-workgroup partials; each partial holds the numerator plane
-// H[nbins] followed by the weight plane W[nbins].  A workgroup takes
+// H[nbins] followed by the weight plane W[nbins].  A workgroup takes V rows of
 // kHistBlock / G consecutive values; each of its G thread groups sums every
 // G-th partial (two interleaved chains), and the group sums are added in
 // group order -- a fixed order, independent of timing, with G times more
-// loads in flight than one thread per value.
+// loads in flight than one thread per value.  Few partials (small served
+// requests) give G = 1 and several rows per workgroup.
 __global__ __launch_bounds__(kHistBlock) void k_hist_reduce(LaunchSet L)
 {
     VP_REQ_PROLOGUE(L);
@@ -293,31 +294,35 @@ __global__ __launch_bounds__(kHistBlock) void k_hist_reduce(LaunchSet L)
     double* __restrict__ H = q.H;
     double* __restrict__ W = q.W;
     __shared__ double red[kHistBlock];
-    const int G = hist_groups(max(q.grid, q.rec_chunks));
-    const int tile = kHistBlock / G;
-    const int b = threadIdx.x % tile, g = threadIdx.x / tile;
-    const int64_t i = (int64_t)bid * tile + b;
-    double s = 0.0;
-    if (i < 2 * nbins) {
-        const int64_t j = i < nbins ? i : i - nbins;
-        const int n_part = j < lbins ? q.grid : q.rec_chunks;
-        double a0 = 0.0, a1 = 0.0;
-        int p = g;
+    const int n_max = max(q.grid, q.rec_chunks);
+    const int G = hist_groups(n_max), V = hist_values(n_max);
+    const int lanes = kHistBlock / G;  // values side by side; each thread takes V of them, lanes apart
+    const int b = threadIdx.x % lanes, g = threadIdx.x / lanes;
+    for (int v = 0; v < V; ++v) {
+        const int64_t i = ((int64_t)bid * V + v) * lanes + b;
+        double s = 0.0;
+        if (i < 2 * nbins) {
+            const int64_t j = i < nbins ? i : i - nbins;
+            const int n_part = j < lbins ? q.grid : q.rec_chunks;
+            double a0 = 0.0, a1 = 0.0;
+            int p = g;
 #pragma unroll 4
-        for (; p + G < n_part; p += 2 * G) {
-            a0 = a0 + part[(int64_t)p * 2 * nbins + i];
-            a1 = a1 + part[(int64_t)(p + G) * 2 * nbins + i];
+            for (; p + G < n_part; p += 2 * G) {
+                a0 = a0 + part[(int64_t)p * 2 * nbins + i];
+                a1 = a1 + part[(int64_t)(p + G) * 2 * nbins + i];
+            }
+            if (p < n_part) a0 = a0 + part[(int64_t)p * 2 * nbins + i];
+            s = a0 + a1;
         }
-        if (p < n_part) a0 = a0 + part[(int64_t)p * 2 * nbins + i];
-        s = a0 + a1;
-    }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (g == 0 && i < 2 * nbins) {
-        double tot = red[b];
-        for (int k = 1; k < G; ++k) tot = tot + red[k * tile + b];
-        if (i >= nbins) W[i - nbins] = tot;
-        else H[i] = tot;
+        red[threadIdx.x] = s;
+        __syncthreads();
+        if (g == 0 && i < 2 * nbins) {
+            double tot = red[b];
+            for (int k = 1; k < G; ++k) tot = tot + red[k * lanes + b];
+            if (i >= nbins) W[i - nbins] = tot;
+            else H[i] = tot;
+        }
+        __syncthreads();
     }
 }
 
@@ -1214,7 +1219,8 @@ void launch_vec(const VecArgs& a, hipStream_t s)
 
 int est_grid(int64_t n_hc)
 {
-    int64_t g = (n_hc + kRedBlock - 1) / kRedBlock;
+    // about 16 hypercubes per thread: small served requests launch few workgroups
+    int64_t g = (n_hc + 16 * kRedBlock - 1) / (16 * kRedBlock);
     if (g > kRedMaxGrid) g = kRedMaxGrid;
     return (int)(g < 1 ? 1 : g);
 }

@@ -21,6 +21,14 @@ __host__ __device__ inline int hist_groups(int n_part)
     while (g < 16 && g * 16 < n_part) g <<= 1;
     return g;
 }
+// Rows of values per workgroup: about 16 partials summed per thread in all.
+__host__ __device__ inline int hist_values(int n_part)
+{
+    const int per = (n_part + hist_groups(n_part) - 1) / hist_groups(n_part);
+    int v = 1;
+    while (v < 8 && v * 2 * per <= 16) v <<= 1;
+    return v;
+}
 constexpr int kRedMaxGrid = 4096;
 constexpr int kRefineBlock = 256;
 constexpr int kFixBlock = 1024;  // edge fix-up: one workgroup per request

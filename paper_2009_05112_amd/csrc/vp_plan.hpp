@@ -68,7 +68,8 @@ public:
         Pending po = add_set([](const ReqArgs&) { return 1; }, &n_one);
         Pending ph = add_set(
             [](const ReqArgs& q) {
-                const int tile = kHistBlock / hist_groups(std::max(q.grid, q.rec_chunks));
+                const int n_max = std::max(q.grid, q.rec_chunks);
+                const int tile = kHistBlock / hist_groups(n_max) * hist_values(n_max);
                 return (int)((2LL * q.dim * q.n_g + tile - 1) / tile);
             },
             &n_hist);
