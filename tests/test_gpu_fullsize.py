@@ -14,7 +14,7 @@ from tests.parity import RTOL64, assert_close, variance_scale
 pytestmark = pytest.mark.gpu
 
 
-def _sampled_ranges(n_h, budget=1_500_000, width=2000, n_random=300, seed=0):
+def _sampled_ranges(n_h, budget=1_500_000, width=2000, n_random=300, seed=0, largest=True):
     n_hc = n_h.size
     starts = [0, n_hc // 3, n_hc // 2, n_hc - width]
     rng = np.random.default_rng(seed)
@@ -29,21 +29,22 @@ def _sampled_ranges(n_h, budget=1_500_000, width=2000, n_random=300, seed=0):
         out.append((s, e))
         used += c
     # the largest hypercubes (span many waves) and random ones
-    for h in list(np.argsort(n_h)[-5:]) + list(rng.integers(0, n_hc, n_random)):
+    big = list(np.argsort(n_h)[-5:]) if largest else []
+    for h in big + list(rng.integers(0, n_hc, n_random)):
         if used + int(n_h[h]) <= 4 * budget:
             out.append((int(h), int(h) + 1))
             used += int(n_h[h])
     return out
 
 
-def _check_iteration(gp, op, fmap, n_h, it, rtol=RTOL64, floor=0.0):
+def _check_iteration(gp, op, fmap, n_h, it, rtol=RTOL64, floor=0.0, largest=True):
     """rtol, floor: the per-hypercube sums' bar (the split precisions compare
     sums of single-precision values; everything after the sums is double
     precision and held to 1e-12 either way)."""
     acc = gp.accum()
     res = gp.result()
     top1, top2 = np.abs(acc["S1"]).max(), np.abs(acc["S2"]).max()
-    for (a, b) in _sampled_ranges(n_h, seed=it):
+    for (a, b) in _sampled_ranges(n_h, seed=it, largest=largest):
         o = op.sample_range(fmap, n_h, it, a, b)
         s1, s2 = acc["S1"][a:b], acc["S2"][a:b]
         sc1 = np.maximum(np.maximum(np.abs(s1), np.abs(o["S1"])), floor * top1 / rtol)
@@ -97,5 +98,25 @@ def test_fullsize_split_d8_two_iterations():
         gp.iterate(1)
         res = _check_iteration(gp, op, fmap, n_h, it, rtol=2e-6, floor=1e-12)
     assert res["n_evals"] > 1.5e8
+    gp.close()
+    ctx.close()
+
+
+def test_maxsize_d8_one_iteration():
+    """The largest N_ev the interface accepts (2^31 - 1) at D=8: N_st = 12,
+    N_hc = 12^8 = 429,981,696 (R = 1000/12 is not an integer), four samples per
+    hypercube, 1.72e9 samples in one launch.  The first iteration's allocation
+    is uniform, so the largest-hypercube ranges are left out (an argsort of
+    4.3e8 counts would dominate the test)."""
+    ctx = B.Context(0)
+    p, f = W.cfg_diag_d8(n_ev=2**31 - 1)
+    gp = B.Problem(ctx, p, f)
+    op = oracle.Problem(p, f, n_st=gp.n_st)
+    assert (gp.n_st, gp.n_hc) == (12, 12 ** 8)
+    fmap, n_h, it = gp.map(), gp.alloc(), gp.it
+    assert int(n_h.min()) == int(n_h.max()) == 4
+    gp.iterate(1)
+    res = _check_iteration(gp, op, fmap, n_h, it, largest=False)
+    assert res["n_evals"] == 4 * 12 ** 8
     gp.close()
     ctx.close()
