@@ -491,16 +491,30 @@ __global__ __launch_bounds__(kRedBlock) void k_est_partial(LaunchSet L)
     double* __restrict__ dh = q.dh;
     const int quarter = beta_quarter(beta);
     double I = 0.0, V = 0.0, Sd = 0.0;
-#pragma unroll 4
-    for (int64_t h = (int64_t)bid * blockDim.x + threadIdx.x; h < n_hc; h += (int64_t)nblk * blockDim.x) {
+    // hypercubes in pairs, moved by 16-byte loads and stores (the arrays are
+    // 256-byte aligned); an odd last hypercube goes to the grid's first thread
+    auto term = [&](double s1, double s2, int32_t n) {
         double m, var, d;
-        const int32_t n = n_h[h];
-        hypercube_terms(S1[h], S2[h], n, omega, omega2, beta, quarter, &m, &var, &d);
-        dh[h] = d;
+        hypercube_terms(s1, s2, n, omega, omega2, beta, quarter, &m, &var, &d);
         I = I + m;
         V = V + var / ((double)n - 1.0);
         Sd = Sd + d;
+        return d;
+    };
+    const int64_t np = n_hc / 2;
+    const int2* __restrict__ n2 = reinterpret_cast<const int2*>(n_h);
+    const double2* __restrict__ a2 = reinterpret_cast<const double2*>(S1);
+    const double2* __restrict__ b2 = reinterpret_cast<const double2*>(S2);
+    double2* __restrict__ d2 = reinterpret_cast<double2*>(dh);
+#pragma unroll 2
+    for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < np; i += (int64_t)nblk * blockDim.x) {
+        const int2 n = n2[i];
+        const double2 a = a2[i], b = b2[i];
+        const double d0 = term(a.x, b.x, n.x);
+        const double d1 = term(a.y, b.y, n.y);
+        d2[i] = make_double2(d0, d1);
     }
+    if ((n_hc & 1) && bid == 0 && threadIdx.x == 0) dh[n_hc - 1] = term(S1[n_hc - 1], S2[n_hc - 1], n_h[n_hc - 1]);
     __shared__ double red[3][kRedBlock / kWave];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     I = wave_sum(I);
@@ -657,9 +671,8 @@ __global__ __launch_bounds__(kRedBlock) void k_realloc(LaunchSet L)
     if (!(sumd > 0.0) || frozen(q)) return;
     unsigned long long nt = 0;
     const double first_visible = plus2 ? 1.0 : 3.0;
-#pragma unroll 4
-    for (int64_t h = (int64_t)bid * blockDim.x + threadIdx.x; h < n_hc; h += (int64_t)nblk * blockDim.x) {
-        const double qv = n_ev * (dh[h] / sumd);
+    auto count = [&](double d) {
+        const double qv = n_ev * (d / sumd);
         const double fl = floor(qv);
         const double r = rint(qv);
         const double tol = 1e-9 * (qv > 1.0 ? qv : 1.0);
@@ -668,8 +681,21 @@ __global__ __launch_bounds__(kRedBlock) void k_realloc(LaunchSet L)
         if (plus2) n = n + 2;
         else if (n < 2) n = 2;
         if (n > 2147483647) n = 2147483647;
-        n_h[h] = (int32_t)n;
+        return (int32_t)n;
+    };
+    // hypercubes in pairs (16-byte loads, 8-byte stores), as in k_est_partial
+    const int64_t np = n_hc / 2;
+    const double2* __restrict__ d2 = reinterpret_cast<const double2*>(dh);
+    int2* __restrict__ o2 = reinterpret_cast<int2*>(n_h);
+#pragma unroll 2
+    for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < np; i += (int64_t)nblk * blockDim.x) {
+        const double2 d = d2[i];
+        int2 o;
+        o.x = count(d.x);
+        o.y = count(d.y);
+        o2[i] = o;
     }
+    if ((n_hc & 1) && bid == 0 && threadIdx.x == 0) n_h[n_hc - 1] = count(dh[n_hc - 1]);
     for (int d = kWave / 2; d >= 1; d >>= 1) nt += __shfl_down(nt, d);
     if ((threadIdx.x & (kWave - 1)) == 0 && nt) atomicAdd(ties, nt);
 }
