@@ -162,12 +162,23 @@ __device__ __forceinline__ RunSum run_combine(const RunSum& x, const RunSum& y)
 // memory instead).
 constexpr int kFixPer = 16;
 
+__device__ __forceinline__ RunSum run_shfl(const RunSum& x, int src)
+{
+    RunSum r;
+    r.hf = __shfl((long long)x.hf, src);
+    r.hl = __shfl((long long)x.hl, src);
+    r.a = __shfl(x.a, src);
+    r.b = __shfl(x.b, src);
+    r.has = __shfl(x.has, src);
+    r.single = __shfl(x.single, src);
+    return r;
+}
+
 __global__ __launch_bounds__(kFixBlock) void k_edge_fixup(LaunchSet L)
 {
     VP_REQ_PROLOGUE(L);
-    __shared__ RunSum sh[kFixBlock];
-    __shared__ int64_t nxt_h[kFixBlock];
-    __shared__ int nxt_has[kFixBlock];
+    __shared__ RunSum wrun[kFixBlock / kWave];
+    __shared__ int64_t wfirst[kFixBlock / kWave];
     const EdgeRec* __restrict__ e = q.edges;
     const int64_t n_rec = 2 * q.n_waves;
     const int t = threadIdx.x;
@@ -216,32 +227,36 @@ __global__ __launch_bounds__(kFixBlock) void k_edge_fixup(LaunchSet L)
             mine.single = 0;
         }
     });
-    // inclusive scan from the left, and the first record to the right
-    sh[t] = mine;
-    nxt_has[t] = mine.has;
-    nxt_h[t] = mine.hf;
-    __syncthreads();
-    for (int d = 1; d < kFixBlock; d <<= 1) {
-        RunSum v = sh[t];
-        if (t >= d) v = run_combine(sh[t - d], v);
-        int hv = nxt_has[t];
-        int64_t hh = nxt_h[t];
-        if (!hv && t + d < kFixBlock) {
-            hv = nxt_has[t + d];
-            hh = nxt_h[t + d];
-        }
-        __syncthreads();
-        sh[t] = v;
-        nxt_has[t] = hv;
-        nxt_h[t] = hh;
-        __syncthreads();
+    // The run reaching each thread from the left (an inclusive scan of the
+    // slice summaries) and the first record to its right (a suffix scan of
+    // the slices' first hypercubes, -1 for none): within each wave by
+    // shuffles, across the waves through one summary per wave, in a fixed
+    // shape.
+    const int lane = t & (kWave - 1), w = t / kWave;
+    RunSum incl = mine;
+    int64_t first = mine.has ? mine.hf : -1;  // first record at or right of this thread, in the wave
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const RunSum u = run_shfl(incl, lane - d);
+        if (lane >= d) incl = run_combine(u, incl);
+        const int64_t f = __shfl((long long)first, lane + d);
+        if (first < 0 && lane + d < kWave) first = f;
     }
+    // (every lane takes part in these shuffles: a lane that has left the
+    // kernel gives no value)
+    const RunSum left = run_shfl(incl, lane - 1);
+    int64_t next_h = __shfl((long long)first, lane + 1);
+    if (lane == kWave - 1) next_h = -1;
+    if (lane == kWave - 1) wrun[w] = incl;
+    if (lane == 0) wfirst[w] = first;
+    __syncthreads();
     if (!mine.has) return;
     RunSum carry;
     carry.has = 0;
-    if (t > 0) carry = sh[t - 1];
-    const int next_has = t + 1 < kFixBlock ? nxt_has[t + 1] : 0;
-    const int64_t next_h = t + 1 < kFixBlock ? nxt_h[t + 1] : -1;
+    for (int v = 0; v < w; ++v) carry = run_combine(carry, wrun[v]);
+    if (lane > 0) carry = run_combine(carry, left);
+    for (int v = w + 1; v < kFixBlock / kWave && next_h < 0; ++v) next_h = wfirst[v];
+    const int next_has = next_h >= 0;
     double* __restrict__ S1 = q.S1;
     double* __restrict__ S2 = q.S2;
     bool open = false;
