@@ -51,16 +51,26 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_local(LaunchSet L)
     const int64_t n_hc = q.n_hc;
     int64_t* __restrict__ offs = q.offs;
     int64_t* __restrict__ bsum = q.bsum;
-    // each thread scans kScanPer consecutive counts; whole runs move as
-    // 16-byte loads and stores (the arrays are 256-byte aligned)
-    const int64_t base = (int64_t)bid * kScanTile + (int64_t)threadIdx.x * kScanPer;
-    const bool whole = base + kScanPer <= n_hc;
+    // each thread scans kScanPer consecutive counts.  A whole tile moves
+    // through LDS so that the lanes of each 16-byte load and store touch
+    // consecutive addresses (the arrays are 256-byte aligned); the last,
+    // partial tile is read and written element by element.
+    __shared__ int64_t stage[kScanTile];
+    int32_t* const cnt = reinterpret_cast<int32_t*>(stage);
+    const int64_t tile0 = (int64_t)bid * kScanTile;
+    const int64_t base = tile0 + (int64_t)threadIdx.x * kScanPer;
+    const bool whole = tile0 + kScanTile <= n_hc;  // uniform over the workgroup
     int64_t v[kScanPer];
     int64_t t = 0;
     if (whole) {
+        const int4* __restrict__ src = reinterpret_cast<const int4*>(n_h + tile0);
+#pragma unroll
+        for (int i = 0; i < kScanPer / 4; ++i)
+            reinterpret_cast<int4*>(cnt)[i * kScanBlock + threadIdx.x] = src[i * kScanBlock + threadIdx.x];
+        __syncthreads();
 #pragma unroll
         for (int i = 0; i < kScanPer; i += 4) {
-            const int4 c = *reinterpret_cast<const int4*>(n_h + base + i);
+            const int4 c = reinterpret_cast<const int4*>(cnt)[(threadIdx.x * kScanPer + i) / 4];
             v[i] = c.x;
             v[i + 1] = c.y;
             v[i + 2] = c.z;
@@ -73,7 +83,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_local(LaunchSet L)
 #pragma unroll
     for (int i = 0; i < kScanPer; ++i) t += v[i];
     int64_t total;
-    int64_t run = block_excl_scan(t, &total);
+    int64_t run = block_excl_scan(t, &total);  // synchronises the workgroup: the counts are read
     int64_t o[kScanPer];
 #pragma unroll
     for (int i = 0; i < kScanPer; ++i) {
@@ -83,7 +93,12 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_local(LaunchSet L)
     if (whole) {
 #pragma unroll
         for (int i = 0; i < kScanPer; i += 2)
-            *reinterpret_cast<longlong2*>(offs + base + i) = make_longlong2(o[i], o[i + 1]);
+            reinterpret_cast<longlong2*>(stage)[(threadIdx.x * kScanPer + i) / 2] = make_longlong2(o[i], o[i + 1]);
+        __syncthreads();
+        longlong2* __restrict__ dst = reinterpret_cast<longlong2*>(offs + tile0);
+#pragma unroll
+        for (int i = 0; i < kScanPer / 2; ++i)
+            dst[i * kScanBlock + threadIdx.x] = reinterpret_cast<const longlong2*>(stage)[i * kScanBlock + threadIdx.x];
     } else {
 #pragma unroll
         for (int i = 0; i < kScanPer; ++i)
