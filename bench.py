@@ -36,7 +36,7 @@ METRIC = "integrand samples/sec/GPU (D=8, 1e8/iter) + p50/p99 solve latency vs p
 PEAK_VALU_SLOTS = 256 * 64 * 2.4e9  # full-rate VALU lane-operations per second: 256 CUs x 64 lanes x 2.4 GHz
 # Algorithmic VALU slots per sample of the fused sampling kernel at D=8 with
 # three Gaussian terms (derivation in the design notes; instruction costs
-# measured by paper_2009_05112_amd/isa_rates): Philox blocks x 10 rounds x
+# measured by an instruction-rate microbenchmark): Philox blocks x 10 rounds x
 # (2 full-rate 64-bit multiply-adds + 2 three-way xors), the uniform-to-
 # increment arithmetic, the map, the integrand and the sums.  FP32 operations
 # issue at twice the FP64/integer rate on gfx950 and count half a slot; the
@@ -299,20 +299,7 @@ def main():
                     help="served batch only, without the plain path's one-after-another comparison (for profiling)")
     ap.add_argument("--loads", default="0.8,0.5,0.95",
                     help="plain-path utilisations that set the stream rates (comma list; the first is the headline)")
-    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
-                    help="only copy a buffer of this many MiB on the GPU (a plain copy kernel of known "
-                         "size, the reference for the HBM byte counters) and exit")
     args = ap.parse_args()
-    if args.copy_probe:
-        import torch
-        n = args.copy_probe << 20
-        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": n}))
-        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the method's per-iteration "
               "state is sharded across GPUs only in the design notes, not built", file=sys.stderr)

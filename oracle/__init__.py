@@ -382,7 +382,7 @@ def refine_axis(params, H, W, x):
     """Refine one axis (N_g = len(H)) in place on a copy; returns the new grid."""
     p = _Params(1, 1, len(H), 1, float(params.alpha), float(params.beta), 0, 0, 0, 0)
     xx = np.array(x, dtype=np.float64, copy=True)
-    work = np.empty(2 * max(len(H), 2))
+    work = np.empty(4 * (len(H) + 1))
     lib().or_refine_axis(C.byref(p), _dp(np.ascontiguousarray(H, dtype=np.float64)),
                          _dp(np.ascontiguousarray(W, dtype=np.float64)), _dp(xx), _dp(work))
     return xx

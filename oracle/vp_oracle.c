@@ -759,17 +759,26 @@ int64_t or_realloc(const or_params* p, const double* S1, const double* S2, const
 /*  2. Smoothing with weights (7,1)/8, (1,6,1)/8, (1,7)/8 and normalisation   */
 /*     by the raw sum of the d_i.                                             */
 /*  3. Range compression d -> ((1 - d) / ln(1/d))^alpha, 0 for d = 0.         */
-/*  4. The four-step regrid that puts an equal share of sum d into each new  */
-/*     increment by linear interpolation inside the old increments.           */
+/*  4. Regrid: the new grid gives every new increment an equal share          */
+/*     delta_d = (sum c) / N_g of the compressed values c_j, each c_j spread  */
+/*     uniformly over its old increment.  So new point i is the inverse, at   */
+/*     i delta_d, of the cumulative C(x) that is linear on every old          */
+/*     increment with C(x_j) = c_0 + ... + c_{j-1}: in the old increment j    */
+/*     with C(x_j) < i delta_d <= C(x_{j+1}),                                 */
+/*       x'_i = x_j + (i delta_d - C(x_j)) / c_j (x_{j+1} - x_j).              */
+/*     (The paper reaches the same points by a running walk over the c_j.)    */
 /* An axis is left untouched when alpha = 0, N_g = 1, or every d_i is zero.  */
-/* x: the axis's N_g + 1 grid points, replaced in place.  work: 2 N_g doubles.*/
+/* x: the axis's N_g + 1 grid points, replaced in place.                      */
+/* work: 4 (N_g + 1) doubles.                                                 */
 /* ------------------------------------------------------------------------ */
 int or_refine_axis(const or_params* p, const double* H, const double* W, double* x, double* work)
 {
     const int32_t NG = p->n_g;
     if (p->alpha == 0.0 || NG < 2) return 0;
     double* d = work;
-    double* c = work + NG;
+    double* c = work + (NG + 1);
+    double* cum = work + 2 * (NG + 1);
+    double* xn = work + 3 * (NG + 1);
     or_ksum ks = {0.0, 0.0};
     for (int32_t i = 0; i < NG; ++i) {
         d[i] = (W[i] > 0.0) ? H[i] / W[i] : 0.0;
@@ -783,29 +792,31 @@ int or_refine_axis(const or_params* p, const double* H, const double* W, double*
     c[NG - 1] = (d[NG - 2] + 7.0 * d[NG - 1]) / 8.0;
     for (int32_t i = 0; i < NG; ++i) c[i] = c[i] / s;
     /* compression */
-    or_ksum kc = {0.0, 0.0};
     for (int32_t i = 0; i < NG; ++i) {
         double di = c[i];
         c[i] = (di == 0.0) ? 0.0 : pow((1.0 - di) / (-log(di)), p->alpha);
-        or_kadd(&kc, c[i]);
     }
-    const double csum = or_kval(&kc);
-    /* regrid; with nothing to share out (the compressed sum underflowed or is
-     * not finite) step 1's delta d is not positive and the axis is kept */
-    const double delta_d = csum / (double)NG;
+    /* cumulative at the old grid points, cum[j] = C(x_j) (compensated sums) */
+    or_ksum kc = {0.0, 0.0};
+    cum[0] = 0.0;
+    for (int32_t j = 0; j < NG; ++j) {
+        or_kadd(&kc, c[j]);
+        cum[j + 1] = or_kval(&kc);
+    }
+    /* with nothing to share out (the compressed sum underflowed or is not
+     * finite) the share is not positive and the axis is kept */
+    const double delta_d = cum[NG] / (double)NG;
     if (!(delta_d > 0.0)) return 0;
-    double* xn = d; /* d no longer needed; reuse for the new points */
     xn[0] = x[0];
     int32_t j = 0;
-    double acc = 0.0;
     for (int32_t i = 1; i < NG; ++i) {
-        while (acc < delta_d && j < NG) {
-            acc = acc + c[j];
-            j = j + 1;
-        }
-        acc = acc - delta_d;
-        double frac_left = (acc > 0.0) ? acc / c[j - 1] : 0.0;
-        xn[i] = x[j] - frac_left * (x[j] - x[j - 1]);
+        const double target = (double)i * delta_d;
+        /* the old increment holding the target: cum[j] < target <= cum[j + 1] */
+        while (j < NG - 1 && cum[j + 1] < target) ++j;
+        double frac = (c[j] > 0.0) ? (target - cum[j]) / c[j] : 1.0;
+        if (frac < 0.0) frac = 0.0;
+        if (frac > 1.0) frac = 1.0;
+        xn[i] = x[j] + frac * (x[j + 1] - x[j]);
     }
     for (int32_t i = 1; i < NG; ++i) x[i] = xn[i];
     return 1;
@@ -840,7 +851,7 @@ int or_refine_stages(const or_params* p, const double* H, const double* W, doubl
 int or_refine(const or_params* p, const double* H, const double* W, double* map)
 {
     const int32_t D = p->dim, NG = p->n_g;
-    double* work = (double*)malloc(sizeof(double) * 2 * (size_t)(NG > 1 ? NG : 2));
+    double* work = (double*)malloc(sizeof(double) * 4 * ((size_t)NG + 1));
     if (!work) return -1;
     for (int32_t mu = 0; mu < D; ++mu)
         or_refine_axis(p, H + (int64_t)mu * NG, W + (int64_t)mu * NG, map + (int64_t)mu * (NG + 1),

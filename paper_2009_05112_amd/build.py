@@ -13,7 +13,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvegasp.so")
-RATES = os.path.join(HERE, "isa_rates")  # instruction-rate diagnostic (not part of the library)
 EXAMPLES = os.path.join(HERE, "libvegasp_examples.so")  # example batched integrands
 def _instances():
     import importlib.util
@@ -64,16 +63,12 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
-    r = subprocess.run([_hipcc()] + [f for f in FLAGS if f != "-fPIC"] +
-                       [os.path.join(CSRC, "isa_rates.hip"), "-o", RATES], capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError("isa_rates failed:\n" + r.stdout + r.stderr)
     r = subprocess.run([_hipcc()] + FLAGS + ["-shared", os.path.join(CSRC, "vp_examples.hip"), "-o", EXAMPLES],
                        capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("vp_examples failed:\n" + r.stdout + r.stderr)
     if verbose:
-        print("built", LIB, RATES, "and", EXAMPLES)
+        print("built", LIB, "and", EXAMPLES)
     return LIB
 
 

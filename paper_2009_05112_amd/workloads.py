@@ -51,6 +51,10 @@ class Integrand:
     chol: Optional[np.ndarray] = None
     scale: float = 1.0
     exact: Optional[float] = None  # exact integral over the box, when known
+    # correlated Gaussian only: the rotation Q and standard deviations s the
+    # covariance Sigma = Q diag(s^2) Q^T was built from (generator inputs)
+    rotation: Optional[np.ndarray] = None
+    sdevs: Optional[np.ndarray] = None
 
     def __post_init__(self):
         assert self.kind in KINDS, self.kind
@@ -238,7 +242,8 @@ def corr_gauss(rng: np.random.Generator, dim: int, s_max: float = 0.05, cond: fl
     u = np.linalg.cholesky(prec).T  # upper: U^T U = prec
     mu = rng.uniform(mu_range[0], mu_range[1], size=dim)
     exact = (2.0 * math.pi) ** (dim / 2.0) * float(np.prod(s))
-    return Integrand("corr_gauss", dim, mu.reshape(1, -1), [0.5], [1.0], chol=np.triu(u), exact=exact)
+    return Integrand("corr_gauss", dim, mu.reshape(1, -1), [0.5], [1.0], chol=np.triu(u), exact=exact,
+                     rotation=q, sdevs=s)
 
 
 def served_stream(n_req: int, rate: float, seed: int = 1, d_range=(3, 21), nev_log=(5.0, 7.0),

@@ -369,3 +369,30 @@ def test_weighted_training_data_unbiased_under_adapted_allocation(orc):
     print(f"weighted: max |z| {np.abs(zw).max():.2f}; printed formula: max |z| {np.abs(zl).max():.1f}")
     assert np.abs(zw).max() < 5.0
     assert np.abs(zl).max() > 10.0
+
+
+@pytest.mark.parametrize("beta", [1.0, 0.5])
+def test_plus2_rule_exact_counts(orc, beta):
+    """Sec. 3 step 4, the alternative to Eq. nh: n_h = floor(q) + 2 with
+    q = N_ev d_h / sum d.  The injected sigma_h make every q an exact
+    half-integer m_h + 1/2 (far from any rounding boundary): d_h = 2 m_h + 1
+    and N_ev = (sum d) / 2.  The +2 rule must give m_h + 2, the default rule
+    max(2, m_h)."""
+    p = W.Params(dim=2, n_ev=1000, n_g=10, beta=beta)
+    pr = orc.Problem(p, W.const(2), n_st=4)   # 16 hypercubes
+    m = np.array([0, 1, 2, 3, 5, 8, 13, 0, 1, 21, 34, 2, 4, 6, 7, 9])
+    d = 2 * m + 1
+    assert d.sum() % 2 == 0
+    n_ev = int(d.sum()) // 2
+    sig = d.astype(float) ** (1.0 / beta)
+    n = np.full(pr.n_hc, 4, dtype=np.int32)
+    S1, S2 = _sums_for_sigma(orc, pr, sig, n.astype(float))
+    q = n_ev * d / d.sum()
+    np.testing.assert_array_equal(q, m + 0.5)
+    plus2 = orc.Problem(p.with_(n_ev=n_ev, realloc_plus2=True), W.const(2), n_st=4)
+    got, ties = plus2.realloc(S1, S2, n)
+    np.testing.assert_array_equal(got, m + 2)
+    assert ties == 0
+    plain = orc.Problem(p.with_(n_ev=n_ev), W.const(2), n_st=4)
+    got0, _ = plain.realloc(S1, S2, n)
+    np.testing.assert_array_equal(got0, np.maximum(2, m))
