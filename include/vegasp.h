@@ -277,6 +277,26 @@ vp_status vp_iteration_set(vp_problem* p, int32_t it);
  * increment).  Any pointer may be NULL. */
 vp_status vp_accum_get(vp_problem* p, double* S1, double* S2, double* H, double* W);
 
+/* Per-sample dump, for inspection and parity tests (the uniform y of Sec. 3
+ * in each hypercube; the map of Sec. 2.2, Eqs. y and jac).  vp_debug_dump
+ * arms it for the next iteration: its sampling kernel records samples
+ * [first, first + count) of that iteration, numbered in hypercube order
+ * (sample s = offset(h) + j, offset the exclusive sum of n_h), with their
+ * hypercube h, index j within it, increment index i^mu and point x^mu on
+ * every axis, Jacobian J and f(x) (v = J f is the value summed).  Split
+ * precisions report their single-precision values widened to double.
+ * count 0 disarms; count <= 2^24.  Not available for VP_F_BATCH
+ * (VP_ERR_STATE).  The device buffer is the library's, kept until the next
+ * call or the problem's destruction.  Synchronising.
+ * vp_debug_dump_get: synchronising; *n_out receives the number of samples
+ * recorded (fewer than count when the iteration had fewer samples after
+ * `first`); h, j, jac, fx: host [n_out]; idx, x: host [dim][n_out]; any
+ * array may be NULL.  VP_ERR_STATE when no dump is armed or its iteration
+ * has not run yet. */
+vp_status vp_debug_dump(vp_problem* p, int64_t first, int64_t count);
+vp_status vp_debug_dump_get(vp_problem* p, int64_t* n_out, int64_t* h, int32_t* j, int32_t* idx, double* x,
+                            double* jac, double* fx);
+
 /* Synchronising.  Preconditioned map (Sec. 5.2): trains the map on given
  * samples {x, f(x)} (from MCMC, a peak finder, ...) before integrating.  Each
  * of n_iter passes finds every point's increment on every axis by inverting

@@ -80,6 +80,9 @@ def lib():
         L.or_sample_indices.argtypes = [C.POINTER(_Params), ip, C.c_int32, C.c_int64, C.c_int64,
                                         ip, dp, C.c_int64]
         L.or_sample_indices.restype = C.c_int
+        L.or_sample_points.argtypes = [C.POINTER(_Params), C.POINTER(_Integrand), dp, ip, C.c_int32, C.c_int64,
+                                       C.c_int64, C.POINTER(C.c_int64), ip, ip, dp, dp, dp, C.c_int64]
+        L.or_sample_points.restype = C.c_int
         L.or_reduce.argtypes = [C.POINTER(_Params), ip, dp, dp, dp, dp]
         L.or_realloc.argtypes = [C.POINTER(_Params), dp, dp, ip, ip]
         L.or_realloc.restype = C.c_int64
@@ -94,7 +97,7 @@ def lib():
                                    dp, dp, dp, dp, dp, dp]
         L.or_iteration.restype = C.c_int64
         L.or_integrate.argtypes = [C.POINTER(_Params), C.POINTER(_Integrand), dp, ip, C.c_int32,
-                                   C.c_int32, dp, dp, C.POINTER(C.c_int64)]
+                                   C.c_int32, dp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.or_integrate.restype = C.c_int
         _lib = L
     return _lib
@@ -224,6 +227,26 @@ class Problem:
             raise RuntimeError("or_sample_indices failed")
         return (idx, t) if with_t else idx
 
+    def sample_points(self, fmap, n_h, it, h0=0, h1=None):
+        """Every sample of hypercubes [h0, h1) in (h, j) order: h, j [n];
+        idx, x [n][dim]; jac, fx [n]."""
+        P = self.params
+        h1 = self.n_hc if h1 is None else h1
+        n_h = np.ascontiguousarray(n_h, dtype=np.int32)
+        ns = int(n_h[h0:h1].astype(np.int64).sum())
+        h = np.empty(ns, dtype=np.int64)
+        j = np.empty(ns, dtype=np.int32)
+        idx = np.empty((ns, P.dim), dtype=np.int32)
+        x = np.empty((ns, P.dim))
+        jac = np.empty(ns)
+        fx = np.empty(ns)
+        rc = lib().or_sample_points(C.byref(self.p), C.byref(self.fi), _dp(np.ascontiguousarray(fmap, dtype=np.float64)),
+                                    _ip(n_h), it, h0, h1, h.ctypes.data_as(C.POINTER(C.c_int64)), _ip(j), _ip(idx),
+                                    _dp(x), _dp(jac), _dp(fx), ns)
+        if rc != 0:
+            raise RuntimeError("or_sample_points failed")
+        return {"h": h, "j": j, "idx": idx, "x": x, "jac": jac, "fx": fx}
+
     def vec_iteration(self, fmap, n_h, it, e1, e2):
         """Vector estimates of one iteration (Sec. 6) for the components
         f * (x_e1 or 1) * (x_e2 or 1): I [M], C [M][M] and the scale [M] of
@@ -309,14 +332,15 @@ class Problem:
         I = np.empty(n_iter)
         V = np.empty(n_iter)
         ties = C.c_int64(0)
+        evals = C.c_int64(0)
         rc = lib().or_integrate(C.byref(self.p), C.byref(self.fi), _dp(m), _ip(n), it0, n_iter, _dp(I),
-                                _dp(V), C.byref(ties))
+                                _dp(V), C.byref(ties), C.byref(evals))
         if rc != 0:
             raise RuntimeError("or_integrate failed")
         sig = np.sqrt(V)
         mean, sdev, chi2, dof = combine(I, sig, self.params.n_discard, getattr(self.params, "average", "weighted"))
         return {"I": I, "V": V, "sig": sig, "mean": mean, "sdev": sdev, "chi2": chi2, "dof": dof,
-                "map": m, "n_h": n, "ties": int(ties.value)}
+                "map": m, "n_h": n, "ties": int(ties.value), "n_evals": int(evals.value)}
 
 
 def combine(I, sig, n_discard: int = 0, average: str = "weighted"):

@@ -440,6 +440,29 @@ static double or_point64(int32_t D, int32_t NG, const double* R, const int32_t* 
     return jac;
 }
 
+/* The single-precision sample point of the precision split: u = (w >> 8) 2^-24
+ * from the high word of each axis alone, then the steps of or_point64 in
+ * float arithmetic with the map rounded to float.  Returns J. */
+static float or_point32(int32_t D, int32_t NG, const float* R32, const int32_t* k, const uint32_t* w,
+                        const float* map32, float* xs32, int32_t* idx)
+{
+    float jac = 1.0f;
+    for (int32_t mu = 0; mu < D; ++mu) {
+        float u = (float)(w[mu] >> 8) * 0x1p-24f;
+        float t = ((float)k[mu] + u) * R32[mu];
+        int32_t i = (int32_t)floorf(t);
+        if (i > NG - 1) i = NG - 1;
+        float delta = t - (float)i;
+        if (delta > 1.0f) delta = 1.0f;
+        const float* xm = map32 + (int64_t)mu * (NG + 1);
+        float dx = xm[i + 1] - xm[i];
+        xs32[mu] = fmaf(dx, delta, xm[i]);
+        jac = jac * ((float)NG * dx);
+        idx[mu] = i;
+    }
+    return jac;
+}
+
 int or_sample_range(const or_params* p, const or_integrand* f, const double* map,
                     const int32_t* n_h, int32_t it, int64_t h_begin, int64_t h_end,
                     double* S1, double* S2, double* H, double* W,
@@ -521,20 +544,7 @@ int or_sample_range(const or_params* p, const or_integrand* f, const double* map
                 jac_out = jac;
                 f_out = fx;
             } else {
-                float jac = 1.0f;
-                for (int32_t mu = 0; mu < D; ++mu) {
-                    float u = (float)(w[mu] >> 8) * 0x1p-24f;
-                    float t = ((float)k[mu] + u) * R32[mu];
-                    int32_t i = (int32_t)floorf(t);
-                    if (i > NG - 1) i = NG - 1;
-                    float delta = t - (float)i;
-                    if (delta > 1.0f) delta = 1.0f;
-                    const float* xm = map32 + (int64_t)mu * (NG + 1);
-                    float dx = xm[i + 1] - xm[i];
-                    xs32[mu] = fmaf(dx, delta, xm[i]);
-                    jac = jac * ((float)NG * dx);
-                    idx[mu] = i;
-                }
+                float jac = or_point32(D, NG, R32, k, w, map32, xs32, idx);
                 float fx = or_integrand_eval_f32(f, xs32);
                 float v32 = jac * fx;
                 v = (double)v32;
@@ -669,6 +679,71 @@ int or_sample_indices(const or_params* p, const int32_t* n_h, int32_t it, int64_
             }
         }
     }
+    return 0;
+}
+
+/* Every sample of hypercubes [h_begin, h_end) in (h, j) order, for per-sample
+ * inspection: its hypercube h and index j, increment index and point x on
+ * every axis ([n_samples][dim]), J and f(x) (split precisions: their single-
+ * precision values widened).  The same steps as or_sample_range. */
+int or_sample_points(const or_params* p, const or_integrand* f, const double* map, const int32_t* n_h,
+                     int32_t it, int64_t h_begin, int64_t h_end, int64_t* h_out, int32_t* j_out,
+                     int32_t* idx_out, double* x_out, double* jac_out, double* fx_out, int64_t cap)
+{
+    const int32_t D = p->dim, NG = p->n_g;
+    if (D < 1 || D > 64 || NG < 1) return -1;
+    int32_t NST[64];
+    double R[64];
+    float R32[64];
+    for (int32_t mu = 0; mu < D; ++mu) {
+        NST[mu] = or_nst_axis(p, mu);
+        R[mu] = (double)NG / (double)NST[mu];
+        R32[mu] = (float)NG / (float)NST[mu];
+    }
+    const uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32)};
+    const int fp32 = (p->precision != OR_FP64);
+    const int nblk = ((fp32 ? D : 2 * D) + 3) / 4;
+    float* map32 = NULL;
+    if (fp32) {
+        map32 = (float*)malloc(sizeof(float) * (size_t)D * (NG + 1));
+        if (!map32) return -2;
+        for (int64_t q = 0; q < (int64_t)D * (NG + 1); ++q) map32[q] = (float)map[q];
+    }
+    uint32_t w[4 * 33];
+    int32_t k[64], idx[64];
+    double xs[64];
+    float xs32[64];
+    int64_t s = 0;
+    for (int64_t h = h_begin; h < h_end; ++h) {
+        int64_t rem = h;
+        for (int32_t mu = D - 1; mu >= 0; --mu) {
+            k[mu] = (int32_t)(rem % NST[mu]);
+            rem /= NST[mu];
+        }
+        for (int32_t j = 0; j < n_h[h]; ++j, ++s) {
+            if (s >= cap) {
+                free(map32);
+                return -1;
+            }
+            for (int b = 0; b < nblk; ++b) {
+                uint32_t ctr[4] = {(uint32_t)j, (uint32_t)h, (uint32_t)it, (uint32_t)b};
+                or_philox4x32_10(ctr, key, &w[4 * b]);
+            }
+            h_out[s] = h;
+            j_out[s] = j;
+            if (!fp32) {
+                jac_out[s] = or_point64(D, NG, R, k, w, map, xs, idx);
+                fx_out[s] = or_integrand_eval(f, xs);
+                for (int32_t mu = 0; mu < D; ++mu) x_out[s * D + mu] = xs[mu];
+            } else {
+                jac_out[s] = (double)or_point32(D, NG, R32, k, w, map32, xs32, idx);
+                fx_out[s] = (double)or_integrand_eval_f32(f, xs32);
+                for (int32_t mu = 0; mu < D; ++mu) x_out[s * D + mu] = (double)xs32[mu];
+            }
+            for (int32_t mu = 0; mu < D; ++mu) idx_out[s * D + mu] = idx[mu];
+        }
+    }
+    free(map32);
     return 0;
 }
 
@@ -1110,9 +1185,11 @@ int64_t or_iteration(const or_params* p, const or_integrand* f, double* map, int
 /* Full driver over n_iter iterations starting from the given map and
  * allocation (callers use or_map_init / or_alloc_init for a fresh start).
  * I_j and V_j (variances) of each iteration are returned; ties_total counts
- * near-ties over all reallocations. */
+ * near-ties over all reallocations, evals_total the samples drawn (the sum
+ * of n_h over the iterations). */
 int or_integrate(const or_params* p, const or_integrand* f, double* map, int32_t* n_h,
-                 int32_t it0, int32_t n_iter, double* I_j, double* V_j, int64_t* ties_total)
+                 int32_t it0, int32_t n_iter, double* I_j, double* V_j, int64_t* ties_total,
+                 int64_t* evals_total)
 {
     const int64_t nhc = or_n_hypercubes(p);
     double* S1 = (double*)malloc(sizeof(double) * (size_t)nhc);
@@ -1123,13 +1200,15 @@ int or_integrate(const or_params* p, const or_integrand* f, double* map, int32_t
         free(S1); free(S2); free(H); free(W);
         return -1;
     }
-    int64_t ties = 0;
+    int64_t ties = 0, evals = 0;
     for (int32_t j = 0; j < n_iter; ++j) {
+        for (int64_t h = 0; h < nhc; ++h) evals += n_h[h];
         int64_t t = or_iteration(p, f, map, n_h, it0 + j, S1, S2, H, W, &I_j[j], &V_j[j]);
         if (t < 0) { ties = -1; break; }
         ties += t;
     }
     free(S1); free(S2); free(H); free(W);
     if (ties_total) *ties_total = ties;
+    if (evals_total) *evals_total = evals;
     return ties < 0 ? -1 : 0;
 }

@@ -121,6 +121,8 @@ def lib():
             "vp_iteration_get": ([vp, ip], C.c_int),
             "vp_iteration_set": ([vp, C.c_int32], C.c_int),
             "vp_accum_get": ([vp, dp, dp, dp, dp], C.c_int),
+            "vp_debug_dump": ([vp, C.c_int64, C.c_int64], C.c_int),
+            "vp_debug_dump_get": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), ip, ip, dp, dp, dp], C.c_int),
             "vp_state_export": ([vp, vp, C.POINTER(C.c_size_t)], C.c_int),
             "vp_state_import": ([vp, vp, C.c_size_t], C.c_int),
             "vp_profile_enable": ([vp, C.c_int32], C.c_int),
@@ -328,6 +330,28 @@ class Problem:
         W = np.empty((P.dim, P.n_g))
         check(lib().vp_accum_get(self.h, _dp(S1), _dp(S2), _dp(H), _dp(W)), "vp_accum_get")
         return {"S1": S1, "S2": S2, "H": H, "W": W}
+
+    def debug_dump(self, first: int, count: int):
+        """Arms the per-sample dump of the next iteration (vp_debug_dump)."""
+        check(lib().vp_debug_dump(self.h, int(first), int(count)), "vp_debug_dump")
+        self._dump_count = int(count)
+
+    def debug_dump_get(self):
+        """The dumped samples (vp_debug_dump_get): h, j [n]; idx, x [n][dim]; jac, fx [n]."""
+        c = self._dump_count
+        D = self.params.dim
+        n = C.c_int64()
+        h = np.empty(c, dtype=np.int64)
+        j = np.empty(c, dtype=np.int32)
+        idx = np.empty(D * c, dtype=np.int32)
+        x = np.empty(D * c)
+        jac = np.empty(c)
+        fx = np.empty(c)
+        check(lib().vp_debug_dump_get(self.h, C.byref(n), h.ctypes.data_as(C.POINTER(C.c_int64)), _ip(j), _ip(idx),
+                                      _dp(x), _dp(jac), _dp(fx)), "vp_debug_dump_get")
+        m = n.value
+        return {"h": h[:m].copy(), "j": j[:m].copy(), "idx": idx[:D * m].reshape(D, m).T.copy(),
+                "x": x[:D * m].reshape(D, m).T.copy(), "jac": jac[:m].copy(), "fx": fx[:m].copy()}
 
     def export_state(self) -> bytes:
         n = C.c_size_t(0)

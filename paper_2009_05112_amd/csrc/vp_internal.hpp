@@ -91,6 +91,21 @@ __device__ __forceinline__ int64_t batch_pos(int64_t pos, int64_t n_tot)
 }
 
 
+// Per-sample dump of one iteration (vp_debug_dump): samples [first, first +
+// count) of the iteration whose Philox index is `it`, as structure of arrays
+// of `count` entries (x and idx: [dim][count]); count == 0 is off.
+struct DumpArgs {
+    int64_t* h;
+    int32_t* j;
+    int32_t* idx;
+    double* x;
+    double* jac;
+    double* fx;
+    int64_t first, count;
+    uint32_t it;
+    uint32_t pad;
+};
+
 struct SampleArgs {
     const double* map;      // [dim][n_g + 1]
     const float* map32;     // FP32 copy (split paths)
@@ -126,6 +141,7 @@ struct SampleArgs {
     int32_t hist_axes;      // training data of axes [0, hist_axes) privatised in LDS
     int32_t map_lds;        // map placement (MapPlace)
     int32_t chunk;          // samples per lane per tile
+    DumpArgs dump;          // per-sample dump (debugging and parity tests)
 };
 
 // Scalars every iteration kernel may need about one request (the single

@@ -23,6 +23,8 @@
 
 using namespace vp;
 
+static constexpr int64_t kMaxDump = (int64_t)1 << 24;
+
 namespace {
 thread_local std::string g_err;
 }
@@ -258,6 +260,7 @@ void vp::problem_free(vp_problem* p)
     } else {
         (void)hipFree(p->arena);
     }
+    if (p->dump_mem) (void)hipFree(p->dump_mem);
     for (auto e : p->ev_pending) (void)hipEventDestroy(e);
     for (auto e : p->ev_free) (void)hipEventDestroy(e);
     delete p;
@@ -1154,6 +1157,80 @@ vp_status vp_accum_get(vp_problem* p, double* S1, double* S2, double* H, double*
     if (S2) VP_HIP(hipMemcpy(S2, p->S2, sizeof(double) * p->n_hc, hipMemcpyDeviceToHost));
     if (H) VP_HIP(hipMemcpy(H, p->H, sizeof(double) * nb, hipMemcpyDeviceToHost));
     if (W) VP_HIP(hipMemcpy(W, p->W, sizeof(double) * nb, hipMemcpyDeviceToHost));
+    return VP_OK;
+}
+
+// Per-sample dump: the next iteration's sampling kernel writes samples
+// [first, first + count) through a second copy of its sample walk, taken only
+// by tiles that hold such samples.
+vp_status vp_debug_dump(vp_problem* p, int64_t first, int64_t count)
+{
+    if (!p || first < 0 || count < 0 || count > kMaxDump)
+        return fail(VP_ERR_INVALID_ARG, "problem is NULL, first < 0 or count outside [0, %lld]", (long long)kMaxDump);
+    if (p->batch_fn) return fail(VP_ERR_STATE, "the per-sample dump is not available for batched integrands");
+    VP_HIP(hipSetDevice(p->ctx->device));
+    VP_HIP(hipStreamSynchronize(p->ctx->stream));
+    const int D = p->P.dim;
+    const size_t need = (size_t)count * (sizeof(int64_t) + sizeof(int32_t) * (1 + D) + sizeof(double) * (D + 2));
+    if (count > 0 && need > p->dump_bytes) {
+        if (p->dump_mem) VP_HIP(hipFree(p->dump_mem));
+        p->dump_mem = nullptr;
+        p->dump_bytes = 0;
+        if (hipMalloc((void**)&p->dump_mem, need) != hipSuccess) {
+            p->dump_mem = nullptr;
+            return fail(VP_ERR_OOM, "dump of %lld samples", (long long)count);
+        }
+        p->dump_bytes = need;
+    }
+    DumpArgs d = {};
+    if (count > 0) {
+        char* b = p->dump_mem;
+        d.h = reinterpret_cast<int64_t*>(b);
+        d.x = reinterpret_cast<double*>(b + (size_t)count * 8);
+        d.jac = d.x + (size_t)count * D;
+        d.fx = d.jac + count;
+        d.j = reinterpret_cast<int32_t*>(d.fx + count);
+        d.idx = d.j + count;
+        d.first = first;
+        d.count = count;
+        d.it = (uint32_t)p->it;
+        // entries the iteration does not reach keep h = -1
+        VP_HIP(hipMemset(d.h, 0xff, (size_t)count * sizeof(int64_t)));
+    }
+    p->dump = d;
+    p->req.s.dump = d;
+    VP_HIP(hipMemcpy((char*)p->d_req + offsetof(ReqArgs, s) + offsetof(SampleArgs, dump), &d, sizeof d,
+                     hipMemcpyHostToDevice));
+    return VP_OK;
+}
+
+vp_status vp_debug_dump_get(vp_problem* p, int64_t* n_out, int64_t* h, int32_t* j, int32_t* idx, double* x,
+                            double* jac, double* fx)
+{
+    if (!p || !n_out) return fail(VP_ERR_INVALID_ARG, "problem and n_out are required");
+    if (p->dump.count == 0) return fail(VP_ERR_STATE, "no dump is armed");
+    VP_HIP(hipSetDevice(p->ctx->device));
+    VP_HIP(hipStreamSynchronize(p->ctx->stream));
+    if (p->it <= (int32_t)p->dump.it) return fail(VP_ERR_STATE, "the dumped iteration has not run");
+    const int64_t c = p->dump.count;
+    const int D = p->P.dim;
+    std::vector<int64_t> hh((size_t)c);
+    VP_HIP(hipMemcpy(hh.data(), p->dump.h, sizeof(int64_t) * c, hipMemcpyDeviceToHost));
+    int64_t n = 0;
+    while (n < c && hh[(size_t)n] >= 0) ++n;
+    *n_out = n;
+    // the arrays are [count] and [dim][count] on the device; the caller's are
+    // [n] and [dim][n]
+    if (h) memcpy(h, hh.data(), sizeof(int64_t) * n);
+    if (j && n) VP_HIP(hipMemcpy(j, p->dump.j, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    if (jac && n) VP_HIP(hipMemcpy(jac, p->dump.jac, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (fx && n) VP_HIP(hipMemcpy(fx, p->dump.fx, sizeof(double) * n, hipMemcpyDeviceToHost));
+    for (int d = 0; d < D && n; ++d) {
+        if (idx) VP_HIP(hipMemcpy(idx + (size_t)d * n, p->dump.idx + (size_t)d * c, sizeof(int32_t) * n,
+                                  hipMemcpyDeviceToHost));
+        if (x) VP_HIP(hipMemcpy(x + (size_t)d * n, p->dump.x + (size_t)d * c, sizeof(double) * n,
+                                hipMemcpyDeviceToHost));
+    }
     return VP_OK;
 }
 

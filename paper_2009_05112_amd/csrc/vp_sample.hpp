@@ -436,10 +436,18 @@ struct BatchOut {
     int64_t n, cap, pos;
 };
 
-template <int D, int MAPL, int KT, typename FP, bool GEN = false, bool MIX = false>
+// Where a dumped sample goes (vp_debug_dump): entry `pos` of the dump's
+// arrays (x and idx [dim][count]); J and f(x) are written apart.
+struct DumpPos {
+    const DumpArgs* d;
+    int64_t pos;
+};
+
+template <int D, int MAPL, int KT, typename FP, bool GEN = false, bool MIX = false, bool DUMP = false>
 __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair64<MAPL>& map, FP fc,
                                               uint32_t j, uint32_t h, const int32_t* k,
-                                              int32_t* idx, int kind, int K, const BatchOut* out = nullptr)
+                                              int32_t* idx, int kind, int K, const BatchOut* out = nullptr,
+                                              const DumpPos* dp = nullptr)
 {
     // Axes are processed in groups of four: group g takes its high words from
     // block g and its low words from the block(s) holding words D+4g..D+4g+3,
@@ -488,21 +496,30 @@ __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair6
             } else {
                 f_axis<D, KT, double, FP>(fc, kind, K, mu, x, st);
             }
+            if constexpr (DUMP) {
+                dp->d->x[mu * dp->d->count + dp->pos] = x;
+                dp->d->idx[mu * dp->d->count + dp->pos] = i;
+            }
         }
     }
     if constexpr (GEN) {
         out->jac[out->pos] = jac;
         return 0.0;
     } else {
-        return jac * f_finish<D, KT, double, FP>(fc, kind, K, st);
+        const double fx = f_finish<D, KT, double, FP>(fc, kind, K, st);
+        if constexpr (DUMP) {
+            dp->d->jac[dp->pos] = jac;
+            dp->d->fx[dp->pos] = fx;
+        }
+        return jac * fx;
     }
 }
 
 // FP32 split: u = (w >> 8) 2^-24 from the high word of each axis alone.
-template <int D, int MAPL, int KT, typename FP, bool MIX = false>
+template <int D, int MAPL, int KT, typename FP, bool MIX = false, bool DUMP = false>
 __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32<MAPL>& map, FP fc,
                                              uint32_t j, uint32_t h, const int32_t* k, int32_t* idx,
-                                             int kind, int K)
+                                             int kind, int K, const DumpPos* dp = nullptr)
 {
     constexpr int NG4 = (D + 3) / 4;
     const int n_g = a.n_g;
@@ -532,9 +549,18 @@ __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32
             jac = jac * ((float)n_g * dx);
             idx[mu] = i;
             f_axis<D, KT, float, FP>(fc, kind, K, mu, x, st);
+            if constexpr (DUMP) {
+                dp->d->x[mu * dp->d->count + dp->pos] = (double)x;
+                dp->d->idx[mu * dp->d->count + dp->pos] = i;
+            }
         }
     }
-    return jac * f_finish<D, KT, float, FP>(fc, kind, K, st);
+    const float fx = f_finish<D, KT, float, FP>(fc, kind, K, st);
+    if constexpr (DUMP) {
+        dp->d->jac[dp->pos] = (double)jac;
+        dp->d->fx[dp->pos] = (double)fx;
+    }
+    return jac * fx;
 }
 
 // ---------------------------------------------------------------- the kernel
@@ -564,6 +590,97 @@ __device__ __forceinline__ void put_training(double* rec, int64_t stride, int ha
 #pragma unroll
         for (int mu = 0; mu < D; ++mu)
             if (mu >= ha) rb[(mu - ha) * stride + pos] = (uint16_t)idx[mu];
+    }
+}
+
+// Per-sample dump (vp_debug_dump) of the samples of [s_a, s_b) that lie in
+// the dumped range: each is evaluated again through the same per-sample
+// function as in the walk, from its hypercube h (binary search over the
+// offsets) and index j, and written with x, the increment indices, J and
+// f(x).  It sets up its own copies of the map and constant accessors (the
+// LDS contents are still those of the walk).
+template <int D, int PREC, int MAPL, int KIND, bool REC, int KT, bool MIX>
+__device__ __forceinline__ void dump_share(const SampleArgs& a, int64_t s_a, int64_t s_b, int lane,
+                                        unsigned char* lds_raw)
+{
+    typedef typename std::conditional<PREC == P_FP64, double, float>::type MapT;
+    const int n_g = a.n_g;
+    const int ha = REC ? a.hist_axes : D;
+    const size_t hist_bytes = (size_t)ha * n_g * 16;
+    MapT* lds_map = reinterpret_cast<MapT*>(lds_raw + hist_bytes);
+    const MapT* lds_fc = reinterpret_cast<const MapT*>(lds_raw + fc_lds_offset(hist_bytes, MAPL, PREC, D, n_g));
+    const MapT* gmap;
+    if constexpr (PREC == P_FP64) gmap = a.map;
+    else gmap = a.map32;
+    typedef typename std::conditional<PREC == P_FP64, MapPair64<MAPL>, MapPair32<MAPL>>::type MapAcc;
+    MapAcc map;
+    map.lds = lds_map;
+    map.inner0 = (uint32_t)((D - kMapInnerAxes) * (n_g + 1));
+    map.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)gmap, (short)0,
+                                                 (int)((size_t)D * (n_g + 1) * sizeof(MapT)), kBufferWord3);
+    constexpr bool FC_SMEM = (KIND == K_GAUSS_MIX);
+    typedef __attribute__((address_space(4))) const MapT ConstT;
+    ConstT* fcg = (ConstT*)a.fc;
+    const int kind = KIND ? KIND : a.f->kind;
+    const int K = a.f->n_terms;
+    SampleHot hot;
+    hot.key0 = a.key0;
+    hot.key1 = a.key1;
+    hot.it = a.it;
+    hot.n_g = n_g;
+    hot.R = a.R;
+    hot.R32 = a.R32;
+    const MapT* mix_r = lds_fc + fc_strat_offset(kind, D);
+    const MapT* mix_n = mix_r + D;
+    if constexpr (PREC == P_FP64) {
+        hot.Rv = reinterpret_cast<const double*>(mix_r);
+        hot.Rv32 = nullptr;
+    } else {
+        hot.Rv = nullptr;
+        hot.Rv32 = reinterpret_cast<const float*>(mix_r);
+    }
+    const int64_t* offs = a.offs;
+    const int64_t* ob = a.obase;
+    const int64_t n_hc = a.n_hc;
+    const uint32_t n_st = (uint32_t)a.n_st;
+    const int64_t d0 = s_a > a.dump.first ? s_a : a.dump.first;
+    const int64_t d_end = a.dump.first + a.dump.count;
+    const int64_t d1 = s_b < d_end ? s_b : d_end;
+    for (int64_t sd = d0 + lane; sd < d1; sd += kWave) {
+        int64_t lo = 0, hi = n_hc;  // offset(lo) <= sd < offset(hi)
+        while (hi - lo > 1) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (gofs(offs, ob, mid) <= sd) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t h = (uint32_t)lo;
+        const uint32_t j = (uint32_t)(sd - gofs(offs, ob, lo));
+        int32_t k[D], idx[D];
+        uint32_t r = h;
+#pragma unroll
+        for (int m = D - 1; m >= 0; --m) {
+            const uint32_t nm = MIX ? (uint32_t)mix_n[m] : n_st;
+            k[m] = (int32_t)(r % nm);
+            r /= nm;
+        }
+        DumpPos dp;
+        dp.d = &a.dump;
+        dp.pos = sd - a.dump.first;
+        a.dump.h[dp.pos] = (int64_t)h;
+        a.dump.j[dp.pos] = (int32_t)j;
+        if constexpr (PREC == P_FP64) {
+            if constexpr (FC_SMEM)
+                (void)sample_fp64<D, MAPL, KT, ConstT*, false, false, true>(hot, map, fcg, j, h, k, idx, kind, K,
+                                                                           nullptr, &dp);
+            else
+                (void)sample_fp64<D, MAPL, KT, const MapT*, false, MIX, true>(hot, map, lds_fc, j, h, k, idx, kind, K,
+                                                                             nullptr, &dp);
+        } else {
+            if constexpr (FC_SMEM)
+                (void)sample_fp32<D, MAPL, KT, ConstT*, false, true>(hot, map, fcg, j, h, k, idx, kind, K, &dp);
+            else
+                (void)sample_fp32<D, MAPL, KT, const MapT*, MIX, true>(hot, map, lds_fc, j, h, k, idx, kind, K, &dp);
+        }
     }
 }
 
@@ -926,6 +1043,17 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
         empty.s2 = 0.0;
         edges[2 * wave] = empty;
         edges[2 * wave + 1] = empty;
+    }
+
+    // Per-sample dump (vp_debug_dump), after the share is done.  Every value
+    // it needs is read again through a pointer the compiler cannot trace to
+    // the one above, so that nothing is kept live across the walk for it.
+    if constexpr (!GEN && !ACC) {
+        int z;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+        const SampleArgs* ap = &a + z;
+        if (ap->dump.count > 0 && ap->dump.it == ap->it)
+            dump_share<D, PREC, MAPL, KIND, REC, KT, MIX>(*ap, s_a, s_b, lane, lds_raw);
     }
 
     // non-finite samples: one atomic per wave

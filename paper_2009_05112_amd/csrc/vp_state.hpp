@@ -124,6 +124,10 @@ struct vp_problem {
     size_t lds;
     int64_t n_waves;
     int32_t hist_cap;            // capacity of the estimate history
+    // per-sample dump (vp_debug_dump): its own allocation
+    char* dump_mem = nullptr;
+    size_t dump_bytes = 0;
+    vp::DumpArgs dump = {};
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> ev_pending;  // pairs: k1 start, k1 end, it start, it end

@@ -281,3 +281,22 @@ def test_nonfinite_reported(ctx):
         gp.result()
     assert e.value.status == B.VP_ERR_NUMERIC
     assert gp.result(allow_nonfinite=True)["nonfinite"] > 0
+
+
+@pytest.mark.parametrize("dim,n_ev,n_iter", [(4, 100_000, 6), (8, 1_000_000, 4)])
+def test_stepwise_plus2_rule(ctx, dim, n_ev, n_iter):
+    """The alternative allocation rule of Sec. 3 step 4, n_h = floor(q) + 2:
+    every iteration compared with the oracle, the next allocation exactly."""
+    if dim == 4:
+        p, f = W.cfg_small_d4()
+    else:
+        p, f = W.cfg_diag_d8(n_ev=n_ev)
+    p = p.with_(realloc_plus2=True, n_iter=n_iter, seed=31)
+    gp, op = _pair(ctx, p, f)
+    for _ in range(n_iter):
+        out = step_and_compare(gp, op)
+    n = out["n_new"]
+    assert n.min() >= 2
+    # the +2 rule adds two samples to every hypercube's floor(q): the total
+    # exceeds N_ev by about 1.5 per hypercube, unlike the max(2, .) rule
+    assert n.sum() > p.n_ev + gp.n_hc

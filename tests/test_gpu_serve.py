@@ -240,3 +240,61 @@ def test_destroy_with_work_in_flight(ctx):
         s.submit(p.with_(n_iter=100_000, seed=i), f)
     time.sleep(0.05)
     s.close()
+
+
+def oracle_mix():
+    """Small requests the CPU oracle can run end to end: the served-batch
+    shape (Gaussian mixtures, D 2..16, N_g = 500), the stream shape
+    (correlated Gaussians, D >= 13, N_g = 300), a frozen phase with the
+    unweighted average, mixed stratification, given per-axis counts, the +2
+    allocation rule, and the single-precision split."""
+    reqs = [(r.params, r.integrand) for r in
+            W.served_batch(n_req=5, seed=13, nev_log=(3.6, 4.3), n_iter=4, n_g=500)]
+    for r in W.served_stream(n_req=3, rate=0.0, seed=17, d_range=(13, 21), nev_log=(4.0, 4.4),
+                             it_range=(2, 4), n_g=300):
+        reqs.append((r.params, r.integrand))
+    p, f = W.cfg_small_d4()
+    reqs.append((p.with_(n_ev=20_000, n_iter=6, n_adapt=3, n_discard=3, average="unweighted", seed=91), f))
+    reqs.append((p.with_(n_ev=30_000, n_iter=4, strat="mixed", seed=92), f))
+    reqs.append((p.with_(n_ev=20_000, n_iter=3, n_st_axes=np.array([7, 1, 5, 2]), seed=93), f))
+    reqs.append((p.with_(n_ev=25_000, n_iter=5, realloc_plus2=True, seed=94), f))
+    pd, fd = W.cfg_diag_d8(n_ev=60_000)
+    reqs.append((pd.with_(n_iter=3, seed=95, realloc_plus2=True), fd))
+    reqs.append((pd.with_(n_iter=3, seed=96, precision="fp32_acc64"), fd))
+    return reqs
+
+
+def test_served_results_equal_oracle(ctx):
+    """Every served request against the CPU oracle run end to end on the same
+    parameters (Sec. 3 steps 1-4, per request): sample counts and degrees of
+    freedom exactly; mean and error at 1e-12 (same-precision oracle and 2e-6
+    for the single-precision split), chi^2 at 1e-9.  A request where either
+    side met an allocation near-tie may take other sample counts after it (a
+    single hypercube counts its exact q = N_ev as one, on both sides, although
+    nothing can differ there).  Such a request is held to the tight bar whenever the sample
+    counts agree, else to 5 sigma; at most one may differ."""
+    import oracle
+    reqs = oracle_mix()
+    s = B.Server(ctx)
+    tickets = [s.submit(p, f) for p, f in reqs]
+    res = [s.wait(t) for t in tickets]
+    st = s.stats()
+    s.close()
+    assert st["peak_active"] > 1
+    tied = 0
+    for i, ((p, f), r) in enumerate(zip(reqs, res)):
+        o = oracle.Problem(p, f).integrate()
+        what = f"request {i} (D={p.dim}, N_ev={p.n_ev}, {f.kind}, {p.precision})"
+        assert r["n_iter_done"] == p.n_iter, what
+        if (r["ties"] or o["ties"]) and r["n_evals"] != o["n_evals"]:
+            tied += 1
+            assert abs(r["mean"] - o["mean"]) <= 5 * np.hypot(r["sdev"], o["sdev"]), what
+            continue
+        assert r["n_evals"] == o["n_evals"], (what, r["n_evals"], o["n_evals"])
+        assert r["dof"] == o["dof"], what
+        rtol = 1e-12 if p.precision == "fp64" else 2e-6
+        assert abs(r["mean"] - o["mean"]) <= rtol * abs(o["mean"]), (what, r["mean"], o["mean"])
+        assert abs(r["sdev"] - o["sdev"]) <= rtol * abs(o["sdev"]), (what, r["sdev"], o["sdev"])
+        if np.isfinite(o["chi2"]):
+            assert abs(r["chi2"] - o["chi2"]) <= (1e-9 if p.precision == "fp64" else 1e-3) * max(abs(o["chi2"]), 1e-3), what
+    assert tied <= 1

@@ -396,3 +396,32 @@ def test_plus2_rule_exact_counts(orc, beta):
     plain = orc.Problem(p.with_(n_ev=n_ev), W.const(2), n_st=4)
     got0, _ = plain.realloc(S1, S2, n)
     np.testing.assert_array_equal(got0, np.maximum(2, m))
+
+
+def test_sample_points_consistent(orc):
+    """The per-sample view (h, j, increment indices, x, J, f) agrees with the
+    index enumeration, with the recorded values v = J f of the sampling pass,
+    and with the map: x lies in its increment, J is the product of N_g dx."""
+    p = W.Params(dim=3, n_ev=5000, n_g=17, seed=4)
+    f = W.gauss_single(3, coef=20.0)
+    pr = orc.Problem(p, f)
+    rng = np.random.default_rng(2)
+    x0 = np.sort(rng.random((3, 16)), axis=1)
+    fmap = np.concatenate([np.zeros((3, 1)), x0, np.ones((3, 1))], axis=1)
+    n_h = rng.integers(2, 9, size=pr.n_hc).astype(np.int32)
+    pts = pr.sample_points(fmap, n_h, it=2)
+    ns = int(n_h.sum())
+    np.testing.assert_array_equal(pts["h"], np.repeat(np.arange(pr.n_hc), n_h))
+    np.testing.assert_array_equal(pts["j"], np.concatenate([np.arange(n) for n in n_h]))
+    np.testing.assert_array_equal(pts["idx"], pr.sample_indices(n_h, it=2))
+    rec = pr.sample_range(fmap, n_h, 2, records=ns)["rec"]
+    np.testing.assert_array_equal(pts["jac"], rec["jac"])
+    np.testing.assert_array_equal(pts["fx"], rec["fx"])
+    np.testing.assert_array_equal(pts["jac"] * pts["fx"], rec["v"])
+    for m in range(3):
+        lo = fmap[m, pts["idx"][:, m]]
+        hi = fmap[m, pts["idx"][:, m] + 1]
+        assert np.all((pts["x"][:, m] >= lo) & (pts["x"][:, m] <= hi))
+    dx = np.stack([fmap[m, pts["idx"][:, m] + 1] - fmap[m, pts["idx"][:, m]] for m in range(3)], axis=1)
+    np.testing.assert_allclose(pts["jac"], np.prod(p.n_g * dx, axis=1), rtol=1e-14)
+    np.testing.assert_allclose(pts["fx"], [pr.f_eval(x) for x in pts["x"]], rtol=1e-15)
