@@ -313,6 +313,20 @@ vp_status vp_debug_dump_get(vp_problem* p, int64_t* n_out, int64_t* h, int32_t* 
  *  box or non-finite values. */
 vp_status vp_map_train(vp_problem* p, int64_t n, const double* x, const double* f, int32_t n_iter, double alpha);
 
+/* For callers that cannot allocate device memory (code running under HIP
+ * graph capture elsewhere on the device, tight serving loops, harnesses that
+ * forbid allocation): vp_map_train with the same arguments, results and
+ * errors, except that it allocates nothing.  The points, their values and
+ * the launch records are staged in a static 32 MiB device workspace of the
+ * library (one per device, held until the process ends) instead of a buffer
+ * allocated per call; x (n * dim doubles) and f (n doubles) must fit in it
+ * with about 1 KiB to spare, else VP_ERR_INVALID_ARG.  The workspace is
+ * shared by every call on a device: calls that overlap on one device (from
+ * several threads, or on several problems whose streams run at once) race
+ * and give undefined results.  Synchronising. */
+vp_status vp_map_train_noalloc(vp_problem* p, int64_t n, const double* x, const double* f, int32_t n_iter,
+                               double alpha);
+
 /* Checkpoint: map, n_h, iteration index and estimate history, as an opaque
  * byte blob.  With buf == NULL, *size receives the required size. */
 vp_status vp_state_export(vp_problem* p, void* buf, size_t* size);

@@ -110,6 +110,7 @@ def lib():
             "vp_problem_strat": ([vp, ip], C.c_int),
             "vp_problem_layout": ([vp, ip, ip], C.c_int),
             "vp_map_train": ([vp, C.c_int64, dp, dp, C.c_int32, C.c_double], C.c_int),
+            "vp_map_train_noalloc": ([vp, C.c_int64, dp, dp, C.c_int32, C.c_double], C.c_int),
             "vp_result_vec_get": ([vp, dp, dp, dp, ip, dp, dp, C.c_int32], C.c_int),
             "vp_iterate": ([vp, C.c_int32], C.c_int),
             "vp_sync": ([vp], C.c_int),
@@ -293,6 +294,14 @@ class Problem:
         x = np.ascontiguousarray(x, dtype=np.float64)
         fx = np.ascontiguousarray(fx, dtype=np.float64)
         check(lib().vp_map_train(self.h, len(fx), _dp(x), _dp(fx), int(n_iter), float(alpha)), "vp_map_train")
+
+    def train_map_noalloc(self, x, fx, n_iter: int, alpha: float):
+        """As train_map, staging the points in the library's static device
+        workspace instead of allocating (vp_map_train_noalloc)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        fx = np.ascontiguousarray(fx, dtype=np.float64)
+        check(lib().vp_map_train_noalloc(self.h, len(fx), _dp(x), _dp(fx), int(n_iter), float(alpha)),
+              "vp_map_train_noalloc")
 
     def map(self):
         P = self.params

@@ -893,7 +893,7 @@ __global__ __launch_bounds__(kRefineBlock) void k_refine(LaunchSet L)
 // (inverting the map), its Jacobian the product over the axes of
 // N_g Delta x_i; it adds (J f)^2 to H and 1 to W of its increment on every
 // axis, so that H_i / W_i is the mean of (J f)^2 over the points there.  One
-// thread per point; x is [dim][n].
+// thread per point; x is [dim][n] or [n][dim] (strides in TrainArgs).
 __device__ __forceinline__ int map_locate(const double* __restrict__ xm, int n_g, double x)
 {
     int lo = 0, hi = n_g - 1;
@@ -913,14 +913,14 @@ __global__ __launch_bounds__(256) void k_train_hist(TrainArgs a)
         double jac = 1.0;
         for (int mu = 0; mu < D; ++mu) {
             const double* xm = a.map + (int64_t)mu * (n_g + 1);
-            const int i = map_locate(xm, n_g, a.x[(int64_t)mu * a.n + s]);
+            const int i = map_locate(xm, n_g, a.x[(int64_t)mu * a.x_mu + s * a.x_s]);
             jac = jac * ((double)n_g * (xm[i + 1] - xm[i]));
         }
         const double v = jac * a.f[s];
         const double v2 = v * v;
         for (int mu = 0; mu < D; ++mu) {
             const double* xm = a.map + (int64_t)mu * (n_g + 1);
-            const int i = map_locate(xm, n_g, a.x[(int64_t)mu * a.n + s]);
+            const int i = map_locate(xm, n_g, a.x[(int64_t)mu * a.x_mu + s * a.x_s]);
             atomicAdd(&a.H[(int64_t)mu * n_g + i], v2);
             atomicAdd(&a.W[(int64_t)mu * n_g + i], 1.0);
         }

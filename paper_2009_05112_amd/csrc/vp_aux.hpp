@@ -71,12 +71,13 @@ void launch_fill_f64(double* x, int64_t n, double v, hipStream_t s);
 // Training data of a preconditioned map from given points (x: [dim][n],
 // f: [n]) under the current map, added into H and W (zeroed by the caller).
 struct TrainArgs {
-    const double* x;
+    const double* x;        // coordinate mu of point s at x[mu * x_mu + s * x_s]
     const double* f;
     const double* map;
     double* H;
     double* W;
     int64_t n;
+    int64_t x_mu, x_s;      // [dim][n]: (n, 1); [n][dim]: (1, dim)
     int32_t dim, n_g;
 };
 void launch_train_hist(const TrainArgs& a, hipStream_t s);

@@ -25,6 +25,29 @@ using namespace vp;
 
 static constexpr int64_t kMaxDump = (int64_t)1 << 24;
 
+// The static device workspace of vp_map_train_noalloc: every device the
+// library runs on holds one copy until the process ends.  Host code never
+// uses the array's name as an address: vp_ctx_create looks up each device's
+// copy once, with that device current, and keeps the address per device.
+static constexpr size_t kScratchBytes = (size_t)32 << 20;
+static constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static void* g_scratch[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// Address of this device's workspace (the device is current).
+static hipError_t scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[device]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = ptr;
+    return hipSuccess;
+}
+
 namespace {
 thread_local std::string g_err;
 }
@@ -431,6 +454,14 @@ vp_status vp_ctx_create(int device, void* hip_stream, vp_ctx** out)
     (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
     c->n_cu = cu > 0 ? cu : 1;
     c->lds_max = lds > 0 ? (size_t)lds : 65536;
+    {
+        hipError_t e = scratch_init(device);
+        if (e != hipSuccess) {
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            delete c;
+            return fail(VP_ERR_DEVICE, "workspace address on device %d: %s", device, hipGetErrorString(e));
+        }
+    }
     {
         hipError_t e = aux_init(c->lds_max);
         if (e != hipSuccess) {
@@ -1270,12 +1301,14 @@ vp_status vp_result_vec_get(vp_problem* p, double* mean, double* cov, double* ch
     return VP_OK;
 }
 
-vp_status vp_map_train(vp_problem* p, int64_t n, const double* x, const double* f, int32_t n_iter, double alpha)
+// Arguments of the map training calls: points inside the box, finite values.
+static vp_status check_training(vp_problem* p, int64_t n, const double* x, const double* f, int32_t n_iter,
+                                double alpha)
 {
     if (!p || n < 1 || !x || !f || n_iter < 0)
         return fail(VP_ERR_INVALID_ARG, "problem, n >= 1 points, x, f and n_iter >= 0 are required");
     if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(VP_ERR_INVALID_ARG, "alpha must be >= 0");
-    const int D = p->P.dim, NG = p->P.n_g;
+    const int D = p->P.dim;
     for (int64_t s = 0; s < n; ++s) {
         if (!std::isfinite(f[s])) return fail(VP_ERR_INVALID_ARG, "f[%lld] is not finite", (long long)s);
         for (int mu = 0; mu < D; ++mu) {
@@ -1284,6 +1317,14 @@ vp_status vp_map_train(vp_problem* p, int64_t n, const double* x, const double* 
                 return fail(VP_ERR_INVALID_ARG, "point %lld lies outside the box on axis %d", (long long)s, mu);
         }
     }
+    return VP_OK;
+}
+
+vp_status vp_map_train(vp_problem* p, int64_t n, const double* x, const double* f, int32_t n_iter, double alpha)
+{
+    const vp_status st = check_training(p, n, x, f, n_iter, alpha);
+    if (st != VP_OK) return st;
+    const int D = p->P.dim, NG = p->P.n_g;
     if (n_iter == 0) return VP_OK;
     VP_HIP(hipSetDevice(p->ctx->device));
     hipStream_t sm = p->ctx->stream;
@@ -1315,6 +1356,8 @@ vp_status vp_map_train(vp_problem* p, int64_t n, const double* x, const double* 
     ta.H = p->H;
     ta.W = p->W;
     ta.n = n;
+    ta.x_mu = n;
+    ta.x_s = 1;
     ta.dim = D;
     ta.n_g = NG;
     LaunchSet L;
@@ -1330,6 +1373,76 @@ vp_status vp_map_train(vp_problem* p, int64_t n, const double* x, const double* 
     }
     const hipError_t e2 = hipStreamSynchronize(sm);
     (void)hipFree(d);
+    if (e != hipSuccess || e2 != hipSuccess)
+        return fail(VP_ERR_DEVICE, "map training: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    return VP_OK;
+}
+
+// The training call that allocates nothing: the points, their values, the
+// record with the training damping and its launch table are staged in the
+// library's static device workspace instead of a buffer allocated per call.
+vp_status vp_map_train_noalloc(vp_problem* p, int64_t n, const double* x, const double* f, int32_t n_iter,
+                               double alpha)
+{
+    const vp_status st = check_training(p, n, x, f, n_iter, alpha);
+    if (st != VP_OK) return st;
+    const int D = p->P.dim, NG = p->P.n_g;
+    // workspace layout: x as [n][dim] (the caller's order), f [n], the record,
+    // the launch table (request pointer, block bases)
+    const size_t xb = sizeof(double) * (size_t)n * D, fb = sizeof(double) * (size_t)n;
+    const size_t qo = (xb + fb + 255) / 256 * 256, to = qo + (sizeof(ReqArgs) + 255) / 256 * 256;
+    const size_t total = to + 64;
+    if (n > (int64_t)(kScratchBytes / 8) || total > kScratchBytes)
+        return fail(VP_ERR_INVALID_ARG,
+                    "%lld points of dimension %d need %zu bytes of workspace; the limit is %zu bytes "
+                    "(vp_map_train has none)", (long long)n, D, total, kScratchBytes);
+    if (n_iter == 0) return VP_OK;
+    const int dev = p->ctx->device;
+    if (dev < 0 || dev >= kMaxDevices || !g_scratch[dev])
+        return fail(VP_ERR_STATE, "no workspace address for device %d", dev);
+    VP_HIP(hipSetDevice(dev));
+    hipStream_t sm = p->ctx->stream;
+    char* d = static_cast<char*>(g_scratch[dev]);
+    ReqArgs q = p->req;
+    q.alpha = alpha;
+    q.n_adapt = 0;
+    ReqArgs* dq = reinterpret_cast<ReqArgs*>(d + qo);
+    struct {
+        ReqArgs* req;
+        int32_t pad[2];
+        int32_t bb[2];
+    } table = {dq, {0, 0}, {0, D}};
+    static_assert(offsetof(decltype(table), bb) == 16, "block bases at offset 16 of the launch table");
+    // earlier work on the stream may still read the workspace
+    VP_HIP(hipStreamSynchronize(sm));
+    hipError_t e = hipMemcpyAsync(d, x, xb, hipMemcpyHostToDevice, sm);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + xb, f, fb, hipMemcpyHostToDevice, sm);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + qo, &q, sizeof q, hipMemcpyHostToDevice, sm);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + to, &table, sizeof table, hipMemcpyHostToDevice, sm);
+    TrainArgs ta;
+    ta.x = reinterpret_cast<const double*>(d);
+    ta.f = reinterpret_cast<const double*>(d + xb);
+    ta.map = p->map;
+    ta.H = p->H;
+    ta.W = p->W;
+    ta.n = n;
+    ta.x_mu = 1;
+    ta.x_s = D;
+    ta.dim = D;
+    ta.n_g = NG;
+    LaunchSet L;
+    L.reqs = reinterpret_cast<ReqArgs* const*>(d + to);
+    L.bbase = reinterpret_cast<const int32_t*>(d + to + 16);
+    L.n = 1;
+    for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
+        launch_fill_f64(p->H, (int64_t)D * NG, 0.0, sm);
+        launch_fill_f64(p->W, (int64_t)D * NG, 0.0, sm);
+        launch_train_hist(ta, sm);
+        launch_refine(L, D, NG, sm);
+        e = hipGetLastError();
+    }
+    // the copies read q, table and the caller's arrays until they complete
+    const hipError_t e2 = hipStreamSynchronize(sm);
     if (e != hipSuccess || e2 != hipSuccess)
         return fail(VP_ERR_DEVICE, "map training: %s", hipGetErrorString(e != hipSuccess ? e : e2));
     return VP_OK;
