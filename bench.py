@@ -71,29 +71,68 @@ def measured_traffic(precision):
     return float(vals["traffic_bytes_per_launch:"])
 
 
-def cpu_baseline(p, f, budget_s=12.0):
-    """The CPU oracle (single thread) on a bounded sample of the same workload:
-    iteration 0 over leading hypercubes, about budget_s seconds of work."""
+def cpu_threads():
+    """Host threads for the oracle's all-core leg: the cores this process may
+    use, at most the OMP_NUM_THREADS share the host gives a GPU job."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cap = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return max(1, min(n, cap) if cap > 0 else n)
+
+
+def cpu_baseline(p, f, budget_s=10.0):
+    """The CPU oracle on the same workload, timed on the host.
+
+    All cores: one whole iteration (iteration 0: sampling of every hypercube,
+    estimate, reallocation and refinement), the hypercubes split into one
+    contiguous block per thread (the oracle's range call, run from that many
+    threads; its sums are merged in block order).  The value is samples per
+    second of that iteration.  Single core: the sampling of iteration 0 over
+    leading hypercubes, about budget_s seconds."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
 
     import oracle
     op = oracle.Problem(p, f)
     fmap = op.map_init()
     n_h = op.alloc_init()
-    # calibrate on a small slice, then size the sample to the budget
+    threads = cpu_threads()
+    edges = [op.n_hc * t // threads for t in range(threads + 1)]
     t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda t: op.sample_range(fmap, n_h, 0, edges[t], edges[t + 1]), range(threads)))
+    t_sample = time.perf_counter() - t0
+    S1 = np.concatenate([q["S1"] for q in parts])
+    S2 = np.concatenate([q["S2"] for q in parts])
+    H = parts[0]["H"].copy()
+    Wt = parts[0]["W"].copy()
+    for q in parts[1:]:
+        H += q["H"]
+        Wt += q["W"]
+    I, V = op.reduce(n_h, S1, S2)
+    op.realloc(S1, S2, n_h)
+    op.refine(H, Wt, fmap)
+    dt = time.perf_counter() - t0
+    samples = int(np.asarray(n_h, dtype=np.int64).sum())
+    assert sum(q["n_samples"] for q in parts) == samples
+    # single core, bounded
+    c0 = time.perf_counter()
     op.sample_range(fmap, n_h, 0, 0, 20000)
-    dt = time.perf_counter() - t0
-    per_hc = max(dt / 20000, 1e-9)
+    per_hc = max((time.perf_counter() - c0) / 20000, 1e-9)
     n = int(min(op.n_hc, max(20000, budget_s / per_hc)))
-    t0 = time.perf_counter()
+    c0 = time.perf_counter()
     out = op.sample_range(fmap, n_h, 0, 0, n)
-    dt = time.perf_counter() - t0
-    samples = int(np.asarray(n_h[:n], dtype=np.int64).sum())
-    assert out["n_samples"] == samples
-    return {"value": samples / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"iteration 0 of the D=8 N_ev=1e8 workload over hypercubes [0, {n}) "
-                      f"({samples} samples, {dt:.1f} s, single thread)"}
+    c1 = time.perf_counter() - c0
+    s1 = int(np.asarray(n_h[:n], dtype=np.int64).sum())
+    assert out["n_samples"] == s1
+    return {"value": samples / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"one whole iteration (iteration 0) of the D=8 N_ev=1e8 workload: sampling of all "
+                      f"{op.n_hc} hypercubes ({samples} samples) in {threads} contiguous blocks on {threads} "
+                      f"threads ({t_sample:.1f} s), then the estimate, reallocation and refinement "
+                      f"({dt - t_sample:.1f} s, one thread); {dt:.1f} s in all",
+            "iteration_estimate": I,
+            "single_core": {"value": s1 / c1, "unit": "samples/s", "cores": 1,
+                            "sample": f"sampling of iteration 0 over hypercubes [0, {n}) ({s1} samples, "
+                                      f"{c1:.1f} s)"}}
 
 
 def pct(x, q):
@@ -213,25 +252,23 @@ def run_batch(B, W, ctx, n_req, plain_too=True):
     }
 
 
-def run_stream(B, W, ctx, n_req, loads):
-    """Poisson arrivals of the stream workload, served live, at the rates at
-    which the plain path (service times measured one by one, replayed as a
-    first-come-first-served queue) is loads[0], loads[1], ... busy; the first
-    load is the headline, the others are summarised under by_load."""
+def run_stream(B, W, ctx, n_req, loads, n_cal=300):
+    """Poisson arrivals of the stream workload at fixed rates, run live twice
+    per rate: submitted in real time to the continuous-batching server, and
+    to the plain path (a worker that solves the requests with vp_integrate
+    one at a time in arrival order, as they arrive).  The rates are the
+    loads[0], loads[1], ... fractions of the plain path's capacity, 1 / (mean
+    service time), measured beforehand on the first n_cal requests one by
+    one; loads[0] is the headline, the others are summarised under by_load."""
+    import threading
+
     import numpy as np
     reqs = W.served_stream(n_req=n_req, rate=1.0)
     unit = np.array([r.arrival for r in reqs])  # arrivals at rate 1
-    svc, plain = run_plain(B, ctx, reqs)
+    cal, _ = run_plain(B, ctx, reqs[:n_cal])
+    mean_svc = float(np.mean(cal))
 
-    def at_load(load):
-        rate = load / float(np.mean(svc))  # requests/s at which the plain path is `load` busy
-        arr = unit / rate
-        # plain: first come, first served, one at a time
-        fin, t = [], 0.0
-        for a, s_ in zip(arr, svc):
-            t = max(t, a) + s_
-            fin.append(t)
-        plain_lat = [f - a for f, a in zip(fin, arr)]
+    def serve(arr):
         srv = B.Server(ctx, max_slots=n_req)
         tickets = [None] * n_req
 
@@ -243,7 +280,6 @@ def run_stream(B, W, ctx, n_req, loads):
                     time.sleep(d)
                 tickets[i] = srv.submit(r.params, r.integrand)
 
-        import threading
         th = threading.Thread(target=producer)
         th.start()
         th.join()
@@ -251,31 +287,52 @@ def run_stream(B, W, ctx, n_req, loads):
         times = [srv.times(t) for t in tickets]
         st = srv.stats()
         srv.close()
-        lat = [t[2] - t[0] for t in times]
-        return rate, served, times, st, lat, plain_lat
+        return served, [t[2] - t[0] for t in times], times, st
 
-    rate, served, times, st, lat, plain_lat = at_load(loads[0])
-    samples = sum(r["n_evals"] for r in served)
-    span = max(t[2] for t in times) - min(t[0] for t in times)
-    out = {
-        "workload": f"{n_req} correlated-Gaussian requests (cond 100, scale 0.05), D 3..21, N_ev 1e5..1e7 "
-                    f"log-uniform, 5-20 iterations, N_g=1000, fp64; Poisson arrivals at {rate:.1f}/s "
-                    f"(plain path {100 * loads[0]:.0f}% busy)",
-        "rate_per_s": rate,
-        "samples": samples,
-        "served": {"span_s": span, "samples_per_s": samples / span, **lat_summary(lat),
-                   "steps": st["steps"], "graph_launches": st["graph_launches"],
-                   "graph_captures": st["graph_captures"], "peak_active": st["peak_active"],
-                   "mem_peak_bytes": st["mem_peak"],
-                   "scheduler_s": {k: st[k] for k in ("t_admit", "t_plan", "t_step", "t_retire")}},
-        "plain": {"busy_s": float(sum(svc)), "samples_per_s": samples / float(sum(svc)), **lat_summary(plain_lat)},
-        "max_diff_in_sdev": agreement(served, plain),
-    }
+    def plain_live(arr):
+        """One worker, first come first served, each request started when it
+        has arrived and the previous one is done."""
+        res, lat = [], []
+        t0 = time.perf_counter()
+        busy = 0.0
+        for i, r in enumerate(reqs):
+            d = arr[i] - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            a = time.perf_counter()
+            res.append(B.integrate(ctx, r.params, r.integrand))
+            e = time.perf_counter()
+            busy += e - a
+            lat.append((e - t0) - arr[i])
+        return res, lat, busy
+
+    out = {}
     by = {}
-    for load in loads[1:]:
-        r_, sv_, _, st_, lat_, pl_ = at_load(load)
-        by[f"{load:g}"] = {"rate_per_s": r_, "served": {**lat_summary(lat_), "peak_active": st_["peak_active"]},
-                           "plain": lat_summary(pl_), "max_diff_in_sdev": agreement(sv_, plain)}
+    for k, load in enumerate(loads):
+        rate = load / mean_svc
+        arr = unit / rate
+        print(f"  stream at {100 * load:.0f}% load ({rate:.0f}/s): served ...", file=sys.stderr, flush=True)
+        served, lat, times, st = serve(arr)
+        print(f"  stream at {100 * load:.0f}% load: plain ...", file=sys.stderr, flush=True)
+        plain, plain_lat, busy = plain_live(arr)
+        samples = sum(r["n_evals"] for r in served)
+        span = max(t[2] for t in times) - min(t[0] for t in times)
+        entry = {"rate_per_s": rate,
+                 "served": {**lat_summary(lat), "span_s": span, "samples_per_s": samples / span,
+                            "steps": st["steps"], "graph_launches": st["graph_launches"],
+                            "graph_captures": st["graph_captures"], "peak_active": st["peak_active"],
+                            "mem_peak_bytes": st["mem_peak"],
+                            "scheduler_s": {q: st[q] for q in ("t_admit", "t_plan", "t_step", "t_retire")}},
+                 "plain": {**lat_summary(plain_lat), "busy_s": busy, "utilisation": busy / (arr[-1] + plain_lat[-1])},
+                 "max_diff_in_sdev": agreement(served, plain), "samples": samples}
+        if k == 0:
+            out = {"workload": f"{n_req} correlated-Gaussian requests (cond 100, scale 0.05), D 3..21, N_ev 1e5..1e7 "
+                               f"log-uniform, 5-20 iterations, N_g=1000, fp64; Poisson arrivals at {rate:.1f}/s "
+                               f"(plain path {100 * load:.0f}% busy at the mean service time of the first "
+                               f"{n_cal} requests, {1e3 * mean_svc:.2f} ms); served and plain both run live",
+                   **entry}
+        else:
+            by[f"{load:g}"] = entry
     if by:
         out["by_load"] = by
     return out
@@ -294,7 +351,7 @@ def main():
                     help="extra sections to run after the headline steps (comma list of split, batchfn "
                          "(batched-integrand path), batch (served batch), stream)")
     ap.add_argument("--batch", type=int, default=4096, help="requests in the served batch")
-    ap.add_argument("--stream", type=int, default=300, help="requests in the Poisson stream")
+    ap.add_argument("--stream", type=int, default=2000, help="requests in the Poisson stream")
     ap.add_argument("--no-plain", action="store_true",
                     help="served batch only, without the plain path's one-after-another comparison (for profiling)")
     ap.add_argument("--loads", default="0.8,0.5,0.95",
@@ -310,20 +367,30 @@ def main():
 
     p, f = W.cfg_diag_d8(n_ev=args.n_ev, precision=args.precision)
     ctx = B.Context(0)
-    gp = B.Problem(ctx, p, f)
+    gp = B.Problem(ctx, p.with_(n_iter=args.warmup + args.steps), f)
     gp.iterate(args.warmup)
     r0 = gp.result()
     gp.profile(True)
     gp.sync()
-    t0 = time.perf_counter()
-    gp.iterate(args.steps)
-    gp.sync()
-    t1 = time.perf_counter()
+    # the K timed steps run as five consecutive runs (as equal as K allows),
+    # each bracketed by stream synchronisation; value = all K steps' samples
+    # over their summed time, beside the median of the five runs' rates
+    n_runs = min(5, args.steps)
+    bounds = [args.steps * r // n_runs for r in range(n_runs + 1)]
+    wall, runs, prev = 0.0, [], r0["n_evals"]
+    for r in range(n_runs):
+        t0 = time.perf_counter()
+        gp.iterate(bounds[r + 1] - bounds[r])
+        gp.sync()
+        dt_run = time.perf_counter() - t0
+        wall += dt_run
+        ev = gp.result()["n_evals"]
+        runs.append((ev - prev) / dt_run)
+        prev = ev
     r1 = gp.result()
     k_ms, k_n = gp.kernel_time(0)
     it_ms, it_n = gp.kernel_time(1)
     samples = r1["n_evals"] - r0["n_evals"]
-    wall = t1 - t0
     value = samples / wall
     per_launch = samples / max(k_n, 1)
     k_avg_s = k_ms / max(k_n, 1) / 1e3
@@ -349,6 +416,8 @@ def main():
                      "traffic": measured_traffic(args.precision),
                      "kernel": "k_sample (fused sampling)", "kernel_ms": 1e3 * k_avg_s,
                      "slots_per_sample": SLOTS_PER_SAMPLE[args.precision]},
+        "runs": {"count": n_runs, "steps_each": [bounds[r + 1] - bounds[r] for r in range(n_runs)],
+                 "samples_per_s": runs, "median_samples_per_s": sorted(runs)[n_runs // 2]},
         "iteration_ms_device": it_ms / max(it_n, 1),
         "estimate": {"mean": r1["mean"], "sdev": r1["sdev"], "chi2_dof": r1["chi2"] / max(r1["dof"], 1),
                      "exact": 1.0},

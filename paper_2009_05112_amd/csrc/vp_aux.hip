@@ -404,18 +404,17 @@ __global__ __launch_bounds__(kRecBlock) void k_hist_records(LaunchSet L)
     }
 }
 
-__global__ void k_init(InitArgs a)
+// Threads t0, t0 + stride, ... of the initialisation of one problem.
+__device__ __forceinline__ void init_problem(const InitArgs& a, int64_t t0, int64_t stride)
 {
     const int64_t nm = (int64_t)a.dim * (a.n_g + 1);
     const int64_t n = max(nm, max(a.n_hc, a.nbins));
     if (a.head_src) {
         const uint64_t* __restrict__ src = reinterpret_cast<const uint64_t*>(a.head_src);
         uint64_t* __restrict__ dst = reinterpret_cast<uint64_t*>(a.head_dst);
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.head_bytes / 8;
-             i += (int64_t)gridDim.x * blockDim.x)
-            dst[i] = src[i];
+        for (int64_t i = t0; i < a.head_bytes / 8; i += stride) dst[i] = src[i];
     }
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = t0; i < n; i += stride) {
         if (i < nm) {
             const int d = (int)(i / (a.n_g + 1)), k = (int)(i - (int64_t)d * (a.n_g + 1));
             const double lo = a.bounds[d], hi = a.bounds[a.dim + d];
@@ -433,6 +432,24 @@ __global__ void k_init(InitArgs a)
             a.W[i] = 0.0;
         }
     }
+}
+
+__global__ void k_init(InitArgs a)
+{
+    init_problem(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+}
+
+// Problem blockIdx.y of the table, with gridDim.x workgroups.
+__global__ void k_init_batch(const InitArgs* __restrict__ table)
+{
+    const InitArgs a = table[blockIdx.y];
+    if (a.n_hc < 0) return;
+    init_problem(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+}
+
+void launch_init_batch(const InitArgs* table, int n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_init_batch, dim3(8, (unsigned)n), dim3(256), 0, s, table);
 }
 
 void launch_init(const InitArgs& a, hipStream_t s)

@@ -64,6 +64,9 @@ struct InitArgs {
     int32_t dim, n_g, n0;
 };
 void launch_init(const InitArgs& a, hipStream_t s);
+// The initialisation of n problems in one launch; table: n InitArgs in memory
+// the device reads (entries with n_hc < 0 are skipped).
+void launch_init_batch(const InitArgs* table, int n, hipStream_t s);
 // Copies the estimate scalars of n problems into host-visible memory.
 void launch_gather_states(DevState* const* states, int n, DevState* out, hipStream_t s);
 void launch_fill_f64(double* x, int64_t n, double v, hipStream_t s);

@@ -3,9 +3,8 @@
 // Requests are carved out of large slabs (hipMalloc once) by first fit over
 // each slab's free ranges, which are coalesced on release.  A steady stream of
 // admissions and retirements therefore makes no allocation call into the HIP
-// runtime.  The pool is used by one thread (the scheduler) and only between
-// steps, after the stream has been synchronised, so a released range is never
-// still in use by a kernel.
+// runtime.  The pool is used by one thread (the scheduler), which releases a
+// request's range only once no queued or running kernel uses it.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -90,25 +89,28 @@ public:
     {
         for (Slab& s : slabs_) (void)hipFree(s.base);
         slabs_.clear();
-        for (Chunk& c : chunks_) (void)hipHostFree(c.base);
-        chunks_.clear();
-        chunk_ = 0;
-        chunk_off_ = 0;
+        for (Stage& g : stages_) {
+            for (Chunk& c : g.chunks) (void)hipHostFree(c.base);
+            g = Stage();
+        }
     }
 
     // Pinned host memory holding the initial image of admitted requests'
     // state, which the initialisation kernel reads directly (*dev: the same
-    // memory's device address).  Valid until reset_stage(), which the caller
-    // invokes only with those kernels complete; nullptr when no pinned memory
-    // can be had.
+    // memory's device address).  Two independent sets: images go to the set
+    // chosen by select_stage(), and a set is reset (reset_stage) only once the
+    // kernels reading it are complete, while the other set takes new images.
+    // nullptr when no pinned memory can be had.
+    void select_stage(int i) { cur_ = i & 1; }
     char* stage(size_t bytes, const char** dev)
     {
+        Stage& g = stages_[cur_];
         bytes = round_up(bytes ? bytes : 1);
-        while (chunk_ < chunks_.size() && chunk_off_ + bytes > chunks_[chunk_].size) {
-            ++chunk_;
-            chunk_off_ = 0;
+        while (g.chunk < g.chunks.size() && g.off + bytes > g.chunks[g.chunk].size) {
+            ++g.chunk;
+            g.off = 0;
         }
-        if (chunk_ == chunks_.size()) {
+        if (g.chunk == g.chunks.size()) {
             Chunk c;
             c.size = bytes > kStageChunk ? bytes : kStageChunk;
             if (hipHostMalloc((void**)&c.base, c.size, hipHostMallocDefault) != hipSuccess) return nullptr;
@@ -118,19 +120,19 @@ public:
                 return nullptr;
             }
             c.dev = (const char*)d;
-            chunks_.push_back(c);
-            chunk_off_ = 0;
+            g.chunks.push_back(c);
+            g.off = 0;
         }
-        char* p = chunks_[chunk_].base + chunk_off_;
-        *dev = chunks_[chunk_].dev + chunk_off_;
-        chunk_off_ += bytes;
+        char* p = g.chunks[g.chunk].base + g.off;
+        *dev = g.chunks[g.chunk].dev + g.off;
+        g.off += bytes;
         return p;
     }
-    bool stage_used() const { return chunk_ > 0 || chunk_off_ > 0; }
-    void reset_stage()
+    bool stage_used(int i) const { return stages_[i & 1].chunk > 0 || stages_[i & 1].off > 0; }
+    void reset_stage(int i)
     {
-        chunk_ = 0;
-        chunk_off_ = 0;
+        stages_[i & 1].chunk = 0;
+        stages_[i & 1].off = 0;
     }
 
     size_t reserved() const
@@ -172,8 +174,12 @@ private:
         size_t size = 0;
     };
     static constexpr size_t kStageChunk = size_t(16) << 20;
-    std::vector<Chunk> chunks_;
-    size_t chunk_ = 0, chunk_off_ = 0;
+    struct Stage {
+        std::vector<Chunk> chunks;
+        size_t chunk = 0, off = 0;
+    };
+    Stage stages_[2];
+    int cur_ = 0;
 };
 
 }  // namespace vp

@@ -761,8 +761,9 @@ vp_status vp::problem_bytes(vp_ctx* ctx, const vp_params* P, const vp_integrand*
 
 
 vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
-                             DevicePool* pool, vp_problem** out)
+                             DevicePool* pool, vp_problem** out, InitArgs* init_out)
 {
+    if (init_out && !pool) return fail(VP_ERR_INVALID_ARG, "a deferred initialisation needs a pool");
     if (!ctx || !out) return fail(VP_ERR_INVALID_ARG, "ctx and out are required");
     *out = nullptr;
     vp_status s = validate(P, f);
@@ -911,8 +912,13 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
         ia.dim = D;
         ia.n_g = NG;
         ia.n0 = (int32_t)n0;
-        launch_init(ia, sm);
-        e = hipGetLastError();
+        if (init_out && head_dev) {
+            *init_out = ia;
+        } else {
+            if (init_out) init_out->n_hc = -1;  // initialised here (no pinned image)
+            launch_init(ia, sm);
+            e = hipGetLastError();
+        }
     }
     // stream-ordered creation leaves the initialisation queued before the
     // request's first kernels on the same stream (the staging copy lives in

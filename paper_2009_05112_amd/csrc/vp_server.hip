@@ -7,12 +7,17 @@
 //  2. if the set of active requests changed, builds the batched iteration
 //     plan (one launch per kernel for all requests, one sampling launch per
 //     kernel instantiation) and drops the captured graph;
-//  3. runs one step -- one iteration of every active request -- replaying the
-//     step's captured HIP graph when the set is unchanged (the per-request
+//  3. enqueues one step -- one iteration of every active request -- replaying
+//     the step's captured HIP graph when the set is unchanged (the per-request
 //     Philox iteration and history slot live in device memory and are
-//     advanced by the step itself, so a replay is the next iteration);
-//  4. retires requests that reached their iteration count (or were
-//     cancelled): copies their result, frees their memory, wakes waiters.
+//     advanced by the step itself, so a replay is the next iteration), and
+//     behind it the gather of the estimates of the requests that this step
+//     finishes;
+//  4. waits for the previous turn's step and retires the requests it
+//     finished (or that were cancelled): copies their result, frees their
+//     memory, wakes waiters.
+// A step therefore always has the next one queued behind it while the host
+// admits, plans and retires: the GPU does not wait for the scheduler.
 // Requests submitted while a step runs are admitted at the next turn, so the
 // GPU work of new and old requests overlaps in the same launches.
 #include <hip/hip_runtime.h>
@@ -33,10 +38,15 @@ using namespace vp;
 
 namespace {
 
-// Sampling workgroups of a served request hold about this many samples: small
-// requests still spread over many CUs (a step's launches are short), while
-// the per-workgroup LDS set-up and flush stay a few percent of the work.
-constexpr int64_t kServeSamplesPerWG = 8192;
+// Sampling workgroups of a served request hold about this many samples (one
+// tile of 16 per lane for 1024 threads): small requests still spread over
+// many CUs (a step's launches are short), while the per-workgroup LDS set-up
+// and the flush of its training-data partials stay a few percent of the work.
+constexpr int64_t kServeSamplesPerWG = 16384;
+// A plan is captured into a graph once it has run this many steps unchanged
+// (the sets of a stream of arrivals often change after a few steps, and a
+// capture costs the host as much as tens of direct launches).
+constexpr int64_t kCaptureAfter = 3;
 
 enum ReqState { R_PENDING = 0, R_ACTIVE = 1, R_DONE = 2, R_CANCELLED = 3, R_FAILED = 4 };
 
@@ -79,20 +89,32 @@ struct vp_server {
         int64_t steps = 0, graph_launches = 0, graph_captures = 0;
         double t_admit = 0, t_plan = 0, t_step = 0, t_retire = 0;
     } ss;  // the scheduler's own counters, published into st under mu
-    PlanBuilder planner;
+    // two plan builders used in turn: a new plan's launch tables are written
+    // while the step of the previous plan may still be running
+    PlanBuilder planner[2];
+    int pb = 0;
     IterPlan plan;
     DevicePool pool;  // device memory of admitted requests
     bool plan_valid = false;
     int64_t plan_steps = 0;  // steps run with the current plan
     hipGraphExec_t gexec = nullptr;
+    std::vector<hipGraphExec_t> dead_graphs;  // destroyed once the step that used them is complete
+    // the step in flight: its completion event (recorded behind the gather of
+    // the estimates of the requests it finishes), those requests, and the
+    // cancelled requests that it still touches
+    bool inflight = false;
+    int64_t turn = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::vector<ServedReq*> fin_inflight, drop_inflight;
     SideStreams side;  // sampling launches of different kernel groups side by side
     std::chrono::steady_clock::time_point t0;
     // gather of finished requests' estimates: pointers and results, host
-    // (pinned) and device copies, max_slots entries each
-    DevState** h_ptrs = nullptr;
-    DevState* h_out = nullptr;
-    DevState** d_ptrs = nullptr;
-    DevState* d_out = nullptr;
+    // (pinned) and device copies, max_slots entries each, for each of the two
+    // steps that can be queued at once
+    DevState** h_ptrs[2] = {nullptr, nullptr};
+    DevState* h_out[2] = {nullptr, nullptr};
+    DevState** d_ptrs[2] = {nullptr, nullptr};
+    DevState* d_out[2] = {nullptr, nullptr};
 
     double tsec(std::chrono::steady_clock::time_point a) const
     {
@@ -138,14 +160,18 @@ static void copy_request(ServedReq* r, const vp_params* P, const vp_integrand* f
 
 static void free_gather(vp_server* s)
 {
-    (void)hipHostFree(s->h_ptrs);
-    (void)hipHostFree(s->h_out);
-    (void)hipFree(s->d_ptrs);
-    (void)hipFree(s->d_out);
-    s->h_ptrs = nullptr;
-    s->h_out = nullptr;
-    s->d_ptrs = nullptr;
-    s->d_out = nullptr;
+    for (int b = 0; b < 2; ++b) {
+        (void)hipHostFree(s->h_ptrs[b]);
+        (void)hipHostFree(s->h_out[b]);
+        (void)hipFree(s->d_ptrs[b]);
+        (void)hipFree(s->d_out[b]);
+        s->h_ptrs[b] = nullptr;
+        s->h_out[b] = nullptr;
+        s->d_ptrs[b] = nullptr;
+        s->d_out[b] = nullptr;
+        if (s->ev[b]) (void)hipEventDestroy(s->ev[b]);
+        s->ev[b] = nullptr;
+    }
 }
 
 // Side streams for the sampling launches (default priority, like the main
@@ -180,21 +206,30 @@ static void free_side(vp_server* s)
     d = SideStreams();
 }
 
+// The current graph may still be replayed by the step in flight: it is
+// destroyed once that step is complete.
 static void drop_graph(vp_server* s)
 {
     if (s->gexec) {
-        (void)hipGraphExecDestroy(s->gexec);
+        s->dead_graphs.push_back(s->gexec);
         s->gexec = nullptr;
     }
 }
 
-// Runs one step and waits for it; returns false on a device error.  A plan is
-// launched directly on its first step and captured into a graph on its
-// second, so sets of requests that change every step pay no capture.
-static bool run_step(vp_server* s)
+static void destroy_dead_graphs(vp_server* s)
+{
+    for (hipGraphExec_t g : s->dead_graphs) (void)hipGraphExecDestroy(g);
+    s->dead_graphs.clear();
+}
+
+// Enqueues one step without waiting for it; returns false on a launch error.
+// A plan is launched directly on its first kCaptureAfter steps and captured
+// into a graph after them, so sets of requests that change every few steps
+// pay no capture.
+static bool enqueue_step(vp_server* s)
 {
     hipStream_t st = s->ctx->stream;
-    if (s->graphs && s->plan_steps >= 1) {
+    if (s->graphs && s->plan_steps >= kCaptureAfter) {
         if (!s->gexec) {
             const auto t0 = std::chrono::steady_clock::now();
             hipGraph_t g = nullptr;
@@ -210,21 +245,15 @@ static bool run_step(vp_server* s)
             s->ss.graph_captures += 1;
             s->ss.t_plan += s->tsec(t0);
         }
-        const auto t0 = std::chrono::steady_clock::now();
         if (hipGraphLaunch(s->gexec, st) != hipSuccess) return false;
         s->ss.graph_launches += 1;
-        const bool ok = hipStreamSynchronize(st) == hipSuccess;
-        s->ss.t_step += s->tsec(t0);
         s->plan_steps += 1;
-        return ok;
+        return true;
     }
-    const auto t0 = std::chrono::steady_clock::now();
     enqueue_iteration(s->plan, st, nullptr, nullptr, &s->side);
     if (hipGetLastError() != hipSuccess) return false;
-    const bool ok = hipStreamSynchronize(st) == hipSuccess;
-    s->ss.t_step += s->tsec(t0);
     s->plan_steps += 1;
-    return ok;
+    return true;
 }
 
 static void retire(vp_server* s, ServedReq* r, int state)
@@ -246,6 +275,69 @@ static void retire(vp_server* s, ServedReq* r, int state)
         s->st.failed += 1;
     }
     s->cv_done.notify_all();
+}
+
+// Fails every request the scheduler holds after a device error, once the
+// stream has drained.
+static void fail_all(vp_server* s, const char* why)
+{
+    (void)hipStreamSynchronize(s->ctx->stream);
+    std::vector<ServedReq*> all = s->active;
+    all.insert(all.end(), s->fin_inflight.begin(), s->fin_inflight.end());
+    for (ServedReq* r : all) {
+        r->status = VP_ERR_DEVICE;
+        r->err = why;
+        retire(s, r, R_FAILED);
+    }
+    for (ServedReq* r : s->drop_inflight) retire(s, r, R_CANCELLED);
+    s->active.clear();
+    s->fin_inflight.clear();
+    s->drop_inflight.clear();
+    s->inflight = false;
+    drop_graph(s);
+    destroy_dead_graphs(s);
+    s->plan_valid = false;
+}
+
+// Waits for the step in flight and retires what it finished: the requests
+// whose last iteration it ran (their estimates were gathered behind it) and
+// the cancelled requests it still touched.  Returns false on a device error.
+static bool complete_inflight(vp_server* s)
+{
+    if (!s->inflight) return true;
+    const int b = (int)((s->turn - 1) & 1);
+    const auto t0 = std::chrono::steady_clock::now();
+    const bool ok = hipEventSynchronize(s->ev[b]) == hipSuccess;
+    s->ss.t_step += s->tsec(t0);
+    s->inflight = false;
+    if (!ok) return false;
+    const auto t_ret = std::chrono::steady_clock::now();
+    destroy_dead_graphs(s);
+    // the admissions staged before that step have been read by now
+    s->pool.reset_stage(b);
+    for (size_t i = 0; i < s->fin_inflight.size(); ++i) {
+        ServedReq* r = s->fin_inflight[i];
+        r->status = result_from_state(s->h_out[b][i], &r->res);
+        if (r->status != VP_OK) r->err = vp_last_error();
+        retire(s, r, r->status == VP_OK || r->status == VP_ERR_NUMERIC ? R_DONE : R_FAILED);
+    }
+    for (ServedReq* r : s->drop_inflight) retire(s, r, R_CANCELLED);
+    s->fin_inflight.clear();
+    s->drop_inflight.clear();
+    s->ss.t_retire += s->tsec(t_ret);
+    return true;
+}
+
+static void publish_stats(vp_server* s)
+{
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->st.steps = s->ss.steps;
+    s->st.graph_launches = s->ss.graph_launches;
+    s->st.graph_captures = s->ss.graph_captures;
+    s->st.t_admit = s->ss.t_admit;
+    s->st.t_plan = s->ss.t_plan;
+    s->st.t_step = s->ss.t_step;
+    s->st.t_retire = s->ss.t_retire;
 }
 
 static void scheduler(vp_server* s)
@@ -274,33 +366,54 @@ static void scheduler(vp_server* s)
                     r->t_admit = s->now();
                     admit.push_back(r);
                 }
-                if (!s->active.empty() || !admit.empty()) break;
+                if (!s->active.empty() || !admit.empty() || s->inflight) break;
                 if (s->stop) return;
                 s->cv_work.wait(lk);
             }
         }
+        const int b = (int)(s->turn & 1);  // buffers of the step this turn enqueues
         bool changed = false;
         const auto t_adm = std::chrono::steady_clock::now();
-        if (!admit.empty() && s->pool.stage_used()) {
-            // the previous admissions' initial copies read the pinned staging
-            // memory; it is reused once they are complete
-            (void)hipStreamSynchronize(s->ctx->stream);
-            s->pool.reset_stage();
-        }
+        // initial images of this turn's admissions go to staging set b (the
+        // other set may still be read by the step in flight)
+        s->pool.select_stage(b);
+        std::vector<InitArgs> inits;
+        inits.reserve(admit.size());
         for (ServedReq* r : admit) {
-            vp_status st = problem_create(s->ctx, &r->P, &r->f, kServeSamplesPerWG, &s->pool, &r->prob);
+            InitArgs ia;
+            vp_status st = problem_create(s->ctx, &r->P, &r->f, kServeSamplesPerWG, &s->pool, &r->prob, &ia);
             if (st != VP_OK) {
                 r->status = st;
                 r->err = vp_last_error();
                 retire(s, r, R_FAILED);
                 continue;
             }
+            inits.push_back(ia);
             r->iters_left = r->P.n_iter;
             s->active.push_back(r);
             changed = true;
         }
+        if (!inits.empty()) {
+            // one launch initialises every admitted request (its table sits
+            // in the same pinned staging memory as their images)
+            const char* tdev = nullptr;
+            char* th = s->pool.stage(sizeof(InitArgs) * inits.size(), &tdev);
+            if (th) {
+                memcpy(th, inits.data(), sizeof(InitArgs) * inits.size());
+                launch_init_batch(reinterpret_cast<const InitArgs*>(tdev), (int)inits.size(), s->ctx->stream);
+            } else {
+                for (const InitArgs& ia : inits)
+                    if (ia.n_hc >= 0) launch_init(ia, s->ctx->stream);
+            }
+            if (hipGetLastError() != hipSuccess) {
+                fail_all(s, "initialising admitted requests failed");
+                publish_stats(s);
+                continue;
+            }
+        }
         if (!admit.empty()) s->ss.t_admit += s->tsec(t_adm);
-        // cancellations of active requests, and requests with nothing to do
+        // cancellations of active requests, and requests with nothing to do;
+        // a request the step in flight still runs is freed once it is done
         for (size_t i = 0; i < s->active.size();) {
             ServedReq* r = s->active[i];
             bool cancel;
@@ -309,91 +422,90 @@ static void scheduler(vp_server* s)
                 cancel = r->cancel;
             }
             if (cancel || r->iters_left <= 0) {
-                if (!cancel) r->status = vp_result_get(r->prob, &r->res, nullptr, nullptr, 0);
                 s->active.erase(s->active.begin() + i);
-                retire(s, r, cancel ? R_CANCELLED : R_DONE);
                 changed = true;
+                if (!cancel) {
+                    r->status = vp_result_get(r->prob, &r->res, nullptr, nullptr, 0);
+                    retire(s, r, R_DONE);
+                } else if (r->prob && r->prob->slot > 0 && s->inflight) {
+                    s->drop_inflight.push_back(r);
+                } else {
+                    retire(s, r, R_CANCELLED);
+                }
             } else {
                 ++i;
             }
         }
-        if (s->active.empty()) continue;
-        if (changed || !s->plan_valid) {
-            const auto t_pl = std::chrono::steady_clock::now();
-            std::vector<PlanReq> pr;
-            pr.reserve(s->active.size());
-            for (ServedReq* r : s->active) pr.push_back({&r->prob->req, r->prob->d_req, r->prob->entry, r->prob->lds});
-            drop_graph(s);
-            s->plan_steps = 0;
-            s->plan_valid = s->planner.build(pr, &s->plan) == hipSuccess;
-            s->ss.t_plan += s->tsec(t_pl);
-            if (!s->plan_valid) {
-                for (ServedReq* r : s->active) {
-                    r->status = VP_ERR_DEVICE;
-                    r->err = "building the batched plan failed";
-                    retire(s, r, R_FAILED);
+        bool ok = true;
+        const bool stepping = !s->active.empty();
+        if (stepping) {
+            if (changed || !s->plan_valid) {
+                const auto t_pl = std::chrono::steady_clock::now();
+                std::vector<PlanReq> pr;
+                pr.reserve(s->active.size());
+                for (ServedReq* r : s->active)
+                    pr.push_back({&r->prob->req, r->prob->d_req, r->prob->entry, r->prob->lds});
+                drop_graph(s);
+                s->plan_steps = 0;
+                // the other builder: the step in flight reads the current one's tables
+                s->pb ^= 1;
+                s->plan_valid = s->planner[s->pb].build(pr, &s->plan) == hipSuccess;
+                s->ss.t_plan += s->tsec(t_pl);
+                if (!s->plan_valid) {
+                    fail_all(s, "building the batched plan failed");
+                    publish_stats(s);
+                    continue;
                 }
-                s->active.clear();
-                continue;
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->st.peak_active = std::max<int32_t>(s->st.peak_active, (int32_t)s->active.size());
             }
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->st.peak_active = std::max<int32_t>(s->st.peak_active, (int32_t)s->active.size());
+            ok = enqueue_step(s);
+            s->ss.steps += 1;
         }
-        const bool ok = run_step(s);
-        s->ss.steps += 1;
-        const auto t_ret = std::chrono::steady_clock::now();
-        std::vector<ServedReq*> keep, fin;
-        keep.reserve(s->active.size());
-        for (ServedReq* r : s->active) {
-            if (!ok) {
-                r->status = VP_ERR_DEVICE;
-                r->err = "device error during a batched step";
-                retire(s, r, R_FAILED);
-                continue;
+        // the previous step (queued ahead of this one) completes meanwhile
+        if (ok) ok = complete_inflight(s);
+        if (!ok) {
+            fail_all(s, "device error during a batched step");
+            publish_stats(s);
+            continue;
+        }
+        if (stepping) {
+            // bookkeeping of the step just enqueued; the requests it finishes
+            // have their estimates gathered behind it
+            std::vector<ServedReq*> keep;
+            keep.reserve(s->active.size());
+            for (ServedReq* r : s->active) {
+                r->prob->it += 1;
+                r->prob->slot += 1;
+                r->iters_left -= 1;
+                (r->iters_left <= 0 ? s->fin_inflight : keep).push_back(r);
             }
-            r->prob->it += 1;
-            r->prob->slot += 1;
-            r->iters_left -= 1;
-            (r->iters_left <= 0 ? fin : keep).push_back(r);
-        }
-        s->active.swap(keep);
-        if (!fin.empty()) {
-            // the estimates of every finished request in one gather and copy
-            const int n = (int)fin.size();
-            for (int i = 0; i < n; ++i) s->h_ptrs[i] = fin[i]->prob->st;
+            s->active.swap(keep);
             hipStream_t st = s->ctx->stream;
-            bool got = hipMemcpyAsync(s->d_ptrs, s->h_ptrs, n * sizeof(DevState*), hipMemcpyHostToDevice, st) ==
-                       hipSuccess;
-            if (got) {
-                launch_gather_states(s->d_ptrs, n, s->d_out, st);
-                got = hipGetLastError() == hipSuccess &&
-                      hipMemcpyAsync(s->h_out, s->d_out, n * sizeof(DevState), hipMemcpyDeviceToHost, st) ==
-                          hipSuccess &&
-                      hipStreamSynchronize(st) == hipSuccess;
-            }
-            for (int i = 0; i < n; ++i) {
-                ServedReq* r = fin[i];
+            const int n = (int)s->fin_inflight.size();
+            bool got = true;
+            if (n > 0) {
+                for (int i = 0; i < n; ++i) s->h_ptrs[b][i] = s->fin_inflight[i]->prob->st;
+                got = hipMemcpyAsync(s->d_ptrs[b], s->h_ptrs[b], n * sizeof(DevState*), hipMemcpyHostToDevice, st) ==
+                      hipSuccess;
                 if (got) {
-                    r->status = result_from_state(s->h_out[i], &r->res);
-                    if (r->status != VP_OK) r->err = vp_last_error();
-                } else {
-                    r->status = VP_ERR_DEVICE;
-                    r->err = "reading the estimates failed";
+                    launch_gather_states(s->d_ptrs[b], n, s->d_out[b], st);
+                    got = hipGetLastError() == hipSuccess &&
+                          hipMemcpyAsync(s->h_out[b], s->d_out[b], n * sizeof(DevState), hipMemcpyDeviceToHost, st) ==
+                              hipSuccess;
                 }
-                retire(s, r, r->status == VP_OK || r->status == VP_ERR_NUMERIC ? R_DONE : R_FAILED);
+                s->plan_valid = false;  // the next step runs without them
             }
-            s->plan_valid = false;
+            got = got && hipEventRecord(s->ev[b], st) == hipSuccess;
+            s->inflight = true;
+            s->turn += 1;
+            if (!got) {
+                fail_all(s, "reading the estimates failed");
+                publish_stats(s);
+                continue;
+            }
         }
-        if (!ok) s->plan_valid = false;
-        s->ss.t_retire += s->tsec(t_ret);
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->st.steps = s->ss.steps;
-        s->st.graph_launches = s->ss.graph_launches;
-        s->st.graph_captures = s->ss.graph_captures;
-        s->st.t_admit = s->ss.t_admit;
-        s->st.t_plan = s->ss.t_plan;
-        s->st.t_step = s->ss.t_step;
-        s->st.t_retire = s->ss.t_retire;
+        publish_stats(s);
     }
 }
 
@@ -417,10 +529,15 @@ vp_status vp_server_create(vp_ctx* ctx, size_t mem_budget_bytes, int32_t max_slo
     }
     vp_server* s = new vp_server();
     s->ctx = own;
-    if (hipHostMalloc((void**)&s->h_ptrs, sizeof(DevState*) * max_slots, 0) != hipSuccess ||
-        hipHostMalloc((void**)&s->h_out, sizeof(DevState) * max_slots, 0) != hipSuccess ||
-        hipMalloc((void**)&s->d_ptrs, sizeof(DevState*) * max_slots) != hipSuccess ||
-        hipMalloc((void**)&s->d_out, sizeof(DevState) * max_slots) != hipSuccess) {
+    (void)hipSetDevice(own->device);
+    bool got = true;
+    for (int b = 0; b < 2 && got; ++b)
+        got = hipHostMalloc((void**)&s->h_ptrs[b], sizeof(DevState*) * max_slots, 0) == hipSuccess &&
+              hipHostMalloc((void**)&s->h_out[b], sizeof(DevState) * max_slots, 0) == hipSuccess &&
+              hipMalloc((void**)&s->d_ptrs[b], sizeof(DevState*) * max_slots) == hipSuccess &&
+              hipMalloc((void**)&s->d_out[b], sizeof(DevState) * max_slots) == hipSuccess &&
+              hipEventCreateWithFlags(&s->ev[b], hipEventDisableTiming) == hipSuccess;
+    if (!got) {
         free_gather(s);
         vp_ctx_destroy(own);
         delete s;
@@ -574,7 +691,9 @@ vp_status vp_server_destroy(vp_server* s)
         s->cv_work.notify_all();
     }
     if (s->th.joinable()) s->th.join();
+    (void)hipStreamSynchronize(s->ctx->stream);
     drop_graph(s);
+    destroy_dead_graphs(s);
     for (auto& kv : s->all) {
         if (kv.second->prob) problem_free(kv.second->prob);
         delete kv.second;

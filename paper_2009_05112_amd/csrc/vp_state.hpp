@@ -146,8 +146,11 @@ vp_status validate(const vp_params* P, const vp_integrand* f);
 // pool: the state is carved from the pool (a server's) instead of its own
 // hipMalloc, and its initialisation is queued on the context's stream without
 // waiting for it.
+// init_out (pool only): the initialisation kernel's arguments are returned
+// there instead of launched, so that a caller admitting many problems can
+// initialise them all with one launch (launch_init_batch).
 vp_status problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
-                         DevicePool* pool, vp_problem** out);
+                         DevicePool* pool, vp_problem** out, InitArgs* init_out = nullptr);
 // Device bytes problem_create would allocate for these parameters.
 vp_status problem_bytes(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
                         size_t* bytes);

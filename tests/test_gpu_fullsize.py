@@ -2,7 +2,9 @@
 configuration the benchmark times.  The oracle recomputes sampled hypercubes
 one range at a time; the reductions, the allocation and the refinement are
 recomputed in full from the GPU's sums; the training data are checked through
-invariants that hold at any size."""
+invariants that hold at any size.  The samples of one range of hypercubes per
+iteration are dumped by the sampling kernel (vp_debug_dump) and compared one
+by one with the oracle's: indices bit for bit, x and J to the last bit."""
 import numpy as np
 import pytest
 
@@ -35,6 +37,24 @@ def _sampled_ranges(n_h, budget=1_500_000, width=2000, n_random=300, seed=0, lar
             out.append((int(h), int(h) + 1))
             used += int(n_h[h])
     return out
+
+
+def _arm_dump(gp, n_h, h0, width=2000):
+    """Dump of the samples of hypercubes [h0, h0 + width) of the next iteration."""
+    first = int(n_h[:h0].astype(np.int64).sum())
+    count = int(n_h[h0:h0 + width].astype(np.int64).sum())
+    gp.debug_dump(first, count)
+    return h0, h0 + width
+
+
+def _check_dump(gp, op, fmap, n_h, it, hr, rtol_f=1e-12):
+    d = gp.debug_dump_get()
+    o = op.sample_points(fmap, n_h, it, hr[0], hr[1])
+    assert len(d["h"]) == len(o["h"])
+    for k in ("h", "j", "idx", "x", "jac"):
+        np.testing.assert_array_equal(d[k], o[k], err_msg=f"dumped {k} of hypercubes {hr}")
+    np.testing.assert_allclose(d["fx"], o["fx"], rtol=rtol_f, atol=rtol_f * 1e-3 * np.abs(o["fx"]).max(),
+                               err_msg=f"dumped f(x) of hypercubes {hr}")
 
 
 def _check_iteration(gp, op, fmap, n_h, it, rtol=RTOL64, floor=0.0, largest=True):
@@ -74,10 +94,12 @@ def test_fullsize_diag_d8_two_iterations():
     gp = B.Problem(ctx, p, f)
     op = oracle.Problem(p, f, n_st=gp.n_st)
     assert (gp.n_st, gp.n_hc) == (8, 8 ** 8)
-    for _ in range(2):
+    for k in range(2):
         fmap, n_h, it = gp.map(), gp.alloc(), gp.it
+        hr = _arm_dump(gp, n_h, gp.n_hc // 2 if k == 0 else gp.n_hc - 2000)
         gp.iterate(1)
         res = _check_iteration(gp, op, fmap, n_h, it)
+        _check_dump(gp, op, fmap, n_h, it, hr)
     assert res["n_evals"] > 1.5e8
     gp.close()
     ctx.close()
@@ -95,8 +117,10 @@ def test_fullsize_split_d8_two_iterations():
     assert gp.map_place == "global" and gp.hist_axes == 8
     for _ in range(2):
         fmap, n_h, it = gp.map(), gp.alloc(), gp.it
+        hr = _arm_dump(gp, n_h, gp.n_hc // 3)
         gp.iterate(1)
         res = _check_iteration(gp, op, fmap, n_h, it, rtol=2e-6, floor=1e-12)
+        _check_dump(gp, op, fmap, n_h, it, hr, rtol_f=2e-6)
     assert res["n_evals"] > 1.5e8
     gp.close()
     ctx.close()
@@ -115,8 +139,10 @@ def test_maxsize_d8_one_iteration():
     assert (gp.n_st, gp.n_hc) == (12, 12 ** 8)
     fmap, n_h, it = gp.map(), gp.alloc(), gp.it
     assert int(n_h.min()) == int(n_h.max()) == 4
+    hr = _arm_dump(gp, n_h, gp.n_hc - 1000, width=1000)  # samples numbered beyond 2^31
     gp.iterate(1)
     res = _check_iteration(gp, op, fmap, n_h, it, largest=False)
+    _check_dump(gp, op, fmap, n_h, it, hr)
     assert res["n_evals"] == 4 * 12 ** 8
     gp.close()
     ctx.close()
