@@ -69,10 +69,24 @@ struct EdgeRec {
 // plus one base per block: offset(h) = loc[h] + base[h / kOffsTile]; the
 // entry for h = n_hc is N_tot.
 constexpr int kOffsTile = 4096;
+static_assert((kOffsTile & (kOffsTile - 1)) == 0, "block index by a shift");
+
+// Pointers into device (global) memory.  Accesses through them compile to
+// global loads and stores, which count only against the vector-memory
+// counter; through generic pointers they become flat accesses, and waiting
+// for one of those also waits for every LDS operation the wave has in
+// flight (the sampler's training-data atomics).
+#define VP_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ VP_GLOBAL T* global_ptr(T* p)
+{
+    return (VP_GLOBAL T*)p;
+}
+
 __device__ __forceinline__ int64_t gofs(const int64_t* __restrict__ loc, const int64_t* __restrict__ base,
                                         int64_t h)
 {
-    return loc[h] + base[h / kOffsTile];
+    return global_ptr(loc)[h] + global_ptr(base)[(uint64_t)h / kOffsTile];
 }
 
 // Position of sample pos in the point buffers of a batched integrand.  The
@@ -141,6 +155,10 @@ struct SampleArgs {
     int32_t hist_axes;      // training data of axes [0, hist_axes) privatised in LDS
     int32_t map_lds;        // map placement (MapPlace)
     int32_t chunk;          // samples per lane per tile
+    // split precisions: the weight plane of the LDS training data is an
+    // unsigned 64-bit fixed-point sum, each weight (1/n_h, or 1 in the literal
+    // mode) rounded to a multiple of 1/wscale (see fixed_weight_scale)
+    double wscale, wscale_inv;
     DumpArgs dump;          // per-sample dump (debugging and parity tests)
 };
 

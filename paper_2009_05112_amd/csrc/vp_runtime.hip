@@ -319,6 +319,29 @@ static vp_status drain_events(vp_problem* p)
     return VP_OK;
 }
 
+// Scale of the fixed-point weight plane of the split precisions' LDS
+// training data: a weight w (1/n_h, or 1 in the literal mode) is added as
+// rint(w 2^F).  A bin gathers at most one unit of weight from each hypercube
+// whose slab on its axis contains it, so at most H = max over the axes of
+// N_hc / N_st^mu units; F = 62 - ceil(log2 H) keeps every sum (with the
+// rounding excess, at most half a step per sample) below 2^63.  The rounding
+// error of a bin is at most half a step per sample, (N_tot / N_hc) 2^-(F+1) of
+// an axis's total weight N_hc over all bins: below 2^-29 for every accepted
+// problem.  The literal mode adds whole counts (F = 0): exact.
+static void fixed_weight_scale(const vp_problem* p, double* scale, double* inv)
+{
+    int F = 0;
+    if (p->P.hist_mode == VP_HIST_WEIGHTED) {
+        int64_t most = 1;
+        for (int32_t n : p->nst_ax) most = std::max<int64_t>(most, p->n_hc / n);
+        int bits = 0;
+        while (bits < 62 && ((int64_t)1 << bits) < most) ++bits;
+        F = 62 - bits;
+    }
+    *scale = std::ldexp(1.0, F);
+    *inv = std::ldexp(1.0, -F);
+}
+
 // Argument record of a problem for the batched kernels.
 static void fill_req(vp_problem* p)
 {
@@ -358,6 +381,7 @@ static void fill_req(vp_problem* p)
     a.hist_axes = p->hist_axes;
     a.map_lds = p->map_lds;
     a.chunk = p->chunk;
+    fixed_weight_scale(p, &a.wscale, &a.wscale_inv);
     q.n_h = p->n_h;
     q.offs = p->offs;
     q.bsum = p->bsum;
@@ -618,14 +642,20 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     const bool rec = sh->hist_axes < D;
     // Map placement.  Double precision: the whole map in LDS when it fits
     // beside the training data, else its innermost axes when they fit, else
-    // global memory.  The split precisions read it from global memory (their
-    // kernels are bound by the LDS atomics of the training data).  The
-    // accumulate mode of a batched integrand reads no map.
+    // global memory.  The split precisions stage only the innermost axes (the
+    // ones whose increments the lanes of a wave scatter over the whole axis;
+    // the outer axes' reads fall in a few cache lines per wave and stay with
+    // the vector-memory path, which keeps them out of the LDS queue of the
+    // training-data atomics).  The accumulate mode of a batched integrand
+    // reads no map.
     sh->map_lds = MAP_GLOBAL;
     if (!batch && !rec && prec == VP_FP64) {
         if (hb + map_lds_bytes(prec, D, NG, MAP_LDS) + fcb <= ctx->lds_max) sh->map_lds = MAP_LDS;
         else if (D > kMapInnerAxes && hb + map_lds_bytes(prec, D, NG, MAP_INNER) + fcb <= ctx->lds_max)
             sh->map_lds = MAP_INNER;
+    } else if (!batch && !rec && D > kMapInnerAxes &&
+               hb + map_lds_bytes(prec, D, NG, MAP_INNER) + fcb <= ctx->lds_max) {
+        sh->map_lds = MAP_INNER;
     }
     sh->entry = sample_entry(prec, f->kind, f->n_terms, D, sh->map_lds, rec, sh->mix);
     if (!sh->entry.launch && sh->map_lds != MAP_GLOBAL) {

@@ -125,6 +125,15 @@ __device__ __forceinline__ int64_t locate(const int64_t* __restrict__ offs,
     return res;
 }
 
+// An edge record into device memory (member by member: a global-address
+// object has no implicit assignment).
+__device__ __forceinline__ void put_edge(VP_GLOBAL EdgeRec* p, const EdgeRec& r)
+{
+    p->h = r.h;
+    p->s1 = r.s1;
+    p->s2 = r.s2;
+}
+
 // ---------------------------------------------------------------- run sums
 // Sums of J f and (J f)^2 over a run of samples of one hypercube.
 struct AccD {
@@ -219,14 +228,14 @@ struct AccOf<P_FP32_NEUMAIER> {
     typedef AccN type;
 };
 
-// Compensated single-precision training data in LDS.  Each bin is one 8-byte
-// word holding the pair (sum, compensation); an update reads the pair, takes
-// Neumaier's step with the new value, and stores the result with a 64-bit
-// compare-and-swap, retried while another lane or wave changed the word in
-// between.  (Single-precision LDS atomic adds are several times slower than
-// the 64-bit compare-and-swap on this hardware.)  The 2 D updates of a sample
-// go out together: all reads, then all swaps, then the retries of the lanes
-// whose swap lost.
+// Compensated single-precision training data in LDS.  Each numerator bin is
+// one 8-byte word holding the pair (sum, compensation); an update reads the
+// pair, takes Neumaier's step with the new value, and stores the result with
+// a 64-bit compare-and-swap, retried while another lane or wave changed the
+// word in between.  (Single-precision LDS atomic adds cost about ten times a
+// 64-bit integer add on this hardware.)  The D updates of a sample go out
+// together: all reads, then all swaps, then the retries of the lanes whose
+// swap lost.  The weights go to the fixed-point plane by integer adds.
 __device__ __forceinline__ uint64_t pack_pair(float s, float c)
 {
     return ((uint64_t)__float_as_uint(c) << 32) | (uint64_t)__float_as_uint(s);
@@ -234,28 +243,28 @@ __device__ __forceinline__ uint64_t pack_pair(float s, float c)
 
 template <int D>
 __device__ __forceinline__ void lds_neumaier_sample(uint64_t* pairs, int lbins, int n_g, const int32_t* idx,
-                                                    float hh, float hw)
+                                                    float hh, uint64_t wq)
 {
-    uint64_t* addr[2 * D];
-    uint64_t cur[2 * D];
+    uint64_t* addr[D];
+    uint64_t cur[D];
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) {
         const int bin = mu * n_g + idx[mu];
         addr[mu] = pairs + bin;
-        addr[D + mu] = pairs + lbins + bin;
+        atomicAdd(reinterpret_cast<unsigned long long*>(pairs + lbins + bin), (unsigned long long)wq);
     }
 #pragma unroll
-    for (int m = 0; m < 2 * D; ++m)
+    for (int m = 0; m < D; ++m)
         cur[m] = __hip_atomic_load(addr[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    static_assert(2 * D <= 32, "one pending bit per update");
-    uint32_t pending = (uint32_t)(((uint64_t)1 << (2 * D)) - 1u);
+    static_assert(D <= 32, "one pending bit per update");
+    uint32_t pending = (uint32_t)(((uint64_t)1 << D) - 1u);
     do {
 #pragma unroll
-        for (int m = 0; m < 2 * D; ++m) {
+        for (int m = 0; m < D; ++m) {
             if (pending & (1u << m)) {
                 float s = __uint_as_float((uint32_t)cur[m]);
                 float c = __uint_as_float((uint32_t)(cur[m] >> 32));
-                neumaier_add(s, c, m < D ? hh : hw);
+                neumaier_add(s, c, hh);
                 const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(addr[m]),
                                                (unsigned long long)cur[m], (unsigned long long)pack_pair(s, c));
                 if (old == cur[m]) pending &= ~(1u << m);
@@ -263,6 +272,12 @@ __device__ __forceinline__ void lds_neumaier_sample(uint64_t* pairs, int lbins, 
             }
         }
     } while (pending);
+}
+
+// A weight as a multiple of 1/scale, rounded to nearest (0 <= w * scale < 2^63).
+__device__ __forceinline__ uint64_t fixed_weight(double w, double scale)
+{
+    return (uint64_t)__builtin_rint(w * scale);
 }
 
 // ---------------------------------------------------------------- integrands
@@ -570,22 +585,29 @@ __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32
 // axes, and for the other axes a record at the sample's position -- the
 // numerator value, n_h and those axes' increment indices (k_hist_records bins
 // them).  The three record arrays follow each other at rec (see SampleArgs).
-template <int D, bool REC>
+// WFIX: the weight plane is the unsigned 64-bit fixed-point sum (weight wq);
+// else a double-precision sum (weight hw).
+template <int D, bool REC, bool WFIX>
 __device__ __forceinline__ void put_training(double* rec, int64_t stride, int ha, double* lds_hist, int lbins, int n_g,
-                                             int64_t pos, double hh, double hw, uint32_t n, const int32_t* idx)
+                                             int64_t pos, double hh, double hw, uint64_t wq, uint32_t n,
+                                             const int32_t* idx)
 {
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) {
         if (mu < ha) {
             const int bin = mu * n_g + idx[mu];
             atomicAdd(&lds_hist[bin], hh);
-            atomicAdd(&lds_hist[lbins + bin], hw);
+            if constexpr (WFIX)
+                atomicAdd(reinterpret_cast<unsigned long long*>(&lds_hist[lbins + bin]), (unsigned long long)wq);
+            else
+                atomicAdd(&lds_hist[lbins + bin], hw);
         }
     }
     if (REC && ha < D) {
-        uint32_t* rn = reinterpret_cast<uint32_t*>(rec + stride);
-        uint16_t* rb = reinterpret_cast<uint16_t*>(rn + stride);
-        rec[pos] = hh;
+        uint32_t* rn0 = reinterpret_cast<uint32_t*>(rec + stride);
+        VP_GLOBAL uint32_t* rn = global_ptr(rn0);
+        VP_GLOBAL uint16_t* rb = global_ptr(reinterpret_cast<uint16_t*>(rn0 + stride));
+        global_ptr(rec)[pos] = hh;
         rn[pos] = n;
 #pragma unroll
         for (int mu = 0; mu < D; ++mu)
@@ -779,9 +801,10 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
     const int C = a.chunk;
     const uint32_t n_st = (uint32_t)a.n_st;
     const bool literal = (a.hist_mode != 0);
-    double* __restrict__ S1 = a.S1;
-    double* __restrict__ S2 = a.S2;
-    EdgeRec* __restrict__ edges = a.edges;
+    const double wscale = a.wscale;
+    VP_GLOBAL double* __restrict__ S1 = global_ptr(a.S1);
+    VP_GLOBAL double* __restrict__ S2 = global_ptr(a.S2);
+    VP_GLOBAL EdgeRec* __restrict__ edges = global_ptr(a.edges);
     double* rec = REC ? a.rec_h : nullptr;
     const int64_t rec_stride = REC ? a.rec_stride : 0;
     BatchOut bout;
@@ -858,6 +881,15 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                 uint32_t n_cur = (uint32_t)(gofs(offs, ob, h + 1) - o_cur0);
                 double inv_n = recip_count(n_cur);
                 float inv_n32 = 1.0f / (float)n_cur;
+                // split precisions: the hypercube's weight in the fixed-point plane
+                // (the double-precision 1/n_h, or the single-precision one of the
+                // compensated form; 1 in the literal mode)
+                auto weight_q = [&]() -> uint64_t {
+                    if constexpr (PREC == P_FP64) return 0;
+                    else if constexpr (PREC == P_FP32_ACC64) return fixed_weight(literal ? 1.0 : inv_n, wscale);
+                    else return fixed_weight(literal ? 1.0 : (double)inv_n32, wscale);
+                };
+                uint64_t wq = weight_q();
                 for (uint32_t s = (uint32_t)(s_l - s_a); s < s_end; ++s, ++j) {
                     if (s == next) {
                         if (in_head) {
@@ -878,6 +910,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                         next = nn;
                         inv_n = recip_count(n_cur);
                         inv_n32 = 1.0f / (float)n_cur;
+                        wq = weight_q();
                         // next hypercube: increment the last coordinate with
                         // carry, without branches (the lanes of a wave switch
                         // hypercubes at different samples)
@@ -919,7 +952,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                         const double v2 = v * v;
                         const double hh = literal ? v2 : v2 * inv_n;
                         const double hw = literal ? 1.0 : inv_n;
-                        put_training<D, REC>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
+                        put_training<D, REC, false>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw,
+                                                    wq, n_cur, idx);
                     } else if constexpr (PREC == P_FP32_ACC64) {
                         const float v32 = (FC_SMEM ? sample_fp32<D, MAPL, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
                                            : sample_fp32<D, MAPL, KT, const MapT*, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
@@ -929,7 +963,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                         const double v2 = v * v;
                         const double hh = literal ? v2 : v2 * inv_n;
                         const double hw = literal ? 1.0 : inv_n;
-                        put_training<D, REC>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw, n_cur, idx);
+                        put_training<D, REC, true>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw,
+                                                   wq, n_cur, idx);
                     } else {
                         const float v32 = (FC_SMEM ? sample_fp32<D, MAPL, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
                                            : sample_fp32<D, MAPL, KT, const MapT*, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
@@ -937,8 +972,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                         if (!isfinite(v32)) ++bad;
                         const float v2 = v32 * v32;
                         const float hh = literal ? v2 : v2 * inv_n32;
-                        const float hw = literal ? 1.0f : inv_n32;
-                        lds_neumaier_sample<D>(lds_pairs, lbins, n_g, idx, hh, hw);
+                        lds_neumaier_sample<D>(lds_pairs, lbins, n_g, idx, hh, wq);
                     }
                 }
                 if (s_end == next) {
@@ -995,7 +1029,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                     r.h = head_h;
                     r.s1 = tot.sa();
                     r.s2 = tot.sb();
-                    if constexpr (!GEN) edges[2 * wave] = r;
+                    if constexpr (!GEN) put_edge(edges + (2 * wave), r);
                 } else if constexpr (!GEN) {
                     S1[head_h] = tot.sa();
                     S2[head_h] = tot.sb();
@@ -1026,14 +1060,14 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                 r.s2 = carry.sb();
                 if (carry_ext) {
                     r.h = h_a;
-                    edges[2 * wave] = r;
-                    edges[2 * wave + 1] = empty;
+                    put_edge(edges + (2 * wave), r);
+                    put_edge(edges + (2 * wave + 1), empty);
                 } else {
                     r.h = h_open;
-                    edges[2 * wave + 1] = r;
+                    put_edge(edges + (2 * wave + 1), r);
                 }
             } else {
-                edges[2 * wave + 1] = empty;
+                put_edge(edges + (2 * wave + 1), empty);
             }
         }
     } else if (lane == 0 && !GEN) {
@@ -1041,8 +1075,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
         empty.h = -1;
         empty.s1 = 0.0;
         empty.s2 = 0.0;
-        edges[2 * wave] = empty;
-        edges[2 * wave + 1] = empty;
+        put_edge(edges + (2 * wave), empty);
+        put_edge(edges + (2 * wave + 1), empty);
     }
 
     // Per-sample dump (vp_debug_dump), after the share is done.  Every value
@@ -1062,12 +1096,18 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
 
     __syncthreads();
     {
-        double* out = a.hist_part + (size_t)bid * 2 * nbins;
+        VP_GLOBAL double* out = global_ptr(a.hist_part + (size_t)bid * 2 * nbins);
         if constexpr (PREC == P_FP32_NEUMAIER) {
             for (int i = threadIdx.x; i < lbins; i += blockDim.x) {
-                const uint64_t ph = lds_pairs[i], pw = lds_pairs[lbins + i];
+                const uint64_t ph = lds_pairs[i];
                 out[i] = (double)__uint_as_float((uint32_t)ph) + (double)__uint_as_float((uint32_t)(ph >> 32));
-                out[nbins + i] = (double)__uint_as_float((uint32_t)pw) + (double)__uint_as_float((uint32_t)(pw >> 32));
+                out[nbins + i] = (double)lds_pairs[lbins + i] * a.wscale_inv;
+            }
+        } else if constexpr (PREC == P_FP32_ACC64) {
+            const uint64_t* wplane = reinterpret_cast<const uint64_t*>(lds_hist) + lbins;
+            for (int i = threadIdx.x; i < lbins; i += blockDim.x) {
+                out[i] = lds_hist[i];
+                out[nbins + i] = (double)wplane[i] * a.wscale_inv;
             }
         } else {
             for (int i = threadIdx.x; i < lbins; i += blockDim.x) {
@@ -1119,11 +1159,10 @@ SampleEntry entry_for(int map, bool rec)
 {
     if (rec) return map == MAP_GLOBAL ? make_entry<D, PREC, MAP_GLOBAL, KIND, true, KT, MIX>() : kNoEntry;
     if (map == MAP_GLOBAL) return make_entry<D, PREC, MAP_GLOBAL, KIND, false, KT, MIX>();
-    if constexpr (PREC == P_FP64) {
+    if constexpr (PREC == P_FP64)
         if (map == MAP_LDS) return make_entry<D, PREC, MAP_LDS, KIND, false, KT, MIX>();
-        if constexpr (D > kMapInnerAxes)
-            if (map == MAP_INNER) return make_entry<D, PREC, MAP_INNER, KIND, false, KT, MIX>();
-    }
+    if constexpr (D > kMapInnerAxes)
+        if (map == MAP_INNER) return make_entry<D, PREC, MAP_INNER, KIND, false, KT, MIX>();
     return kNoEntry;
 }
 
@@ -1140,8 +1179,11 @@ SampleEntry entry_for_global(int map, bool rec)
 template <int D, int PREC, int KIND, int KT = 0, bool MIX = false>
 SampleEntry entry_for_global_lds_only(int map, bool rec)
 {
-    if (rec || map != MAP_GLOBAL) return kNoEntry;
-    return make_entry<D, PREC, MAP_GLOBAL, KIND, false, KT, MIX>();
+    if (rec) return kNoEntry;
+    if (map == MAP_GLOBAL) return make_entry<D, PREC, MAP_GLOBAL, KIND, false, KT, MIX>();
+    if constexpr (D > kMapInnerAxes)
+        if (map == MAP_INNER) return make_entry<D, PREC, MAP_INNER, KIND, false, KT, MIX>();
+    return kNoEntry;
 }
 
 }  // namespace vp

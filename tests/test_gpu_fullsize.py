@@ -114,7 +114,7 @@ def test_fullsize_split_d8_two_iterations():
     p, f = W.cfg_diag_d8(precision="fp32_acc64")
     gp = B.Problem(ctx, p, f)
     op = oracle.Problem(p, f, n_st=gp.n_st)
-    assert gp.map_place == "global" and gp.hist_axes == 8
+    assert gp.map_place == "inner" and gp.hist_axes == 8
     for _ in range(2):
         fmap, n_h, it = gp.map(), gp.alloc(), gp.it
         hr = _arm_dump(gp, n_h, gp.n_hc // 3)

@@ -50,8 +50,8 @@ def test_split_stepwise_d4(ctx, prec):
     p, f = W.cfg_small_d4()
     p = p.with_(precision=prec)
     gp = B.Problem(ctx, p, f)
-    # the split kernels read the map by buffer loads, even where it would fit in LDS
-    assert gp.map_place == "global" and gp.hist_axes == 4
+    # the split kernels stage the two innermost map axes in LDS and read the others by buffer loads
+    assert gp.map_place == "inner" and gp.hist_axes == 4
     op = oracle.Problem(p, f, n_st=gp.n_st)
     for _ in range(4):
         step_and_compare(gp, op, rtol=RTOL32, rtol_hist=RTOL32, floor=FLOOR32)
