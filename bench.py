@@ -35,15 +35,17 @@ sys.path.insert(0, ROOT)
 METRIC = "integrand samples/sec/GPU (D=8, 1e8/iter) + p50/p99 solve latency vs plain"
 PEAK_VALU_SLOTS = 256 * 64 * 2.4e9  # full-rate VALU lane-operations per second: 256 CUs x 64 lanes x 2.4 GHz
 # Algorithmic VALU slots per sample of the fused sampling kernel at D=8 with
-# three Gaussian terms (derivation in the design notes; instruction costs
-# measured by an instruction-rate microbenchmark): Philox blocks x 10 rounds x
-# (2 full-rate 64-bit multiply-adds + 2 three-way xors), the uniform-to-
-# increment arithmetic, the map, the integrand and the sums.  FP32 operations
-# issue at twice the FP64/integer rate on gfx950 and count half a slot; the
-# compensated FP32 sums take 4 operations per addition for the two
-# per-hypercube sums and the 2D training-data values.
-SLOTS_PER_SAMPLE = {"fp64": 416.0, "fp32_acc64": 204.0, "fp32_neumaier": 204.0 + 3 * (2 + 2 * 8)}
-COUNTERS = os.path.join(ROOT, "profiles", "k_sample_d8_fp64_counters.md")
+# three Gaussian terms: the minimal operation list of each stage (Philox
+# blocks x 10 rounds x (2 multiplies + 2 xors), u -> t, the map, the
+# integrand, the sums and training-data values), priced with the issue costs an
+# instruction-rate microbenchmark measured on this device: a 32x32->64-bit
+# multiply-add issues at the FP64-FMA rate (one slot), the FP32 exponential
+# costs about three slots, an FP64 exponential about 25 operations.
+#   FP64:   4 blocks 160 + u->t 72 + map 72 + integrand 48+6+3x25 + sums 16 = 449
+#   FP32:   2 blocks  80 + u->t 32 + map 64 + integrand 24+6+3x3  + sums 16 = 231
+#   compensated FP32: + 3 slots for each of the 2 + D compensated additions = 261
+SLOTS_PER_SAMPLE = {"fp64": 449.0, "fp32_acc64": 231.0, "fp32_neumaier": 231.0 + 3 * (2 + 8)}
+COUNTERS = os.path.join(ROOT, "profiles", "k_sample_d8_counters.md")
 
 
 def measured_traffic(precision):
