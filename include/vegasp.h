@@ -37,7 +37,8 @@ typedef enum {
     VP_ERR_NUMERIC = 4,     /* non-finite integrand values were produced            */
     VP_ERR_NOT_READY = 5,   /* a served request has not finished                    */
     VP_ERR_CANCELLED = 6,   /* a served request was cancelled                       */
-    VP_ERR_STATE = 7        /* the call does not fit the object's current state     */
+    VP_ERR_STATE = 7,       /* the call does not fit the object's current state     */
+    VP_ERR_INVARIANT = 8    /* a device-side check found a broken invariant         */
 } vp_status;
 
 /* Static description of a status; the caller does not free it. */
@@ -166,7 +167,21 @@ enum { VP_HIST_WEIGHTED = 0, VP_HIST_LITERAL = 1 };
  *        (e.g. 46, 46, 1, ..., 1); their product must keep 2 samples per
  *        hypercube and stay below 2^31.
  * Hypercube h has digits k_mu in the mixed radix of the counts, axis 0 most
- * significant; y^mu = (k_mu + u) / N_st^mu. */
+ * significant; y^mu = (k_mu + u) / N_st^mu.
+ *  flags: 0 or an OR of
+ *    VP_FLAG_CHECKS: at the start of every iteration a device kernel checks
+ *        the state the iteration consumes (see vp_check_get); a violation
+ *        makes vp_result_get (and a served request) report VP_ERR_INVARIANT;
+ *    VP_FLAG_DETERMINISTIC: bitwise reproducible iterations (the same inputs
+ *        on the same device give the same bits; a served request and a
+ *        plain problem split the work differently and agree to rounding
+ *        only).  The training
+ *        data of every axis go through per-sample records that one wave per
+ *        workgroup bins in sample order, and the per-chunk partials are added
+ *        in a fixed order, so no sum depends on the timing of atomics (the
+ *        other sums already are fixed-order).  Costs the records' memory
+ *        (8 + 4 + 2 dim bytes per sample) and a binning pass; not available
+ *        with VP_FP32_NEUMAIER. */
 typedef struct {
     int32_t dim;
     int64_t n_ev;
@@ -186,7 +201,10 @@ typedef struct {
     int32_t average;
     int32_t strat;
     const int32_t* n_st_axes;
+    int32_t flags;
 } vp_params;
+
+enum { VP_FLAG_CHECKS = 1, VP_FLAG_DETERMINISTIC = 2 };
 
 enum { VP_AVG_WEIGHTED = 0, VP_AVG_UNWEIGHTED = 1 };
 enum { VP_STRAT_UNIFORM = 0, VP_STRAT_MIXED = 1 };
@@ -246,9 +264,27 @@ vp_status vp_iterate(vp_problem* p, int32_t n_iter);
 vp_status vp_sync(vp_problem* p);
 
 /* Synchronising.  Combined estimate; optionally the per-iteration estimates
- * I_j and variances V_j = sigma_j^2 (host arrays of at least cap entries;
- * the first min(cap, n_iter_done) are written). */
-vp_status vp_result_get(vp_problem* p, vp_result* out, double* I_j, double* V_j, int32_t cap);
+ * I_j (Eq. Iest), their standard deviations sigma_j and variances
+ * V_j = sigma_j^2 (Eq. sigest): host arrays of at least cap entries, any of
+ * them NULL; the first min(cap, n_iter_done) entries are written. */
+vp_status vp_result_get(vp_problem* p, vp_result* out, double* I_j, double* sig_j, double* V_j, int32_t cap);
+
+/* Device-side invariant checks (VP_FLAG_CHECKS), run on the state each
+ * iteration starts from:
+ *  VP_CHECK_MAP_ORDER  a map point is not finite, or an axis's points are not
+ *                      strictly increasing (every increment of the map of
+ *                      Sec. 2.2 has positive width);
+ *  VP_CHECK_MAP_ENDS   an axis's end points differ from the integration box;
+ *  VP_CHECK_NH_MIN     some n_h < 2 (the allocation rules of Sec. 3 keep two
+ *                      samples per hypercube, which Eq. sigest needs);
+ *  VP_CHECK_NH_SUM     the scanned sample total differs from sum n_h, or
+ *                      exceeds n_ev + 2 N_hc.
+ * Synchronising.  flags: OR of the bits seen so far (0: none); first_it: the
+ * iteration index at which the first violation was seen, -1 if none.  Either
+ * pointer may be NULL.  VP_ERR_STATE if the problem was created without
+ * VP_FLAG_CHECKS. */
+enum { VP_CHECK_MAP_ORDER = 1, VP_CHECK_MAP_ENDS = 2, VP_CHECK_NH_MIN = 4, VP_CHECK_NH_SUM = 8 };
+vp_status vp_check_get(vp_problem* p, uint32_t* flags, int32_t* first_it);
 
 /* Synchronising.  Vector results (n_out components, 1 for a scalar problem)
  * over iterations n_discard .. n_iter_done - 1:

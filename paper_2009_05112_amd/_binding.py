@@ -23,7 +23,9 @@ _AVG = {"weighted": 0, "unweighted": 1}
 _STRAT = {"uniform": 0, "mixed": 1}
 
 VP_OK, VP_ERR_INVALID_ARG, VP_ERR_OOM, VP_ERR_DEVICE, VP_ERR_NUMERIC, VP_ERR_NOT_READY, \
-    VP_ERR_CANCELLED, VP_ERR_STATE = range(8)
+    VP_ERR_CANCELLED, VP_ERR_STATE, VP_ERR_INVARIANT = range(9)
+VP_FLAG_CHECKS, VP_FLAG_DETERMINISTIC = 1, 2
+VP_CHECK_MAP_ORDER, VP_CHECK_MAP_ENDS, VP_CHECK_NH_MIN, VP_CHECK_NH_SUM = 1, 2, 4, 8
 
 
 class VegaspError(RuntimeError):
@@ -64,7 +66,7 @@ class vp_params(C.Structure):
                 ("upper", C.POINTER(C.c_double)), ("seed", C.c_uint64), ("precision", C.c_int32),
                 ("hist_mode", C.c_int32), ("realloc_plus2", C.c_int32), ("n_discard", C.c_int32),
                 ("n_st", C.c_int32), ("n_adapt", C.c_int32), ("average", C.c_int32),
-                ("strat", C.c_int32), ("n_st_axes", C.POINTER(C.c_int32))]
+                ("strat", C.c_int32), ("n_st_axes", C.POINTER(C.c_int32)), ("flags", C.c_int32)]
 
 
 class vp_result(C.Structure):
@@ -114,8 +116,9 @@ def lib():
             "vp_result_vec_get": ([vp, dp, dp, dp, ip, dp, dp, C.c_int32], C.c_int),
             "vp_iterate": ([vp, C.c_int32], C.c_int),
             "vp_sync": ([vp], C.c_int),
-            "vp_result_get": ([vp, C.POINTER(vp_result), dp, dp, C.c_int32], C.c_int),
+            "vp_result_get": ([vp, C.POINTER(vp_result), dp, dp, dp, C.c_int32], C.c_int),
             "vp_map_get": ([vp, dp], C.c_int),
+            "vp_check_get": ([vp, C.POINTER(C.c_uint32), ip], C.c_int),
             "vp_map_set": ([vp, dp], C.c_int),
             "vp_alloc_get": ([vp, ip], C.c_int),
             "vp_alloc_set": ([vp, ip], C.c_int),
@@ -222,7 +225,8 @@ def marshal(params, integrand):
                    arr(p.upper), int(p.seed) & ((1 << 64) - 1), _PREC[p.precision], _HIST[p.hist_mode],
                    1 if p.realloc_plus2 else 0, int(p.n_discard), int(getattr(p, "n_st", 0) or 0),
                    int(getattr(p, "n_adapt", 0) or 0), _AVG[getattr(p, "average", "weighted")],
-                   _STRAT[getattr(p, "strat", "uniform")], None if axes is None else _ip(axes))
+                   _STRAT[getattr(p, "strat", "uniform")], None if axes is None else _ip(axes),
+                   int(getattr(p, "flags", 0) or 0))
     return pp, fi, keep
 
 
@@ -260,13 +264,21 @@ class Problem:
         cap = cap if cap is not None else 65536
         I = np.zeros(cap)
         V = np.zeros(cap)
-        st = lib().vp_result_get(self.h, C.byref(r), _dp(I), _dp(V), cap)
+        sig = np.zeros(cap)
+        st = lib().vp_result_get(self.h, C.byref(r), _dp(I), _dp(sig), _dp(V), cap)
         if not (allow_nonfinite and st == VP_ERR_NUMERIC):
             check(st, "vp_result_get")
         n = r.n_iter_done
         return {"mean": r.mean, "sdev": r.sdev, "chi2": r.chi2, "dof": r.dof, "n_iter_done": n,
                 "n_evals": r.n_evals, "ties": r.n_near_ties, "nonfinite": r.n_nonfinite,
-                "I": I[:n].copy(), "V": V[:n].copy(), "sig": np.sqrt(V[:n])}
+                "I": I[:n].copy(), "V": V[:n].copy(), "sig": sig[:n].copy()}
+
+    def checks(self):
+        """Device-side invariant findings (vp_check_get): (flags, first iteration)."""
+        fl = C.c_uint32()
+        it = C.c_int32()
+        check(lib().vp_check_get(self.h, C.byref(fl), C.byref(it)), "vp_check_get")
+        return fl.value, it.value
 
     def result_vec(self, m: int, cap: int = 4096):
         """Vector results (vp_result_vec_get) of an integrand with m components."""
@@ -283,7 +295,7 @@ class Problem:
 
     def it_done(self):
         r = vp_result()
-        st = lib().vp_result_get(self.h, C.byref(r), None, None, 0)
+        st = lib().vp_result_get(self.h, C.byref(r), None, None, None, 0)
         if st not in (0, VP_ERR_NUMERIC):
             check(st, "vp_result_get")
         return r.n_iter_done

@@ -1150,6 +1150,83 @@ __global__ __launch_bounds__(kVecBlock) void k_vec_final(VecArgs a)
     *chi2 = c2;
 }
 
+// ---------------------------------------------------------------- invariant checks
+// The state an iteration starts from, after the allocation scan: every map
+// point finite and every axis strictly increasing from the box's lower to its
+// upper end (the map of Sec. 2.2), every n_h >= 2 (Sec. 3), and the scanned
+// total equal to sum n_h and at most n_ev + 2 N_hc.  Workgroups OR their
+// findings and add their share of sum n_h into the problem's state; the last
+// one to finish compares the sum, records the findings with the iteration
+// index and clears the running fields for the next launch.
+__global__ __launch_bounds__(kCheckBlock) void k_check(LaunchSet L)
+{
+    VP_REQ_PROLOGUE(L);
+    __shared__ unsigned long long wsum[kCheckBlock / kWave];
+    __shared__ unsigned int wbad[kCheckBlock / kWave];
+    __shared__ bool last;
+    const int D = q.dim, NG = q.n_g;
+    const int64_t nm = (int64_t)D * (NG + 1);
+    const int64_t n = nm > q.n_hc ? nm : q.n_hc;
+    const double* __restrict__ map = q.map;
+    const int32_t* __restrict__ nh = q.n_h;
+    unsigned int bad = 0;
+    unsigned long long sum = 0;
+    for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n; i += (int64_t)nblk * blockDim.x) {
+        if (i < nm) {
+            const int d = (int)(i / (NG + 1));
+            const int k = (int)(i - (int64_t)d * (NG + 1));
+            const double v = map[i];
+            if (!isfinite(v) || (k > 0 && !(v > map[i - 1]))) bad |= CHECK_MAP_ORDER;
+            if ((k == 0 && v != q.bounds[d]) || (k == NG && v != q.bounds[D + d])) bad |= CHECK_MAP_ENDS;
+        }
+        if (i < q.n_hc) {
+            const int32_t c = nh[i];
+            if (c < 2) bad |= CHECK_NH_MIN;
+            sum += (unsigned long long)(c > 0 ? c : 0);
+        }
+    }
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        sum += (unsigned long long)__shfl_xor((long long)sum, o);
+        bad |= (unsigned int)__shfl_xor((int)bad, o);
+    }
+    if (lane == 0) {
+        wsum[w] = sum;
+        wbad[w] = bad;
+    }
+    __syncthreads();
+    DevState* st = q.st;
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        unsigned int b = 0;
+        for (int i = 0; i < kCheckBlock / kWave; ++i) {
+            s += wsum[i];
+            b |= wbad[i];
+        }
+        atomicAdd(&st->check_sum, s);
+        if (b) atomicOr(&st->check_pending, b);
+        __threadfence();
+        last = atomicAdd(&st->check_ticket, 1u) == (unsigned int)nblk - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long total = atomicAdd(&st->check_sum, 0ull);
+        unsigned int b = atomicOr(&st->check_pending, 0u);
+        const int64_t scanned = gofs(q.offs, q.bsum, q.n_hc);
+        if ((unsigned long long)scanned != total || (double)scanned > q.n_ev + 2.0 * (double)q.n_hc)
+            b |= CHECK_NH_SUM;
+        if (b) {
+            if (st->check_flags == 0) st->check_it = q.s.it;
+            st->check_flags |= b;
+        }
+        st->check_sum = 0;
+        st->check_pending = 0;
+        st->check_ticket = 0;
+    }
+}
+
 // ---------------------------------------------------------------- advance
 // End of an iteration: the next iteration's Philox counter and history slot.
 __global__ void k_advance(LaunchSet L)
@@ -1182,6 +1259,7 @@ void enqueue_head(const IterPlan& P, hipStream_t s)
 {
     launch(k_scan_local, P.scan_local, P.n_scan_local, kScanBlock, 0, s);
     launch(k_scan_top, P.one, P.n_one, kScanBlock, 0, s);
+    launch(k_check, P.check, P.n_check, kCheckBlock, 0, s);
 }
 
 void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin, hipEvent_t sample_end,
@@ -1226,6 +1304,7 @@ void enqueue_tail(const IterPlan& P, hipStream_t s, const SideStreams* side)
         (void)hipEventRecord(side->fork, s);
         (void)hipStreamWaitEvent(m, side->fork, 0);
         launch(k_hist_records, P.rec, P.n_rec, kRecBlock, P.rec_lds, m);
+        launch(k_hist_records, P.rec_det, P.n_rec_det, kRecDetBlock, P.rec_lds, m);
         launch(k_hist_reduce, P.hist, P.n_hist, kHistBlock, 0, m);
         launch(k_refine, P.refine, P.n_refine, kRefineBlock, refine_lds, m);
         (void)hipEventRecord(side->join[0], m);
@@ -1238,6 +1317,7 @@ void enqueue_tail(const IterPlan& P, hipStream_t s, const SideStreams* side)
         return;
     }
     launch(k_hist_records, P.rec, P.n_rec, kRecBlock, P.rec_lds, s);
+    launch(k_hist_records, P.rec_det, P.n_rec_det, kRecDetBlock, P.rec_lds, s);
     launch(k_edge_fixup, P.fixup, P.n_fixup, kFixBlock, 0, s);
     launch(k_hist_reduce, P.hist, P.n_hist, kHistBlock, 0, s);
     launch(k_est_partial, P.est, P.n_est, kRedBlock, 0, s);

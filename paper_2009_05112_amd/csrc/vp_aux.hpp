@@ -30,6 +30,19 @@ __host__ __device__ inline int hist_values(int n_part)
     return v;
 }
 constexpr int kRedMaxGrid = 4096;
+// Invariant-check findings (the public VP_CHECK_* bits).
+enum CheckBits { CHECK_MAP_ORDER = 1, CHECK_MAP_ENDS = 2, CHECK_NH_MIN = 4, CHECK_NH_SUM = 8 };
+// Invariant checks: kCheckBlock threads, up to kCheckMaxGrid workgroups per request.
+constexpr int kCheckBlock = 256;
+constexpr int kCheckMaxGrid = 1024;
+inline int check_blocks(int64_t n_hc, int64_t n_map)
+{
+    const int64_t n = n_hc > n_map ? n_hc : n_map;
+    const int64_t g = (n + 4 * kCheckBlock - 1) / (4 * kCheckBlock);
+    return (int)(g < 1 ? 1 : (g > kCheckMaxGrid ? kCheckMaxGrid : g));
+}
+// Deterministic training records: one wave per binning workgroup.
+constexpr int kRecDetBlock = 64;
 constexpr int kRefineBlock = 256;
 constexpr int kFixBlock = 1024;  // edge fix-up: one workgroup per request
 
@@ -42,6 +55,14 @@ struct DevState {
     int32_t dof;
     unsigned long long ties;     // near-ties in reallocation
     unsigned long long nonfinite;
+    // device-side invariant checks (k_check): bits seen so far, the iteration
+    // of the first violation (-1: none), and the running state of the
+    // current check launch (reset by its last workgroup)
+    unsigned int check_flags;
+    int32_t check_it;
+    unsigned long long check_sum;
+    unsigned int check_pending;
+    unsigned int check_ticket;
 };
 
 inline int64_t scan_blocks(int64_t n_hc) { return (n_hc + kScanTile - 1) / kScanTile; }
@@ -126,8 +147,8 @@ struct SampleGroup {
 // Every launch of one batched iteration over a set of requests: the launch
 // sets share the request table and differ in their workgroup counts.
 struct IterPlan {
-    LaunchSet scan_local, one, hist, rec, fixup, est, refine;
-    int n_scan_local, n_one, n_hist, n_rec, n_fixup, n_est, n_refine;
+    LaunchSet scan_local, one, hist, rec, rec_det, fixup, est, refine, check;
+    int n_scan_local, n_one, n_hist, n_rec, n_rec_det, n_fixup, n_est, n_refine, n_check;
     size_t rec_lds;  // dynamic LDS of the records-to-histogram pass
     SampleGroup groups[kMaxGroups];
     int n_groups;
@@ -153,7 +174,8 @@ struct SideStreams {
 // events bracket the sampling launches, and side streams take some of them.
 void enqueue_iteration(const IterPlan& P, hipStream_t s, hipEvent_t sample_begin, hipEvent_t sample_end,
                        const SideStreams* side = nullptr);
-// The parts of an iteration before the sampling launches (allocation scan)
+// The parts of an iteration before the sampling launches (allocation scan,
+// then the invariant checks of the requests that asked for them)
 // and after them (training data, estimate, reallocation, refinement).  With a
 // side stream, the tail's two independent chains run side by side: training
 // data and map refinement on the first side stream, edge fix-up, estimate and

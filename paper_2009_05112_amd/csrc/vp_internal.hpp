@@ -198,6 +198,9 @@ struct ReqArgs {
     int32_t rec_chunks;     // records: sample chunks, each one partial
     int32_t rec_slices;     // records: axis slices per chunk
     int32_t rec_axes;       // records: axes per slice (the last may hold fewer)
+    int32_t checks;         // 1: run the invariant checks (k_check) every iteration
+    int32_t det;            // 1: training records binned by one wave per workgroup
+    const double* bounds;   // [2][dim]: lower, upper (device)
 };
 
 // One batched launch over n requests: request r's argument record is

@@ -63,7 +63,7 @@ public:
             *total = acc;
             return p;
         };
-        int n_scan = 0, n_one = 0, n_hist = 0, n_rec = 0, n_fix = 0, n_est = 0, n_ref = 0;
+        int n_scan = 0, n_one = 0, n_hist = 0, n_rec = 0, n_rec_det = 0, n_fix = 0, n_est = 0, n_ref = 0, n_chk = 0;
         Pending ps = add_set([](const ReqArgs& q) { return (int)scan_blocks(q.n_hc); }, &n_scan);
         Pending po = add_set([](const ReqArgs&) { return 1; }, &n_one);
         Pending ph = add_set(
@@ -74,7 +74,14 @@ public:
             },
             &n_hist);
         Pending prc = add_set(
-            [](const ReqArgs& q) { return q.hist_axes < q.dim ? q.rec_chunks * q.rec_slices : 0; }, &n_rec);
+            [](const ReqArgs& q) { return q.hist_axes < q.dim && !q.det ? q.rec_chunks * q.rec_slices : 0; }, &n_rec);
+        // deterministic requests: the same binning, one wave per workgroup
+        Pending prd = add_set(
+            [](const ReqArgs& q) { return q.hist_axes < q.dim && q.det ? q.rec_chunks * q.rec_slices : 0; },
+            &n_rec_det);
+        Pending pck = add_set(
+            [](const ReqArgs& q) { return q.checks ? check_blocks(q.n_hc, (int64_t)q.dim * (q.n_g + 1)) : 0; },
+            &n_chk);
         Pending pf = add_set([](const ReqArgs&) { return 1; }, &n_fix);
         Pending pe = add_set([](const ReqArgs& q) { return q.est_blocks; }, &n_est);
         Pending pr = add_set([](const ReqArgs& q) { return q.dim; }, &n_ref);
@@ -131,6 +138,8 @@ public:
         out->one = mk(po);
         out->hist = mk(ph);
         out->rec = mk(prc);
+        out->rec_det = mk(prd);
+        out->check = mk(pck);
         out->fixup = mk(pf);
         out->est = mk(pe);
         out->refine = mk(pr);
@@ -138,6 +147,8 @@ public:
         out->n_one = n_one;
         out->n_hist = n_hist;
         out->n_rec = n_rec;
+        out->n_rec_det = n_rec_det;
+        out->n_check = n_chk;
         out->n_fixup = n_fix;
         out->n_est = n_est;
         out->n_refine = n_ref;

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "vp_state.hpp"
+#include "vp_trace.hpp"
 
 using namespace vp;
 
@@ -235,6 +236,12 @@ vp_status vp::validate(const vp_params* P, const vp_integrand* f)
     }
     if (f->kind != VP_F_BATCH && f->n_out > 1)
         return fail(VP_ERR_INVALID_ARG, "vector-valued integrands (n_out > 1) are batched integrands");
+    if (P->flags & ~(VP_FLAG_CHECKS | VP_FLAG_DETERMINISTIC))
+        return fail(VP_ERR_INVALID_ARG, "unknown flags 0x%x", (unsigned)P->flags);
+    if ((P->flags & VP_FLAG_DETERMINISTIC) && P->precision == VP_FP32_NEUMAIER)
+        return fail(VP_ERR_INVALID_ARG, "the deterministic mode is not available with compensated sums");
+    if ((P->flags & VP_FLAG_DETERMINISTIC) && f->kind == VP_F_BATCH)
+        return fail(VP_ERR_INVALID_ARG, "the deterministic mode is not available with batched integrands");
     return VP_OK;
 }
 
@@ -418,6 +425,9 @@ static void fill_req(vp_problem* p)
     q.rec_chunks = p->rec_chunks;
     q.rec_slices = p->rec_slices;
     q.rec_axes = p->rec_axes;
+    q.checks = (P.flags & VP_FLAG_CHECKS) ? 1 : 0;
+    q.det = (P.flags & VP_FLAG_DETERMINISTIC) ? 1 : 0;
+    q.bounds = p->bounds_d;
 }
 
 // Writes the device copies of the iteration counters.
@@ -446,6 +456,7 @@ const char* vp_status_string(vp_status s)
     case VP_ERR_NOT_READY: return "not ready";
     case VP_ERR_CANCELLED: return "cancelled";
     case VP_ERR_STATE: return "invalid state";
+    case VP_ERR_INVARIANT: return "invariant violated";
     }
     return "unknown status";
 }
@@ -633,8 +644,12 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     // training data: as many axes as fit privatised in LDS beside the
     // integrand constants, the rest as records
     const size_t fcb = fc_lds_bytes(prec, f->kind, D) + 16;
-    const int fit = std::max<int>(1, (int)((ctx->lds_max - fcb) / (2 * sizeof(double) * (size_t)NG)));
-    sh->hist_axes = std::min(D, fit);
+    const bool det = (P->flags & VP_FLAG_DETERMINISTIC) != 0;
+    int fit = std::max<int>(1, (int)((ctx->lds_max - fcb) / (2 * sizeof(double) * (size_t)NG)));
+    // deterministic mode: every axis as records, binned in slices of at most
+    // two axes (small workgroups of one wave, several per CU)
+    if (det) fit = std::min(fit, 2);
+    sh->hist_axes = det ? 0 : std::min(D, fit);
     if (prec == VP_FP32_NEUMAIER && sh->hist_axes < D)
         return fail(VP_ERR_INVALID_ARG, "compensated sums need dim * n_g * 16 <= %zu bytes of LDS", ctx->lds_max);
     const size_t hb = hist_lds_bytes(sh->hist_axes, NG);
@@ -705,7 +720,8 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
         const int rem = D - sh->hist_axes;
         sh->rec_slices = (rem + fit - 1) / fit;
         sh->rec_axes = (rem + sh->rec_slices - 1) / sh->rec_slices;
-        const int64_t want = (2 * (int64_t)ctx->n_cu + sh->rec_slices - 1) / sh->rec_slices;
+        const int64_t per_cu = det ? 16 : 2;
+        const int64_t want = (per_cu * (int64_t)ctx->n_cu + sh->rec_slices - 1) / sh->rec_slices;
         sh->rec_chunks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(want, (n_tot_max + 65535) / 65536));
         // a multiple of 64, so that the three record arrays (8-, 4- and 2-byte
         // elements) follow each other exactly at 256-byte boundaries
@@ -913,6 +929,11 @@ vp_status vp::problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand
         head = p->staging.data();
     }
     memcpy(head + lay.f_d, &p->fh, sizeof(IntegrandDev));
+    DevState st0;
+    memset(&st0, 0, sizeof st0);
+    st0.check_it = -1;
+    memcpy(head + lay.st, &st0, sizeof st0);
+    p->bounds_d = (const double*)(base + lay.bounds);
     fill_req(p);
     memcpy(head + lay.d_req, &p->req, sizeof(ReqArgs));
     memcpy(head + lay.bounds, p->lower.data(), D * sizeof(double));
@@ -972,6 +993,9 @@ vp_status vp::result_from_state(const DevState& st, vp_result* out)
     out->n_evals = st.n_evals;
     out->n_near_ties = (int64_t)st.ties;
     out->n_nonfinite = (int64_t)st.nonfinite;
+    if (st.check_flags)
+        return fail(VP_ERR_INVARIANT, "device checks found broken invariants (flags 0x%x, first at iteration %d)",
+                    st.check_flags, st.check_it);
     if (st.nonfinite) return fail(VP_ERR_NUMERIC, "%llu non-finite integrand values", st.nonfinite);
     return VP_OK;
 }
@@ -1055,6 +1079,7 @@ extern "C" {
 
 vp_status vp_problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, vp_problem** out)
 {
+    TraceRange tr("vp_problem_create");
     return problem_create(ctx, P, f, 0, nullptr, out);
 }
 
@@ -1094,6 +1119,7 @@ vp_status vp_problem_strat(vp_problem* p, int32_t* n_st_axes)
 
 vp_status vp_iterate(vp_problem* p, int32_t n_iter)
 {
+    TraceRange tr("vp_iterate");
     if (!p || n_iter < 0) return fail(VP_ERR_INVALID_ARG, "problem is NULL or n_iter < 0");
     if (p->slot + n_iter > p->hist_cap) return fail(VP_ERR_STATE, "more than %d iterations", p->hist_cap);
     if (p->n_out > 1 && p->slot + n_iter > kVecHistory)
@@ -1107,6 +1133,7 @@ vp_status vp_iterate(vp_problem* p, int32_t n_iter)
     }
     if (p->batch_fn) return iterate_batch(p, n_iter);
     for (int32_t r = 0; r < n_iter; ++r) {
+        TraceRange tri("vegas+ iteration: enqueue");
         if (p->prof) {
             hipEvent_t e0 = take_event(p), e1 = take_event(p), e2 = take_event(p), e3 = take_event(p);
             VP_HIP(hipEventRecord(e2, s));
@@ -1133,16 +1160,40 @@ vp_status vp_sync(vp_problem* p)
     return VP_OK;
 }
 
-vp_status vp_result_get(vp_problem* p, vp_result* out, double* I_j, double* V_j, int32_t cap)
+vp_status vp_result_get(vp_problem* p, vp_result* out, double* I_j, double* sig_j, double* V_j, int32_t cap)
 {
+    TraceRange tr("vp_result_get");
     if (!p || !out) return fail(VP_ERR_INVALID_ARG, "problem and out are required");
     VP_HIP(hipStreamSynchronize(p->ctx->stream));
     DevState st;
     VP_HIP(hipMemcpy(&st, p->st, sizeof st, hipMemcpyDeviceToHost));
     const int32_t n = std::min<int32_t>(cap, st.n_iter_done);
     if (I_j && n > 0) VP_HIP(hipMemcpy(I_j, p->hist_I, sizeof(double) * n, hipMemcpyDeviceToHost));
-    if (V_j && n > 0) VP_HIP(hipMemcpy(V_j, p->hist_V, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if ((V_j || sig_j) && n > 0) {
+        std::vector<double> v(n);
+        VP_HIP(hipMemcpy(v.data(), p->hist_V, sizeof(double) * n, hipMemcpyDeviceToHost));
+        for (int32_t i = 0; i < n; ++i) {
+            if (V_j) V_j[i] = v[i];
+            if (sig_j) sig_j[i] = std::sqrt(v[i]);
+        }
+    }
     return result_from_state(st, out);
+}
+
+vp_status vp_check_get(vp_problem* p, uint32_t* flags, int32_t* first_it)
+{
+    if (!p) return fail(VP_ERR_INVALID_ARG, "problem is NULL");
+    if (!(p->P.flags & VP_FLAG_CHECKS)) return fail(VP_ERR_STATE, "the problem was created without VP_FLAG_CHECKS");
+    static_assert(VP_CHECK_MAP_ORDER == CHECK_MAP_ORDER && VP_CHECK_MAP_ENDS == CHECK_MAP_ENDS &&
+                      VP_CHECK_NH_MIN == CHECK_NH_MIN && VP_CHECK_NH_SUM == CHECK_NH_SUM,
+                  "check bits of the header and the kernels agree");
+    VP_HIP(hipSetDevice(p->ctx->device));
+    VP_HIP(hipStreamSynchronize(p->ctx->stream));
+    DevState st;
+    VP_HIP(hipMemcpy(&st, p->st, sizeof st, hipMemcpyDeviceToHost));
+    if (flags) *flags = st.check_flags;
+    if (first_it) *first_it = st.check_it;
+    return VP_OK;
 }
 
 vp_status vp_map_get(vp_problem* p, double* map)
@@ -1309,7 +1360,7 @@ vp_status vp_result_vec_get(vp_problem* p, double* mean, double* cov, double* ch
     if (m <= 1) {
         // a scalar problem: its result as a vector of one component
         vp_result r;
-        vp_status st = vp_result_get(p, &r, I_j, C_j, cap);
+        vp_status st = vp_result_get(p, &r, I_j, nullptr, C_j, cap);
         if (st != VP_OK && st != VP_ERR_NUMERIC) return st;
         if (mean) mean[0] = r.mean;
         if (cov) cov[0] = r.sdev * r.sdev;
@@ -1586,12 +1637,13 @@ vp_status vp_kernel_time(vp_problem* p, int32_t which, double* total_ms, int64_t
 
 vp_status vp_integrate(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, vp_result* out)
 {
+    TraceRange tr("vp_integrate");
     if (!out) return fail(VP_ERR_INVALID_ARG, "out is NULL");
     vp_problem* p = nullptr;
     vp_status s = vp_problem_create(ctx, P, f, &p);
     if (s != VP_OK) return s;
     s = vp_iterate(p, P->n_iter);
-    if (s == VP_OK) s = vp_result_get(p, out, nullptr, nullptr, 0);
+    if (s == VP_OK) s = vp_result_get(p, out, nullptr, nullptr, nullptr, 0);
     vp_problem_destroy(p);
     return s;
 }

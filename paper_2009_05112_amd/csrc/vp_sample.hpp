@@ -233,9 +233,9 @@ struct AccOf<P_FP32_NEUMAIER> {
 // pair, takes Neumaier's step with the new value, and stores the result with
 // a 64-bit compare-and-swap, retried while another lane or wave changed the
 // word in between.  (Single-precision LDS atomic adds cost about ten times a
-// 64-bit integer add on this hardware.)  The D updates of a sample go out
-// together: all reads, then all swaps, then the retries of the lanes whose
-// swap lost.  The weights go to the fixed-point plane by integer adds.
+// 64-bit integer add on this hardware.)  Each of the D updates of a sample
+// reads its word and swaps at once; then the lanes whose swap lost retry.
+// The weights go to the fixed-point plane by integer adds.
 __device__ __forceinline__ uint64_t pack_pair(float s, float c)
 {
     return ((uint64_t)__float_as_uint(c) << 32) | (uint64_t)__float_as_uint(s);
@@ -253,12 +253,23 @@ __device__ __forceinline__ void lds_neumaier_sample(uint64_t* pairs, int lbins, 
         addr[mu] = pairs + bin;
         atomicAdd(reinterpret_cast<unsigned long long*>(pairs + lbins + bin), (unsigned long long)wq);
     }
-#pragma unroll
-    for (int m = 0; m < D; ++m)
-        cur[m] = __hip_atomic_load(addr[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    // first attempt: each swap right after its read, so that the window in
+    // which another lane or wave can change the word is one read's latency
     static_assert(D <= 32, "one pending bit per update");
-    uint32_t pending = (uint32_t)(((uint64_t)1 << D) - 1u);
-    do {
+    uint32_t pending = 0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+        cur[m] = __hip_atomic_load(addr[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        float s = __uint_as_float((uint32_t)cur[m]);
+        float c = __uint_as_float((uint32_t)(cur[m] >> 32));
+        neumaier_add(s, c, hh);
+        const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(addr[m]),
+                                       (unsigned long long)cur[m], (unsigned long long)pack_pair(s, c));
+        if (old != cur[m]) pending |= 1u << m;
+        cur[m] = old;
+    }
+    // retries of the lanes whose swap lost, from the value the swap returned
+    while (pending) {
 #pragma unroll
         for (int m = 0; m < D; ++m) {
             if (pending & (1u << m)) {
@@ -271,7 +282,7 @@ __device__ __forceinline__ void lds_neumaier_sample(uint64_t* pairs, int lbins, 
                 cur[m] = old;
             }
         }
-    } while (pending);
+    }
 }
 
 // A weight as a multiple of 1/scale, rounded to nearest (0 <= w * scale < 2^63).

@@ -28,11 +28,13 @@
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <optional>
 #include <thread>
 #include <unordered_map>
 #include <vector>
 
 #include "vp_state.hpp"
+#include "vp_trace.hpp"
 
 using namespace vp;
 
@@ -374,6 +376,8 @@ static void scheduler(vp_server* s)
         const int b = (int)(s->turn & 1);  // buffers of the step this turn enqueues
         bool changed = false;
         const auto t_adm = std::chrono::steady_clock::now();
+        std::optional<TraceRange> tr_adm;
+        if (!admit.empty()) tr_adm.emplace("vp_server: admit");
         // initial images of this turn's admissions go to staging set b (the
         // other set may still be read by the step in flight)
         s->pool.select_stage(b);
@@ -412,6 +416,7 @@ static void scheduler(vp_server* s)
             }
         }
         if (!admit.empty()) s->ss.t_admit += s->tsec(t_adm);
+        tr_adm.reset();
         // cancellations of active requests, and requests with nothing to do;
         // a request the step in flight still runs is freed once it is done
         for (size_t i = 0; i < s->active.size();) {
@@ -425,7 +430,7 @@ static void scheduler(vp_server* s)
                 s->active.erase(s->active.begin() + i);
                 changed = true;
                 if (!cancel) {
-                    r->status = vp_result_get(r->prob, &r->res, nullptr, nullptr, 0);
+                    r->status = vp_result_get(r->prob, &r->res, nullptr, nullptr, nullptr, 0);
                     retire(s, r, R_DONE);
                 } else if (r->prob && r->prob->slot > 0 && s->inflight) {
                     s->drop_inflight.push_back(r);
@@ -440,6 +445,7 @@ static void scheduler(vp_server* s)
         const bool stepping = !s->active.empty();
         if (stepping) {
             if (changed || !s->plan_valid) {
+                TraceRange tr_plan("vp_server: plan");
                 const auto t_pl = std::chrono::steady_clock::now();
                 std::vector<PlanReq> pr;
                 pr.reserve(s->active.size());
@@ -459,11 +465,17 @@ static void scheduler(vp_server* s)
                 std::lock_guard<std::mutex> lk(s->mu);
                 s->st.peak_active = std::max<int32_t>(s->st.peak_active, (int32_t)s->active.size());
             }
-            ok = enqueue_step(s);
+            {
+                TraceRange tr_step("vp_server: step");
+                ok = enqueue_step(s);
+            }
             s->ss.steps += 1;
         }
         // the previous step (queued ahead of this one) completes meanwhile
-        if (ok) ok = complete_inflight(s);
+        if (ok) {
+            TraceRange tr_ret("vp_server: wait and retire");
+            ok = complete_inflight(s);
+        }
         if (!ok) {
             fail_all(s, "device error during a batched step");
             publish_stats(s);

@@ -57,6 +57,7 @@ struct vp_problem {
     vp_ctx* ctx;
     vp_params P;
     std::vector<double> lower, upper;
+    const double* bounds_d = nullptr;  // [2][dim] lower, upper in device memory
     std::vector<int32_t> nst_ax;  // stratifications of every axis
     int n_out = 1;               // components of a vector-valued batched integrand
     int vec_grid = 0;

@@ -91,6 +91,7 @@ class Params:
     n_st_axes: Optional[np.ndarray] = None  # explicit per-axis stratifications (override strat)
     lower: Optional[np.ndarray] = None
     upper: Optional[np.ndarray] = None
+    flags: int = 0              # library options: 1 device-side checks, 2 deterministic training data
 
     def with_(self, **kw) -> "Params":
         return replace(self, **kw)

@@ -63,6 +63,8 @@ def test_end_to_end_cfg_small_d4(ctx):
     assert ro["ties"] == 0 and rg["ties"] == 0
     assert_close(rg["I"], ro["I"], RTOL64, what="I_j")
     assert_close(rg["V"], ro["V"], RTOL64, what="V_j")
+    assert_close(rg["sig"], np.sqrt(ro["V"]), RTOL64, what="sigma_j")  # returned by the library
+    np.testing.assert_array_equal(rg["sig"], np.sqrt(rg["V"]))
     assert_close(rg["mean"], ro["mean"], RTOL64, what="mean")
     assert_close(rg["sdev"], ro["sdev"], RTOL64, what="sdev")
     assert_close(rg["chi2"], ro["chi2"], 1e-9, what="chi2")
