@@ -429,6 +429,13 @@ vp_status vp_server_create(vp_ctx* ctx, size_t mem_budget_bytes, int32_t max_slo
  * as vp_problem_create would, or VP_ERR_OOM when the request alone exceeds
  * the budget.  *ticket identifies the request. */
 vp_status vp_server_submit(vp_server* s, const vp_params* params, const vp_integrand* f, uint64_t* ticket);
+/* Thread-safe.  n requests at once (params[i], f[i]; tickets[i] receives
+ * request i's ticket): all are checked as vp_server_submit checks one, and
+ * either all are queued together -- in array order, so that the scheduler
+ * sees them in one admission turn -- or none is (the status of the first
+ * request that fails, its index in the detail message). */
+vp_status vp_server_submit_many(vp_server* s, int32_t n, const vp_params* params, const vp_integrand* f,
+                                uint64_t* tickets);
 /* Thread-safe.  Device bytes the request would hold while admitted (the
  * figure the memory budget is charged), without submitting it. */
 vp_status vp_server_request_bytes(vp_server* s, const vp_params* params, const vp_integrand* f, size_t* bytes);

@@ -135,6 +135,8 @@ def lib():
             "vp_server_create": ([vp, C.c_size_t, C.c_int32, C.c_int32, C.POINTER(vp)], C.c_int),
             "vp_server_submit": ([vp, C.POINTER(vp_params), C.POINTER(vp_integrand), C.POINTER(C.c_uint64)],
                                  C.c_int),
+            "vp_server_submit_many": ([vp, C.c_int32, C.POINTER(vp_params), C.POINTER(vp_integrand),
+                                       C.POINTER(C.c_uint64)], C.c_int),
             "vp_server_request_bytes": ([vp, C.POINTER(vp_params), C.POINTER(vp_integrand),
                                          C.POINTER(C.c_size_t)], C.c_int),
             "vp_server_poll": ([vp, C.c_uint64, C.POINTER(vp_result)], C.c_int),
@@ -409,8 +411,10 @@ class Problem:
             pass
 
 
-def integrate(ctx: Context, params, integrand):
-    pp, fi, keep = marshal(params, integrand)
+def integrate(ctx: Context, params, integrand, prepared=None):
+    """vp_integrate; prepared: the (params, integrand) structures from
+    marshal(), when the caller built them beforehand."""
+    pp, fi, keep = prepared if prepared is not None else marshal(params, integrand)
     r = vp_result()
     check(lib().vp_integrate(ctx.h, C.byref(pp), C.byref(fi), C.byref(r)), "vp_integrate")
     return {"mean": r.mean, "sdev": r.sdev, "chi2": r.chi2, "dof": r.dof, "n_evals": r.n_evals,
@@ -438,6 +442,28 @@ class Server:
         t = C.c_uint64()
         check(lib().vp_server_submit(self.h, C.byref(pp), C.byref(fi), C.byref(t)), "vp_server_submit")
         return t.value
+
+    @staticmethod
+    def prepare(reqs):
+        """The C structures of (params, integrand) pairs, for submit_many."""
+        n = len(reqs)
+        P = (vp_params * n)()
+        F = (vp_integrand * n)()
+        keep = []
+        for i, (p, f) in enumerate(reqs):
+            pp, fi, k = marshal(p, f)
+            P[i] = pp
+            F[i] = fi
+            keep.append(k)
+        return n, P, F, keep
+
+    def submit_many(self, reqs) -> list:
+        """vp_server_submit_many: a list of (params, integrand) pairs, or
+        what prepare() returned for one; the tickets in order."""
+        n, P, F, keep = reqs if isinstance(reqs, tuple) else self.prepare(reqs)
+        T = (C.c_uint64 * max(n, 1))()
+        check(lib().vp_server_submit_many(self.h, n, P, F, T), "vp_server_submit_many")
+        return [int(T[i]) for i in range(n)]
 
     def request_bytes(self, params, integrand) -> int:
         pp, fi, keep = marshal(params, integrand)

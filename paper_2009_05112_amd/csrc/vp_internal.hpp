@@ -32,6 +32,11 @@ enum BatchMode { K_BATCH_GEN = 101, K_BATCH_ACC = 102 };
 constexpr int sample_block(int prec, int kind, int dim, bool map_lds)
 {
     if (prec == 0) {
+        // the batched integrand's modes hold little state: the accumulate mode
+        // (training data in LDS, one workgroup per CU) takes four waves per
+        // SIMD, the generate mode (the map in LDS, two workgroups per CU) six
+        if (kind == K_BATCH_ACC) return 1024;
+        if (kind == K_BATCH_GEN) return map_lds || dim > 16 ? 768 : 1024;
         if (kind != K_GAUSS_MIX) return 512;
         if (dim == 8) return map_lds ? 768 : 1024;
         return dim < 8 ? 1024 : (dim <= 12 ? 768 : 512);

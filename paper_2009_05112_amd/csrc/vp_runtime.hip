@@ -780,7 +780,7 @@ static Layout layout_of(const vp_params* P, const Shape& sh)
     L.bx = take((size_t)sh.bcap * D * sizeof(double));
     L.bj = take((size_t)sh.bcap * sizeof(double));
     L.bf = take((size_t)sh.bcap * sh.n_out * sizeof(double));
-    L.bidx = take((size_t)sh.bcap * D * sizeof(uint16_t));
+    L.bidx = take((size_t)sh.bcap * ((D + 7) / 8) * 8 * sizeof(uint16_t));
     // vector-valued integrand: per-iteration estimates and covariances,
     // partial sums, combined result
     const size_t M = sh.n_out > 1 ? (size_t)sh.n_out : 0;

@@ -454,7 +454,10 @@ struct SampleHot {
 // FP64: u from 53 bits -- the high word of axis mu is word mu of the
 // stream, its low word is word D + mu.
 // Where the generate mode of a batched integrand puts a sample: x at
-// x[mu * n + pos], J at jac[pos], the increment index at idx[mu * cap + pos].
+// x[mu * n + pos], J at jac[pos]; its increment indices, 16-bit, in groups of
+// eight axes at idx[(pos * ceil(D / 8) + g) * 8 ..] (one 16-byte store and
+// load per group; the index buffer is the library's own).
+typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
 struct BatchOut {
     double* x;
     double* jac;
@@ -517,8 +520,9 @@ __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair6
             jac = jac * ((double)n_g * dx);
             idx[mu] = i;
             if constexpr (GEN) {
-                out->x[mu * out->n + out->pos] = x;
-                out->idx[mu * out->cap + out->pos] = (uint16_t)i;
+                // global (not flat) stores: a flat store would also hold up
+                // every later wait for the map reads from LDS
+                global_ptr(out->x)[mu * out->n + out->pos] = x;
             } else {
                 f_axis<D, KT, double, FP>(fc, kind, K, mu, x, st);
             }
@@ -529,7 +533,7 @@ __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair6
         }
     }
     if constexpr (GEN) {
-        out->jac[out->pos] = jac;
+        global_ptr(out->jac)[out->pos] = jac;
         return 0.0;
     } else {
         const double fx = f_finish<D, KT, double, FP>(fc, kind, K, st);
@@ -877,6 +881,12 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                 const int64_t o_cur0 = gofs(offs, ob, h);
                 uint32_t hh32 = (uint32_t)h;
                 uint32_t next = (uint32_t)(gofs(offs, ob, h + 1) - s_a);
+                // generate mode: the boundary after the next one is loaded one
+                // switch ahead.  Its stores and loads share one counter, so a
+                // boundary loaded at the switch that needs it would wait for
+                // every point written before it.
+                int64_t pref = 0;
+                if constexpr (GEN) pref = h + 2 <= n_hc ? gofs(offs, ob, h + 2) : 0;
                 uint32_t j = (uint32_t)(s_l - o_cur0);
                 const uint32_t s_end = (uint32_t)(e_l - s_a);
                 int32_t k[D];
@@ -901,6 +911,20 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                     else return fixed_weight(literal ? 1.0 : (double)inv_n32, wscale);
                 };
                 uint64_t wq = weight_q();
+                constexpr int IDXG = (D + 7) / 8;  // 16-byte groups of increment indices
+                // accumulate mode: J, f and the indices of the lane's next
+                // sample are loaded while the current one is added up
+                double pj = 0.0, pf = 0.0;
+                U32x4 pw[IDXG];
+                auto acc_load = [&](uint32_t s_rel) {
+                    const int64_t pos = batch_pos(s_a + (int64_t)s_rel, n_tot);
+                    pj = global_ptr(bout.jac)[pos];
+                    pf = global_ptr(bf)[pos];
+#pragma unroll
+                    for (int g = 0; g < IDXG; ++g)
+                        pw[g] = *global_ptr(reinterpret_cast<const U32x4*>(bout.idx + (pos * IDXG + g) * 8));
+                };
+                if constexpr (ACC) acc_load((uint32_t)(s_l - s_a));
                 for (uint32_t s = (uint32_t)(s_l - s_a); s < s_end; ++s, ++j) {
                     if (s == next) {
                         if (in_head) {
@@ -916,7 +940,13 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                         run.zero();
                         ++hh32;
                         j = 0;
-                        const uint32_t nn = (uint32_t)(gofs(offs, ob, (int64_t)hh32 + 1) - s_a);
+                        uint32_t nn;
+                        if constexpr (GEN) {
+                            nn = (uint32_t)(pref - s_a);
+                            if ((int64_t)hh32 + 2 <= n_hc) pref = gofs(offs, ob, (int64_t)hh32 + 2);
+                        } else {
+                            nn = (uint32_t)(gofs(offs, ob, (int64_t)hh32 + 1) - s_a);
+                        }
                         n_cur = nn - next;
                         next = nn;
                         inv_n = recip_count(n_cur);
@@ -947,13 +977,36 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                         bout.pos = bpos;
                         (void)sample_fp64<D, MAPL, 0, const MapT*, true, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K,
                                                                            &bout);
+#pragma unroll
+                        for (int g = 0; g < IDXG; ++g) {
+                            uint32_t w[4];
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const int m0 = 8 * g + 2 * r, m1 = m0 + 1;
+                                w[r] = (m0 < D ? (uint32_t)idx[m0] : 0u) | ((m1 < D ? (uint32_t)idx[m1] : 0u) << 16);
+                            }
+                            U32x4* dst = reinterpret_cast<U32x4*>(bout.idx + (bpos * IDXG + g) * 8);
+                            *global_ptr(dst) = U32x4{w[0], w[1], w[2], w[3]};
+                        }
                     } else if constexpr (PREC == P_FP64) {
                         double v;
                         if constexpr (ACC) {
-                            const int64_t pos = bpos;
-                            v = bout.jac[pos] * (bscale * bf[pos]);
+                            v = pj * (bscale * pf);
+                            U32x4 cw[IDXG];
 #pragma unroll
-                            for (int mu = 0; mu < D; ++mu) idx[mu] = bout.idx[mu * bout.cap + pos];
+                            for (int g = 0; g < IDXG; ++g) cw[g] = pw[g];
+                            if (s + 1 < s_end) acc_load(s + 1);
+#pragma unroll
+                            for (int g = 0; g < IDXG; ++g) {
+                                const U32x4 wv = cw[g];
+                                const uint32_t w[4] = {wv[0], wv[1], wv[2], wv[3]};
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) {
+                                    const int m0 = 8 * g + 2 * r, m1 = m0 + 1;
+                                    if (m0 < D) idx[m0] = (int32_t)(w[r] & 0xffffu);
+                                    if (m1 < D) idx[m1] = (int32_t)(w[r] >> 16);
+                                }
+                            }
                         } else {
                             v = (FC_SMEM ? sample_fp64<D, MAPL, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
                                          : sample_fp64<D, MAPL, KT, const MapT*, false, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));

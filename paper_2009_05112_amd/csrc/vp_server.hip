@@ -594,6 +594,47 @@ vp_status vp_server_submit(vp_server* s, const vp_params* P, const vp_integrand*
     return VP_OK;
 }
 
+vp_status vp_server_submit_many(vp_server* s, int32_t n, const vp_params* P, const vp_integrand* f,
+                                uint64_t* tickets)
+{
+    if (!s || n < 0 || (n > 0 && (!P || !f || !tickets)))
+        return fail(VP_ERR_INVALID_ARG, "server, n >= 0 and the three arrays are required");
+    std::vector<ServedReq*> made;
+    made.reserve(n);
+    auto drop = [&]() {
+        for (ServedReq* r : made) delete r;
+    };
+    for (int32_t i = 0; i < n; ++i) {
+        vp_status st = validate(&P[i], &f[i]);
+        if (st == VP_OK && f[i].kind == VP_F_BATCH)
+            st = fail(VP_ERR_INVALID_ARG, "batched integrands call host code between kernels and are not servable");
+        size_t bytes = 0;
+        if (st == VP_OK) st = problem_bytes(s->ctx, &P[i], &f[i], kServeSamplesPerWG, &bytes);
+        if (st == VP_OK && bytes > s->budget)
+            st = fail(VP_ERR_OOM, "request needs %zu device bytes, the budget is %zu", bytes, s->budget);
+        if (st != VP_OK) {
+            drop();
+            return fail(st, "request %d of %d: %s", i, n, vp_last_error());
+        }
+        ServedReq* r = new ServedReq();
+        copy_request(r, &P[i], &f[i]);
+        r->bytes = bytes;
+        made.push_back(r);
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    const double t = s->now();
+    for (int32_t i = 0; i < n; ++i) {
+        ServedReq* r = made[i];
+        r->ticket = s->next_ticket++;
+        r->t_submit = t;
+        s->all[r->ticket] = r;
+        s->pending.push_back(r);
+        tickets[i] = r->ticket;
+    }
+    if (n > 0) s->cv_work.notify_one();
+    return VP_OK;
+}
+
 vp_status vp_server_request_bytes(vp_server* s, const vp_params* P, const vp_integrand* f, size_t* bytes)
 {
     if (!s || !bytes) return fail(VP_ERR_INVALID_ARG, "server and bytes are required");

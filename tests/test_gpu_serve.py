@@ -96,6 +96,27 @@ def test_mix_at_once_equals_alone(ctx, mix, alone):
         same(a, r, f"request {i}")
 
 
+def test_submit_many_equals_alone(ctx, mix, alone):
+    """The whole mix in one vp_server_submit_many call: admitted in one turn,
+    each result as when run alone; a list with one invalid request queues
+    nothing."""
+    s = B.Server(ctx)
+    tickets = s.submit_many(mix)
+    assert tickets == sorted(tickets) and len(set(tickets)) == len(mix)
+    res = [s.wait(t) for t in tickets]
+    st = s.stats()
+    assert st["peak_active"] == len(mix) and st["completed"] == len(mix)
+    for i, (a, r) in enumerate(zip(alone, res)):
+        same(a, r, f"request {i}")
+    bad = list(mix[:3]) + [(mix[0][0].with_(n_g=0), mix[0][1])]
+    with pytest.raises(B.VegaspError) as e:
+        s.submit_many(bad)
+    assert e.value.status == B.VP_ERR_INVALID_ARG and "request 3 of 4" in str(e.value)
+    assert s.stats()["pending"] == 0 and s.stats()["completed"] == len(mix)
+    assert s.submit_many([]) == []
+    s.close()
+
+
 def test_staggered_arrivals_equal_alone(ctx, mix, alone):
     """Requests arrive from another thread while earlier ones are on the GPU."""
     s = B.Server(ctx)
