@@ -49,6 +49,11 @@ constexpr int64_t kServeSamplesPerWG = 16384;
 // (the sets of a stream of arrivals often change after a few steps, and a
 // capture costs the host as much as tens of direct launches).
 constexpr int64_t kCaptureAfter = 3;
+// Requests admitted per scheduler turn: a large batch arriving at once starts
+// on the GPU after the first share is set up, and the rest are set up while
+// the steps run (4096 requests of the served-batch workload: 0.334 s makespan
+// admitted at once, 0.320 s by 1024 per turn).
+constexpr int kAdmitPerTurn = 1024;
 
 enum ReqState { R_PENDING = 0, R_ACTIVE = 1, R_DONE = 2, R_CANCELLED = 3, R_FAILED = 4 };
 
@@ -350,7 +355,8 @@ static void scheduler(vp_server* s)
         {
             std::unique_lock<std::mutex> lk(s->mu);
             for (;;) {
-                while (!s->pending.empty() && (int)(s->active.size() + admit.size()) < s->max_slots) {
+                while (!s->pending.empty() && (int)(s->active.size() + admit.size()) < s->max_slots &&
+                       (int)admit.size() < kAdmitPerTurn) {
                     ServedReq* r = s->pending.front();
                     if (r->cancel) {
                         s->pending.pop_front();
