@@ -386,13 +386,34 @@ __global__ __launch_bounds__(kRecBlock) void k_hist_records(LaunchSet L)
     const uint32_t* __restrict__ rn = a.rec_n;
     const uint16_t* __restrict__ rb = a.rec_bin;
     const int64_t stride = a.rec_stride;
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-        const double hh = rh[p];
-        const double hw = literal ? 1.0 : 1.0 / (double)rn[p];
+    // kRecUnroll records per thread and pass: their loads are in flight
+    // together (a workgroup of one wave would otherwise wait out one load
+    // latency per record); the additions follow in a fixed order
+    constexpr int U = kRecUnroll;
+    const int64_t step = (int64_t)U * blockDim.x;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += step) {
+        double hh[U], hw[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t r = p + (int64_t)u * blockDim.x;
+            hh[u] = r < p1 ? rh[r] : 0.0;
+            hw[u] = r < p1 ? (literal ? 1.0 : 1.0 / (double)rn[r]) : 0.0;
+        }
         for (int mu = a0; mu < a1; ++mu) {
-            const int bin = (mu - a0) * n_g + (int)rb[(mu - q.hist_axes) * stride + p];
-            atomicAdd(&lh[bin], hh);
-            atomicAdd(&lw[bin], hw);
+            const uint16_t* __restrict__ rbm = rb + (int64_t)(mu - q.hist_axes) * stride;
+            int bin[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t r = p + (int64_t)u * blockDim.x;
+                bin[u] = (mu - a0) * n_g + (r < p1 ? (int)rbm[r] : 0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (p + (int64_t)u * blockDim.x < p1) {
+                    atomicAdd(&lh[bin[u]], hh[u]);
+                    atomicAdd(&lw[bin[u]], hw[u]);
+                }
+            }
         }
     }
     __syncthreads();

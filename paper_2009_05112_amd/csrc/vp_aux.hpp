@@ -43,6 +43,8 @@ inline int check_blocks(int64_t n_hc, int64_t n_map)
 }
 // Deterministic training records: one wave per binning workgroup.
 constexpr int kRecDetBlock = 64;
+// Records each thread of the binning pass loads before adding them.
+constexpr int kRecUnroll = 4;
 constexpr int kRefineBlock = 256;
 constexpr int kFixBlock = 1024;  // edge fix-up: one workgroup per request
 

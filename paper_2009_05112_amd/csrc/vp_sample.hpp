@@ -597,9 +597,10 @@ __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32
 // KIND fixes the integrand at compile time (K_GAUSS_MIX, K_CORR_GAUSS), or is
 // 0 for the generic kernel that dispatches on the integrand's kind at run time.
 // Training data of one sample: atomics into the LDS bins of the privatised
-// axes, and for the other axes a record at the sample's position -- the
-// numerator value, n_h and those axes' increment indices (k_hist_records bins
-// them).  The three record arrays follow each other at rec (see SampleArgs).
+// axes, and for the other axes a record at position pos (the sample's
+// position, permuted within aligned groups) -- the numerator value, n_h and
+// those axes' increment indices (k_hist_records bins them in any order).  The
+// three record arrays follow each other at rec (see SampleArgs).
 // WFIX: the weight plane is the unsigned 64-bit fixed-point sum (weight wq);
 // else a double-precision sum (weight hw).
 template <int D, bool REC, bool WFIX>
@@ -911,6 +912,14 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                     else return fixed_weight(literal ? 1.0 : (double)inv_n32, wscale);
                 };
                 uint64_t wq = weight_q();
+                // where a sample's training record goes: its position permuted
+                // within aligned groups (batch_pos), so that the lanes of a
+                // wave, each walking 16 consecutive samples, write consecutive
+                // records
+                auto rpos = [&](uint32_t s_rel) -> int64_t {
+                    if constexpr (REC) return batch_pos(s_a + (int64_t)s_rel, n_tot);
+                    else return 0;
+                };
                 constexpr int IDXG = (D + 7) / 8;  // 16-byte groups of increment indices
                 // accumulate mode: J, f and the indices of the lane's next
                 // sample are loaded while the current one is added up
@@ -1016,7 +1025,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                         const double v2 = v * v;
                         const double hh = literal ? v2 : v2 * inv_n;
                         const double hw = literal ? 1.0 : inv_n;
-                        put_training<D, REC, false>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw,
+                        put_training<D, REC, false>(rec, rec_stride, ha, lds_hist, lbins, n_g, rpos(s), hh, hw,
                                                     wq, n_cur, idx);
                     } else if constexpr (PREC == P_FP32_ACC64) {
                         const float v32 = (FC_SMEM ? sample_fp32<D, MAPL, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
@@ -1027,7 +1036,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                         const double v2 = v * v;
                         const double hh = literal ? v2 : v2 * inv_n;
                         const double hw = literal ? 1.0 : inv_n;
-                        put_training<D, REC, true>(rec, rec_stride, ha, lds_hist, lbins, n_g, s_a + (int64_t)s, hh, hw,
+                        put_training<D, REC, true>(rec, rec_stride, ha, lds_hist, lbins, n_g, rpos(s), hh, hw,
                                                    wq, n_cur, idx);
                     } else {
                         const float v32 = (FC_SMEM ? sample_fp32<D, MAPL, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
