@@ -29,7 +29,7 @@ enum BatchMode { K_BATCH_GEN = 101, K_BATCH_ACC = 102 };
 // the largest of 1024 / 768 / 512 threads whose register budget (128 / 168 /
 // 256 VGPRs) holds the kernel body without spilling, i.e. four, three or two
 // waves per SIMD.
-constexpr int sample_block(int prec, int kind, int dim, bool map_lds)
+constexpr int sample_block(int prec, int kind, int dim, bool map_lds, bool rec = false)
 {
     if (prec == 0) {
         // the batched integrand's modes hold little state: the accumulate mode
@@ -38,8 +38,9 @@ constexpr int sample_block(int prec, int kind, int dim, bool map_lds)
         if (kind == K_BATCH_ACC) return 1024;
         if (kind == K_BATCH_GEN) return map_lds || dim > 16 ? 768 : 1024;
         if (kind != K_GAUSS_MIX) return 512;
-        if (dim == 8) return map_lds ? 768 : 1024;
-        return dim < 8 ? 1024 : (dim <= 12 ? 768 : 512);
+        if (dim == 8) return map_lds || rec ? 768 : 1024;
+        if (dim < 8) return 1024;
+        return dim <= 12 || (dim <= 15 && !rec) ? 768 : 512;
     }
     return dim <= 12 ? 1024 : 768;
 }

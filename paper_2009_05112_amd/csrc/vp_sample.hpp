@@ -375,6 +375,9 @@ __device__ __forceinline__ T f_finish(FP fc, int kind, int K, FState<D, T>& st)
 #pragma unroll
             for (int e = d; e < D; ++e) z = vfma(chol[d * D + e], st.t[e], z);
             q = vfma(z, z, q);
+            // one row of the factor at a time: without this fence the
+            // scheduler hoists the loads of every row (D^2 values) and spills
+            __builtin_amdgcn_sched_barrier(0);
         }
         return scale * vexp((T)(-0.5) * q);
     }
@@ -704,6 +707,14 @@ __device__ __forceinline__ void dump_share(const SampleArgs& a, int64_t s_a, int
         DumpPos dp;
         dp.d = &a.dump;
         dp.pos = sd - a.dump.first;
+        // constants staged in LDS read afresh for each sample (hoisted out of
+        // this loop, a D x D factor would be held in registers and spilled)
+        const MapT* fcl = lds_fc;
+        {
+            int z;
+            asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+            fcl = lds_fc + z;
+        }
         a.dump.h[dp.pos] = (int64_t)h;
         a.dump.j[dp.pos] = (int32_t)j;
         if constexpr (PREC == P_FP64) {
@@ -711,13 +722,13 @@ __device__ __forceinline__ void dump_share(const SampleArgs& a, int64_t s_a, int
                 (void)sample_fp64<D, MAPL, KT, ConstT*, false, false, true>(hot, map, fcg, j, h, k, idx, kind, K,
                                                                            nullptr, &dp);
             else
-                (void)sample_fp64<D, MAPL, KT, const MapT*, false, MIX, true>(hot, map, lds_fc, j, h, k, idx, kind, K,
+                (void)sample_fp64<D, MAPL, KT, const MapT*, false, MIX, true>(hot, map, fcl, j, h, k, idx, kind, K,
                                                                              nullptr, &dp);
         } else {
             if constexpr (FC_SMEM)
                 (void)sample_fp32<D, MAPL, KT, ConstT*, false, true>(hot, map, fcg, j, h, k, idx, kind, K, &dp);
             else
-                (void)sample_fp32<D, MAPL, KT, const MapT*, MIX, true>(hot, map, lds_fc, j, h, k, idx, kind, K, &dp);
+                (void)sample_fp32<D, MAPL, KT, const MapT*, MIX, true>(hot, map, fcl, j, h, k, idx, kind, K, &dp);
         }
     }
 }
@@ -729,7 +740,7 @@ __device__ __forceinline__ void dump_share(const SampleArgs& a, int64_t s_a, int
 // MIX: per-axis stratification counts (Sec. 4), read with R_mu from the
 // constants staged in LDS; only kernels that stage them there have it.
 template <int D, int PREC, int MAPL, int KIND, bool REC, int KT, bool MIX>
-__global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void k_sample(LaunchSet L)
+__global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS, REC)) void k_sample(LaunchSet L)
 {
     static_assert(MAPL != MAP_INNER || D > kMapInnerAxes, "staging the innermost axes needs more axes");
     VP_REQ_PROLOGUE(L);
@@ -912,14 +923,6 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                     else return fixed_weight(literal ? 1.0 : (double)inv_n32, wscale);
                 };
                 uint64_t wq = weight_q();
-                // where a sample's training record goes: its position permuted
-                // within aligned groups (batch_pos), so that the lanes of a
-                // wave, each walking 16 consecutive samples, write consecutive
-                // records
-                auto rpos = [&](uint32_t s_rel) -> int64_t {
-                    if constexpr (REC) return batch_pos(s_a + (int64_t)s_rel, n_tot);
-                    else return 0;
-                };
                 constexpr int IDXG = (D + 7) / 8;  // 16-byte groups of increment indices
                 // accumulate mode: J, f and the indices of the lane's next
                 // sample are loaded while the current one is added up
@@ -976,15 +979,24 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                     // an offset the compiler cannot see through keeps the
                     // scalar loads of the constants inside the loop
                     ConstT* fcs = fcg;
-                    if constexpr (FC_SMEM) {
+                    const MapT* fcl = lds_fc;
+                    {
                         int z;
                         asm volatile("s_mov_b32 %0, 0" : "=s"(z));
-                        fcs = fcg + z;
+                        if constexpr (FC_SMEM) fcs = fcg + z;
+                        // likewise the reads of constants staged in LDS (the
+                        // correlated Gaussian's D x D factor would otherwise be
+                        // hoisted into registers and spilled)
+                        else fcl = lds_fc + z;
                     }
+                    // the sample's position permuted within aligned groups: where
+                    // a batched integrand's point goes, and where a training
+                    // record goes (the lanes of a wave, each walking 16
+                    // consecutive samples, then write consecutive addresses)
                     const int64_t bpos = batch_pos(s_a + (int64_t)s, n_tot);
                     if constexpr (GEN) {
                         bout.pos = bpos;
-                        (void)sample_fp64<D, MAPL, 0, const MapT*, true, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K,
+                        (void)sample_fp64<D, MAPL, 0, const MapT*, true, MIX>(hot, map, fcl, j, hh32, k, idx, kind, K,
                                                                            &bout);
 #pragma unroll
                         for (int g = 0; g < IDXG; ++g) {
@@ -1018,29 +1030,29 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS)) void 
                             }
                         } else {
                             v = (FC_SMEM ? sample_fp64<D, MAPL, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
-                                         : sample_fp64<D, MAPL, KT, const MapT*, false, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
+                                         : sample_fp64<D, MAPL, KT, const MapT*, false, MIX>(hot, map, fcl, j, hh32, k, idx, kind, K));
                         }
                         run.add(v);
                         if (!isfinite(v)) ++bad;
                         const double v2 = v * v;
                         const double hh = literal ? v2 : v2 * inv_n;
                         const double hw = literal ? 1.0 : inv_n;
-                        put_training<D, REC, false>(rec, rec_stride, ha, lds_hist, lbins, n_g, rpos(s), hh, hw,
+                        put_training<D, REC, false>(rec, rec_stride, ha, lds_hist, lbins, n_g, REC ? bpos : 0, hh, hw,
                                                     wq, n_cur, idx);
                     } else if constexpr (PREC == P_FP32_ACC64) {
                         const float v32 = (FC_SMEM ? sample_fp32<D, MAPL, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
-                                           : sample_fp32<D, MAPL, KT, const MapT*, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
+                                           : sample_fp32<D, MAPL, KT, const MapT*, MIX>(hot, map, fcl, j, hh32, k, idx, kind, K));
                         const double v = (double)v32;
                         run.add(v);
                         if (!isfinite(v32)) ++bad;
                         const double v2 = v * v;
                         const double hh = literal ? v2 : v2 * inv_n;
                         const double hw = literal ? 1.0 : inv_n;
-                        put_training<D, REC, true>(rec, rec_stride, ha, lds_hist, lbins, n_g, rpos(s), hh, hw,
+                        put_training<D, REC, true>(rec, rec_stride, ha, lds_hist, lbins, n_g, REC ? bpos : 0, hh, hw,
                                                    wq, n_cur, idx);
                     } else {
                         const float v32 = (FC_SMEM ? sample_fp32<D, MAPL, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
-                                           : sample_fp32<D, MAPL, KT, const MapT*, MIX>(hot, map, lds_fc, j, hh32, k, idx, kind, K));
+                                           : sample_fp32<D, MAPL, KT, const MapT*, MIX>(hot, map, fcl, j, hh32, k, idx, kind, K));
                         run.addf(v32);
                         if (!isfinite(v32)) ++bad;
                         const float v2 = v32 * v32;
@@ -1215,7 +1227,7 @@ SampleEntry make_entry()
     SampleEntry e;
     e.launch = launch_sample<D, PREC, MAPL, KIND, REC, KT, MIX>;
     e.occupancy = sample_occupancy<D, PREC, MAPL, KIND, REC, KT, MIX>;
-    e.block = sample_block(PREC, KIND, D, MAPL == MAP_LDS);
+    e.block = sample_block(PREC, KIND, D, MAPL == MAP_LDS, REC);
     return e;
 }
 
