@@ -21,7 +21,7 @@ Beside it, outside the timed steps:
                    first-served queue whose service times are measured one by
                    one.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision fp64]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 10] [--precision fp64]
 """
 import argparse
 import json
@@ -358,7 +358,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="fp64", choices=list(SLOTS_PER_SAMPLE))
     ap.add_argument("--n-ev", type=int, default=100_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
