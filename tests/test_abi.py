@@ -34,11 +34,14 @@ def test_batch_integrand_struct():
 
 def test_status_strings_and_header_enums():
     L = B.lib()
-    for s in range(8):
+    for s in range(9):
         assert L.vp_status_string(s)
+    assert L.vp_status_string(B.VP_ERR_INVARIANT) == b"invariant violated"
     src = open(B.HEADER).read()
     for name, v in (("VP_F_GAUSS_MIX", 1), ("VP_F_CORR_GAUSS", 2), ("VP_FP32_NEUMAIER", 2),
-                    ("VP_HIST_LITERAL", 1)):
+                    ("VP_HIST_LITERAL", 1), ("VP_ERR_INVARIANT", 8), ("VP_FLAG_CHECKS", 1),
+                    ("VP_FLAG_DETERMINISTIC", 2), ("VP_CHECK_MAP_ORDER", 1), ("VP_CHECK_MAP_ENDS", 2),
+                    ("VP_CHECK_NH_MIN", 4), ("VP_CHECK_NH_SUM", 8)):
         assert f"{name} = {v}" in src
 
 
@@ -95,3 +98,13 @@ def test_oracle_is_not_reachable_from_the_product():
             if fn.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 src = open(os.path.join(root, fn)).read()
                 assert "import oracle" not in src and "vp_oracle" not in src, fn
+
+
+def test_library_links_the_roctx_marker_library():
+    """The host phases are ROCTx ranges: the library depends on
+    rocprofiler-sdk's marker library (no-ops without a profiler)."""
+    out = subprocess.run(["readelf", "-d", B.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    needed = [l for l in out.splitlines() if "(NEEDED)" in l]
+    assert any("rocprofiler-sdk-roctx" in l for l in needed), needed
+    lib = ctypes.CDLL(B.LIB_PATH)  # resolves at load time
+    assert hasattr(lib, "vp_iterate")
