@@ -774,11 +774,28 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS, REC)) 
     MapT* lds_fc = reinterpret_cast<MapT*>(lds_raw + fc_lds_offset(hist_bytes, MAPL, PREC, D, n_g));
 
     for (int i = threadIdx.x; i < 2 * lbins; i += blockDim.x) lds_hist[i] = 0.0;
-    if constexpr (MAPL == MAP_LDS)
-        for (int i = threadIdx.x; i < D * (n_g + 1); i += blockDim.x) lds_map[i] = gmap[i];
+    // the map values to stage in LDS: kStageU loads per thread in flight
+    // before their stores (the set-up is latency that nothing else on the CU
+    // hides, and a served request's workgroup walks about one tile per wave)
     const uint32_t inner0 = (uint32_t)((D - kMapInnerAxes) * (n_g + 1));
-    if constexpr (MAPL == MAP_INNER)
-        for (int i = threadIdx.x; i < kMapInnerAxes * (n_g + 1); i += blockDim.x) lds_map[i] = gmap[inner0 + i];
+    if constexpr (MAPL == MAP_LDS || MAPL == MAP_INNER) {
+        constexpr int kStageU = 8;
+        const int n_stage = MAPL == MAP_LDS ? D * (n_g + 1) : kMapInnerAxes * (n_g + 1);
+        const VP_GLOBAL MapT* src = global_ptr(MAPL == MAP_INNER ? gmap + inner0 : gmap);
+        for (int i0 = threadIdx.x; i0 < n_stage; i0 += kStageU * blockDim.x) {
+            MapT v[kStageU];
+#pragma unroll
+            for (int u = 0; u < kStageU; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+                v[u] = i < n_stage ? src[i] : MapT(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kStageU; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+                if (i < n_stage) lds_map[i] = v[u];
+            }
+        }
+    }
     // Gaussian-mixture constants (4 D + 16 values) are read through the
     // scalar cache at every sample, from the constant address space: the
     // VALU takes them as scalar operands, and they occupy no register across
@@ -790,7 +807,7 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS, REC)) 
     typedef __attribute__((address_space(4))) const MapT ConstT;
     ConstT* fcg = (ConstT*)a.fc;
     if constexpr (!FC_SMEM) {
-        const MapT* src = reinterpret_cast<const MapT*>(a.fc);
+        const VP_GLOBAL MapT* src = global_ptr(reinterpret_cast<const MapT*>(a.fc));
         for (int i = threadIdx.x; i < fc_count(kind, D); i += blockDim.x) lds_fc[i] = src[i];
     }
     __syncthreads();
@@ -874,10 +891,19 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS, REC)) 
         bool carry_live = true;  // an unfinished run reaches the next lane
         int64_t h_open = h_a;
 
-        for (int64_t s0 = s_a; s0 < s_b; s0 += (int64_t)kWave * C) {
-            const int64_t s_l = s0 + (int64_t)lane * C;
+        for (int64_t s0 = s_a; s0 < s_b;) {
+            // A share's last tile spreads what is left over all the lanes
+            // (Ct = ceil(left / 64) samples each instead of C), so that it
+            // takes only the steps its fullest lane needs: a served request's
+            // workgroup of 768 threads walks 1.33 tiles per wave, and its
+            // second tile would otherwise run 16 steps for a third of the lanes.
+            // The batched-integrand modes keep C: their shares are whole groups
+            // of the point buffers.
+            const int64_t left = s_b - s0;
+            const int Ct = (GEN || ACC || left >= (int64_t)kWave * C) ? C : (int)((left + kWave - 1) / kWave);
+            const int64_t s_l = s0 + (int64_t)lane * Ct;
             const bool active = s_l < s_b;
-            const int64_t e_l = active ? (s_l + C < s_b ? s_l + C : s_b) : s_l;
+            const int64_t e_l = active ? (s_l + Ct < s_b ? s_l + Ct : s_b) : s_l;
             int64_t h = locate(offs, ob, n_hc, h_cur, s_l, active, lane);
 
             Acc run, headacc;
@@ -1127,12 +1153,13 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS, REC)) 
             carry = B63;
             carry_ext = A63 && carry_ext;
             // the last active lane decides whether a run is still open, and where
-            const int64_t rem = (s_b - 1 - s0) / C;
+            const int64_t rem = (s_b - 1 - s0) / Ct;
             const int last_active = rem < kWave - 1 ? (int)rem : kWave - 1;
             const bool live_own = active && (!head_closed || open_end);
             carry_live = __shfl((int)live_own, last_active) != 0;
             h_open = shfl64(h_end, last_active);
             h_cur = shfl64(h_end, kWave - 1);
+            s0 += (int64_t)kWave * Ct;
         }
         if (lane == 0 && !GEN) {
             EdgeRec empty;
@@ -1180,24 +1207,39 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS, REC)) 
     if (lane == 0 && bad) atomicAdd(a.nonfinite, (unsigned long long)bad);
 
     __syncthreads();
-    {
+    // The training data to this workgroup's partial: four bins' LDS reads per
+    // thread in flight before their stores.
+    if constexpr (!GEN) {
         VP_GLOBAL double* out = global_ptr(a.hist_part + (size_t)bid * 2 * nbins);
-        if constexpr (PREC == P_FP32_NEUMAIER) {
-            for (int i = threadIdx.x; i < lbins; i += blockDim.x) {
+        const double wsi = a.wscale_inv;
+        auto bin = [&](int i, double& h, double& w) {
+            if constexpr (PREC == P_FP32_NEUMAIER) {
                 const uint64_t ph = lds_pairs[i];
-                out[i] = (double)__uint_as_float((uint32_t)ph) + (double)__uint_as_float((uint32_t)(ph >> 32));
-                out[nbins + i] = (double)lds_pairs[lbins + i] * a.wscale_inv;
+                h = (double)__uint_as_float((uint32_t)ph) + (double)__uint_as_float((uint32_t)(ph >> 32));
+                w = (double)lds_pairs[lbins + i] * wsi;
+            } else if constexpr (PREC == P_FP32_ACC64) {
+                h = lds_hist[i];
+                w = (double)reinterpret_cast<const uint64_t*>(lds_hist)[lbins + i] * wsi;
+            } else {
+                h = lds_hist[i];
+                w = lds_hist[lbins + i];
             }
-        } else if constexpr (PREC == P_FP32_ACC64) {
-            const uint64_t* wplane = reinterpret_cast<const uint64_t*>(lds_hist) + lbins;
-            for (int i = threadIdx.x; i < lbins; i += blockDim.x) {
-                out[i] = lds_hist[i];
-                out[nbins + i] = (double)wplane[i] * a.wscale_inv;
+        };
+        constexpr int U = 4;
+        for (int i0 = threadIdx.x; i0 < lbins; i0 += U * blockDim.x) {
+            double h[U], w[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+                if (i < lbins) bin(i, h[u], w[u]);
             }
-        } else {
-            for (int i = threadIdx.x; i < lbins; i += blockDim.x) {
-                out[i] = lds_hist[i];
-                out[nbins + i] = lds_hist[lbins + i];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+                if (i < lbins) {
+                    out[i] = h[u];
+                    out[nbins + i] = w[u];
+                }
             }
         }
     }
