@@ -919,12 +919,34 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS, REC)) 
                 const int64_t o_cur0 = gofs(offs, ob, h);
                 uint32_t hh32 = (uint32_t)h;
                 uint32_t next = (uint32_t)(gofs(offs, ob, h + 1) - s_a);
-                // generate mode: the boundary after the next one is loaded one
-                // switch ahead.  Its stores and loads share one counter, so a
-                // boundary loaded at the switch that needs it would wait for
-                // every point written before it.
-                int64_t pref = 0;
-                if constexpr (GEN) pref = h + 2 <= n_hc ? gofs(offs, ob, h + 2) : 0;
+                // Batched-integrand modes: the boundaries of the hypercubes the
+                // lane can reach in this tile (h + 2 .. h + 1 + kPreB) are
+                // loaded here, once per tile, as positions relative to s_a.
+                // Loads and stores share one counter, so a boundary loaded at
+                // the switch that needs it would wait there for every point
+                // the generate mode stored before it (and in the accumulate
+                // mode for the next sample's prefetched values).  With
+                // n_h >= 2 the tile's C = 16 samples cross at most 8
+                // boundaries; a lane that runs out loads the next one at its
+                // switch.  The offsets' low words suffice (the walk is 32-bit),
+                // and kPreB < kOffsTile, so at most two block bases occur.
+                constexpr int kPreB = 8;
+                uint32_t bq[kPreB];
+                int nbq = 0;
+                if constexpr (GEN || ACC) {
+                    const VP_GLOBAL uint32_t* lo = global_ptr(reinterpret_cast<const uint32_t*>(offs));
+                    const VP_GLOBAL uint32_t* bo = global_ptr(reinterpret_cast<const uint32_t*>(ob));
+                    const int64_t ha = h + 2 < n_hc ? h + 2 : n_hc;
+                    const int64_t hb = h + 1 + kPreB < n_hc ? h + 1 + kPreB : n_hc;
+                    const int64_t blk_a = ha / kOffsTile;
+                    const uint32_t base_a = bo[2 * blk_a], base_b = bo[2 * (hb / kOffsTile)];
+#pragma unroll
+                    for (int i = 0; i < kPreB; ++i) {
+                        const int64_t hq = h + 2 + i < n_hc ? h + 2 + i : n_hc;
+                        bq[i] = lo[2 * hq] + (hq / kOffsTile == blk_a ? base_a : base_b) - (uint32_t)s_a;
+                    }
+                    nbq = kPreB;
+                }
                 uint32_t j = (uint32_t)(s_l - o_cur0);
                 const uint32_t s_end = (uint32_t)(e_l - s_a);
                 int32_t k[D];
@@ -979,9 +1001,11 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS, REC)) 
                         ++hh32;
                         j = 0;
                         uint32_t nn;
-                        if constexpr (GEN) {
-                            nn = (uint32_t)(pref - s_a);
-                            if ((int64_t)hh32 + 2 <= n_hc) pref = gofs(offs, ob, (int64_t)hh32 + 2);
+                        if ((GEN || ACC) && nbq > 0) {
+                            nn = bq[0];
+#pragma unroll
+                            for (int i = 0; i + 1 < kPreB; ++i) bq[i] = bq[i + 1];
+                            --nbq;
                         } else {
                             nn = (uint32_t)(gofs(offs, ob, (int64_t)hh32 + 1) - s_a);
                         }
