@@ -67,6 +67,40 @@ def test_batched_equals_builtin(ctx, dim, k, n_ev, n_g):
         B.examples().vp_example_free_user(bf.user)
 
 
+def test_batched_two_samples_per_hypercube(ctx):
+    """n_h = 2 everywhere (the smallest allocation, Sec. 3): a lane's 16
+    samples of a tile then cross eight hypercube boundaries, every one of
+    those the batched modes load at the start of the tile.  Against the
+    built-in path from the same state, with H and W element by element."""
+    dim = 4
+    f = _mix(dim, 2, 77)
+    p = W.Params(dim=dim, n_ev=131_072, n_g=200, n_iter=3, seed=3)
+    bf = B.example_gauss_mix(f)
+    try:
+        gb = B.Problem(ctx, p, bf)
+        gf = B.Problem(ctx, p, f)
+        assert gf.n_hc > 20_000
+        two = np.full(gf.n_hc, 2, dtype=np.int32)
+        for _ in range(p.n_iter):
+            gf.set_alloc(two)
+            gb.set_map(gf.map())
+            gb.set_alloc(two)
+            gb.set_it(gf.it)
+            gb.iterate(1)
+            gf.iterate(1)
+            ab, af = gb.accum(), gf.accum()
+            np.testing.assert_allclose(ab["S1"], af["S1"], rtol=1e-12, atol=1e-300)
+            np.testing.assert_allclose(ab["S2"], af["S2"], rtol=1e-12, atol=1e-300)
+            for key in ("H", "W"):
+                for m in range(dim):
+                    tot = np.abs(af[key][m]).sum()
+                    assert np.abs(ab[key][m] - af[key][m]).max() <= 1e-12 * tot, (key, m)
+        gb.close()
+        gf.close()
+    finally:
+        B.examples().vp_example_free_user(bf.user)
+
+
 @pytest.mark.parametrize("dim,n_ev,n_g", [(4, 50_000, 100), (11, 200_000, 1000)])
 def test_batched_stepwise_against_oracle(ctx, dim, n_ev, n_g):
     """The oracle evaluates the same mixture itself; D=11 at N_g=1000 takes
