@@ -34,7 +34,9 @@ constexpr int sample_block(int prec, int kind, int dim, bool map_lds, bool rec =
     if (prec == 0) {
         // the batched integrand's modes hold little state: the accumulate mode
         // (training data in LDS, one workgroup per CU) takes four waves per
-        // SIMD, the generate mode (the map in LDS, two workgroups per CU) six
+        // SIMD, the generate mode with the map in LDS three (one workgroup per
+        // CU: its registers allow five waves per SIMD, not the six of two
+        // workgroups, and capped to fit two it ran no faster)
         if (kind == K_BATCH_ACC) return 1024;
         if (kind == K_BATCH_GEN) return map_lds || dim > 16 ? 768 : 1024;
         if (kind != K_GAUSS_MIX) return 512;

@@ -28,6 +28,27 @@ class PlanBuilder {
 public:
     ~PlanBuilder() { (void)hipFree(dev_); }
 
+    // Device memory for the tables of up to n requests, allocated ahead of
+    // the first build (hipFree of an outgrown table waits for the device, so
+    // a builder that grows while a step runs would stall the host until it
+    // ends).  Per request: two pointer words and one base in each of the nine
+    // per-request sets and in the sampling groups; per set and group: one
+    // alignment word and the final base.
+    hipError_t reserve(int n)
+    {
+        const size_t words = 30 * (size_t)n + 2 * (9 + (size_t)kMaxGroups) + 16;
+        const size_t bytes = words * sizeof(int32_t);
+        if (bytes <= cap_) return hipSuccess;
+        (void)hipFree(dev_);
+        dev_ = nullptr;
+        cap_ = 0;
+        hipError_t e = hipMalloc((void**)&dev_, bytes + 16);
+        if (e != hipSuccess) return e;
+        cap_ = bytes;
+        host_.reserve(words);
+        return hipSuccess;
+    }
+
     // Builds the plan; the integer arrays are copied to the device before
     // returning (synchronous), so the plan may be enqueued or captured at once.
     hipError_t build(const std::vector<PlanReq>& reqs, IterPlan* out)

@@ -102,6 +102,27 @@ public:
     // kernels reading it are complete, while the other set takes new images.
     // nullptr when no pinned memory can be had.
     void select_stage(int i) { cur_ = i & 1; }
+    // Pins one chunk of at least `bytes` for each set ahead of use (pinning
+    // host memory takes milliseconds; a server does it once, when created,
+    // rather than in its first turns).  False when the memory cannot be had
+    // (the sets then grow on demand, as without it).
+    bool reserve_stage(size_t bytes)
+    {
+        for (Stage& g : stages_) {
+            if (!g.chunks.empty()) continue;
+            Chunk c;
+            c.size = round_up(bytes > kStageChunk ? bytes : kStageChunk);
+            if (hipHostMalloc((void**)&c.base, c.size, hipHostMallocDefault) != hipSuccess) return false;
+            void* d = nullptr;
+            if (hipHostGetDevicePointer(&d, c.base, 0) != hipSuccess) {
+                (void)hipHostFree(c.base);
+                return false;
+            }
+            c.dev = (const char*)d;
+            g.chunks.push_back(c);
+        }
+        return true;
+    }
     char* stage(size_t bytes, const char** dev)
     {
         Stage& g = stages_[cur_];

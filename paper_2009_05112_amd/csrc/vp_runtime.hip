@@ -792,6 +792,19 @@ static Layout layout_of(const vp_params* P, const Shape& sh)
     return L;
 }
 
+size_t vp::problem_head_bytes_max()
+{
+    // the head (integrand, state, argument record, bounds, constants) grows
+    // with the dimension only
+    vp_params P;
+    memset(&P, 0, sizeof P);
+    P.dim = kMaxDim;
+    P.n_g = 1;
+    Shape sh;
+    memset(&sh, 0, sizeof sh);
+    return layout_of(&P, sh).head_end;
+}
+
 vp_status vp::problem_bytes(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
                             size_t* bytes)
 {

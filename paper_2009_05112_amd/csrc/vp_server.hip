@@ -567,6 +567,16 @@ vp_status vp_server_create(vp_ctx* ctx, size_t mem_budget_bytes, int32_t max_slo
     // slabs of at most 1 GiB and a quarter of the budget
     s->pool.set_slab_bytes(std::min<size_t>(size_t(1) << 30, mem_budget_bytes / 4));
     s->max_slots = max_slots;
+    // set-up that would otherwise fall into the first turns: the plan tables
+    // of both builders for max_slots requests (at most 16384, about 2 MB
+    // each), and pinned staging for one turn's admissions (their initial
+    // images and the table of their initialisation); either may fail, and a
+    // turn then allocates what it needs itself
+    (void)s->planner[0].reserve(std::min(max_slots, 16384));
+    (void)s->planner[1].reserve(std::min(max_slots, 16384));
+    (void)hipGetLastError();
+    (void)s->pool.reserve_stage((size_t)std::min(max_slots, kAdmitPerTurn) *
+                                (problem_head_bytes_max() + sizeof(InitArgs)));
     s->graphs = (flags & VP_SERVER_NO_GRAPH) == 0;
     memset(&s->st, 0, sizeof s->st);
     s->t0 = std::chrono::steady_clock::now();

@@ -156,6 +156,9 @@ vp_status problem_create(vp_ctx* ctx, const vp_params* P, const vp_integrand* f,
 vp_status problem_bytes(vp_ctx* ctx, const vp_params* P, const vp_integrand* f, int64_t samples_per_wg,
                         size_t* bytes);
 void problem_free(vp_problem* p);
+// Largest initial image (the records problem_create writes first) of any
+// problem: what a request's admission stages in host memory at most.
+size_t problem_head_bytes_max();
 // The caller's view of a problem's estimate scalars; VP_ERR_NUMERIC (result
 // still filled) when non-finite integrand values were seen.
 vp_status result_from_state(const DevState& st, vp_result* out);
