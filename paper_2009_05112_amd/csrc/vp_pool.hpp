@@ -102,10 +102,10 @@ public:
     // kernels reading it are complete, while the other set takes new images.
     // nullptr when no pinned memory can be had.
     void select_stage(int i) { cur_ = i & 1; }
-    // Pins one chunk of at least `bytes` for each set ahead of use (pinning
-    // host memory takes milliseconds; a server does it once, when created,
-    // rather than in its first turns).  False when the memory cannot be had
-    // (the sets then grow on demand, as without it).
+    // Pins one chunk of at least `bytes` for each set ahead of use (a server
+    // does it once, when created, rather than in its first turns).  False
+    // when the memory cannot be had (the sets then grow on demand, as
+    // without it).
     bool reserve_stage(size_t bytes)
     {
         for (Stage& g : stages_) {
