@@ -487,6 +487,12 @@ __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair6
     // words are live at a time.
     constexpr int NG4 = (D + 3) / 4;
     const int n_g = a.n_g;
+    // A wave drawing and mapping its sample (up to its map reads and the
+    // per-axis sums) runs at raised priority, dropped for the integrand's
+    // exponentials: among the ready waves of a SIMD, those about to issue
+    // their map reads go first, so more reads are in flight while other
+    // waves compute (0.5-1% on the FP64 kernel, 1.5-3% on the split ones).
+    if constexpr (!GEN && !DUMP) __builtin_amdgcn_s_setprio(1);
     FState<D, double> st;
 #pragma unroll
     for (int kk = 0; kk < kMaxTerms; ++kk) st.q[kk] = 0.0;
@@ -539,6 +545,7 @@ __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair6
         global_ptr(out->jac)[out->pos] = jac;
         return 0.0;
     } else {
+        if constexpr (!DUMP) __builtin_amdgcn_s_setprio(0);
         const double fx = f_finish<D, KT, double, FP>(fc, kind, K, st);
         if constexpr (DUMP) {
             dp->d->jac[dp->pos] = jac;
@@ -556,6 +563,8 @@ __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32
 {
     constexpr int NG4 = (D + 3) / 4;
     const int n_g = a.n_g;
+    // raised priority up to the integrand, as in sample_fp64
+    if constexpr (!DUMP) __builtin_amdgcn_s_setprio(1);
     FState<D, float> st;
 #pragma unroll
     for (int kk = 0; kk < kMaxTerms; ++kk) st.q[kk] = 0.0f;
@@ -588,6 +597,7 @@ __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32
             }
         }
     }
+    if constexpr (!DUMP) __builtin_amdgcn_s_setprio(0);
     const float fx = f_finish<D, KT, float, FP>(fc, kind, K, st);
     if constexpr (DUMP) {
         dp->d->jac[dp->pos] = (double)jac;
