@@ -556,10 +556,15 @@ __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair6
 }
 
 // FP32 split: u = (w >> 8) 2^-24 from the high word of each axis alone.
-template <int D, int MAPL, int KT, typename FP, bool MIX = false, bool DUMP = false>
+// Early: called with (axis, increment index) as soon as an axis is mapped
+// (the split precision adds its fixed-point weights there).
+struct NoEarly {
+    __device__ void operator()(int, int) const {}
+};
+template <int D, int MAPL, int KT, typename FP, bool MIX = false, bool DUMP = false, typename Early = NoEarly>
 __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32<MAPL>& map, FP fc,
                                              uint32_t j, uint32_t h, const int32_t* k, int32_t* idx,
-                                             int kind, int K, const DumpPos* dp = nullptr)
+                                             int kind, int K, const DumpPos* dp = nullptr, Early early = Early())
 {
     constexpr int NG4 = (D + 3) / 4;
     const int n_g = a.n_g;
@@ -590,6 +595,7 @@ __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32
             const float x = fmaf(dx, delta, x0);
             jac = jac * ((float)n_g * dx);
             idx[mu] = i;
+            early(mu, i);
             f_axis<D, KT, float, FP>(fc, kind, K, mu, x, st);
             if constexpr (DUMP) {
                 dp->d->x[mu * dp->d->count + dp->pos] = (double)x;
@@ -615,8 +621,9 @@ __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32
 // those axes' increment indices (k_hist_records bins them in any order).  The
 // three record arrays follow each other at rec (see SampleArgs).
 // WFIX: the weight plane is the unsigned 64-bit fixed-point sum (weight wq);
-// else a double-precision sum (weight hw).
-template <int D, bool REC, bool WFIX>
+// else a double-precision sum (weight hw).  WDONE: the weights of the LDS
+// axes were added already, as each axis was mapped.
+template <int D, bool REC, bool WFIX, bool WDONE = false>
 __device__ __forceinline__ void put_training(double* rec, int64_t stride, int ha, double* lds_hist, int lbins, int n_g,
                                              int64_t pos, double hh, double hw, uint64_t wq, uint32_t n,
                                              const int32_t* idx)
@@ -626,7 +633,8 @@ __device__ __forceinline__ void put_training(double* rec, int64_t stride, int ha
         if (mu < ha) {
             const int bin = mu * n_g + idx[mu];
             atomicAdd(&lds_hist[bin], hh);
-            if constexpr (WFIX)
+            if constexpr (WDONE) {
+            } else if constexpr (WFIX)
                 atomicAdd(reinterpret_cast<unsigned long long*>(&lds_hist[lbins + bin]), (unsigned long long)wq);
             else
                 atomicAdd(&lds_hist[lbins + bin], hw);
@@ -1100,16 +1108,26 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS, REC)) 
                         put_training<D, REC, false>(rec, rec_stride, ha, lds_hist, lbins, n_g, REC ? bpos : 0, hh, hw,
                                                     wq, n_cur, idx);
                     } else if constexpr (PREC == P_FP32_ACC64) {
-                        const float v32 = (FC_SMEM ? sample_fp32<D, MAPL, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
-                                           : sample_fp32<D, MAPL, KT, const MapT*, MIX>(hot, map, fcl, j, hh32, k, idx, kind, K));
+                        // Up to D = 11 the weight (known before the integrand) goes
+                        // to its bin as soon as the axis's increment is known,
+                        // which spreads the sample's LDS atomics over its map
+                        // phase (from D = 12 the hook's registers would spill).
+                        constexpr bool WE = D <= 11;
+                        auto wadd = [&](int mu, int i) {
+                            if (WE && mu < ha)
+                                atomicAdd(reinterpret_cast<unsigned long long*>(&lds_hist[lbins + mu * n_g + i]),
+                                          (unsigned long long)wq);
+                        };
+                        const float v32 = (FC_SMEM ? sample_fp32<D, MAPL, KT, ConstT*, false, false>(hot, map, fcs, j, hh32, k, idx, kind, K, nullptr, wadd)
+                                           : sample_fp32<D, MAPL, KT, const MapT*, MIX, false>(hot, map, fcl, j, hh32, k, idx, kind, K, nullptr, wadd));
                         const double v = (double)v32;
                         run.add(v);
                         if (!isfinite(v32)) ++bad;
                         const double v2 = v * v;
                         const double hh = literal ? v2 : v2 * inv_n;
                         const double hw = literal ? 1.0 : inv_n;
-                        put_training<D, REC, true>(rec, rec_stride, ha, lds_hist, lbins, n_g, REC ? bpos : 0, hh, hw,
-                                                   wq, n_cur, idx);
+                        put_training<D, REC, true, WE>(rec, rec_stride, ha, lds_hist, lbins, n_g, REC ? bpos : 0, hh, hw,
+                                                       wq, n_cur, idx);
                     } else {
                         const float v32 = (FC_SMEM ? sample_fp32<D, MAPL, KT, ConstT*>(hot, map, fcs, j, hh32, k, idx, kind, K)
                                            : sample_fp32<D, MAPL, KT, const MapT*, MIX>(hot, map, fcl, j, hh32, k, idx, kind, K));
