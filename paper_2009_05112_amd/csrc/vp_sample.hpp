@@ -954,10 +954,10 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS, REC)) 
                 if constexpr (GEN || ACC) {
                     const VP_GLOBAL uint32_t* lo = global_ptr(reinterpret_cast<const uint32_t*>(offs));
                     const VP_GLOBAL uint32_t* bo = global_ptr(reinterpret_cast<const uint32_t*>(ob));
-                    const int64_t ha = h + 2 < n_hc ? h + 2 : n_hc;
-                    const int64_t hb = h + 1 + kPreB < n_hc ? h + 1 + kPreB : n_hc;
-                    const int64_t blk_a = ha / kOffsTile;
-                    const uint32_t base_a = bo[2 * blk_a], base_b = bo[2 * (hb / kOffsTile)];
+                    const int64_t h_lo = h + 2 < n_hc ? h + 2 : n_hc;
+                    const int64_t h_hi = h + 1 + kPreB < n_hc ? h + 1 + kPreB : n_hc;
+                    const int64_t blk_a = h_lo / kOffsTile;
+                    const uint32_t base_a = bo[2 * blk_a], base_b = bo[2 * (h_hi / kOffsTile)];
 #pragma unroll
                     for (int i = 0; i < kPreB; ++i) {
                         const int64_t hq = h + 2 + i < n_hc ? h + 2 + i : n_hc;
