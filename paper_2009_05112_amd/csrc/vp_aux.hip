@@ -174,8 +174,9 @@ __device__ __forceinline__ RunSum run_combine(const RunSum& x, const RunSum& y)
 }
 
 // Records per thread held in registers (more per thread are read twice from
-// memory instead).
-constexpr int kFixPer = 16;
+// memory instead).  Eight cover the 2 x 4096 records of a full-device grid
+// with 1024 threads; sixteen took the kernel to 128 registers and spilled.
+constexpr int kFixPer = 8;
 
 __device__ __forceinline__ RunSum run_shfl(const RunSum& x, int src)
 {
