@@ -177,6 +177,7 @@ __device__ __forceinline__ RunSum run_combine(const RunSum& x, const RunSum& y)
 // memory instead).  Eight cover the 2 x 4096 records of a full-device grid
 // with 1024 threads; sixteen took the kernel to 128 registers and spilled.
 constexpr int kFixPer = 8;
+static_assert(kFixSmallRecs <= kFixSmallBlock * kFixPer, "small requests' records are held in registers");
 
 __device__ __forceinline__ RunSum run_shfl(const RunSum& x, int src)
 {
@@ -190,15 +191,16 @@ __device__ __forceinline__ RunSum run_shfl(const RunSum& x, int src)
     return r;
 }
 
-__global__ __launch_bounds__(kFixBlock) void k_edge_fixup(LaunchSet L)
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_edge_fixup(LaunchSet L)
 {
     VP_REQ_PROLOGUE(L);
-    __shared__ RunSum wrun[kFixBlock / kWave];
-    __shared__ int64_t wfirst[kFixBlock / kWave];
+    __shared__ RunSum wrun[BLOCK / kWave];
+    __shared__ int64_t wfirst[BLOCK / kWave];
     const EdgeRec* __restrict__ e = q.edges;
     const int64_t n_rec = 2 * q.n_waves;
     const int t = threadIdx.x;
-    const int64_t per = (n_rec + kFixBlock - 1) / kFixBlock;
+    const int64_t per = (n_rec + BLOCK - 1) / BLOCK;
     const int64_t r0 = min(n_rec, (int64_t)t * per), r1 = min(n_rec, r0 + per);
     const bool held = per <= kFixPer;
     // the thread's records, loaded independently of each other
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(kFixBlock) void k_edge_fixup(LaunchSet L)
     carry.has = 0;
     for (int v = 0; v < w; ++v) carry = run_combine(carry, wrun[v]);
     if (lane > 0) carry = run_combine(carry, left);
-    for (int v = w + 1; v < kFixBlock / kWave && next_h < 0; ++v) next_h = wfirst[v];
+    for (int v = w + 1; v < BLOCK / kWave && next_h < 0; ++v) next_h = wfirst[v];
     const int next_has = next_h >= 0;
     double* __restrict__ S1 = q.S1;
     double* __restrict__ S2 = q.S2;
@@ -1330,7 +1332,8 @@ void enqueue_tail(const IterPlan& P, hipStream_t s, const SideStreams* side)
         launch(k_hist_reduce, P.hist, P.n_hist, kHistBlock, 0, m);
         launch(k_refine, P.refine, P.n_refine, kRefineBlock, refine_lds, m);
         (void)hipEventRecord(side->join[0], m);
-        launch(k_edge_fixup, P.fixup, P.n_fixup, kFixBlock, 0, s);
+        launch(k_edge_fixup<kFixBlock>, P.fixup, P.n_fixup, kFixBlock, 0, s);
+        launch(k_edge_fixup<kFixSmallBlock>, P.fixup_s, P.n_fixup_s, kFixSmallBlock, 0, s);
         launch(k_est_partial, P.est, P.n_est, kRedBlock, 0, s);
         launch(k_est_final, P.one, P.n_one, kRedBlock, 0, s);
         launch(k_realloc, P.est, P.n_est, kRedBlock, 0, s);
@@ -1340,7 +1343,8 @@ void enqueue_tail(const IterPlan& P, hipStream_t s, const SideStreams* side)
     }
     launch(k_hist_records, P.rec, P.n_rec, kRecBlock, P.rec_lds, s);
     launch(k_hist_records, P.rec_det, P.n_rec_det, kRecDetBlock, P.rec_lds, s);
-    launch(k_edge_fixup, P.fixup, P.n_fixup, kFixBlock, 0, s);
+    launch(k_edge_fixup<kFixBlock>, P.fixup, P.n_fixup, kFixBlock, 0, s);
+    launch(k_edge_fixup<kFixSmallBlock>, P.fixup_s, P.n_fixup_s, kFixSmallBlock, 0, s);
     launch(k_hist_reduce, P.hist, P.n_hist, kHistBlock, 0, s);
     launch(k_est_partial, P.est, P.n_est, kRedBlock, 0, s);
     launch(k_est_final, P.one, P.n_one, kRedBlock, 0, s);

@@ -47,6 +47,11 @@ constexpr int kRecDetBlock = 64;
 constexpr int kRecUnroll = 4;
 constexpr int kRefineBlock = 256;
 constexpr int kFixBlock = 1024;  // edge fix-up: one workgroup per request
+// Requests with at most kFixSmallRecs edge records (most served requests)
+// take a workgroup of kFixSmallBlock threads instead: many then fit on a CU
+// at once, where the full workgroup left most of its threads idle.
+constexpr int kFixSmallBlock = 256;
+constexpr int kFixSmallRecs = 2048;  // kFixSmallBlock x the records a thread holds
 
 // Device-resident scalars of one problem.
 struct DevState {
@@ -149,8 +154,8 @@ struct SampleGroup {
 // Every launch of one batched iteration over a set of requests: the launch
 // sets share the request table and differ in their workgroup counts.
 struct IterPlan {
-    LaunchSet scan_local, one, hist, rec, rec_det, fixup, est, refine, check;
-    int n_scan_local, n_one, n_hist, n_rec, n_rec_det, n_fixup, n_est, n_refine, n_check;
+    LaunchSet scan_local, one, hist, rec, rec_det, fixup, fixup_s, est, refine, check;
+    int n_scan_local, n_one, n_hist, n_rec, n_rec_det, n_fixup, n_fixup_s, n_est, n_refine, n_check;
     size_t rec_lds;  // dynamic LDS of the records-to-histogram pass
     SampleGroup groups[kMaxGroups];
     int n_groups;

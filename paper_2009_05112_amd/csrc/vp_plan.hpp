@@ -31,12 +31,12 @@ public:
     // Device memory for the tables of up to n requests, allocated ahead of
     // the first build (hipFree of an outgrown table waits for the device, so
     // a builder that grows while a step runs would stall the host until it
-    // ends).  Per request: two pointer words and one base in each of the nine
+    // ends).  Per request: two pointer words and one base in each of the ten
     // per-request sets and in the sampling groups; per set and group: one
     // alignment word and the final base.
     hipError_t reserve(int n)
     {
-        const size_t words = 30 * (size_t)n + 2 * (9 + (size_t)kMaxGroups) + 16;
+        const size_t words = 33 * (size_t)n + 2 * (10 + (size_t)kMaxGroups) + 16;
         const size_t bytes = words * sizeof(int32_t);
         if (bytes <= cap_) return hipSuccess;
         (void)hipFree(dev_);
@@ -84,7 +84,8 @@ public:
             *total = acc;
             return p;
         };
-        int n_scan = 0, n_one = 0, n_hist = 0, n_rec = 0, n_rec_det = 0, n_fix = 0, n_est = 0, n_ref = 0, n_chk = 0;
+        int n_scan = 0, n_one = 0, n_hist = 0, n_rec = 0, n_rec_det = 0, n_fix = 0, n_fix_s = 0, n_est = 0, n_ref = 0,
+            n_chk = 0;
         Pending ps = add_set([](const ReqArgs& q) { return (int)scan_blocks(q.n_hc); }, &n_scan);
         Pending po = add_set([](const ReqArgs&) { return 1; }, &n_one);
         Pending ph = add_set(
@@ -103,7 +104,10 @@ public:
         Pending pck = add_set(
             [](const ReqArgs& q) { return q.checks ? check_blocks(q.n_hc, (int64_t)q.dim * (q.n_g + 1)) : 0; },
             &n_chk);
-        Pending pf = add_set([](const ReqArgs&) { return 1; }, &n_fix);
+        // edge fix-up: one workgroup per request, a small one for requests
+        // with few edge records (two per wave)
+        Pending pf = add_set([](const ReqArgs& q) { return 2 * q.n_waves > kFixSmallRecs ? 1 : 0; }, &n_fix);
+        Pending pfs = add_set([](const ReqArgs& q) { return 2 * q.n_waves > kFixSmallRecs ? 0 : 1; }, &n_fix_s);
         Pending pe = add_set([](const ReqArgs& q) { return q.est_blocks; }, &n_est);
         Pending pr = add_set([](const ReqArgs& q) { return q.dim; }, &n_ref);
         // sampling groups: requests with the same kernel instantiation
@@ -162,6 +166,7 @@ public:
         out->rec_det = mk(prd);
         out->check = mk(pck);
         out->fixup = mk(pf);
+        out->fixup_s = mk(pfs);
         out->est = mk(pe);
         out->refine = mk(pr);
         out->n_scan_local = n_scan;
@@ -171,6 +176,7 @@ public:
         out->n_rec_det = n_rec_det;
         out->n_check = n_chk;
         out->n_fixup = n_fix;
+        out->n_fixup_s = n_fix_s;
         out->n_est = n_est;
         out->n_refine = n_ref;
         out->n_groups = (int)keys.size();
