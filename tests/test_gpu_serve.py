@@ -319,3 +319,26 @@ def test_served_results_equal_oracle(ctx):
         if np.isfinite(o["chi2"]):
             assert abs(r["chi2"] - o["chi2"]) <= (1e-9 if p.precision == "fp64" else 1e-3) * max(abs(o["chi2"]), 1e-3), what
     assert tied <= 1
+
+
+def test_served_fixup_sizes_equal_oracle(ctx):
+    """A served request with more than 2048 edge records (its hypercube sums
+    joined across waves by the 1024-thread fix-up) beside one with fewer (the
+    256-thread fix-up), each against the CPU oracle end to end (Sec. 3 steps
+    1-4): sample counts exactly, mean and error at 1e-12."""
+    import oracle
+    p, f = W.cfg_small_d4()
+    reqs = [(p.with_(n_ev=1_300_000, n_iter=3, seed=71), f), (p.with_(n_ev=300_000, n_iter=3, seed=72), f)]
+    s = B.Server(ctx)
+    tickets = [s.submit(pp, ff) for pp, ff in reqs]
+    res = [s.wait(t) for t in tickets]
+    s.close()
+    for (pp, ff), r in zip(reqs, res):
+        o = oracle.Problem(pp, ff).integrate()
+        what = f"N_ev={pp.n_ev}"
+        if (r["ties"] or o["ties"]) and r["n_evals"] != o["n_evals"]:
+            assert abs(r["mean"] - o["mean"]) <= 5 * np.hypot(r["sdev"], o["sdev"]), what
+            continue
+        assert r["n_evals"] == o["n_evals"], what
+        assert abs(r["mean"] - o["mean"]) <= 1e-12 * abs(o["mean"]), (what, r["mean"], o["mean"])
+        assert abs(r["sdev"] - o["sdev"]) <= 1e-12 * abs(o["sdev"]), (what, r["sdev"], o["sdev"])
