@@ -158,6 +158,8 @@ struct SampleArgs {
     int32_t n_g, n_st;
     double R;               // n_g / n_st
     float R32;
+    double R53;             // R 2^-53 and R32 2^-24 (the packed form of k + u)
+    float R32s;
     uint32_t key0, key1, it;
     int32_t hist_mode;      // 0 weighted, 1 literal
     int32_t hist_axes;      // training data of axes [0, hist_axes) privatised in LDS

@@ -381,6 +381,8 @@ static void fill_req(vp_problem* p)
     a.n_st = p->n_st;
     a.R = p->R;
     a.R32 = (float)P.n_g / (float)p->n_st;
+    a.R53 = std::ldexp(a.R, -53);
+    a.R32s = std::ldexp(a.R32, -24);
     a.key0 = (uint32_t)(P.seed & 0xffffffffu);
     a.key1 = (uint32_t)(P.seed >> 32);
     a.it = (uint32_t)p->it;
@@ -641,6 +643,11 @@ static vp_status compute_shape(vp_ctx* ctx, const vp_params* P, const vp_integra
     }
     sh->n_hc = nhc;
     const int prec = P->precision;
+    // the sampling kernels join a digit and the random bits of its axis in
+    // one 32-bit word at these dimensions (uniform counts only); validation
+    // already keeps N_st^D <= n_ev / 2 < 2^30, which bounds the digits
+    if (!sh->mix && ((prec == VP_FP64 && D >= 6 && sh->n_st > 32) || (prec != VP_FP64 && D >= 4 && sh->n_st > 256)))
+        return fail(VP_ERR_INVALID_ARG, "n_st %d too large for dim %d", sh->n_st, D);
     // training data: as many axes as fit privatised in LDS beside the
     // integrand constants, the rest as records
     const size_t fcb = fc_lds_bytes(prec, f->kind, D) + 16;

@@ -445,6 +445,8 @@ struct SampleHot {
     int32_t n_g;
     double R;
     float R32;
+    double R53;
+    float R32s;
     const double* Rv;    // mixed stratification: R_mu per axis (LDS)
     const float* Rv32;
 };
@@ -456,6 +458,23 @@ struct SampleHot {
 // x = x_i + Delta x_i delta, J = prod_mu N_g Delta x_i.
 // FP64: u from 53 bits -- the high word of axis mu is word mu of the
 // stream, its low word is word D + mu.
+// Packed form of k + u: where every digit is known to be small, the digit
+// joins the high random bits in one 32-bit word (one funnel shift), so the
+// integer k 2^53 + U (split precisions: k 2^24 + U) is rounded once on its
+// conversion or fma, just as k + u is rounded in the plain form; the power
+// of two moves into R.  The same t bit for bit, with three operations fewer
+// per axis.  The uniform stratification keeps N_st^D <= n_ev / 2 < 2^30, so
+// the digits are below 32 for D >= 6 and below 182 for D >= 4: the packed
+// form is taken there (k < 32 with 27 random bits beside it in double
+// precision, k < 256 with 24 in the split ones).
+template <int D, bool MIX>
+constexpr bool kPack64 = !MIX && D >= 6;
+template <int D, bool MIX>
+constexpr bool kPack32 = !MIX && D >= 4;
+__device__ __forceinline__ uint32_t join_digit(int32_t k, uint32_t w, int shift)
+{
+    return __builtin_amdgcn_alignbit((uint32_t)k, w, (uint32_t)shift);
+}
 // Where the generate mode of a batched integrand puts a sample: x at
 // x[mu * n + pos], J at jac[pos]; its increment indices, 16-bit, in groups of
 // eight axes at idx[(pos * ceil(D / 8) + g) * 8 ..] (one 16-byte store and
@@ -514,10 +533,16 @@ __device__ __forceinline__ double sample_fp64(const SampleHot& a, const MapPair6
                 philox4x32_10(j, h, a.it, (uint32_t)lb, a.key0, a.key1, lo_blk);
                 lo_have = lb;
             }
-            const double hi = (double)(hi_blk[r] >> 5);
-            const double lo = (double)(lo_blk[lw % 4] >> 6);
-            const double u = fma(hi, 0x1p-27, lo * 0x1p-53);  // exact: a 53-bit integer times 2^-53
-            const double t = ((double)k[mu] + u) * (MIX ? a.Rv[mu] : a.R);
+            double t;
+            if constexpr (kPack64<D, MIX>) {
+                const double hk = (double)join_digit(k[mu], hi_blk[r], 5);  // k 2^27 + (w >> 5), exact
+                t = fma(hk, 0x1p26, (double)(lo_blk[lw % 4] >> 6)) * a.R53;
+            } else {
+                const double hi = (double)(hi_blk[r] >> 5);
+                const double lo = (double)(lo_blk[lw % 4] >> 6);
+                const double u = fma(hi, 0x1p-27, lo * 0x1p-53);  // exact: a 53-bit integer times 2^-53
+                t = ((double)k[mu] + u) * (MIX ? a.Rv[mu] : a.R);
+            }
             int i = (int)t;
             i = i < n_g - 1 ? i : n_g - 1;
             double delta = t - (double)i;
@@ -583,8 +608,13 @@ __device__ __forceinline__ float sample_fp32(const SampleHot& a, const MapPair32
         for (int r = 0; r < 4; ++r) {
             const int mu = 4 * g + r;
             if (mu >= D) break;
-            const float u = (float)(w[r] >> 8) * 0x1p-24f;
-            const float t = ((float)k[mu] + u) * (MIX ? a.Rv32[mu] : a.R32);
+            float t;
+            if constexpr (kPack32<D, MIX>) {
+                t = (float)join_digit(k[mu], w[r], 8) * a.R32s;
+            } else {
+                const float u = (float)(w[r] >> 8) * 0x1p-24f;
+                t = ((float)k[mu] + u) * (MIX ? a.Rv32[mu] : a.R32);
+            }
             int i = (int)t;
             i = i < n_g - 1 ? i : n_g - 1;
             float delta = t - (float)i;
@@ -689,6 +719,8 @@ __device__ __forceinline__ void dump_share(const SampleArgs& a, int64_t s_a, int
     hot.n_g = n_g;
     hot.R = a.R;
     hot.R32 = a.R32;
+    hot.R53 = a.R53;
+    hot.R32s = a.R32s;
     const MapT* mix_r = lds_fc + fc_strat_offset(kind, D);
     const MapT* mix_n = mix_r + D;
     if constexpr (PREC == P_FP64) {
@@ -888,6 +920,8 @@ __global__ __launch_bounds__(sample_block(PREC, KIND, D, MAPL == MAP_LDS, REC)) 
     hot.n_g = n_g;
     hot.R = a.R;
     hot.R32 = a.R32;
+    hot.R53 = a.R53;
+    hot.R32s = a.R32s;
     // mixed stratification: R_mu, then N_st^mu, after the integrand constants
     const MapT* mix_r = lds_fc + fc_strat_offset(kind, D);
     const MapT* mix_n = mix_r + D;
