@@ -146,3 +146,29 @@ def test_maxsize_d8_one_iteration():
     assert res["n_evals"] == 4 * 12 ** 8
     gp.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("prec,dim,n_st", [("fp64", 6, 17), ("fp32_acc64", 4, 70)])
+def test_fullsize_high_digits(prec, dim, n_st):
+    """Digits of 16 and more (double precision, D=6) and of 64 and more (the
+    split, D=4) reach the top bits of the 32-bit word in which the sampler
+    joins a hypercube's digit with its axis's random bits (Sec. 3, uniform y
+    within each hypercube).  About 2.4e7 hypercubes, four samples each; the
+    last hypercubes (every digit at its largest) are dumped and compared
+    sample by sample, the sampled sums and the steps after them as above."""
+    ctx = B.Context(0)
+    p = W.Params(dim=dim, n_ev=100_000_000, n_g=1000, n_iter=1, seed=6, precision=prec,
+                 n_st_axes=np.full(dim, n_st, dtype=np.int32))
+    f = W.gauss_single(dim, coef=20.0)
+    gp = B.Problem(ctx, p, f)
+    op = oracle.Problem(p, f, n_st=gp.n_st)
+    assert (gp.n_st, gp.n_hc) == (n_st, n_st ** dim)
+    fmap, n_h, it = gp.map(), gp.alloc(), gp.it
+    assert int(n_h.min()) >= 4
+    hr = _arm_dump(gp, n_h, gp.n_hc - 2000)
+    gp.iterate(1)
+    kw = {} if prec == "fp64" else {"rtol": 2e-6, "floor": 1e-12}
+    _check_iteration(gp, op, fmap, n_h, it, **kw)
+    _check_dump(gp, op, fmap, n_h, it, hr, rtol_f=1e-12 if prec == "fp64" else 2e-6)
+    gp.close()
+    ctx.close()
