@@ -21,8 +21,10 @@ from tests.parity import step_and_compare
 
 pytestmark = pytest.mark.gpu
 RTOL32 = 2e-6
-# per-hypercube sums below 1e-12 of the largest are compared absolutely (the
-# GPU flushes single-precision denormals; such values weigh nothing)
+# per-hypercube sums below 1e-12 of the largest are compared absolutely
+# (single-precision values near underflow are denormal, with few significant
+# bits, so one-ulp differences there are large relative errors; such values
+# weigh nothing)
 FLOOR32 = 1e-12
 
 
