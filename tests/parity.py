@@ -39,7 +39,8 @@ def step_and_compare(gp: B.Problem, op: oracle.Problem, rtol=RTOL64, rtol_hist=R
     same (map, n_h, it), compare every output.  Returns the oracle's outputs.
     floor: per-hypercube sums are compared up to an absolute floor of
     floor * max|sum| (single-precision paths: values near the FP32 underflow
-    threshold are flushed on the GPU and carry no weight in any result)."""
+    threshold are denormal, with few significant bits, and carry no weight in
+    any result)."""
     fmap = gp.map()
     n_h = gp.alloc()
     it = gp.it

@@ -1,10 +1,17 @@
 """GPU parity at the full D=8, N_ev=1e8 size (16.7M hypercubes), in the launch
-configuration the benchmark times.  The oracle recomputes sampled hypercubes
-one range at a time; the reductions, the allocation and the refinement are
-recomputed in full from the GPU's sums; the training data are checked through
-invariants that hold at any size.  The samples of one range of hypercubes per
-iteration are dumped by the sampling kernel (vp_debug_dump) and compared one
-by one with the oracle's: indices bit for bit, x and J to the last bit."""
+configuration the benchmark times.  The oracle runs the whole iteration on the
+host's threads (one contiguous block of hypercubes each): every hypercube's
+sums and every bin of the training data are compared with it, and the
+reductions, the allocation and the refinement are recomputed in full from the
+GPU's sums.  At the largest size the interface accepts (1.72e9 samples)
+sampled ranges of hypercubes are recomputed instead, and the training data are
+checked through invariants that hold at any size.  The samples of one range of
+hypercubes per iteration are dumped by the sampling kernel (vp_debug_dump) and
+compared one by one with the oracle's: indices bit for bit, x and J to the
+last bit."""
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -57,14 +64,49 @@ def _check_dump(gp, op, fmap, n_h, it, hr, rtol_f=1e-12):
                                err_msg=f"dumped f(x) of hypercubes {hr}")
 
 
-def _check_iteration(gp, op, fmap, n_h, it, rtol=RTOL64, floor=0.0, largest=True):
+def _oracle_iteration(op, fmap, n_h, it):
+    """The whole iteration from the oracle: per-hypercube sums S1, S2 and the
+    training data H, W [dim][n_g], the hypercubes in one contiguous block per
+    host thread (the oracle's range call releases the interpreter), the
+    blocks' training data added in block order."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cap = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    n = max(1, min(n, cap) if cap > 0 else n)
+    edges = [op.n_hc * t // n for t in range(n + 1)]
+    with ThreadPoolExecutor(max_workers=n) as ex:
+        parts = list(ex.map(lambda t: op.sample_range(fmap, n_h, it, edges[t], edges[t + 1]), range(n)))
+    H = np.zeros_like(parts[0]["H"])
+    W = np.zeros_like(parts[0]["W"])
+    for q in parts:
+        H += q["H"]
+        W += q["W"]
+    return np.concatenate([q["S1"] for q in parts]), np.concatenate([q["S2"] for q in parts]), H, W
+
+
+def _check_iteration(gp, op, fmap, n_h, it, rtol=RTOL64, floor=0.0, largest=True, rtol_hist=None,
+                     full=True):
     """rtol, floor: the per-hypercube sums' bar (the split precisions compare
     sums of single-precision values; everything after the sums is double
-    precision and held to 1e-12 either way)."""
+    precision and held to 1e-12 either way).  rtol_hist: the training data's
+    bar, relative to each axis's total (default rtol).  full: compare every
+    hypercube's sums and every bin of the training data with the oracle's
+    whole iteration; else sampled ranges of hypercubes, and the training data
+    by their invariants alone."""
     acc = gp.accum()
     res = gp.result()
     top1, top2 = np.abs(acc["S1"]).max(), np.abs(acc["S2"]).max()
-    for (a, b) in _sampled_ranges(n_h, seed=it, largest=largest):
+    if full:
+        rh = rtol if rtol_hist is None else rtol_hist
+        S1o, S2o, Ho, Wo = _oracle_iteration(op, fmap, n_h, it)
+        s1, s2 = acc["S1"], acc["S2"]
+        sc1 = np.maximum(np.maximum(np.abs(s1), np.abs(S1o)), floor * top1 / rtol)
+        sc2 = np.maximum(np.maximum(np.abs(s2), np.abs(S2o)), floor * top2 / rtol)
+        assert_close(s1, S1o, rtol, scale=sc1, what="S1 (every hypercube)")
+        assert_close(s2, S2o, rtol, scale=sc2, what="S2 (every hypercube)")
+        for m in range(Ho.shape[0]):
+            assert_close(acc["W"][m], Wo[m], rh, scale=np.abs(Wo[m]).sum(), what=f"full-size W[{m}]")
+            assert_close(acc["H"][m], Ho[m], rh, scale=np.abs(Ho[m]).sum(), what=f"full-size H[{m}]")
+    for (a, b) in ([] if full else _sampled_ranges(n_h, seed=it, largest=largest)):
         o = op.sample_range(fmap, n_h, it, a, b)
         s1, s2 = acc["S1"][a:b], acc["S2"][a:b]
         sc1 = np.maximum(np.maximum(np.abs(s1), np.abs(o["S1"])), floor * top1 / rtol)
@@ -141,7 +183,7 @@ def test_maxsize_d8_one_iteration():
     assert int(n_h.min()) == int(n_h.max()) == 4
     hr = _arm_dump(gp, n_h, gp.n_hc - 1000, width=1000)  # samples numbered beyond 2^31
     gp.iterate(1)
-    res = _check_iteration(gp, op, fmap, n_h, it, largest=False)
+    res = _check_iteration(gp, op, fmap, n_h, it, largest=False, full=False)
     _check_dump(gp, op, fmap, n_h, it, hr)
     assert res["n_evals"] == 4 * 12 ** 8
     gp.close()
