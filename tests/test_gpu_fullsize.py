@@ -168,6 +168,29 @@ def test_fullsize_split_d8_two_iterations():
     ctx.close()
 
 
+def test_fullsize_batched_d8_two_iterations():
+    """The benchmark's batched-integrand workload: the D=8 three-Gaussian
+    problem at N_ev=1e8, its points written as structure-of-arrays buffers
+    and f evaluated by the example library's Gaussian mixture (a user
+    function); two iterations, each against the oracle's whole iteration."""
+    ctx = B.Context(0)
+    p, f = W.cfg_diag_d8()
+    bf = B.example_gauss_mix(f)
+    try:
+        gp = B.Problem(ctx, p, bf)
+        op = oracle.Problem(p, f, n_st=gp.n_st)
+        assert (gp.n_st, gp.n_hc) == (8, 8 ** 8)
+        for _ in range(2):
+            fmap, n_h, it = gp.map(), gp.alloc(), gp.it
+            gp.iterate(1)
+            res = _check_iteration(gp, op, fmap, n_h, it)
+        assert res["n_evals"] > 1.5e8
+        gp.close()
+    finally:
+        B.examples().vp_example_free_user(bf.user)
+    ctx.close()
+
+
 def test_maxsize_d8_one_iteration():
     """The largest N_ev the interface accepts (2^31 - 1) at D=8: N_st = 12,
     N_hc = 12^8 = 429,981,696 (R = 1000/12 is not an integer), four samples per
