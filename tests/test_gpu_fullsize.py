@@ -114,8 +114,15 @@ def _check_iteration(gp, op, fmap, n_h, it, rtol=RTOL64, floor=0.0, largest=True
         assert_close(s1, o["S1"], rtol, scale=sc1, what=f"S1[{a}:{b}]")
         assert_close(s2, o["S2"], rtol, scale=sc2, what=f"S2[{a}:{b}]")
     # invariants of the training data: every hypercube adds n_h * (1/n_h) = 1
-    # to W on every axis; every sample adds the same v^2/n_h to one bin per axis
-    np.testing.assert_allclose(acc["W"].sum(axis=1), gp.n_hc, rtol=1e-12)
+    # to W on every axis (the compensated split weighs by the single-precision
+    # 1/n_h, so n_h fl32(1/n_h)); every sample adds the same v^2/n_h to one bin
+    # per axis
+    if op.params.precision == "fp32_neumaier":
+        n32 = n_h.astype(np.float32)
+        w_tot = float(((np.float32(1.0) / n32).astype(np.float64) * n_h).sum())
+    else:
+        w_tot = float(gp.n_hc)
+    np.testing.assert_allclose(acc["W"].sum(axis=1), w_tot, rtol=1e-12)
     hs = acc["H"].sum(axis=1)
     np.testing.assert_allclose(hs, hs[0], rtol=1e-12)
     I, V = op.reduce(n_h, acc["S1"], acc["S2"])
@@ -147,13 +154,15 @@ def test_fullsize_diag_d8_two_iterations():
     ctx.close()
 
 
-def test_fullsize_split_d8_two_iterations():
-    """The precision split (single-precision map and integrand, double sums)
-    at the same size: sampled sums against the oracle in the same precision
-    (2e-6, as in the split's step-wise tests), the double-precision steps from
-    the GPU's sums at 1e-12."""
+@pytest.mark.parametrize("prec", ["fp32_acc64", "fp32_neumaier"])
+def test_fullsize_split_d8_two_iterations(prec):
+    """The precision split (single-precision map and integrand; double sums,
+    or compensated single-precision pairs) at the same size: the sums and
+    the training data against the oracle's whole iteration in the same
+    precision (2e-6, as in the split's step-wise tests), the double-precision
+    steps from the GPU's sums at 1e-12."""
     ctx = B.Context(0)
-    p, f = W.cfg_diag_d8(precision="fp32_acc64")
+    p, f = W.cfg_diag_d8(precision=prec)
     gp = B.Problem(ctx, p, f)
     op = oracle.Problem(p, f, n_st=gp.n_st)
     assert gp.map_place == "inner" and gp.hist_axes == 8
