@@ -200,6 +200,36 @@ def test_fullsize_batched_d8_two_iterations():
     ctx.close()
 
 
+def test_fullsize_deterministic_d8():
+    """The bitwise-deterministic mode at the benchmark's size: two runs of
+    two iterations agree bit for bit in every output, and each iteration of
+    the first passes the whole-iteration comparison with the oracle."""
+    ctx = B.Context(0)
+    p, f = W.cfg_diag_d8()
+    p = p.with_(flags=B.VP_FLAG_DETERMINISTIC)
+    runs = []
+    for k in range(2):
+        gp = B.Problem(ctx, p, f)
+        op = oracle.Problem(p, f, n_st=gp.n_st) if k == 0 else None
+        out = []
+        for _ in range(2):
+            fmap, n_h, it = gp.map(), gp.alloc(), gp.it
+            gp.iterate(1)
+            if op is not None:
+                _check_iteration(gp, op, fmap, n_h, it)
+            acc = gp.accum()
+            out.append({"S1": acc["S1"], "S2": acc["S2"], "H": acc["H"], "W": acc["W"], "map": gp.map(),
+                        "n_h": gp.alloc()})
+        r = gp.result()
+        out.append({key: np.asarray(r[key]) for key in ("mean", "sdev", "I", "V", "n_evals")})
+        runs.append(out)
+        gp.close()
+    for k, (x, y) in enumerate(zip(*runs)):
+        for key in x:
+            np.testing.assert_array_equal(x[key], y[key], err_msg=f"step {k}: {key}")
+    ctx.close()
+
+
 def test_maxsize_d8_one_iteration():
     """The largest N_ev the interface accepts (2^31 - 1) at D=8: N_st = 12,
     N_hc = 12^8 = 429,981,696 (R = 1000/12 is not an integer), four samples per
