@@ -287,13 +287,8 @@ def oracle_mix():
 
 def test_served_results_equal_oracle(ctx):
     """Every served request against the CPU oracle run end to end on the same
-    parameters (Sec. 3 steps 1-4, per request): sample counts and degrees of
-    freedom exactly; mean and error at 1e-12 (same-precision oracle and 2e-6
-    for the single-precision split), chi^2 at 1e-9.  A request where either
-    side met an allocation near-tie may take other sample counts after it (a
-    single hypercube counts its exact q = N_ev as one, on both sides, although
-    nothing can differ there).  Such a request is held to the tight bar whenever the sample
-    counts agree, else to 5 sigma; at most one may differ."""
+    parameters (Sec. 3 steps 1-4, per request), at the bar and near-tie rule
+    of _check_against_oracle."""
     reqs = oracle_mix()
     s = B.Server(ctx)
     tickets = [s.submit(p, f) for p, f in reqs]
@@ -317,15 +312,46 @@ def _oracle_runs(reqs):
         return list(ex.map(lambda pf: oracle.Problem(pf[0], pf[1]).integrate(), reqs))
 
 
+def _chi2_tol(o, p, eps):
+    """Bar for chi^2 = sum_j (I_j - I)^2 / s_j^2 over the kept iterations when
+    every I_j and s_j may differ by eps relative: the propagated error
+    sum_j 2 |I_j - I| eps (|I_j| + |I|) / s_j^2 + 2 eps (I_j - I)^2 / s_j^2,
+    which precise iterations (|I_j - I| small against |I_j|) make much larger
+    than eps chi^2; 1e-9 chi^2 at least."""
+    I = np.asarray(o["I"])[p.n_discard:]
+    sg = np.asarray(o["sig"])[p.n_discard:]
+    m = o["mean"]
+    d = I - m
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = 2.0 * np.abs(d) * eps * (np.abs(I) + abs(m)) / sg ** 2 + 2.0 * eps * d ** 2 / sg ** 2
+    bound = float(np.nansum(t[np.isfinite(t)]))
+    return max(1e-9 * max(abs(o["chi2"]), 1e-3), bound)
+
+
 def _check_against_oracle(reqs, res, max_tied=1):
+    """Each served result against oracle.integrate on the same parameters:
+    sample counts and degrees of freedom exactly; mean and error at 1e-12
+    (2e-6 for the single-precision split, whose oracle runs in the same
+    precision); chi^2 at the bar its conditioning gives (_chi2_tol).  A
+    request on which either side met an allocation near-tie on a problem of
+    more than one hypercube may allocate differently from that iteration on
+    (two ties taken in opposite directions keep even the sample count), so
+    from there it is another run of the method and is held to 5 sigma; at
+    most max_tied such requests, and no more than are held to the tight bar.
+    A single hypercube counts its exact q = N_ev as a tie on both sides
+    although nothing can differ there: it keeps the tight bar."""
+    import oracle
     tied = 0
     outs = _oracle_runs(reqs)
     for i, ((p, f), r, o) in enumerate(zip(reqs, res, outs)):
         what = f"request {i} (D={p.dim}, N_ev={p.n_ev}, {f.kind}, {p.precision})"
         assert r["n_iter_done"] == p.n_iter, what
-        if (r["ties"] or o["ties"]) and r["n_evals"] != o["n_evals"]:
+        if (r["ties"] or o["ties"]) and oracle.Problem(p, f).n_hc > 1:
             tied += 1
-            assert abs(r["mean"] - o["mean"]) <= 5 * np.hypot(r["sdev"], o["sdev"]), what
+            # (an iteration with zero variance gives the plain mean with a
+            # zero error; then the means are held to 1e-12)
+            bar = max(5 * np.hypot(r["sdev"], o["sdev"]), 1e-12 * abs(o["mean"]))
+            assert abs(r["mean"] - o["mean"]) <= bar, (what, r["mean"], o["mean"])
             continue
         assert r["n_evals"] == o["n_evals"], (what, r["n_evals"], o["n_evals"])
         assert r["dof"] == o["dof"], what
@@ -333,8 +359,9 @@ def _check_against_oracle(reqs, res, max_tied=1):
         assert abs(r["mean"] - o["mean"]) <= rtol * abs(o["mean"]), (what, r["mean"], o["mean"])
         assert abs(r["sdev"] - o["sdev"]) <= rtol * abs(o["sdev"]), (what, r["sdev"], o["sdev"])
         if np.isfinite(o["chi2"]):
-            assert abs(r["chi2"] - o["chi2"]) <= (1e-9 if p.precision == "fp64" else 1e-3) * max(abs(o["chi2"]), 1e-3), what
-    assert tied <= max_tied
+            tol = _chi2_tol(o, p, 1e-12) if p.precision == "fp64" else 1e-3 * max(abs(o["chi2"]), 1e-3)
+            assert abs(r["chi2"] - o["chi2"]) <= tol, (what, r["chi2"], o["chi2"], tol)
+    assert tied <= max_tied and tied <= len(reqs) - tied, (tied, len(reqs))
 
 
 def test_served_batch_sample_equal_oracle(ctx):
@@ -351,6 +378,25 @@ def test_served_batch_sample_equal_oracle(ctx):
     s.close()
     del prep
     _check_against_oracle(reqs, res)
+
+
+def test_served_stream_sample_equal_oracle(ctx):
+    """Eight requests of the served stream's distribution (correlated
+    Gaussians, D 3..21, 5-20 iterations, N_g = 1000; N_ev 1e5..1e6, the lower
+    part of the stream's range, so that the oracle finishes in seconds; from
+    D = 11 the training data go through records), submitted together, each
+    against the CPU oracle end to end at the bar of the mix above."""
+    reqs = [(r.params, r.integrand) for r in W.served_stream(n_req=8, rate=0.0, seed=31, nev_log=(5.0, 6.0))]
+    assert max(p.dim for p, _ in reqs) >= 11
+    s = B.Server(ctx)
+    prep = s.prepare(reqs)  # the C structures, kept alive until the requests finish
+    res = [s.wait(t) for t in s.submit_many(prep)]
+    s.close()
+    del prep
+    # at these sizes the narrow correlated peak is often not yet found (the
+    # estimates are 1e-143 .. 1e-35), and allocation near-ties occur in three
+    # of the eight requests
+    _check_against_oracle(reqs, res, max_tied=4)
 
 
 def test_served_fixup_sizes_equal_oracle(ctx):
