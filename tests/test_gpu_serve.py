@@ -268,7 +268,7 @@ def oracle_mix():
     shape (Gaussian mixtures, D 2..16, N_g = 500), the stream shape
     (correlated Gaussians, D >= 13, N_g = 300), a frozen phase with the
     unweighted average, mixed stratification, given per-axis counts, the +2
-    allocation rule, and the single-precision split."""
+    allocation rule, and both single-precision splits."""
     reqs = [(r.params, r.integrand) for r in
             W.served_batch(n_req=5, seed=13, nev_log=(3.6, 4.3), n_iter=4, n_g=500)]
     for r in W.served_stream(n_req=3, rate=0.0, seed=17, d_range=(13, 21), nev_log=(4.0, 4.4),
@@ -282,6 +282,7 @@ def oracle_mix():
     pd, fd = W.cfg_diag_d8(n_ev=60_000)
     reqs.append((pd.with_(n_iter=3, seed=95, realloc_plus2=True), fd))
     reqs.append((pd.with_(n_iter=3, seed=96, precision="fp32_acc64"), fd))
+    reqs.append((pd.with_(n_iter=3, seed=97, precision="fp32_neumaier"), fd))
     return reqs
 
 
