@@ -23,29 +23,6 @@ from tests.parity import RTOL64, assert_close, variance_scale
 pytestmark = pytest.mark.gpu
 
 
-def _sampled_ranges(n_h, budget=1_500_000, width=2000, n_random=300, seed=0, largest=True):
-    n_hc = n_h.size
-    starts = [0, n_hc // 3, n_hc // 2, n_hc - width]
-    rng = np.random.default_rng(seed)
-    out = []
-    used = 0
-    for s in starts:
-        e = min(n_hc, s + width)
-        c = int(n_h[s:e].astype(np.int64).sum())
-        if used + c > budget:
-            e = s + 1
-            c = int(n_h[s])
-        out.append((s, e))
-        used += c
-    # the largest hypercubes (span many waves) and random ones
-    big = list(np.argsort(n_h)[-5:]) if largest else []
-    for h in big + list(rng.integers(0, n_hc, n_random)):
-        if used + int(n_h[h]) <= 4 * budget:
-            out.append((int(h), int(h) + 1))
-            used += int(n_h[h])
-    return out
-
-
 def _arm_dump(gp, n_h, h0, width=2000):
     """Dump of the samples of hypercubes [h0, h0 + width) of the next iteration."""
     first = int(n_h[:h0].astype(np.int64).sum())
@@ -83,36 +60,27 @@ def _oracle_iteration(op, fmap, n_h, it):
     return np.concatenate([q["S1"] for q in parts]), np.concatenate([q["S2"] for q in parts]), H, W
 
 
-def _check_iteration(gp, op, fmap, n_h, it, rtol=RTOL64, floor=0.0, largest=True, rtol_hist=None,
-                     full=True):
-    """rtol, floor: the per-hypercube sums' bar (the split precisions compare
-    sums of single-precision values; everything after the sums is double
-    precision and held to 1e-12 either way).  rtol_hist: the training data's
-    bar, relative to each axis's total (default rtol).  full: compare every
-    hypercube's sums and every bin of the training data with the oracle's
-    whole iteration; else sampled ranges of hypercubes, and the training data
-    by their invariants alone."""
+def _check_iteration(gp, op, fmap, n_h, it, rtol=RTOL64, floor=0.0, rtol_hist=None):
+    """Every hypercube's sums and every bin of the training data against the
+    oracle's whole iteration.  rtol, floor: the per-hypercube sums' bar (the
+    split precisions compare sums of single-precision values; everything
+    after the sums is double precision and held to 1e-12 either way).
+    rtol_hist: the training data's bar, relative to each axis's total
+    (default rtol)."""
     acc = gp.accum()
     res = gp.result()
     top1, top2 = np.abs(acc["S1"]).max(), np.abs(acc["S2"]).max()
-    if full:
-        rh = rtol if rtol_hist is None else rtol_hist
-        S1o, S2o, Ho, Wo = _oracle_iteration(op, fmap, n_h, it)
-        s1, s2 = acc["S1"], acc["S2"]
-        sc1 = np.maximum(np.maximum(np.abs(s1), np.abs(S1o)), floor * top1 / rtol)
-        sc2 = np.maximum(np.maximum(np.abs(s2), np.abs(S2o)), floor * top2 / rtol)
-        assert_close(s1, S1o, rtol, scale=sc1, what="S1 (every hypercube)")
-        assert_close(s2, S2o, rtol, scale=sc2, what="S2 (every hypercube)")
-        for m in range(Ho.shape[0]):
-            assert_close(acc["W"][m], Wo[m], rh, scale=np.abs(Wo[m]).sum(), what=f"full-size W[{m}]")
-            assert_close(acc["H"][m], Ho[m], rh, scale=np.abs(Ho[m]).sum(), what=f"full-size H[{m}]")
-    for (a, b) in ([] if full else _sampled_ranges(n_h, seed=it, largest=largest)):
-        o = op.sample_range(fmap, n_h, it, a, b)
-        s1, s2 = acc["S1"][a:b], acc["S2"][a:b]
-        sc1 = np.maximum(np.maximum(np.abs(s1), np.abs(o["S1"])), floor * top1 / rtol)
-        sc2 = np.maximum(np.maximum(np.abs(s2), np.abs(o["S2"])), floor * top2 / rtol)
-        assert_close(s1, o["S1"], rtol, scale=sc1, what=f"S1[{a}:{b}]")
-        assert_close(s2, o["S2"], rtol, scale=sc2, what=f"S2[{a}:{b}]")
+    rh = rtol if rtol_hist is None else rtol_hist
+    S1o, S2o, Ho, Wo = _oracle_iteration(op, fmap, n_h, it)
+    s1, s2 = acc["S1"], acc["S2"]
+    sc1 = np.maximum(np.maximum(np.abs(s1), np.abs(S1o)), floor * top1 / rtol)
+    sc2 = np.maximum(np.maximum(np.abs(s2), np.abs(S2o)), floor * top2 / rtol)
+    assert_close(s1, S1o, rtol, scale=sc1, what="S1 (every hypercube)")
+    assert_close(s2, S2o, rtol, scale=sc2, what="S2 (every hypercube)")
+    del S1o, S2o, sc1, sc2
+    for m in range(Ho.shape[0]):
+        assert_close(acc["W"][m], Wo[m], rh, scale=np.abs(Wo[m]).sum(), what=f"W[{m}]")
+        assert_close(acc["H"][m], Ho[m], rh, scale=np.abs(Ho[m]).sum(), what=f"H[{m}]")
     # invariants of the training data: every hypercube adds n_h * (1/n_h) = 1
     # to W on every axis (the compensated split weighs by the single-precision
     # 1/n_h, so n_h fl32(1/n_h)); every sample adds the same v^2/n_h to one bin
@@ -244,7 +212,7 @@ def test_maxsize_d8_one_iteration():
     assert int(n_h.min()) == int(n_h.max()) == 4
     hr = _arm_dump(gp, n_h, gp.n_hc - 1000, width=1000)  # samples numbered beyond 2^31
     gp.iterate(1)
-    res = _check_iteration(gp, op, fmap, n_h, it, largest=False)
+    res = _check_iteration(gp, op, fmap, n_h, it)
     _check_dump(gp, op, fmap, n_h, it, hr)
     assert res["n_evals"] == 4 * 12 ** 8
     gp.close()
